@@ -1,0 +1,677 @@
+"""Plain FP64 CPU checker for structure-preserving H(curl) algebraic multigrid.
+
+TEST INFRASTRUCTURE ONLY.  This module is the oracle that the GPU library is
+checked against.  Only the test suite, the smoke check and the CPU-baseline leg
+of the benchmark may import it; the product path never calls it.  It shares no
+code with the GPU library: it takes its inputs from the ``synth`` generator and
+computes everything with numpy/scipy primitives in double precision, following
+the paper (Tuminaro & Glusa, "A structure preserving H-curl algebraic multigrid
+method for the eddy current equations").
+
+Paper references in docstrings name the section, equation, algorithm or table.
+
+Readings where the paper is silent or garbled (each is listed in the design doc):
+  R1  coarse edges of D_H are ordered lexicographically by (I, K), I < K, with
+      -1 at I and +1 at K (Sec. 2, eq. "RS coarse gradient" only says "strictly
+      upper triangular").
+  R3  the weight of Alg. 2 is W = Diag(3 - |D_H| 1) over coarse edges (the
+      printed |D_h| has the wrong dimension for B = |T| |D_H|^T W).
+  R4  Alg. 2 loops over fine edges (rows of P^(e)).
+  R6  Reduce_Dimension drops the column of the largest coarse node id of T_i.
+  R8  sparsity patterns are symbolic: products of absolute values, structural
+      zeros kept (Alg. 2 uses |.|).
+  R9  the energy is measured in A^(e) (footnote to eq. min2_hcurl allows it).
+  R10 P_0 = ones on the pattern, then the local min-norm correction (Sec. 6.1).
+  R11 projected CG is unpreconditioned CG with the Frobenius inner product on
+      the pattern, a fixed number of iterations (Sec. 3).
+  R12 smoothed aggregation uses omega = 4 / (3 rho(D^-1 A^(n))), rho from 20
+      power iterations, no dropping (Sec. 3, eq. "emin iteration"; drop tol 0
+      in Sec. 6.1).
+  R13 the nodal operator is A^(n) = D_h^T A^(e) D_h (the Hiptmair smoother of
+      Sec. 6.1 applies exactly this product).
+  R15 make_irreducible: two-phase, see ``make_irreducible``.
+  R18 Gauss-Seidel runs in a multicolour order (Jones-Plassmann, hashed
+      priorities) shared with the GPU path.
+  R19 PCG stops on the recursive residual, ||r|| <= tol ||b||; the FP32 V-cycle
+      uses the flexible (Polak-Ribiere) beta.
+
+Parity pins that do not exist: the FP32 V-cycle form (parity unpinned by the
+paper; checked by the true residual only).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+from scipy.sparse.csgraph import connected_components
+
+MASK64 = (1 << 64) - 1
+
+
+# ---------------------------------------------------------------------------
+# small helpers
+# ---------------------------------------------------------------------------
+
+def csr(A, shape=None) -> sp.csr_matrix:
+    """(rowptr, col, val) -> scipy CSR with sorted indices, duplicates summed."""
+    if sp.issparse(A):
+        M = A.tocsr()
+    else:
+        rowptr, col, val = A
+        n = len(rowptr) - 1
+        if shape is None:
+            shape = (n, n)
+        M = sp.csr_matrix((np.asarray(val, np.float64), np.asarray(col, np.int64), np.asarray(rowptr, np.int64)),
+                          shape=shape)
+    M = M.copy()
+    M.sum_duplicates()
+    M.sort_indices()
+    return M
+
+
+def gradient_matrix(tail, head, m: int) -> sp.csr_matrix:
+    """Discrete gradient D (n x m): row e has -1 at its tail node and +1 at its
+    head node (Sec. 1, the discrete gradient has at most two +-1 per row)."""
+    n = len(tail)
+    rows = np.repeat(np.arange(n), 2)
+    cols = np.stack([tail, head], axis=1).ravel()
+    vals = np.tile([-1.0, 1.0], n)
+    return csr(sp.csr_matrix((vals, (rows, cols)), shape=(n, m)))
+
+
+def symbolic_product(*mats) -> sp.csr_matrix:
+    """Pattern of |M1| |M2| ... as a 0/1 CSR (reading R8: no cancellation)."""
+    out = abs(mats[0]).astype(np.float64)
+    out.data[:] = 1.0
+    for M in mats[1:]:
+        B = abs(M).astype(np.float64)
+        B.data[:] = 1.0
+        out = out @ B
+        out.data[:] = 1.0
+    out = csr(out)
+    out.data[:] = 1.0
+    return out
+
+
+def on_pattern(pattern: sp.csr_matrix, M: sp.csr_matrix) -> sp.csr_matrix:
+    """Values of M placed on `pattern` (entries of M outside it are dropped,
+    pattern entries absent from M are explicit zeros)."""
+    pattern = csr(pattern)
+    M = csr(M)
+    ncol = pattern.shape[1]
+    prow = np.repeat(np.arange(pattern.shape[0], dtype=np.int64), np.diff(pattern.indptr))
+    pkey = prow * ncol + pattern.indices.astype(np.int64)
+    mrow = np.repeat(np.arange(M.shape[0], dtype=np.int64), np.diff(M.indptr))
+    mkey = mrow * ncol + M.indices.astype(np.int64)
+    pos = np.searchsorted(mkey, pkey)
+    pos = np.minimum(pos, max(len(mkey) - 1, 0))
+    hit = (len(mkey) > 0) & (mkey[pos] == pkey) if len(mkey) else np.zeros(len(pkey), bool)
+    vals = np.where(hit, M.data[pos] if len(mkey) else 0.0, 0.0)
+    return sp.csr_matrix((vals, pattern.indices.copy(), pattern.indptr.copy()), shape=pattern.shape)
+
+
+def product_on_symbolic_pattern(*mats) -> sp.csr_matrix:
+    """Numeric product placed on the symbolic pattern of the product."""
+    pat = symbolic_product(*mats)
+    num = mats[0]
+    for M in mats[1:]:
+        num = num @ M
+    return on_pattern(pat, num)
+
+
+def splitmix64(i: np.ndarray) -> np.ndarray:
+    """SplitMix64 finaliser applied to state i + golden-gamma (Steele, Lea and
+    Flood, 2014); one 64-bit output per integer i."""
+    with np.errstate(over="ignore"):
+        z = (np.asarray(i, np.uint64) + np.uint64(0x9E3779B97F4A7C15))
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def hash_unit(i: np.ndarray) -> np.ndarray:
+    """Uniform double in [0, 1) from the top 53 bits of splitmix64(i)."""
+    return (splitmix64(i) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+# ---------------------------------------------------------------------------
+# nodal hierarchy pieces (Sec. 2, Sec. 4.1, Alg. 3 first lines)
+# ---------------------------------------------------------------------------
+
+def nodal_operator(A: sp.csr_matrix, D: sp.csr_matrix) -> sp.csr_matrix:
+    """A^(n) = D^T A D on its symbolic pattern (reading R13)."""
+    return product_on_symbolic_pattern(D.T.tocsr(), A, D)
+
+
+def tentative_prolongator(agg: np.ndarray, m_coarse: int) -> sp.csr_matrix:
+    """Piecewise-constant P-bar: one 1 per row, in the column of the node's
+    aggregate (Sec. 2)."""
+    m = len(agg)
+    return csr(sp.csr_matrix((np.ones(m), (np.arange(m), np.asarray(agg, np.int64))), shape=(m, m_coarse)))
+
+
+def power_rho(An: sp.csr_matrix, iters: int = 20) -> float:
+    """Largest eigenvalue of D^-1 A^(n) by power iteration (reading R12);
+    start vector x_i = hash_unit(i); returns ||y|| / ||x|| of the last step."""
+    d = An.diagonal()
+    x = hash_unit(np.arange(An.shape[0]))
+    rho = 0.0
+    for _ in range(iters):
+        y = (An @ x) / d
+        nx = np.sqrt(np.dot(x, x))
+        ny = np.sqrt(np.dot(y, y))
+        rho = ny / nx
+        x = y / ny
+    return rho
+
+
+def sa_prolongator(An: sp.csr_matrix, agg: np.ndarray, m_coarse: int, power_iters: int = 20):
+    """Smoothed aggregation P^(n) = (I - omega D^-1 A^(n)) P-bar (the one-step
+    Jacobi view of Sec. 3, eq. "emin iteration", omega = 4/(3 rho)), then each
+    row scaled to sum 1 (Sec. 4.2, constant preservation)."""
+    Pbar = tentative_prolongator(agg, m_coarse)
+    rho = power_rho(An, power_iters)
+    omega = 4.0 / (3.0 * rho)
+    d = An.diagonal()
+    AP = product_on_symbolic_pattern(An, Pbar)
+    pat = symbolic_product(An, Pbar)
+    Pb = on_pattern(pat, Pbar)
+    P = Pb - sp.diags(omega / d) @ AP
+    P = on_pattern(pat, P)
+    rs = np.asarray(P.sum(axis=1)).ravel()
+    P = sp.diags(1.0 / rs) @ P
+    return csr(P), dict(rho=rho, omega=omega, row_sums_before=rs)
+
+
+def coarse_gradient(D: sp.csr_matrix, agg: np.ndarray, m_coarse: int):
+    """Coarse discrete gradient by the Reitzinger-Schoeberl rule with the
+    tentative prolongator (Sec. 2 eq. "RS coarse gradient", Sec. 4.1 eq.
+    "revised RS DH"): Z = Pbar^T D^T D Pbar, one coarse edge per nonzero of the
+    strictly upper triangle, ordered lexicographically (reading R1)."""
+    Pbar = tentative_prolongator(agg, m_coarse)
+    DP = csr(D @ Pbar)
+    DP.eliminate_zeros()
+    Z = csr(DP.T @ DP)
+    Z.eliminate_zeros()
+    U = csr(sp.triu(Z, k=1))
+    rows = np.repeat(np.arange(m_coarse), np.diff(U.indptr))
+    tail = rows.astype(np.int32)
+    head = U.indices.astype(np.int32)
+    return tail, head
+
+
+# ---------------------------------------------------------------------------
+# Emin_Setup (Alg. 2) and the local constraint systems (Sec. 4.2)
+# ---------------------------------------------------------------------------
+
+class Pattern:
+    """Sparsity pattern N of P^(e) and the per-row constraint data.
+
+    Rows are fine edges i; T_i = pattern of row i of |D_h||P^(n)| (coarse
+    nodes, sorted); N_i = coarse edges j with B_ij = 2, B = |T| |D_H|^T W."""
+
+    def __init__(self, N: sp.csr_matrix, T: sp.csr_matrix, R: sp.csr_matrix, DH_tail, DH_head):
+        self.N = N
+        self.T = T
+        self.R = R
+        self.tail = np.asarray(DH_tail)
+        self.head = np.asarray(DH_head)
+
+
+def emin_pattern(D: sp.csr_matrix, Pn: sp.csr_matrix, DH: sp.csr_matrix) -> Pattern:
+    """Alg. 2 first block: T, W, B and the initial pattern N (readings R3, R4)."""
+    T = symbolic_product(D, Pn)
+    absDH = abs(DH)
+    W = sp.diags(3.0 - np.asarray(absDH.sum(axis=1)).ravel())
+    B = csr(T @ absDH.T @ W)
+    N = B.copy()
+    N.data = (B.data == 2.0).astype(np.float64)  # N_ij = 1 if B_ij = 2
+    N.eliminate_zeros()
+    N = csr(N)
+    R = on_pattern(T, D @ Pn)  # r_i, the row of D_h P^(n) on T_i (eq. "one row")
+    return N, T, R
+
+
+def gradient_from_pairs(tail, head, m: int) -> sp.csr_matrix:
+    return gradient_matrix(np.asarray(tail), np.asarray(head), m)
+
+
+def local_graphs(N: sp.csr_matrix, T: sp.csr_matrix, tail, head):
+    """Local endpoint indices: for entry (i, j) of N, the positions of the tail
+    and head of coarse edge j inside T_i (sorted)."""
+    nrow = N.shape[0]
+    mH = T.shape[1]
+    nrow_of = np.repeat(np.arange(nrow, dtype=np.int64), np.diff(N.indptr))
+    trow_of = np.repeat(np.arange(nrow, dtype=np.int64), np.diff(T.indptr))
+    tkey = trow_of * mH + T.indices.astype(np.int64)
+    j = N.indices
+    kt = nrow_of * mH + np.asarray(tail, np.int64)[j]
+    kh = nrow_of * mH + np.asarray(head, np.int64)[j]
+    pt = np.searchsorted(tkey, kt)
+    ph = np.searchsorted(tkey, kh)
+    assert np.all(tkey[pt] == kt) and np.all(tkey[ph] == kh)
+    lt = pt - T.indptr[nrow_of]
+    lh = ph - T.indptr[nrow_of]
+    return lt.astype(np.int64), lh.astype(np.int64)
+
+
+def disconnected_rows(N, T, lt, lh):
+    """Rows whose local graph (T_i nodes, N_i edges) is not connected (Sec. 4.2,
+    irreducibility).  Returns the row ids."""
+    bad = []
+    J = np.diff(T.indptr)
+    for i in np.nonzero(J > 1)[0]:
+        a, b = N.indptr[i], N.indptr[i + 1]
+        nJ = J[i]
+        if b == a:
+            bad.append(i)
+            continue
+        G = sp.csr_matrix((np.ones(b - a), (lt[a:b], lh[a:b])), shape=(nJ, nJ))
+        nc, _ = connected_components(G, directed=False)
+        if nc > 1:
+            bad.append(i)
+    return np.array(bad, np.int64)
+
+
+class LocalSystems:
+    """Per-row factors of the transposed constraint sub-matrix G~_i (Sec. 4.2:
+    QR of the D_H sub-matrix, min-norm solution Q~ R~^-T r~).
+
+    Rows are grouped by shape (n_p, |J|) so that the independent small QRs run
+    as stacked numpy calls; the arithmetic per row is the plain definition."""
+
+    def __init__(self, N, T, R, lt, lh):
+        self.nrow = N.shape[0]
+        npv = np.diff(N.indptr)
+        Jv = np.diff(T.indptr)
+        self.groups = []
+        shapes = np.stack([npv, Jv], axis=1)
+        keys, inv = np.unique(shapes, axis=0, return_inverse=True)
+        inv = inv.ravel()
+        for g, (n_p, nJ) in enumerate(keys):
+            rows = np.nonzero(inv == g)[0]
+            if nJ <= 1:
+                # |T_i| = 1: empty row of P^(e); the constraint needs r_i = 0
+                r = R.data[T.indptr[rows]] if nJ == 1 else np.zeros(0)
+                self.groups.append(dict(rows=rows, n_p=0, k=0, r_empty=r))
+                continue
+            k = nJ - 1  # reading R6: drop the last (largest) coarse node
+            pos = N.indptr[rows][:, None] + np.arange(n_p)[None, :]
+            G = np.zeros((len(rows), n_p, nJ))
+            bidx = np.repeat(np.arange(len(rows)), n_p)
+            eidx = np.tile(np.arange(n_p), len(rows))
+            G[bidx, eidx, lt[pos].ravel()] = -1.0
+            G[bidx, eidx, lh[pos].ravel()] = 1.0
+            Gt = G[:, :, :k]
+            Q, Rr = np.linalg.qr(Gt, mode="reduced")
+            rpos = T.indptr[rows][:, None] + np.arange(nJ)[None, :]
+            rfull = R.data[rpos]
+            self.groups.append(dict(rows=rows, n_p=n_p, k=k, pos=pos, G=G, Gt=Gt, Q=Q, R=Rr,
+                                    rt=rfull[:, :k], rfull=rfull))
+
+    def project(self, x: np.ndarray) -> np.ndarray:
+        """Pi(x) = x - Q~ Q~^T x row by row: the orthogonal projection onto the
+        null space of the constraints (Sec. 3, projected CG; Sec. 4.2)."""
+        y = x.copy()
+        for g in self.groups:
+            if g["n_p"] == 0:
+                continue
+            xv = x[g["pos"]]
+            c = np.einsum("bpk,bp->bk", g["Q"], xv)
+            y[g["pos"]] = xv - np.einsum("bpk,bk->bp", g["Q"], c)
+        return y
+
+    def make_feasible(self, x: np.ndarray) -> np.ndarray:
+        """x + Q~ R~^-T (r~ - G~^T x): the closest point to x satisfying the
+        commuting constraint of every row (Sec. 4.2 min-norm solution)."""
+        y = x.copy()
+        for g in self.groups:
+            if g["n_p"] == 0:
+                continue
+            xv = x[g["pos"]]
+            res = g["rt"] - np.einsum("bpk,bp->bk", g["Gt"], xv)
+            z = np.linalg.solve(np.transpose(g["R"], (0, 2, 1)), res[:, :, None])[:, :, 0]
+            y[g["pos"]] = xv + np.einsum("bpk,bk->bp", g["Q"], z)
+        return y
+
+    def histogram(self):
+        """(|J|, n_p) -> number of rows (the least-squares sub-problem sizes of
+        Tables 2 and 4)."""
+        h = {}
+        for g in self.groups:
+            nJ = g["k"] + 1 if g["n_p"] else (1 if len(g.get("r_empty", [])) else 0)
+            key = (int(nJ), int(g["n_p"]))
+            h[key] = h.get(key, 0) + len(g["rows"])
+        return h
+
+
+def make_irreducible(D, Pn, DH_tail, DH_head, mH):
+    """Reading R15 of make_irreducible (Alg. 2): while some row's local graph is
+    disconnected, collect for every such row one new coarse edge (I, K), I in
+    the component holding the row's smallest coarse node, K outside it, chosen
+    by the largest |(P^T D^T D P)_IK| (ties: smallest (min, max) pair); append
+    the deduplicated new edges, sorted, after the existing ones; rebuild N."""
+    tail = np.asarray(DH_tail, np.int32)
+    head = np.asarray(DH_head, np.int32)
+    added_total = 0
+    Zs = csr(Pn.T @ D.T @ D @ Pn)
+    for _ in range(64):
+        DH = gradient_matrix(tail, head, mH)
+        N, T, R = emin_pattern(D, Pn, DH)
+        lt, lh = local_graphs(N, T, tail, head)
+        bad = disconnected_rows(N, T, lt, lh)
+        if len(bad) == 0:
+            return tail, head, added_total
+        new = set()
+        for i in bad:
+            nodes = T.indices[T.indptr[i]:T.indptr[i + 1]]
+            a, b = N.indptr[i], N.indptr[i + 1]
+            nJ = len(nodes)
+            G = sp.csr_matrix((np.ones(b - a), (lt[a:b], lh[a:b])), shape=(nJ, nJ))
+            _, lab = connected_components(G, directed=False)
+            c0 = lab[0]
+            best = None
+            for p in np.nonzero(lab == c0)[0]:
+                for q in np.nonzero(lab != c0)[0]:
+                    I, K = int(nodes[p]), int(nodes[q])
+                    lo, hi = min(I, K), max(I, K)
+                    w = abs(Zs[lo, hi])
+                    cand = (-w, lo, hi)
+                    if best is None or cand < best:
+                        best = cand
+            new.add((best[1], best[2]))
+        new = sorted(new)
+        tail = np.r_[tail, np.array([e[0] for e in new], np.int32)]
+        head = np.r_[head, np.array([e[1] for e in new], np.int32)]
+        added_total += len(new)
+    raise RuntimeError("make_irreducible did not converge")
+
+
+# ---------------------------------------------------------------------------
+# energy minimisation (Sec. 3, eq. KKT and projected CG; Sec. 4)
+# ---------------------------------------------------------------------------
+
+def masked_product(A: sp.csr_matrix, X: sp.csr_matrix, N: sp.csr_matrix) -> np.ndarray:
+    """Values of A X on the pattern N (the sparsity projection of Sec. 3)."""
+    return on_pattern(N, A @ X).data
+
+
+def with_values(N: sp.csr_matrix, v: np.ndarray) -> sp.csr_matrix:
+    return sp.csr_matrix((v, N.indices, N.indptr), shape=N.shape)
+
+
+def energy(A, N, p) -> float:
+    """sum_j 1/2 ||P_:j||_A^2 = 1/2 <P, A P>_F over the pattern (eq. min_problem)."""
+    return 0.5 * float(np.dot(p, masked_product(A, with_values(N, p), N)))
+
+
+def initial_guess(N, loc: LocalSystems) -> np.ndarray:
+    """P_0: every pattern entry set to one, then the local least-squares (min-norm)
+    correction onto the commuting constraint (Sec. 6.1, reading R10)."""
+    return loc.make_feasible(np.ones(N.nnz))
+
+
+def projected_cg(A, N, loc: LocalSystems, p0: np.ndarray, iters: int):
+    """Projected conjugate gradients on the KKT system (Sec. 3): CG on
+    Pi A-hat Pi with the Frobenius inner product on the pattern (reading R11).
+    Returns the final values and the energy after every iteration."""
+    p = p0.copy()
+    g = masked_product(A, with_values(N, p), N)
+    r = -loc.project(g)
+    d = r.copy()
+    rho = float(np.dot(r, r))
+    energies = [0.5 * float(np.dot(p, g))]
+    info = dict(rho=[rho], gamma=[])
+    for _ in range(iters):
+        if rho == 0.0:
+            break
+        q = loc.project(masked_product(A, with_values(N, d), N))
+        gamma = float(np.dot(d, q))
+        alpha = rho / gamma
+        p = p + alpha * d
+        r = r - alpha * q
+        rho_new = float(np.dot(r, r))
+        d = r + (rho_new / rho) * d
+        rho = rho_new
+        info["rho"].append(rho)
+        info["gamma"].append(gamma)
+        energies.append(energy(A, N, p))
+    p = loc.make_feasible(p)  # rounding cleanup: re-apply the affine step
+    return p, energies, info
+
+
+def projected_jacobi(A, N, loc: LocalSystems, p0: np.ndarray, iters: int, omega: float):
+    """The projected Jacobi emin iteration of Sec. 3 (eq. "emin iteration"):
+    P <- P - omega Pi(mask(D^-1 A P))."""
+    p = p0.copy()
+    dinv = 1.0 / A.diagonal()
+    for _ in range(iters):
+        dp = on_pattern(N, sp.diags(dinv) @ (A @ with_values(N, p))).data
+        p = p - omega * loc.project(dp)
+    return loc.make_feasible(p)
+
+
+# ---------------------------------------------------------------------------
+# Galerkin and the hierarchy (Sec. 2, Alg. 3)
+# ---------------------------------------------------------------------------
+
+def galerkin(P: sp.csr_matrix, A: sp.csr_matrix) -> sp.csr_matrix:
+    """A_H = P^T A P on its symbolic pattern (Sec. 2)."""
+    return product_on_symbolic_pattern(P.T.tocsr(), A, P)
+
+
+def build_level(A, tail, head, m, agg, opts):
+    """One coarsening step of Alg. 3 with smoothed aggregation from the given
+    aggregates; returns the level record and the coarse (A, tail, head, m)."""
+    D = gradient_matrix(tail, head, m)
+    An = nodal_operator(A, D)
+    mH = int(agg.max()) + 1
+    if opts.get("Pn") is not None:
+        Pn = csr(opts["Pn"])
+        sa = {}
+    else:
+        Pn, sa = sa_prolongator(An, agg, mH, opts.get("power_iters", 20))
+    cth, chd = coarse_gradient(D, agg, mH)
+    DH = gradient_matrix(cth, chd, mH)
+    N, T, R = emin_pattern(D, Pn, DH)
+    lt, lh = local_graphs(N, T, cth, chd)
+    bad = disconnected_rows(N, T, lt, lh)
+    added = 0
+    if len(bad):
+        cth, chd, added = make_irreducible(D, Pn, cth, chd, mH)
+        DH = gradient_matrix(cth, chd, mH)
+        N, T, R = emin_pattern(D, Pn, DH)
+        lt, lh = local_graphs(N, T, cth, chd)
+    loc = LocalSystems(N, T, R, lt, lh)
+    p0 = opts.get("p_init")
+    if p0 is None:
+        p0 = initial_guess(N, loc)
+    else:
+        p0 = loc.make_feasible(np.asarray(p0, np.float64))
+    if opts.get("emin_method", "cg") == "cg":
+        p, energies, info = projected_cg(A, N, loc, p0, opts.get("emin_iters", 10))
+    else:
+        p = projected_jacobi(A, N, loc, p0, opts.get("emin_iters", 1), opts.get("emin_omega", 0.5))
+        energies, info = [energy(A, N, p0), energy(A, N, p)], {}
+    Pe = with_values(N, p)
+    AH = galerkin(Pe, A)
+    lvl = dict(A=A, D=D, An=An, tail=np.asarray(tail), head=np.asarray(head), m=m, Pn=Pn, sa=sa, Pe=Pe, N=N, T=T,
+               R=R, lt=lt, lh=lh, loc=loc, p0=p0, energies=energies, cg=info, DH_tail=cth, DH_head=chd,
+               irreducible_added=added)
+    return lvl, (AH, cth, chd, mH)
+
+
+def setup(A, tail, head, m: int, aggregates, opts=None):
+    """The whole hierarchy (Alg. 3 per level): returns a list of levels; the
+    last one holds the coarsest operator and its Cholesky factor."""
+    opts = dict(opts or {})
+    levels = []
+    A = csr(A)
+    for li, agg in enumerate(aggregates):
+        if opts.get("max_levels") and li + 1 >= opts["max_levels"]:
+            break
+        lopts = dict(opts)
+        if li > 0:
+            lopts.pop("Pn", None)
+            lopts.pop("p_init", None)
+        lvl, (A, tail, head, m) = build_level(A, tail, head, m, np.asarray(agg), lopts)
+        levels.append(lvl)
+    D = gradient_matrix(tail, head, m)
+    coarse = dict(A=A, D=D, An=nodal_operator(A, D), tail=np.asarray(tail), head=np.asarray(head), m=m,
+                  chol=sla.cho_factor(A.toarray(), lower=True))
+    levels.append(coarse)
+    for lvl in levels[:-1]:
+        lvl["colors_A"] = color_graph(lvl["A"])
+        lvl["colors_An"] = color_graph(lvl["An"])
+    return levels
+
+
+def commuting_residual(lvl) -> float:
+    """max |P^(e) D_H - D_h P^(n)| (eq. "commute")."""
+    DH = gradient_matrix(lvl["DH_tail"], lvl["DH_head"], lvl["Pn"].shape[1])
+    E = lvl["Pe"] @ DH - lvl["D"] @ lvl["Pn"]
+    return float(abs(E).max()) if E.nnz else 0.0
+
+
+def operator_complexity(levels) -> float:
+    """sum of nnz(A_l) over levels / nnz(A_0) (Sec. 6.1)."""
+    return sum(l["A"].nnz for l in levels) / levels[0]["A"].nnz
+
+
+# ---------------------------------------------------------------------------
+# smoother, V-cycle and PCG (Sec. 6.1)
+# ---------------------------------------------------------------------------
+
+def color_graph(A: sp.csr_matrix) -> np.ndarray:
+    """Jones-Plassmann colouring of the graph of A (reading R18): priority of
+    vertex i is (splitmix64(i), i); every round, each uncoloured vertex whose
+    priority exceeds that of all its uncoloured neighbours takes the smallest
+    colour absent from its coloured neighbours."""
+    n = A.shape[0]
+    A = csr(A)
+    rows = np.repeat(np.arange(n), np.diff(A.indptr))
+    cols = A.indices.astype(np.int64)
+    off = rows != cols
+    rows, cols = rows[off], cols[off]
+    h = splitmix64(np.arange(n))
+    order = np.lexsort((np.arange(n), h))  # ascending (h, i)
+    rank = np.empty(n, np.int64)
+    rank[order] = np.arange(n)
+    color = np.full(n, -1, np.int64)
+    while np.any(color < 0):
+        unc = color < 0
+        e = unc[rows] & unc[cols]
+        mx = np.full(n, -1, np.int64)
+        np.maximum.at(mx, rows[e], rank[cols[e]])
+        sel = unc & (rank > mx)
+        sidx = np.nonzero(sel)[0]
+        pos = np.full(n, -1, np.int64)
+        pos[sidx] = np.arange(len(sidx))
+        e2 = sel[rows] & (color[cols] >= 0)
+        cmax = int(color.max()) + 2 if np.any(color >= 0) else 1
+        used = np.zeros((len(sidx), cmax + 1), bool)
+        used[pos[rows[e2]], color[cols[e2]]] = True
+        color[sidx] = np.argmin(used, axis=1)
+    return color
+
+
+def sgs(A: sp.csr_matrix, colors: np.ndarray, x: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """One symmetric Gauss-Seidel sweep, forward over colours then backward
+    (Sec. 6.1; order by reading R18).  Rows of one colour are not coupled, so
+    updating them together is Gauss-Seidel."""
+    x = x.copy()
+    d = A.diagonal()
+    nc = int(colors.max()) + 1 if len(colors) else 0
+    groups = [np.nonzero(colors == c)[0] for c in range(nc)]
+    for rows in groups + groups[::-1]:
+        Ar = A[rows]
+        x[rows] = x[rows] + (b[rows] - Ar @ x) / d[rows]
+    return x
+
+
+def hiptmair(lvl, x, b):
+    """Hiptmair sweep (Sec. 6.1): SGS on A; SGS on D^T A D c = D^T r from c = 0;
+    x += D c; SGS on A."""
+    A, D = lvl["A"], lvl["D"]
+    x = sgs(A, lvl["colors_A"], x, b)
+    r = b - A @ x
+    c = sgs(lvl["An"], lvl["colors_An"], np.zeros(D.shape[1], x.dtype), D.T @ r)
+    x = x + D @ c
+    x = sgs(A, lvl["colors_A"], x, b)
+    return x
+
+
+def vcycle(levels, b, li: int = 0):
+    """V-cycle: Hiptmair pre/post on every level, direct solve on the coarsest."""
+    if li == len(levels) - 1:
+        return sla.cho_solve(levels[-1]["chol"], b)
+    lvl = levels[li]
+    x = hiptmair(lvl, np.zeros_like(b), b)
+    r = b - lvl["A"] @ x
+    xc = vcycle(levels, lvl["Pe"].T @ r, li + 1)
+    x = x + lvl["Pe"] @ xc
+    return hiptmair(lvl, x, b)
+
+
+def pcg(levels, f, tol: float = 1e-8, maxit: int = 500, precond=None, flexible: bool = False):
+    """CG preconditioned by one V-cycle, x0 = 0, stop at ||r|| <= tol ||f||
+    (Sec. 6.1; reading R19)."""
+    A = levels[0]["A"]
+    M = precond or (lambda r: vcycle(levels, r))
+    x = np.zeros_like(f)
+    r = f.copy()
+    z = M(r)
+    p = z.copy()
+    rz = float(np.dot(r, z))
+    nf = float(np.linalg.norm(f))
+    hist = [1.0]
+    it = 0
+    while it < maxit:
+        q = A @ p
+        alpha = rz / float(np.dot(p, q))
+        x = x + alpha * p
+        r_new = r - alpha * q
+        it += 1
+        rel = float(np.linalg.norm(r_new)) / nf
+        hist.append(rel)
+        if rel <= tol:
+            r = r_new
+            break
+        z_new = M(r_new)
+        if flexible:
+            beta = float(np.dot(r_new, z_new - z)) / rz
+        else:
+            beta = float(np.dot(r_new, z_new)) / rz
+        rz = float(np.dot(r_new, z_new))
+        p = z_new + beta * p
+        r, z = r_new, z_new
+    true_rel = float(np.linalg.norm(f - A @ x)) / nf
+    return x, it, true_rel, hist
+
+
+def fp32_levels(levels):
+    """FP32 copies of A_l, A^(n)_l, P_l for the single-precision V-cycle; the
+    coarsest Cholesky stays FP64."""
+    out = []
+    for lvl in levels[:-1]:
+        l2 = dict(lvl)
+        for k in ("A", "An", "Pe", "D"):
+            l2[k] = lvl[k].astype(np.float32)
+        out.append(l2)
+    out.append(levels[-1])
+    return out
+
+
+def vcycle_fp32(levels32, b):
+    """V-cycle with float32 smoother and transfers; FP64 coarsest solve."""
+    def rec(li, bb):
+        if li == len(levels32) - 1:
+            return sla.cho_solve(levels32[-1]["chol"], bb.astype(np.float64)).astype(np.float32)
+        lvl = levels32[li]
+        x = hiptmair(lvl, np.zeros_like(bb), bb)
+        r = bb - lvl["A"] @ x
+        xc = rec(li + 1, (lvl["Pe"].T @ r).astype(np.float32))
+        x = x + lvl["Pe"] @ xc
+        return hiptmair(lvl, x, bb)
+    return rec(0, b.astype(np.float32)).astype(np.float64)

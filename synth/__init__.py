@@ -1,0 +1,260 @@
+"""Seeded synthetic inputs for the eddy-current model problem.
+
+The model problems of the paper's numerical section (Sec. 6.1) are unit cubes
+meshed by N^3 hexahedra, each split into six tetrahedra, discretised by
+lowest-order edge elements with natural boundary conditions.  This module builds
+those problems at any size, with the conductivity fields and node jitter used by
+the workloads of this project:
+
+* ``kuhn_mesh``      lattice nodes, Kuhn tetrahedra, oriented sorted edges
+* ``sigma_*``        constant, spherical inclusions, per-element lognormal
+* ``assemble``       Whitney curl-curl S, mass M or A = S + M (CSR)
+* ``box_aggregates`` per-level node aggregates (3-wide boxes, or vertex-centred)
+* ``rhs``            uniform[-1, 1] right-hand side
+* ``problem``        the named workloads
+
+Nothing here belongs to the multigrid method: the CPU checker and the GPU path
+both take their inputs from this module.  Random numbers come from numpy's
+PCG64 ``default_rng`` with the seeds given by the caller.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "meshgen.c")
+_SO = os.path.join(_HERE, "libsynth.so")
+_lock = threading.Lock()
+_lib_handle = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the C mesh generator (gcc, OpenMP) next to its source."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def _lib():
+    global _lib_handle
+    with _lock:
+        if _lib_handle is None:
+            build()
+            L = ctypes.CDLL(_SO)
+            P = ctypes.c_void_p
+            i64 = ctypes.c_int64
+            L.synth_edge_ptr.argtypes = [ctypes.c_int, P]
+            L.synth_edge_ptr.restype = i64
+            L.synth_edges.argtypes = [ctypes.c_int, P, P, P]
+            L.synth_tets.argtypes = [ctypes.c_int, P, P, P]
+            L.synth_edge_tets.argtypes = [i64, i64, P, P, P]
+            L.synth_row_counts.argtypes = [i64, P, P, P, P]
+            L.synth_assemble.argtypes = [i64, P, P, P, P, P, P, ctypes.c_int, P, P, P]
+            L.synth_tet_volumes.argtypes = [i64, P, P, P]
+            _lib_handle = L
+    return _lib_handle
+
+
+def _p(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def edge_count(N: int) -> int:
+    """Closed-form edge count of the six-tet split of an N^3 hex lattice:
+    axis edges 3N(N+1)^2, face diagonals 3N^2(N+1), body diagonals N^3."""
+    return 3 * N * (N + 1) ** 2 + 3 * N * N * (N + 1) + N ** 3
+
+
+def kuhn_mesh(N: int, jitter: float = 0.0, seed: int | None = None) -> dict:
+    """Unit-cube lattice with N^3 hexes split into Kuhn tets.
+
+    jitter: interior nodes move by uniform[-jitter*h, jitter*h] per coordinate.
+    """
+    L = _lib()
+    n = N + 1
+    nn = n ** 3
+    eptr = np.empty(nn + 1, np.int64)
+    ne = int(L.synth_edge_ptr(N, _p(eptr)))
+    tail = np.empty(ne, np.int32)
+    head = np.empty(ne, np.int32)
+    L.synth_edges(N, _p(eptr), _p(tail), _p(head))
+    ntet = 6 * N ** 3
+    tets = np.empty((ntet, 4), np.int32)
+    tet_edges = np.empty((ntet, 6), np.int32)
+    L.synth_tets(N, _p(eptr), _p(tets), _p(tet_edges))
+    h = 1.0 / N
+    ax = np.arange(n, dtype=np.float64) * h
+    kk, jj, ii = np.meshgrid(ax, ax, ax, indexing="ij")
+    coords = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1).copy()
+    if jitter > 0.0:
+        rng = np.random.default_rng(seed)
+        d = rng.uniform(-jitter * h, jitter * h, size=coords.shape)
+        lat = np.stack(np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij"), axis=-1).reshape(-1, 3)[:, ::-1]
+        interior = np.all((lat > 0) & (lat < N), axis=1)
+        coords[interior] += d[interior]
+    return dict(N=N, n=n, coords=coords, tets=tets, tet_edges=tet_edges, tail=tail, head=head, eptr=eptr)
+
+
+def tet_volumes(mesh: dict) -> np.ndarray:
+    vol = np.empty(mesh["tets"].shape[0], np.float64)
+    _lib().synth_tet_volumes(mesh["tets"].shape[0], _p(mesh["tets"]), _p(mesh["coords"]), _p(vol))
+    return vol
+
+
+def tet_centroids(mesh: dict) -> np.ndarray:
+    return mesh["coords"][mesh["tets"]].mean(axis=1)
+
+
+def sigma_const(mesh: dict, value: float = 1.0) -> np.ndarray:
+    return np.full(mesh["tets"].shape[0], float(value))
+
+
+def sigma_inclusions(mesh: dict, seed: int, inside: float = 1.0, background: float = 1e-3,
+                     count: int = 32, rmin: float = 0.05, rmax: float = 0.15) -> np.ndarray:
+    """Spherical inclusions: `count` centres ~U[0,1]^3, radii ~U[rmin,rmax]; a tet
+    belongs to an inclusion when its centroid lies inside the sphere."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(0.0, 1.0, size=(count, 3))
+    radii = rng.uniform(rmin, rmax, size=count)
+    c = tet_centroids(mesh)
+    inside_any = np.zeros(c.shape[0], bool)
+    for s in range(count):
+        d2 = ((c - centres[s]) ** 2).sum(axis=1)
+        inside_any |= d2 <= radii[s] ** 2
+    return np.where(inside_any, inside, background).astype(np.float64)
+
+
+def sigma_lognormal(mesh: dict, seed: int, s: float = 2.0, mu: float = 0.0) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return np.exp(mu + s * rng.standard_normal(mesh["tets"].shape[0]))
+
+
+_EDGE_TET_CACHE: dict = {}
+
+
+def _edge_tets(mesh: dict):
+    key = id(mesh["tet_edges"])
+    hit = _EDGE_TET_CACHE.get(key)
+    if hit is not None and hit[0] is mesh["tet_edges"]:
+        return hit[1], hit[2]
+    ne = mesh["tail"].shape[0]
+    ntet = mesh["tets"].shape[0]
+    etp = np.empty(ne + 1, np.int64)
+    etl = np.empty(6 * ntet, np.int32)
+    _lib().synth_edge_tets(ne, ntet, _p(mesh["tet_edges"]), _p(etp), _p(etl))
+    _EDGE_TET_CACHE.clear()
+    _EDGE_TET_CACHE[key] = (mesh["tet_edges"], etp, etl)
+    return etp, etl
+
+
+def assemble(mesh: dict, sigma: np.ndarray, which: str = "A"):
+    """Whitney edge-element operator in CSR (int64 rowptr, int32 col, f64 val).
+
+    which: "A" = S + M, "S" = curl-curl part, "M" = sigma-weighted mass part.
+    Element matrices: with g_a the gradient of barycentric lambda_a and local
+    edge (a,b) oriented tail a -> head b,
+      S[(ab),(cd)] = 4|T| (g_a x g_b).(g_c x g_d)
+      M[(ab),(cd)] = sigma_T [ (g_b.g_d) m_ac - (g_b.g_c) m_ad - (g_a.g_d) m_bc + (g_a.g_c) m_bd ],
+      m_xy = |T| (1 + delta_xy) / 20.
+    """
+    L = _lib()
+    code = {"A": 0, "S": 1, "M": 2}[which]
+    ne = mesh["tail"].shape[0]
+    etp, etl = _edge_tets(mesh)
+    cnt = np.empty(ne, np.int64)
+    L.synth_row_counts(ne, _p(etp), _p(etl), _p(mesh["tet_edges"]), _p(cnt))
+    rowptr = np.zeros(ne + 1, np.int64)
+    np.cumsum(cnt, out=rowptr[1:])
+    nnz = int(rowptr[-1])
+    col = np.empty(nnz, np.int32)
+    val = np.empty(nnz, np.float64)
+    sig = np.ascontiguousarray(sigma, np.float64)
+    L.synth_assemble(ne, _p(etp), _p(etl), _p(mesh["tets"]), _p(mesh["tet_edges"]), _p(mesh["coords"]), _p(sig),
+                     code, _p(rowptr), _p(col), _p(val))
+    return rowptr, col, val
+
+
+def box_aggregates(n: int, width: int = 3, max_maps: int | None = None):
+    """Per-level node aggregates of an n^3 node lattice.
+
+    Level l has n_l nodes per side; its aggregates are boxes along each axis,
+    agg(i) = floor(i * a / n_l) with a = ceil(n_l / width) coarse nodes per side,
+    numbered like lattice nodes.  Levels are added while a >= 2.
+    Returns a list of int32 maps (one per coarsening) and the per-level sides.
+    """
+    maps, sides = [], [n]
+    nl = n
+    while True:
+        a = -(-nl // width)
+        if a < 2 or (max_maps is not None and len(maps) >= max_maps):
+            break
+        f = (np.arange(nl, dtype=np.int64) * a) // nl
+        agg = (f[None, None, :] + a * f[None, :, None] + a * a * f[:, None, None]).ravel().astype(np.int32)
+        maps.append(agg)
+        sides.append(a)
+        nl = a
+    return maps, sides
+
+
+def vertex_centred_aggregates(n: int):
+    """Aggregates {3m-1, 3m, 3m+1} per axis around every third lattice point
+    (two wide at the boundary); one coarsening step."""
+    f = (np.arange(n, dtype=np.int64) + 1) // 3
+    a = int(f[-1]) + 1
+    agg = (f[None, None, :] + a * f[None, :, None] + a * a * f[:, None, None]).ravel().astype(np.int32)
+    return agg, a
+
+
+def rhs(n_edges: int, seed: int) -> np.ndarray:
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, size=n_edges)
+
+
+# Named workloads.  "agg_width" 3 gives the box coarsening used throughout.
+WORKLOADS = {
+    "cube8_const": dict(N=8, jitter=0.0, sigma=("const", 1.0), f_seed=101),
+    "cube32_incl": dict(N=32, jitter=0.0, sigma=("inclusions", 202, 1.0, 1e-3), f_seed=102),
+    "cube64_jitter_lognormal": dict(N=64, jitter=0.2, jitter_seed=303, sigma=("lognormal", 304, 2.0), f_seed=103),
+    "cube96_eval": dict(N=96, jitter=0.1, jitter_seed=404, sigma=("lognormal", 405, 2.0), f_seed=104),
+    "cube128_contrast": dict(N=128, jitter=0.0, sigma=("inclusions", 505, 1.0, 1e-6), f_seed=105),
+}
+
+
+def make_sigma(mesh: dict, spec) -> np.ndarray:
+    kind = spec[0]
+    if kind == "const":
+        return sigma_const(mesh, spec[1])
+    if kind == "inclusions":
+        return sigma_inclusions(mesh, spec[1], inside=spec[2], background=spec[3])
+    if kind == "lognormal":
+        return sigma_lognormal(mesh, spec[1], s=spec[2])
+    raise ValueError(kind)
+
+
+def problem(N: int, jitter: float = 0.0, jitter_seed: int | None = None, sigma=("const", 1.0), f_seed: int = 0,
+            with_S: bool = False, agg_width: int = 3, max_maps: int | None = None) -> dict:
+    """Everything the solver boundary consumes, plus the mesh for checks."""
+    mesh = kuhn_mesh(N, jitter, jitter_seed)
+    sig = make_sigma(mesh, sigma)
+    A = assemble(mesh, sig, "A")
+    out = dict(mesh=mesh, sigma=sig, A=A, tail=mesh["tail"], head=mesh["head"], coords=mesh["coords"])
+    if with_S:
+        out["S"] = assemble(mesh, sig, "S")
+    maps, sides = box_aggregates(mesh["n"], agg_width, max_maps)
+    out["aggregates"] = maps
+    out["sides"] = sides
+    out["f"] = rhs(mesh["tail"].shape[0], f_seed)
+    return out
+
+
+def workload(name: str, **kw) -> dict:
+    spec = dict(WORKLOADS[name])
+    spec.update(kw)
+    return problem(**spec)

@@ -1,0 +1,424 @@
+"""Pins of the FP64 CPU oracle against what the paper and the mathematics fix.
+
+Each test names what it pins.  None of them re-types the oracle's own formula:
+they use printed values (tests/golden), closed forms, library routines on the
+same definition (dense solves, null spaces, triangular solves, eigensolvers) or
+invariants that a dropped term, wrong sign or transposed operand would break.
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import synth
+from oracle import hcurl_oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def c1():
+    p = synth.workload("cube8_const", with_S=True)
+    levels = O.setup(p["A"], p["tail"], p["head"], 9 ** 3, p["aggregates"])
+    return p, levels
+
+
+# --------------------------------------------------------------------------
+# symbolic setup: Table 4 (exact), coarse gradient closed form
+# --------------------------------------------------------------------------
+
+def _table4():
+    out = {}
+    for line in open(os.path.join(GOLDEN, "table4_ls_histogram.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        kind, J, lo, hi, cnt = line.split()
+        out.setdefault(kind, []).append((int(J), int(lo), int(hi), int(cnt)))
+    return out
+
+
+@pytest.mark.parametrize("kind", ["tet", "hex"])
+def test_table4_least_squares_histogram(kind):
+    """Level-0 row of Table 4 on the 82^3 nodal mesh: the number of rows with
+    each column dimension |J| is reproduced exactly, and every row's n_p lies in
+    the printed range.  Inputs: vertex-centred 3-wide aggregates and a nodal
+    prolongator with the pattern of a 27-point nodal operator times P-bar."""
+    n = 82
+    mesh = synth.kuhn_mesh(n - 1)
+    tail, head = mesh["tail"], mesh["head"]
+    if kind == "hex":
+        d = head - tail
+        keep = (d == 1) | (d == n) | (d == n * n)
+        tail, head = tail[keep], head[keep]
+    agg, a = synth.vertex_centred_aggregates(n)
+    T1 = sp.diags([np.ones(n - 1), np.ones(n), np.ones(n - 1)], [-1, 0, 1], format="csr")
+    A27 = sp.kron(T1, sp.kron(T1, T1, format="csr"), format="csr")
+    Pn = O.symbolic_product(A27, O.tentative_prolongator(agg, a ** 3))
+    D = O.gradient_matrix(tail, head, n ** 3)
+    th, hd = O.coarse_gradient(D, agg, a ** 3)
+    DH = O.gradient_matrix(th, hd, a ** 3)
+    N, T, R = O.emin_pattern(D, Pn, DH)
+    J = np.diff(T.indptr)
+    npv = np.diff(N.indptr)
+    expect = _table4()[kind]
+    assert sum(c for _, _, _, c in expect) == D.shape[0]
+    for Jv, lo, hi, cnt in expect:
+        sel = J == Jv
+        assert int(sel.sum()) == cnt
+        assert npv[sel].min() >= lo and npv[sel].max() <= hi
+    assert set(np.unique(J)) == {e[0] for e in expect}
+
+
+@pytest.mark.parametrize("n", [9, 33])
+def test_coarse_gradient_is_coarse_kuhn_lattice(n):
+    """With box aggregates the RS rule (eq. "revised RS DH") connects exactly
+    the aggregates joined by a fine edge; for the Kuhn lattice that is again a
+    Kuhn lattice on the coarse nodes, in lexicographic order."""
+    mesh = synth.kuhn_mesh(n - 1)
+    maps, sides = synth.box_aggregates(n)
+    D = O.gradient_matrix(mesh["tail"], mesh["head"], n ** 3)
+    th, hd = O.coarse_gradient(D, maps[0], sides[1] ** 3)
+    ref = synth.kuhn_mesh(sides[1] - 1)
+    assert np.array_equal(th, ref["tail"]) and np.array_equal(hd, ref["head"])
+
+
+def test_c1_pattern_counts(c1):
+    """nnz(P^(e)_0) and level sizes of the 8^3 workload (lattice counts)."""
+    p, levels = c1
+    assert levels[0]["N"].nnz == 19566
+    assert len(levels[0]["DH_tail"]) == synth.edge_count(2)
+    assert levels[1]["A"].shape[0] == 98
+
+
+# --------------------------------------------------------------------------
+# local systems: Sec. 4.2 figures, projector properties, min-norm solution
+# --------------------------------------------------------------------------
+
+def _fig_matrices():
+    mats, cur, name = {}, None, None
+    for line in open(os.path.join(GOLDEN, "fig_local_submatrices.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        if line.startswith("matrix") or line.startswith("reducible"):
+            name = line.strip()
+            mats[name] = []
+            continue
+        mats[name].append([int(v) for v in line.split()])
+    return {k: np.array(v, float) for k, v in mats.items()}
+
+
+def _one_row_system(G, r):
+    """Wrap one transposed sub-matrix G (edges x nodes) as a single-row pattern."""
+    n_p, nJ = G.shape
+    tail = np.array([np.nonzero(G[e] < 0)[0][0] for e in range(n_p)])
+    head = np.array([np.nonzero(G[e] > 0)[0][0] for e in range(n_p)])
+    N = sp.csr_matrix((np.ones(n_p), np.arange(n_p), [0, n_p]), shape=(1, n_p))
+    T = sp.csr_matrix((np.ones(nJ), np.arange(nJ), [0, nJ]), shape=(1, nJ))
+    R = sp.csr_matrix((r, np.arange(nJ), [0, nJ]), shape=(1, nJ))
+    lt, lh = O.local_graphs(N, T, tail, head)
+    return N, T, R, lt, lh
+
+
+def test_figure_submatrices_rank_and_min_norm():
+    """Sec. 4.2 figure: every drawn sub-matrix has rank |J| - 1 (constant null
+    vector); the local solve returns the min-norm solution of G^T p = r, the
+    same vector as the pseudo-inverse (library routine) of G^T."""
+    rng = np.random.default_rng(1)
+    for name, G in _fig_matrices().items():
+        if name.startswith("reducible"):
+            continue
+        n_p, nJ = G.shape
+        assert np.linalg.matrix_rank(G) == nJ - 1
+        r = rng.standard_normal(nJ)
+        r -= r.mean()  # consistent right-hand side (rows of P^(n) sum to 1)
+        N, T, R, lt, lh = _one_row_system(G, r)
+        assert len(O.disconnected_rows(N, T, lt, lh)) == 0
+        loc = O.LocalSystems(N, T, R, lt, lh)
+        p = loc.make_feasible(np.zeros(n_p))
+        assert np.allclose(p, np.linalg.pinv(G.T) @ r, atol=1e-13)
+        x = rng.standard_normal(n_p)
+        q = loc.make_feasible(x)
+        assert np.allclose(G.T @ q, r, atol=1e-12)
+        # closest feasible point: the correction is orthogonal to the null space
+        Z = sla.null_space(G.T)
+        assert np.allclose(Z.T @ (q - x), 0, atol=1e-12)
+
+
+def test_figure_reducible_graph_detected():
+    """Sec. 4.2 reducible example: null space of dimension two, flagged."""
+    G = _fig_matrices()["reducible 2x4"]
+    assert 4 - np.linalg.matrix_rank(G) == 2
+    N, T, R, lt, lh = _one_row_system(G, np.zeros(4))
+    assert list(O.disconnected_rows(N, T, lt, lh)) == [0]
+
+
+def test_projector_properties(c1):
+    """Pi is the orthogonal projector onto {x : G~_i^T x = 0} for every row:
+    idempotent, symmetric, kills G~ y, output satisfies the homogeneous
+    constraint; and it does not depend on which column is dropped."""
+    p, levels = c1
+    lvl = levels[0]
+    loc = lvl["loc"]
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal(lvl["N"].nnz)
+    y = rng.standard_normal(lvl["N"].nnz)
+    px = loc.project(x)
+    assert np.allclose(loc.project(px), px, atol=1e-12)
+    assert abs(np.dot(px, y) - np.dot(x, loc.project(y))) < 1e-10
+    DH = O.gradient_matrix(lvl["DH_tail"], lvl["DH_head"], lvl["Pn"].shape[1])
+    assert abs(O.with_values(lvl["N"], px) @ DH).max() < 1e-12
+    for g in loc.groups:
+        if g["n_p"] == 0:
+            continue
+        b = len(g["rows"])
+        v = np.zeros(lvl["N"].nnz)
+        yk = rng.standard_normal((b, g["k"]))
+        v[g["pos"]] = np.einsum("bpk,bk->bp", g["G"][:, :, 1:], yk)  # drop column 0 instead
+        assert abs(loc.project(v)).max() < 1e-12
+
+
+def test_single_coarse_edge_rows(c1):
+    """Rows with n_p = 1 have the unique solution p = r_K = -r_I (Sec. 4.2)."""
+    p, levels = c1
+    lvl = levels[0]
+    Pe = lvl["Pe"]
+    N, T, R = lvl["N"], lvl["T"], lvl["R"]
+    one = np.nonzero(np.diff(N.indptr) == 1)[0]
+    assert len(one) == 1170
+    j = N.indices[N.indptr[one]]
+    K = lvl["DH_head"][j]
+    I = lvl["DH_tail"][j]
+    rK = np.array([R[i, k] for i, k in zip(one, K)])
+    rI = np.array([R[i, k] for i, k in zip(one, I)])
+    assert np.allclose(Pe.data[N.indptr[one]], rK, atol=1e-14)
+    assert np.allclose(rK, -rI, atol=1e-14)
+
+
+def test_rs_special_case():
+    """P^(n) = P-bar (no smoothing) gives the Reitzinger-Schoeberl prolongator
+    (Sec. 2): +1 on fine edges from aggregate I to K > I, -1 on edges from K to
+    I, empty rows inside aggregates; energy minimisation cannot change it."""
+    pr = synth.workload("cube8_const")
+    agg = pr["aggregates"][0]
+    Pbar = O.tentative_prolongator(agg, 27)
+    lvl, _ = O.build_level(O.csr(pr["A"]), pr["tail"], pr["head"], 729, agg, dict(Pn=Pbar))
+    Pe = lvl["Pe"].toarray()
+    ia, ib = agg[pr["tail"]], agg[pr["head"]]
+    edge_index = {(a, b): e for e, (a, b) in enumerate(zip(lvl["DH_tail"], lvl["DH_head"]))}
+    ref = np.zeros_like(Pe)
+    for e in range(len(ia)):
+        if ia[e] < ib[e]:
+            ref[e, edge_index[(ia[e], ib[e])]] = 1.0
+        elif ia[e] > ib[e]:
+            ref[e, edge_index[(ib[e], ia[e])]] = -1.0
+    assert np.array_equal(Pe, ref)
+
+
+# --------------------------------------------------------------------------
+# energy minimisation: dense KKT brute force, monotone energy
+# --------------------------------------------------------------------------
+
+def _kkt_dense(lvl):
+    """Minimise sum_j 1/2 P_:j^T A P_:j over the pattern subject to the
+    commuting constraint, by a null-space basis of the stacked constraint
+    matrix and a dense solve (eq. KKT, eliminated)."""
+    A = lvl["A"].toarray()
+    N = lvl["N"]
+    rows = np.repeat(np.arange(N.shape[0]), np.diff(N.indptr))
+    cols = N.indices
+    nz = N.nnz
+    Ahat = np.zeros((nz, nz))
+    for a in range(nz):
+        same = np.nonzero(cols == cols[a])[0]
+        Ahat[a, same] = A[rows[a], rows[same]]
+    DH = O.gradient_matrix(lvl["DH_tail"], lvl["DH_head"], lvl["Pn"].shape[1]).toarray()
+    C, rhs = [], []
+    Rd = (lvl["D"] @ lvl["Pn"]).toarray()
+    for i in range(N.shape[0]):
+        sel = np.nonzero(rows == i)[0]
+        Tn = lvl["T"].indices[lvl["T"].indptr[i]:lvl["T"].indptr[i + 1]]
+        for I in Tn:
+            row = np.zeros(nz)
+            row[sel] = DH[cols[sel], I]
+            C.append(row)
+            rhs.append(Rd[i, I])
+    C = np.array(C)
+    rhs = np.array(rhs)
+    p0 = np.linalg.lstsq(C, rhs, rcond=None)[0]
+    Z = sla.null_space(C)
+    y = np.linalg.solve(Z.T @ Ahat @ Z, -Z.T @ Ahat @ p0)
+    return p0 + Z @ y
+
+
+@pytest.mark.parametrize("N,width", [(3, 2), (5, 3)])
+def test_projected_cg_reaches_dense_kkt_solution(N, width):
+    """Many projected-CG iterations converge to the dense KKT minimiser."""
+    pr = synth.problem(N, jitter=0.1, jitter_seed=4, sigma=("lognormal", 9, 1.0), agg_width=width)
+    m = (N + 1) ** 3
+    lvl, _ = O.build_level(O.csr(pr["A"]), pr["tail"], pr["head"], m, pr["aggregates"][0], dict(emin_iters=400))
+    ref = _kkt_dense(lvl)
+    assert np.max(abs(lvl["Pe"].data - ref)) <= 1e-8 * np.max(abs(ref))
+
+
+def test_energy_monotone_and_cg_decrement(c1):
+    """Energy never increases and drops by rho^2 / (2 gamma) per CG step (the
+    CG minimisation property)."""
+    p, levels = c1
+    lvl = levels[0]
+    E = np.array(lvl["energies"])
+    assert np.all(np.diff(E) < 0)
+    rho = np.array(lvl["cg"]["rho"][:-1])
+    gam = np.array(lvl["cg"]["gamma"])
+    assert np.allclose(E[:-1] - E[1:], rho ** 2 / (2 * gam), rtol=1e-8)
+
+
+# --------------------------------------------------------------------------
+# structure preservation (eq. "commute" and the Galerkin identities)
+# --------------------------------------------------------------------------
+
+def test_commuting_relation_and_coarse_null_space(c1):
+    """P^(e) D_H = D_h P^(n) at rounding; S_H D_H = 0 (Sec. 2); the nodal
+    operator of the coarse level equals P^(n)T A^(n) P^(n)."""
+    p, levels = c1
+    lvl = levels[0]
+    assert O.commuting_residual(lvl) <= 1e-12 * abs(lvl["D"] @ lvl["Pn"]).max()
+    S = O.csr(p["S"])
+    SH = O.galerkin(lvl["Pe"], S)
+    DH = O.gradient_matrix(lvl["DH_tail"], lvl["DH_head"], 27)
+    assert abs(SH @ DH).max() <= 1e-12 * abs(SH).max()
+    AnH = levels[1]["An"]
+    ref = lvl["Pn"].T @ lvl["An"] @ lvl["Pn"]
+    assert abs(AnH - ref).max() <= 1e-11 * abs(ref).max()
+
+
+def test_nodal_operator_is_p1_laplacian():
+    """A^(n) = D^T (S + M) D = D^T M D: the sigma-weighted P1 stiffness."""
+    from tests.test_synth import _p1_stiffness
+    mesh = synth.kuhn_mesh(3, 0.1, 5)
+    sig = synth.sigma_lognormal(mesh, 6, 1.0)
+    A = O.csr(synth.assemble(mesh, sig, "A"))
+    D = O.gradient_matrix(mesh["tail"], mesh["head"], 64)
+    An = O.nodal_operator(A, D)
+    K = _p1_stiffness(mesh, sig)
+    assert abs(An - K).max() <= 1e-12 * abs(K).max()
+
+
+def test_sa_prolongator_properties():
+    """SA: rows sum to one; rho close to the largest eigenvalue of D^-1 A^(n)
+    (library eigensolver); P-bar pattern contained."""
+    pr = synth.workload("cube8_const")
+    D = O.gradient_matrix(pr["tail"], pr["head"], 729)
+    An = O.nodal_operator(O.csr(pr["A"]), D)
+    Pn, info = O.sa_prolongator(An, pr["aggregates"][0], 27)
+    assert np.allclose(np.asarray(Pn.sum(axis=1)).ravel(), 1.0, atol=1e-14)
+    dm = sp.diags(1 / np.sqrt(An.diagonal()))
+    lam = spla.eigsh(dm @ An @ dm, k=1, which="LA")[0][0]
+    assert 0.9 * lam <= info["rho"] <= lam * (1 + 1e-12)
+    assert np.allclose(info["row_sums_before"], 1.0, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# smoother / V-cycle / PCG
+# --------------------------------------------------------------------------
+
+def test_coloring_valid(c1):
+    p, levels = c1
+    for key, A in (("colors_A", levels[0]["A"]), ("colors_An", levels[0]["An"])):
+        c = levels[0][key]
+        co = A.tocoo()
+        off = co.row != co.col
+        assert np.all(c[co.row[off]] != c[co.col[off]])
+        assert np.all(c >= 0)
+
+
+def test_sgs_equals_triangular_solves(c1):
+    """Multicolour SGS equals forward then backward Gauss-Seidel on the matrix
+    permuted to colour order (library triangular solves)."""
+    p, levels = c1
+    A = levels[0]["A"]
+    col = levels[0]["colors_A"]
+    perm = np.argsort(col, kind="stable")
+    Ap = A[perm][:, perm].tocsr()
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(A.shape[0])
+    x0 = rng.standard_normal(A.shape[0])
+    L = sp.tril(Ap, 0, format="csr")
+    U = sp.triu(Ap, 0, format="csr")
+    bp, xp = b[perm], x0[perm]
+    xp = xp + spla.spsolve_triangular(L, bp - Ap @ xp, lower=True)
+    xp = xp + spla.spsolve_triangular(U, bp - Ap @ xp, lower=False)
+    ref = np.empty_like(xp)
+    ref[perm] = xp
+    assert np.allclose(O.sgs(A, col, x0, b), ref, rtol=0, atol=1e-10 * abs(ref).max())
+
+
+def test_vcycle_symmetric_positive_definite(c1):
+    p, levels = c1
+    n = levels[0]["A"].shape[0]
+    rng = np.random.default_rng(4)
+    x, y = rng.standard_normal(n), rng.standard_normal(n)
+    vx, vy = O.vcycle(levels, x), O.vcycle(levels, y)
+    assert abs(np.dot(vx, y) - np.dot(x, vy)) <= 1e-10 * abs(np.dot(vx, y))
+    assert np.dot(x, vx) > 0
+
+
+def test_pcg_matches_dense_solve(c1):
+    p, levels = c1
+    f = p["f"]
+    u, it, rel, hist = O.pcg(levels, f)
+    A = levels[0]["A"].toarray()
+    ustar = np.linalg.solve(A, f)
+    assert rel <= 1e-8
+    kappa = np.linalg.cond(A)
+    assert np.linalg.norm(u - ustar) / np.linalg.norm(ustar) <= kappa * 1e-8
+    assert it <= 20
+
+
+def test_fp32_vcycle_pcg_reaches_tolerance(c1):
+    p, levels = c1
+    l32 = O.fp32_levels(levels)
+    u, it, rel, _ = O.pcg(levels, p["f"], precond=lambda r: O.vcycle_fp32(l32, r), flexible=True)
+    assert rel <= 1e-8
+    assert it <= 25
+
+
+@pytest.mark.slow
+def test_mesh_independent_iterations():
+    """PCG iterations stay within 2 over a 2x refinement (Sec. 6.1 behaviour;
+    larger meshes are covered by the GPU tests)."""
+    its = []
+    for N in (8, 16):
+        pr = synth.problem(N, sigma=("const", 1.0), f_seed=7)
+        lv = O.setup(pr["A"], pr["tail"], pr["head"], (N + 1) ** 3, pr["aggregates"])
+        its.append(O.pcg(lv, pr["f"])[1])
+    assert max(its) - min(its) <= 2, its
+
+
+# --------------------------------------------------------------------------
+# make_irreducible (reading R15), forced with irregular aggregates
+# --------------------------------------------------------------------------
+
+def test_make_irreducible_restores_feasibility():
+    """A nodal prolongator whose row reaches a far aggregate makes the local
+    graph of the fine edges at that node disconnected (Sec. 4.2, figure of the
+    reducible case); make_irreducible adds coarse edges until every row is
+    connected and the commuting relation holds again."""
+    pr = synth.problem(6, sigma=("const", 1.0))
+    agg = pr["aggregates"][0]  # 3 x 3 x 3 box aggregates of the 7^3 nodes
+    Pn = O.tentative_prolongator(agg, 27).tolil()
+    Pn[0, 26] = 0.25  # node 0 sits in aggregate 0 = (0,0,0); 26 = (2,2,2) is far
+    Pn[0, 0] = 0.75
+    Pn = O.csr(Pn.tocsr())
+    D = O.gradient_matrix(pr["tail"], pr["head"], 343)
+    th, hd = O.coarse_gradient(D, agg, 27)
+    N, T, R = O.emin_pattern(D, Pn, O.gradient_matrix(th, hd, 27))
+    lt, lh = O.local_graphs(N, T, th, hd)
+    assert len(O.disconnected_rows(N, T, lt, lh)) > 0
+    lvl, _ = O.build_level(O.csr(pr["A"]), pr["tail"], pr["head"], 343, agg, dict(Pn=Pn))
+    assert lvl["irreducible_added"] > 0
+    assert len(lvl["DH_tail"]) == len(th) + lvl["irreducible_added"]
+    assert len(O.disconnected_rows(lvl["N"], lvl["T"], lvl["lt"], lvl["lh"])) == 0
+    assert O.commuting_residual(lvl) <= 1e-12

@@ -1,0 +1,110 @@
+"""Pins of the synthetic problem generator (not of the method)."""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden_edge_counts():
+    rows = []
+    for line in open(os.path.join(GOLDEN, "table3_edge_counts.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        n, kind, cnt = line.split()
+        rows.append((int(n), kind, int(cnt)))
+    return rows
+
+
+@pytest.mark.parametrize("n,kind,count", _golden_edge_counts())
+def test_edge_counts_table3(n, kind, count):
+    """#edges of Table 3 for n^3 nodal meshes (tets: six-tet split)."""
+    N = n - 1
+    if kind == "tet":
+        assert synth.edge_count(N) == count
+        eptr = np.empty(n ** 3 + 1, np.int64)
+        assert synth._lib().synth_edge_ptr(N, synth._p(eptr)) == count
+    else:
+        assert 3 * N * (N + 1) ** 2 == count
+
+
+def _grad(tail, head, m):
+    n = len(tail)
+    return sp.csr_matrix((np.tile([-1.0, 1.0], n), (np.repeat(np.arange(n), 2), np.stack([tail, head], 1).ravel())),
+                         shape=(n, m))
+
+
+def _mat(t):
+    rowptr, col, val = t
+    return sp.csr_matrix((val, col, rowptr), shape=(len(rowptr) - 1, len(rowptr) - 1))
+
+
+@pytest.mark.parametrize("N,jit", [(3, 0.0), (5, 0.2)])
+def test_curl_grad_null_space(N, jit):
+    """S D_h = 0 (Sec. 1, eq. "discrete null space condition")."""
+    mesh = synth.kuhn_mesh(N, jit, 7)
+    sig = synth.sigma_lognormal(mesh, 3, 1.0)
+    S = _mat(synth.assemble(mesh, sig, "S"))
+    D = _grad(mesh["tail"], mesh["head"], mesh["n"] ** 3)
+    assert abs(S @ D).max() <= 1e-13 * abs(S).max()
+
+
+def _p1_stiffness(mesh, sig):
+    """Independent P1 assembly: sum over tets of sigma |T| grad(l_a).grad(l_b)."""
+    X = mesh["coords"]
+    m = X.shape[0]
+    rows, cols, vals = [], [], []
+    for t, tv in enumerate(mesh["tets"]):
+        M = np.ones((4, 4))
+        M[:, 1:] = X[tv]
+        C = np.linalg.inv(M)  # columns: coefficients of barycentric functions
+        grads = C[1:, :].T  # row a = grad lambda_a
+        vol = abs(np.linalg.det(M)) / 6.0
+        K = sig[t] * vol * grads @ grads.T
+        for a in range(4):
+            for b in range(4):
+                rows.append(tv[a]); cols.append(tv[b]); vals.append(K[a, b])
+    return sp.csr_matrix((vals, (rows, cols)), shape=(m, m))
+
+
+def test_mass_of_gradients_is_p1_stiffness():
+    """D^T M D equals the sigma-weighted P1 stiffness: gradients of nodal hat
+    functions lie in the lowest-order edge space (Sec. 1)."""
+    mesh = synth.kuhn_mesh(3, 0.15, 11)
+    sig = synth.sigma_lognormal(mesh, 5, 1.5)
+    M = _mat(synth.assemble(mesh, sig, "M"))
+    D = _grad(mesh["tail"], mesh["head"], mesh["n"] ** 3)
+    K = _p1_stiffness(mesh, sig)
+    assert abs(D.T @ M @ D - K).max() <= 1e-12 * abs(K).max()
+
+
+def test_operator_symmetric_positive_definite():
+    mesh = synth.kuhn_mesh(4, 0.2, 3)
+    sig = synth.sigma_inclusions(mesh, 1, 1.0, 1e-3)
+    A = _mat(synth.assemble(mesh, sig, "A")).toarray()
+    assert np.allclose(A, A.T, rtol=0, atol=1e-14 * abs(A).max())
+    assert np.linalg.eigvalsh(A).min() > 0
+
+
+def test_jitter_keeps_orientation():
+    mesh = synth.kuhn_mesh(16, 0.2, 303)
+    ref = synth.tet_volumes(synth.kuhn_mesh(16))
+    v = synth.tet_volumes(mesh)
+    assert np.all(np.sign(v) == np.sign(ref))
+    assert abs(abs(v).sum() - 1.0) < 1e-12
+
+
+def test_box_aggregates_levels():
+    """3-wide box coarsening: sides and level counts of the named workloads."""
+    assert synth.box_aggregates(9)[1] == [9, 3]
+    assert synth.box_aggregates(33)[1] == [33, 11, 4, 2]
+    assert synth.box_aggregates(65)[1] == [65, 22, 8, 3]
+    assert synth.box_aggregates(129)[1] == [129, 43, 15, 5, 2]
+    maps, sides = synth.box_aggregates(33)
+    for agg, nc in zip(maps, sides[1:]):
+        assert agg.max() + 1 == nc ** 3
+        assert np.all(np.bincount(agg) > 0)
