@@ -180,8 +180,8 @@ def sa_prolongator(An: sp.csr_matrix, agg: np.ndarray, m_coarse: int, power_iter
     P = Pb - sp.diags(omega / d) @ AP
     P = on_pattern(pat, P)
     rs = np.asarray(P.sum(axis=1)).ravel()
-    P = sp.diags(1.0 / rs) @ P
-    return csr(P), dict(rho=rho, omega=omega, row_sums_before=rs)
+    P.data = P.data / np.repeat(rs, np.diff(P.indptr))  # in place: keeps structural zeros
+    return P, dict(rho=rho, omega=omega, row_sums_before=rs)
 
 
 def coarse_gradient(D: sp.csr_matrix, agg: np.ndarray, m_coarse: int):
