@@ -1,0 +1,195 @@
+/*
+ * hcurl_amg.h -- C ABI of the MI355X (gfx950) structure-preserving H(curl)
+ * algebraic multigrid library.
+ *
+ * Method: Tuminaro & Glusa, "A structure preserving H-curl algebraic multigrid
+ * method for the eddy current equations".  For the edge-element system
+ * A^(e) u = f (Sec. 1, eq. "discrete eddy") the setup builds, on every level,
+ *   - the nodal operator A^(n) = D_h^T A^(e) D_h and a smoothed-aggregation
+ *     nodal prolongator P^(n) from caller-given aggregates (Sec. 2, Sec. 3),
+ *   - the coarse gradient D_H by the Reitzinger-Schoeberl rule on the
+ *     piecewise-constant prolongator (Sec. 2 and Sec. 4.1, eq. "revised RS DH"),
+ *   - the pattern of P^(e) and its local constraint systems (Alg. 2),
+ *   - P^(e) by constrained energy minimisation, projected CG (Sec. 3, Sec. 4,
+ *     eq. "min2_hcurl"), which keeps P^(e) D_H = D_h P^(n) (eq. "commute"),
+ *   - the Galerkin operator A_H = P^(e)T A^(e) P^(e) (Sec. 2),
+ * and the solve runs CG preconditioned by one V-cycle with symmetric Hiptmair
+ * smoothing and a direct coarsest solve (Sec. 6.1).
+ *
+ * Conventions for every call
+ *   - Return value: 0 on success, a negative HCURL_E* code otherwise; the
+ *     message of the last failure on the calling thread is returned by
+ *     hcurl_last_error().  No C++ exception crosses this interface.
+ *   - Index types: int64 row pointers, int32 column indices, double values.
+ *     Internally nnz of every matrix must stay below 2^31 (HCURL_EINVAL).
+ *   - Memory space: opts.mem_space says whether the input arrays of setup and
+ *     the f / u vectors of solve are host or device (HIP) pointers.  Inputs are
+ *     read during the call and never retained or modified.
+ *   - Streams: all work is enqueued on opts.stream (a hipStream_t, NULL = the
+ *     null stream); setup and solve return after their work has completed.
+ *   - Ownership: a handle owns all the device memory it allocates; release it
+ *     with hcurl_amg_destroy.  A handle must not be used by two threads at once.
+ */
+#ifndef HCURL_AMG_H
+#define HCURL_AMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HCURL_OK = 0,
+  HCURL_EINVAL = -1,       /* malformed input (shapes, D_h rows, diagonal, sizes) */
+  HCURL_EHIP = -2,         /* HIP runtime error */
+  HCURL_ENOMEM = -3,       /* device allocation failed */
+  HCURL_EREDUCIBLE = -4,   /* a local coarse-edge graph is disconnected (Sec. 4.2);
+                              the edge-adding repair is not implemented on the GPU */
+  HCURL_ENOTSPD = -5,      /* non-positive curvature in projected CG or a failed
+                              Cholesky of a local or coarsest system */
+  HCURL_EMAXIT = -6,       /* PCG stopped at maxit above the tolerance */
+  HCURL_EUNSUPPORTED = -7  /* a size limit of this implementation was exceeded
+                              (see hcurl_last_error for which) */
+};
+
+enum { HCURL_MEM_HOST = 0, HCURL_MEM_DEVICE = 1 };
+enum { HCURL_EMIN_CG = 0, HCURL_EMIN_JACOBI = 1 };
+enum { HCURL_INIT_ONES = 0, HCURL_INIT_GIVEN = 1 };
+
+/* CSR matrix.  rowptr has nrows+1 entries; column indices sorted per row.
+ * val may be NULL where only the pattern is read. */
+typedef struct {
+  int64_t nrows, ncols, nnz;
+  const int64_t* rowptr;
+  const int32_t* col;
+  const double* val;
+} hcurl_csr;
+
+typedef struct hcurl_amg_s* hcurl_amg;
+
+typedef struct {
+  int max_levels;          /* cap on the number of levels, 0 = aggregates decide */
+  int coarse_max_rows;     /* stop coarsening once a level has <= this many edges
+                              (0 = never stop early); the coarsest level is solved
+                              by a dense factorisation and may have at most 4096 rows */
+  int emin_iters;          /* energy-minimisation iterations per level (default 10) */
+  int emin_method;         /* HCURL_EMIN_CG (projected CG, default) or
+                              HCURL_EMIN_JACOBI (projected Jacobi, Sec. 3 eq. "emin iteration") */
+  double emin_omega;       /* Jacobi damping (default 0.5, Sec. 6.1) */
+  int init_guess;          /* HCURL_INIT_ONES: ones on the pattern then the local
+                              min-norm correction (Sec. 6.1); HCURL_INIT_GIVEN:
+                              init_values on the level-0 pattern, then the same
+                              correction (coarser levels use ones) */
+  const double* init_values; /* nnz(P^(e)_0) values in pattern order (mem_space) */
+  int emin_iters_given;    /* level-0 iterations when init_guess = HCURL_INIT_GIVEN
+                              (default 3) */
+  int vcycle_fp32;         /* 1: smoother and transfers in FP32 inside FP64 PCG */
+  int power_iters;         /* power iterations for rho(D^-1 A^(n)), default 20 */
+  int record_energy;       /* 1: measure 1/2 <P, A P> after every emin iteration */
+  int profile;             /* 1: time kernels with HIP events (hcurl_amg_kernel_stats) */
+  int mem_space;           /* HCURL_MEM_HOST or HCURL_MEM_DEVICE */
+  void* stream;            /* hipStream_t */
+} hcurl_amg_opts;
+
+/* Fills the defaults listed above. */
+void hcurl_amg_default_opts(hcurl_amg_opts* opts);
+
+/*
+ * hcurl_amg_setup -- build the hierarchy (Alg. 3 on every level).
+ *   A       n_h x n_h edge operator A^(e) = S + M, symmetric positive definite,
+ *           positive diagonal (Sec. 1, eq. "discrete eddy").
+ *   Dh      n_h x m_h discrete gradient: every row exactly two entries, -1 at the
+ *           tail node and +1 at the head node (Sec. 1).  Rows with one entry
+ *           (Dirichlet edges) are rejected with HCURL_EINVAL in this version.
+ *   coords  m_h x 3 node coordinates (row-major) or NULL; kept for the learned
+ *           initial guess features, not needed otherwise.
+ *   aggregates[l]  for l < n_agg_levels: int32 map from the nodes of level l to
+ *           aggregate ids 0..m_{l+1}-1, every id used (the non-overlapping
+ *           aggregates of Sec. 2).  Level l+1's nodes are level l's aggregates.
+ *   out     receives the handle.
+ * Errors: HCURL_EINVAL (shapes, D_h rows, non-positive diagonal, aggregate ids),
+ * HCURL_EREDUCIBLE, HCURL_ENOTSPD, HCURL_EUNSUPPORTED, HCURL_EHIP, HCURL_ENOMEM.
+ */
+int hcurl_amg_setup(const hcurl_csr* A, const hcurl_csr* Dh, const double* coords,
+                    const int32_t* const* aggregates, int n_agg_levels,
+                    const hcurl_amg_opts* opts, hcurl_amg* out);
+
+/*
+ * hcurl_amg_solve -- PCG with one V-cycle per iteration (Sec. 6.1), x0 = 0,
+ * stopping when ||r||_2 <= rtol ||f||_2 on the recursive residual.
+ *   f, u    n_h vectors in opts.mem_space of the handle; u is overwritten.
+ *   iters   receives the iteration count; relres the true relative residual
+ *           ||f - A u|| / ||f|| (both may be NULL).
+ * Returns HCURL_EMAXIT (with u, iters and relres written) if maxit is reached.
+ */
+int hcurl_amg_solve(hcurl_amg h, const double* f, double* u, double rtol, int maxit,
+                    int* iters, double* relres);
+
+/* One V-cycle application z = V(r) (FP64 or FP32 per the handle); r, z in
+ * the handle's mem_space. */
+int hcurl_amg_vcycle(hcurl_amg h, const double* r, double* z);
+
+void hcurl_amg_destroy(hcurl_amg h);
+
+int hcurl_amg_num_levels(hcurl_amg h);
+
+/* Sizes of level l: rows (edges) n, nodes m, nnz of A_l, A^(n)_l and, for
+ * l < levels-1, of P^(e)_l, P^(n)_l, T_l, and the number of coarse edges. */
+typedef struct {
+  int64_t n_edges, n_nodes, nnz_A, nnz_An;
+  int64_t nnz_Pe, nnz_Pn, nnz_T, n_coarse_edges;
+  int32_t n_colors_A, n_colors_An;
+  double rho, omega;       /* power-iteration estimate and SA damping */
+} hcurl_level_info;
+
+int hcurl_amg_level_info(hcurl_amg h, int level, hcurl_level_info* info);
+
+/* Export of level data to caller-allocated HOST arrays sized from level_info.
+ * which: */
+enum {
+  HCURL_EXPORT_A = 0,    /* A_l               n x n     */
+  HCURL_EXPORT_AN = 1,   /* A^(n)_l           m x m     */
+  HCURL_EXPORT_PN = 2,   /* P^(n)_l           m x m_H   */
+  HCURL_EXPORT_PE = 3,   /* P^(e)_l           n x n_H   */
+  HCURL_EXPORT_R = 4,    /* D_l P^(n)_l on the pattern T_l, n x m_H */
+  HCURL_EXPORT_DH = 5,   /* D_{l+1} as CSR   n_H x m_H (-1 tail, +1 head) */
+  HCURL_EXPORT_P0 = 6    /* initial guess P_0 on the P^(e)_l pattern */
+};
+int hcurl_amg_export_csr(hcurl_amg h, int level, int which, int64_t* rowptr, int32_t* col, double* val);
+
+enum {
+  HCURL_VEC_COLORS_A = 0,   /* int32[n] colour of every edge row            */
+  HCURL_VEC_COLORS_AN = 1,  /* int32[m] colour of every node row            */
+  HCURL_VEC_ENERGY = 2,     /* double[iters+1] energies (record_energy = 1) */
+  HCURL_VEC_LOCAL_PAIRS = 3 /* uint16[nnz_Pe] local tail | head << 8 in T_i */
+};
+int hcurl_amg_export_vec(hcurl_amg h, int level, int which, void* out, int64_t capacity_bytes);
+
+/* Whole-hierarchy statistics. */
+typedef struct {
+  int num_levels;
+  double operator_complexity;   /* sum nnz(A_l) / nnz(A_0) (Sec. 6.1) */
+  double setup_ms;              /* wall time of the last setup */
+  double solve_ms;              /* wall time of the last solve */
+  int last_iters;
+  double last_relres;
+} hcurl_amg_stats_t;
+
+int hcurl_amg_stats(hcurl_amg h, hcurl_amg_stats_t* s);
+
+/* Per-kernel timings (opts.profile = 1): for kernel k < n, its name, launch
+ * count, summed milliseconds (HIP events on the handle's stream) and summed
+ * algorithmic bytes moved.  Returns the number of kernels recorded. */
+int hcurl_amg_kernel_stats(hcurl_amg h, int max_kernels, char (*names)[48], int64_t* launches,
+                           double* ms, double* bytes);
+void hcurl_amg_reset_kernel_stats(hcurl_amg h);
+
+const char* hcurl_last_error(void);
+const char* hcurl_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,71 @@
+// Hierarchy data structures of the H(curl) AMG library.
+#pragma once
+#include <memory>
+
+#include "prims.hpp"
+
+namespace hc {
+
+// One level of the hierarchy.  Level l owns its edge operator, its discrete
+// gradient, its nodal operator and (unless it is the coarsest) the transfer to
+// level l+1 with everything the energy minimisation built for it.
+struct Level {
+  int n = 0;  // edges (rows of A)
+  int m = 0;  // nodes (columns of D)
+  Csr A;
+  DBuf<int> tail, head;  // endpoints of every edge: D row = -1 at tail, +1 at head
+  Csr D, DT;             // D as CSR (+-1 values) and its transpose
+  Csr An;                // nodal operator D^T A D
+  DBuf<double> dinvA, dinvAn;
+  DBuf<float> dinvA32, dinvAn32;
+
+  // multicolour Gauss-Seidel orderings
+  int ncolA = 0, ncolAn = 0;
+  std::vector<int> cptrA, cptrAn;  // host offsets of each colour in rowsA / rowsAn
+  DBuf<int> rowsA, rowsAn;         // rows grouped by colour
+  DBuf<int> colorA, colorAn;
+
+  // transfer to the next level (empty on the coarsest level)
+  bool has_transfer = false;
+  Csr Pn;                 // nodal prolongator m x m_H
+  Csr R;                  // D P^(n) on the pattern T (n x m_H)
+  Csr Pe, PeT;            // edge prolongator n x n_H and its transpose
+  DBuf<uint16_t> lpair;   // per pattern entry: local tail | local head << 8 in T_i
+  DBuf<double> p0;        // initial guess, kept for export
+  int maxJ = 0, maxNp = 0;
+  int n_coarse = 0;
+  double rho = 0.0, omega = 0.0;
+  std::vector<double> energy;
+
+  // solve workspace
+  DBuf<double> x, b, r, rn, cn;
+  DBuf<float> x32, b32, r32, rn32, cn32;
+};
+
+struct Coarsest {
+  int n = 0;
+  DBuf<double> inv;  // dense inverse of the coarsest operator (row-major)
+};
+
+struct Hierarchy {
+  Ctx ctx;
+  hcurl_amg_opts opts{};
+  std::vector<std::unique_ptr<Level>> lv;
+  Coarsest co;
+  double setup_ms = 0.0, solve_ms = 0.0;
+  int last_iters = 0;
+  double last_relres = 0.0;
+  // PCG workspace (level 0, FP64)
+  DBuf<double> px, pr, pz, pp, pq, pzold;
+};
+
+// setup.hip
+void build_hierarchy(Hierarchy& H, const hcurl_csr& A, const hcurl_csr& Dh, const int32_t* const* aggs, int nagg);
+
+// solve.hip
+void color_rows(const Csr& A, DBuf<int>& color, DBuf<int>& rows, std::vector<int>& cptr, int& ncol, Ctx& c);
+void prepare_solve(Hierarchy& H);
+void apply_vcycle(Hierarchy& H, const double* r, double* z);
+int pcg_solve(Hierarchy& H, const double* f, double* u, double rtol, int maxit, int* iters, double* relres);
+
+}  // namespace hc

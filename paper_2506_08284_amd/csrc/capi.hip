@@ -1,0 +1,294 @@
+// extern "C" entry points (include/hcurl_amg.h).  Every call catches the
+// library's errors and turns them into return codes.
+#include <chrono>
+#include <cstring>
+
+#include "amg.hpp"
+
+struct hcurl_amg_s {
+  hc::Hierarchy H;
+};
+
+namespace {
+thread_local std::string g_last_error;
+
+int guard_error(const hc::Error& e) {
+  g_last_error = e.msg;
+  return e.code;
+}
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    return f();
+  } catch (const hc::Error& e) {
+    return guard_error(e);
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return HCURL_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return HCURL_EHIP;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return HCURL_EHIP;
+  }
+}
+
+hc::Level* level_of(hcurl_amg h, int level) {
+  if (!h || level < 0 || level >= (int)h->H.lv.size()) hc::fail(HCURL_EINVAL, "level out of range");
+  return h->H.lv[level].get();
+}
+
+void export_csr(const hc::Csr& A, int64_t* rowptr, int32_t* col, double* val, hc::Ctx& c) {
+  std::vector<int> rp(A.nrows + 1);
+  hc::d2h(rp.data(), A.rowptr.p, A.nrows + 1, c);
+  if (rowptr)
+    for (int i = 0; i <= A.nrows; ++i) rowptr[i] = rp[i];
+  if (col) hc::d2h(col, A.col.p, A.nnz, c);
+  if (val) {
+    if (!A.val.p) hc::fail(HCURL_EINVAL, "matrix has no values");
+    hc::d2h(val, A.val.p, A.nnz, c);
+  }
+}
+}  // namespace
+
+extern "C" {
+
+void hcurl_amg_default_opts(hcurl_amg_opts* o) {
+  std::memset(o, 0, sizeof(*o));
+  o->max_levels = 0;
+  o->coarse_max_rows = 0;
+  o->emin_iters = 10;
+  o->emin_method = HCURL_EMIN_CG;
+  o->emin_omega = 0.5;
+  o->init_guess = HCURL_INIT_ONES;
+  o->init_values = nullptr;
+  o->emin_iters_given = 3;
+  o->vcycle_fp32 = 0;
+  o->power_iters = 20;
+  o->record_energy = 0;
+  o->profile = 0;
+  o->mem_space = HCURL_MEM_HOST;
+  o->stream = nullptr;
+}
+
+int hcurl_amg_setup(const hcurl_csr* A, const hcurl_csr* Dh, const double* coords, const int32_t* const* aggregates,
+                    int n_agg_levels, const hcurl_amg_opts* opts, hcurl_amg* out) {
+  (void)coords;
+  if (!out) return HCURL_EINVAL;
+  *out = nullptr;
+  if (!A || !Dh) return HCURL_EINVAL;
+  auto* h = new (std::nothrow) hcurl_amg_s();
+  if (!h) return HCURL_ENOMEM;
+  int rc = guarded([&]() -> int {
+    if (opts) h->H.opts = *opts; else hcurl_amg_default_opts(&h->H.opts);
+    if (h->H.opts.emin_iters < 0 || h->H.opts.power_iters < 1) hc::fail(HCURL_EINVAL, "bad iteration counts");
+    h->H.ctx.init((hipStream_t)h->H.opts.stream, h->H.opts.profile != 0);
+    auto t0 = std::chrono::steady_clock::now();
+    hc::build_hierarchy(h->H, *A, *Dh, aggregates, n_agg_levels);
+    h->H.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return HCURL_OK;
+  });
+  if (rc != HCURL_OK) {
+    std::string msg = g_last_error;
+    try { (void)hipStreamSynchronize(h->H.ctx.s); } catch (...) {}
+    delete h;
+    g_last_error = msg;
+    return rc;
+  }
+  *out = h;
+  return HCURL_OK;
+}
+
+int hcurl_amg_solve(hcurl_amg h, const double* f, double* u, double rtol, int maxit, int* iters, double* relres) {
+  if (!h || !f || !u || maxit < 0) return HCURL_EINVAL;
+  return guarded([&]() -> int {
+    auto& H = h->H;
+    auto& c = H.ctx;
+    const int64_t n = H.lv[0]->n;
+    auto t0 = std::chrono::steady_clock::now();
+    int rc;
+    if (H.opts.mem_space == HCURL_MEM_DEVICE) {
+      rc = hc::pcg_solve(H, f, u, rtol, maxit, iters, relres);
+    } else {
+      hc::DBuf<double> df(n, c.s), du(n, c.s);
+      hc::h2d(df.p, f, n, c);
+      rc = hc::pcg_solve(H, df.p, du.p, rtol, maxit, iters, relres);
+      hc::d2h(u, du.p, n, c);
+    }
+    H.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
+  });
+}
+
+int hcurl_amg_vcycle(hcurl_amg h, const double* r, double* z) {
+  if (!h || !r || !z) return HCURL_EINVAL;
+  return guarded([&]() -> int {
+    auto& H = h->H;
+    auto& c = H.ctx;
+    const int64_t n = H.lv[0]->n;
+    if (H.opts.mem_space == HCURL_MEM_DEVICE) {
+      hc::apply_vcycle(H, r, z);
+      c.sync();
+    } else {
+      hc::DBuf<double> dr(n, c.s), dz(n, c.s);
+      hc::h2d(dr.p, r, n, c);
+      hc::apply_vcycle(H, dr.p, dz.p);
+      hc::d2h(z, dz.p, n, c);
+    }
+    return HCURL_OK;
+  });
+}
+
+void hcurl_amg_destroy(hcurl_amg h) {
+  if (!h) return;
+  try {
+    (void)hipStreamSynchronize(h->H.ctx.s);
+  } catch (...) {
+  }
+  delete h;
+}
+
+int hcurl_amg_num_levels(hcurl_amg h) { return h ? (int)h->H.lv.size() : HCURL_EINVAL; }
+
+int hcurl_amg_level_info(hcurl_amg h, int level, hcurl_level_info* info) {
+  if (!info) return HCURL_EINVAL;
+  return guarded([&]() -> int {
+    hc::Level* L = level_of(h, level);
+    std::memset(info, 0, sizeof(*info));
+    info->n_edges = L->n;
+    info->n_nodes = L->m;
+    info->nnz_A = L->A.nnz;
+    info->nnz_An = L->An.nnz;
+    info->nnz_Pe = L->Pe.nnz;
+    info->nnz_Pn = L->Pn.nnz;
+    info->nnz_T = L->R.nnz;
+    info->n_coarse_edges = L->n_coarse;
+    info->n_colors_A = L->ncolA;
+    info->n_colors_An = L->ncolAn;
+    info->rho = L->rho;
+    info->omega = L->omega;
+    return HCURL_OK;
+  });
+}
+
+int hcurl_amg_export_csr(hcurl_amg h, int level, int which, int64_t* rowptr, int32_t* col, double* val) {
+  return guarded([&]() -> int {
+    hc::Level* L = level_of(h, level);
+    auto& c = h->H.ctx;
+    switch (which) {
+      case HCURL_EXPORT_A: export_csr(L->A, rowptr, col, val, c); break;
+      case HCURL_EXPORT_AN: export_csr(L->An, rowptr, col, val, c); break;
+      case HCURL_EXPORT_PN: export_csr(L->Pn, rowptr, col, val, c); break;
+      case HCURL_EXPORT_PE: export_csr(L->Pe, rowptr, col, val, c); break;
+      case HCURL_EXPORT_R: export_csr(L->R, rowptr, col, val, c); break;
+      case HCURL_EXPORT_P0: {
+        if (!L->has_transfer) hc::fail(HCURL_EINVAL, "level has no transfer");
+        export_csr(L->Pe, rowptr, col, nullptr, c);
+        if (val) hc::d2h(val, L->p0.p, L->Pe.nnz, c);
+        break;
+      }
+      case HCURL_EXPORT_DH: {
+        if (!L->has_transfer) hc::fail(HCURL_EINVAL, "level has no transfer");
+        hc::Level* N = level_of(h, level + 1);
+        std::vector<int> t(N->n), hd(N->n);
+        hc::d2h(t.data(), N->tail.p, N->n, c);
+        hc::d2h(hd.data(), N->head.p, N->n, c);
+        for (int e = 0; e < N->n; ++e) {
+          if (rowptr) rowptr[e] = 2LL * e;
+          const bool up = t[e] < hd[e];
+          if (col) { col[2 * e] = up ? t[e] : hd[e]; col[2 * e + 1] = up ? hd[e] : t[e]; }
+          if (val) { val[2 * e] = up ? -1.0 : 1.0; val[2 * e + 1] = up ? 1.0 : -1.0; }
+        }
+        if (rowptr) rowptr[N->n] = 2LL * N->n;
+        break;
+      }
+      default: hc::fail(HCURL_EINVAL, "unknown export");
+    }
+    return HCURL_OK;
+  });
+}
+
+int hcurl_amg_export_vec(hcurl_amg h, int level, int which, void* out, int64_t capacity) {
+  return guarded([&]() -> int {
+    hc::Level* L = level_of(h, level);
+    auto& c = h->H.ctx;
+    auto need = [&](int64_t b) {
+      if (capacity < b) hc::fail(HCURL_EINVAL, "output buffer too small");
+    };
+    switch (which) {
+      case HCURL_VEC_COLORS_A: need(4LL * L->n); hc::d2h((int*)out, L->colorA.p, L->n, c); break;
+      case HCURL_VEC_COLORS_AN: need(4LL * L->m); hc::d2h((int*)out, L->colorAn.p, L->m, c); break;
+      case HCURL_VEC_ENERGY: {
+        need(8LL * (int64_t)L->energy.size());
+        std::memcpy(out, L->energy.data(), 8 * L->energy.size());
+        return (int)L->energy.size();
+      }
+      case HCURL_VEC_LOCAL_PAIRS: need(2LL * L->Pe.nnz); hc::d2h((uint16_t*)out, L->lpair.p, L->Pe.nnz, c); break;
+      default: hc::fail(HCURL_EINVAL, "unknown vector");
+    }
+    return HCURL_OK;
+  });
+}
+
+int hcurl_amg_stats(hcurl_amg h, hcurl_amg_stats_t* s) {
+  if (!h || !s) return HCURL_EINVAL;
+  auto& H = h->H;
+  s->num_levels = (int)H.lv.size();
+  double tot = 0.0;
+  for (auto& L : H.lv) tot += (double)L->A.nnz;
+  s->operator_complexity = H.lv.empty() ? 0.0 : tot / (double)H.lv[0]->A.nnz;
+  s->setup_ms = H.setup_ms;
+  s->solve_ms = H.solve_ms;
+  s->last_iters = H.last_iters;
+  s->last_relres = H.last_relres;
+  return HCURL_OK;
+}
+
+int hcurl_amg_kernel_stats(hcurl_amg h, int max_kernels, char (*names)[48], int64_t* launches, double* ms, double* bytes) {
+  if (!h) return HCURL_EINVAL;
+  return guarded([&]() -> int {
+    auto& c = h->H.ctx;
+    c.drain();
+    const int n = (int)c.stats.size();
+    for (int k = 0; k < n && k < max_kernels; ++k) {
+      if (names) {
+        std::strncpy(names[k], c.stats[k].name.c_str(), 47);
+        names[k][47] = 0;
+      }
+      if (launches) launches[k] = c.stats[k].launches;
+      if (ms) ms[k] = c.stats[k].ms;
+      if (bytes) bytes[k] = c.stats[k].bytes;
+    }
+    return n;
+  });
+}
+
+void hcurl_amg_reset_kernel_stats(hcurl_amg h) {
+  if (!h) return;
+  try {
+    h->H.ctx.drain();
+  } catch (...) {
+  }
+  h->H.ctx.stats.clear();
+}
+
+const char* hcurl_last_error(void) { return g_last_error.c_str(); }
+
+const char* hcurl_error_string(int code) {
+  switch (code) {
+    case HCURL_OK: return "ok";
+    case HCURL_EINVAL: return "invalid argument";
+    case HCURL_EHIP: return "HIP runtime error";
+    case HCURL_ENOMEM: return "out of device memory";
+    case HCURL_EREDUCIBLE: return "disconnected local coarse-edge graph";
+    case HCURL_ENOTSPD: return "not positive definite";
+    case HCURL_EMAXIT: return "maximum iterations reached";
+    case HCURL_EUNSUPPORTED: return "size limit exceeded";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,602 @@
+// Sparse and vector primitives: prefix sums, CSR transpose, hashed SpGEMM
+// with symbolic patterns, SpMV, deterministic reductions.
+#include "prims.hpp"
+
+namespace hc {
+
+// ---------------------------------------------------------------------------
+// exclusive scan (three passes: block sums, scan of block sums, apply)
+// ---------------------------------------------------------------------------
+static constexpr int kScanThreads = 256;
+static constexpr int kScanItems = 8;
+static constexpr int kScanTile = kScanThreads * kScanItems;
+
+__global__ void __launch_bounds__(256) k_scan_sums(const int* __restrict__ in, int64_t n, long long* __restrict__ bsum) {
+  __shared__ long long sh[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  long long s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    int64_t i = base + (int64_t)j * kScanThreads + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) bsum[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__global__ void __launch_bounds__(1024) k_scan_partials(long long* __restrict__ bsum, int nb, long long* __restrict__ total) {
+  __shared__ long long sh[16];
+  __shared__ long long carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < nb; c0 += 1024) {
+    int i = c0 + threadIdx.x;
+    long long v = i < nb ? bsum[i] : 0;
+    // inclusive scan in wave
+    long long x = v;
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      long long t = __shfl_up(x, o, 64);
+      if (l >= o) x += t;
+    }
+    if (l == 63) sh[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x < 16) {
+      long long y = sh[threadIdx.x];
+      for (int o = 1; o < 16; o <<= 1) {
+        long long t = __shfl_up(y, o, 16);
+        if ((int)threadIdx.x >= o) y += t;
+      }
+      sh[threadIdx.x] = y;
+    }
+    __syncthreads();
+    long long woff = (threadIdx.x >> 6) ? sh[(threadIdx.x >> 6) - 1] : 0;
+    long long excl = carry + woff + x - v;
+    if (i < nb) bsum[i] = excl;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry = excl + v;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void __launch_bounds__(256) k_scan_apply(const int* __restrict__ in, int* __restrict__ out, int64_t n,
+                                                    const long long* __restrict__ boff, const long long* __restrict__ total) {
+  __shared__ long long sh[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int v[kScanItems];
+  long long s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    int64_t i = base + j;
+    v[j] = i < n ? in[i] : 0;
+    s += v[j];
+  }
+  long long x = s;
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    long long t = __shfl_up(x, o, 64);
+    if (l >= o) x += t;
+  }
+  if (l == 63) sh[threadIdx.x >> 6] = x;
+  __syncthreads();
+  long long woff = 0;
+  for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) woff += sh[w];
+  long long run = boff[blockIdx.x] + woff + x - s;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    int64_t i = base + j;
+    if (i < n) out[i] = (int)run;
+    run += v[j];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = (int)*total;
+}
+
+int64_t exclusive_scan(const int* in, int* out, int64_t n, Ctx& c) {
+  if (n == 0) {
+    int z = 0;
+    HC_HIP(hipMemcpyAsync(out, &z, sizeof(int), hipMemcpyHostToDevice, c.s));
+    HC_HIP(hipStreamSynchronize(c.s));
+    return 0;
+  }
+  int nb = ceil_div(n, kScanTile);
+  DBuf<long long> bsum(nb + 1, c.s);
+  c.run("scan", 4.0 * n, [&] { k_scan_sums<<<nb, 256, 0, c.s>>>(in, n, bsum.p); });
+  c.run("scan", 8.0 * nb, [&] { k_scan_partials<<<1, 1024, 0, c.s>>>(bsum.p, nb, bsum.p + nb); });
+  long long total = 0;
+  d2h(&total, bsum.p + nb, 1, c);
+  if (total > 0x7fffffffLL) fail(HCURL_EUNSUPPORTED, "a matrix would exceed 2^31-1 nonzeros");
+  c.run("scan", 8.0 * n, [&] { k_scan_apply<<<nb, 256, 0, c.s>>>(in, out, n, bsum.p, bsum.p + nb); });
+  return total;
+}
+
+// ---------------------------------------------------------------------------
+// upload / copy
+// ---------------------------------------------------------------------------
+__global__ void k_i64_to_i32(const int64_t* __restrict__ a, int* __restrict__ b, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (int)a[i];
+}
+
+void upload_csr(const hcurl_csr& in, bool device_ptrs, Csr& out, bool values, Ctx& c) {
+  if (in.nrows < 0 || in.ncols < 0 || in.nnz < 0 || in.nnz > 0x7fffffffLL || in.nrows > 0x7fffffffLL)
+    fail(HCURL_EINVAL, "CSR sizes out of range");
+  if (!in.rowptr || (in.nnz && !in.col) || (values && in.nnz && !in.val)) fail(HCURL_EINVAL, "CSR pointer is NULL");
+  out.nrows = (int)in.nrows;
+  out.ncols = (int)in.ncols;
+  out.nnz = in.nnz;
+  out.rowptr.alloc(in.nrows + 1, c.s);
+  out.col.alloc(in.nnz, c.s);
+  if (values) out.val.alloc(in.nnz, c.s);
+  DBuf<int64_t> rp(in.nrows + 1, c.s);
+  auto kind = device_ptrs ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  HC_HIP(hipMemcpyAsync(rp.p, in.rowptr, (in.nrows + 1) * sizeof(int64_t), kind, c.s));
+  if (in.nnz) HC_HIP(hipMemcpyAsync(out.col.p, in.col, in.nnz * sizeof(int), kind, c.s));
+  if (values && in.nnz) HC_HIP(hipMemcpyAsync(out.val.p, in.val, in.nnz * sizeof(double), kind, c.s));
+  int64_t n1 = in.nrows + 1;
+  k_i64_to_i32<<<ceil_div(n1, 256), 256, 0, c.s>>>(rp.p, out.rowptr.p, n1);
+  HC_LAUNCH_CHECK();
+  HC_HIP(hipStreamSynchronize(c.s));
+}
+
+void copy_csr(const Csr& A, Csr& B, Ctx& c) {
+  B.nrows = A.nrows; B.ncols = A.ncols; B.nnz = A.nnz;
+  B.rowptr.alloc(A.nrows + 1, c.s);
+  B.col.alloc(A.nnz, c.s);
+  d2d(B.rowptr.p, A.rowptr.p, A.nrows + 1, c);
+  d2d(B.col.p, A.col.p, A.nnz, c);
+  if (A.val.p) { B.val.alloc(A.nnz, c.s); d2d(B.val.p, A.val.p, A.nnz, c); }
+}
+
+// ---------------------------------------------------------------------------
+// transpose: count, scan, scatter with cursors, then sort every output row
+// ---------------------------------------------------------------------------
+__global__ void k_col_count(const int* __restrict__ col, int64_t nnz, int* __restrict__ cnt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nnz) atomicAdd(&cnt[col[i]], 1);
+}
+
+__global__ void k_transpose_scatter(const int* __restrict__ rowptr, const int* __restrict__ col,
+                                    const double* __restrict__ val, int nrows, int* __restrict__ cursor,
+                                    int* __restrict__ tcol, double* __restrict__ tval) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  for (int q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+    int pos = atomicAdd(&cursor[col[q]], 1);
+    tcol[pos] = i;
+    if (val) tval[pos] = val[q];
+  }
+}
+
+// Sorts the column indices (unique within a row) of every row, carrying
+// values, by rank counting in LDS: one wave per row, rows up to kSortCap.
+static constexpr int kSortCap = 1024;
+__global__ void __launch_bounds__(64) k_sort_rows(const int* __restrict__ rowptr, int nrows, int* __restrict__ col,
+                                                  double* __restrict__ val, int* __restrict__ too_long) {
+  __shared__ int kk[kSortCap];
+  __shared__ double vv[kSortCap];
+  for (int i = blockIdx.x; i < nrows; i += gridDim.x) {
+    const int a = rowptr[i], len = rowptr[i + 1] - a;
+    if (len <= 1) continue;
+    if (len > kSortCap) {
+      if (threadIdx.x == 0) atomicAdd(too_long, 1);
+      continue;
+    }
+    for (int t = threadIdx.x; t < len; t += 64) {
+      kk[t] = col[a + t];
+      if (val) vv[t] = val[a + t];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < len; t += 64) {
+      const int key = kk[t];
+      int r = 0;
+      for (int u = 0; u < len; ++u) r += kk[u] < key;
+      col[a + r] = key;
+      if (val) val[a + r] = vv[t];
+    }
+    __syncthreads();
+  }
+}
+
+// Fallback for rows longer than kSortCap: insertion sort by one thread.
+__global__ void k_sort_rows_long(const int* __restrict__ rowptr, int nrows, int* __restrict__ col, double* __restrict__ val) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  const int a = rowptr[i], b = rowptr[i + 1];
+  if (b - a <= kSortCap) return;
+  for (int q = a + 1; q < b; ++q) {
+    int key = col[q];
+    double v = val ? val[q] : 0.0;
+    int r = q - 1;
+    while (r >= a && col[r] > key) {
+      col[r + 1] = col[r];
+      if (val) val[r + 1] = val[r];
+      --r;
+    }
+    col[r + 1] = key;
+    if (val) val[r + 1] = v;
+  }
+}
+
+static void sort_rows(Csr& C, Ctx& c) {
+  if (C.nrows == 0 || C.nnz == 0) return;
+  long long* flag = c.iscal.p + 0;
+  HC_HIP(hipMemsetAsync(flag, 0, sizeof(long long), c.s));
+  int nb = std::min(C.nrows, 65536);
+  c.run("sort_rows", 16.0 * C.nnz, [&] { k_sort_rows<<<nb, 64, 0, c.s>>>(C.rowptr.p, C.nrows, C.col.p, C.val.p, (int*)flag); });
+  long long h = 0;
+  d2h(&h, flag, 1, c);
+  if ((int)h > 0)
+    c.run("sort_rows_long", 16.0 * C.nnz,
+          [&] { k_sort_rows_long<<<ceil_div(C.nrows, 64), 64, 0, c.s>>>(C.rowptr.p, C.nrows, C.col.p, C.val.p); });
+}
+
+void transpose(const Csr& A, Csr& AT, bool values, Ctx& c) {
+  values = values && A.val.p;
+  AT.nrows = A.ncols;
+  AT.ncols = A.nrows;
+  AT.nnz = A.nnz;
+  AT.rowptr.alloc(AT.nrows + 1, c.s);
+  AT.col.alloc(A.nnz, c.s);
+  if (values) AT.val.alloc(A.nnz, c.s); else AT.val.release();
+  DBuf<int> cnt(AT.nrows + 1, c.s);
+  HC_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int) * (AT.nrows + 1), c.s));
+  if (A.nnz) c.run("transpose", 8.0 * A.nnz, [&] { k_col_count<<<ceil_div(A.nnz, 256), 256, 0, c.s>>>(A.col.p, A.nnz, cnt.p); });
+  exclusive_scan(cnt.p, AT.rowptr.p, AT.nrows, c);
+  d2d(cnt.p, AT.rowptr.p, AT.nrows, c);
+  if (A.nrows)
+    c.run("transpose", 24.0 * A.nnz, [&] {
+      k_transpose_scatter<<<ceil_div(A.nrows, 256), 256, 0, c.s>>>(A.rowptr.p, A.col.p, values ? A.val.p : nullptr,
+                                                                  A.nrows, cnt.p, AT.col.p, values ? AT.val.p : nullptr);
+    });
+  sort_rows(AT, c);
+}
+
+// ---------------------------------------------------------------------------
+// SpGEMM: one wave per row; the products of a row are flattened over 64
+// lanes (prefix sum of the B-row lengths of each chunk of 64 A entries) and
+// inserted into an LDS open-addressing hash table (symbolic pattern: every
+// product inserts its column whatever its value).  Overflowing rows are
+// redone with a larger table; the fill pass ranks the unique columns to
+// write them sorted.
+// ---------------------------------------------------------------------------
+template <int HT>
+struct HashWave {
+  int keys[HT];
+  double vals[HT];
+  int ck[HT * 3 / 4];
+  double cv[HT * 3 / 4];
+  int kst[64];
+  int pre[64];
+  double av[64];
+  int count;
+  int overflow;
+};
+
+__device__ __forceinline__ unsigned hash_slot(int key, unsigned mask) {
+  return ((unsigned)key * 2654435761u) & mask;
+}
+
+// Inserts all products of row i; returns unique count or -1 on overflow.
+template <int HT, bool NUMERIC>
+__device__ int hash_row(HashWave<HT>& H, int i, const int* __restrict__ Arp, const int* __restrict__ Acol,
+                        const double* __restrict__ Aval, const int* __restrict__ Brp, const int* __restrict__ Bcol,
+                        const double* __restrict__ Bval) {
+  const int l = lane_id();
+  constexpr int CAP = HT * 3 / 4;
+  for (int s = l; s < HT; s += 64) {
+    H.keys[s] = -1;
+    if (NUMERIC) H.vals[s] = 0.0;
+  }
+  if (l == 0) { H.count = 0; H.overflow = 0; }
+  __syncthreads();
+  const int a0 = Arp[i], a1 = Arp[i + 1];
+  for (int c0 = a0; c0 < a1; c0 += 64) {
+    const int j = c0 + l;
+    int k = 0, st = 0, len = 0;
+    double a = 0.0;
+    if (j < a1) {
+      k = Acol[j];
+      if (NUMERIC) a = Aval[j];
+      st = Brp[k];
+      len = Brp[k + 1] - st;
+    }
+    const int incl = wave_incl_scan(len);
+    const int total = __shfl(incl, 63, 64);
+    H.kst[l] = st;
+    H.pre[l] = incl - len;
+    H.av[l] = a;
+    __syncthreads();
+    for (int p = l; p < total; p += 64) {
+      // largest q with pre[q] <= p
+      int lo = 0, hi = 63;
+      while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (H.pre[mid] <= p) lo = mid; else hi = mid - 1;
+      }
+      const int q = lo;
+      const int pos = H.kst[q] + (p - H.pre[q]);
+      const int key = Bcol[pos];
+      unsigned h = hash_slot(key, HT - 1);
+      int slot = -1;
+      for (int probe = 0; probe < HT; ++probe) {
+        int old = atomicCAS(&H.keys[h], -1, key);
+        if (old == -1) {
+          int cnt = atomicAdd(&H.count, 1);
+          if (cnt >= CAP) H.overflow = 1;
+          slot = (int)h;
+          break;
+        }
+        if (old == key) { slot = (int)h; break; }
+        h = (h + 1) & (HT - 1);
+      }
+      if (slot < 0) { H.overflow = 1; continue; }
+      if (NUMERIC) atomicAdd(&H.vals[slot], H.av[q] * Bval[pos]);
+    }
+    __syncthreads();
+    if (H.overflow) break;
+  }
+  __syncthreads();
+  return H.overflow ? -1 : H.count;
+}
+
+template <int HT>
+__global__ void __launch_bounds__(64) k_spgemm_count(const int* __restrict__ rows, int nrows_list, int nrows,
+                                                     const int* __restrict__ Arp, const int* __restrict__ Acol,
+                                                     const int* __restrict__ Brp, const int* __restrict__ Bcol,
+                                                     int* __restrict__ cnt) {
+  __shared__ HashWave<HT> H;
+  const int n = rows ? nrows_list : nrows;
+  for (int t = blockIdx.x; t < n; t += gridDim.x) {
+    const int i = rows ? rows[t] : t;
+    int u = hash_row<HT, false>(H, i, Arp, Acol, nullptr, Brp, Bcol, nullptr);
+    if (lane_id() == 0) cnt[i] = u;
+    __syncthreads();
+  }
+}
+
+template <int HT, bool NUMERIC>
+__global__ void __launch_bounds__(64) k_spgemm_fill(const int* __restrict__ rows, int nrows_list, int nrows,
+                                                    const int* __restrict__ Arp, const int* __restrict__ Acol,
+                                                    const double* __restrict__ Aval, const int* __restrict__ Brp,
+                                                    const int* __restrict__ Bcol, const double* __restrict__ Bval,
+                                                    const int* __restrict__ Crp, int* __restrict__ Ccol,
+                                                    double* __restrict__ Cval) {
+  __shared__ HashWave<HT> H;
+  const int n = rows ? nrows_list : nrows;
+  const int l = lane_id();
+  for (int t = blockIdx.x; t < n; t += gridDim.x) {
+    const int i = rows ? rows[t] : t;
+    int u = hash_row<HT, NUMERIC>(H, i, Arp, Acol, Aval, Brp, Bcol, Bval);
+    if (u < 0) continue;  // cannot happen: counts came from the same table size
+    // compact occupied slots
+    int base = 0;
+    for (int s0 = 0; s0 < HT; s0 += 64) {
+      const int s = s0 + l;
+      const bool occ = H.keys[s] >= 0;
+      const int incl = wave_incl_scan(occ ? 1 : 0);
+      if (occ) {
+        H.ck[base + incl - 1] = H.keys[s];
+        if (NUMERIC) H.cv[base + incl - 1] = H.vals[s];
+      }
+      base += __shfl(incl, 63, 64);
+    }
+    __syncthreads();
+    const int off = Crp[i];
+    for (int t2 = l; t2 < u; t2 += 64) {
+      const int key = H.ck[t2];
+      int r = 0;
+      for (int v = 0; v < u; ++v) r += H.ck[v] < key;
+      Ccol[off + r] = key;
+      if (NUMERIC) Cval[off + r] = H.cv[t2];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_collect_overflow(const int* __restrict__ cnt, int n, int* __restrict__ list, int* __restrict__ nlist) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && cnt[i] < 0) list[atomicAdd(nlist, 1)] = i;
+}
+
+static constexpr int kHtSmall = 512;
+static constexpr int kHtLarge = 2048;
+
+void spgemm(const Csr& A, const Csr& B, Csr& C, bool numeric, Ctx& c) {
+  if (A.ncols != B.nrows) fail(HCURL_EINVAL, "spgemm: inner dimensions differ");
+  numeric = numeric && A.val.p && B.val.p;
+  C.nrows = A.nrows;
+  C.ncols = B.ncols;
+  C.rowptr.alloc(C.nrows + 1, c.s);
+  DBuf<int> cnt(C.nrows + 1, c.s);
+  const int nb = std::max(1, std::min(C.nrows, 1 << 17));
+  const double est_bytes = 12.0 * A.nnz + 8.0 * B.nnz;
+  if (C.nrows)
+    c.run("spgemm_symbolic", est_bytes, [&] {
+      k_spgemm_count<kHtSmall><<<nb, 64, 0, c.s>>>(nullptr, 0, A.nrows, A.rowptr.p, A.col.p, B.rowptr.p, B.col.p, cnt.p);
+    });
+  // rows that overflowed the small table
+  DBuf<int> olist(C.nrows + 1, c.s);
+  int* nover = (int*)(c.iscal.p + 1);
+  HC_HIP(hipMemsetAsync(nover, 0, sizeof(int), c.s));
+  if (C.nrows) {
+    k_collect_overflow<<<ceil_div(C.nrows, 256), 256, 0, c.s>>>(cnt.p, C.nrows, olist.p, nover);
+    HC_LAUNCH_CHECK();
+  }
+  int hover = 0;
+  d2h(&hover, nover, 1, c);
+  if (hover > 0) {
+    c.run("spgemm_symbolic_large", est_bytes, [&] {
+      k_spgemm_count<kHtLarge><<<std::min(hover, 65536), 64, 0, c.s>>>(olist.p, hover, A.nrows, A.rowptr.p, A.col.p,
+                                                                        B.rowptr.p, B.col.p, cnt.p);
+    });
+    std::vector<int> hc_(C.nrows);
+    d2h(hc_.data(), cnt.p, C.nrows, c);
+    for (int v : hc_)
+      if (v < 0) fail(HCURL_EUNSUPPORTED, "spgemm: a product row has more than 1536 nonzeros");
+  }
+  C.nnz = exclusive_scan(cnt.p, C.rowptr.p, C.nrows, c);
+  C.col.alloc(C.nnz, c.s);
+  if (numeric) C.val.alloc(C.nnz, c.s); else C.val.release();
+  if (C.nrows) {
+    if (numeric)
+      c.run("spgemm_numeric", est_bytes + 12.0 * C.nnz, [&] {
+        k_spgemm_fill<kHtSmall, true><<<nb, 64, 0, c.s>>>(nullptr, 0, A.nrows, A.rowptr.p, A.col.p, A.val.p, B.rowptr.p,
+                                                          B.col.p, B.val.p, C.rowptr.p, C.col.p, C.val.p);
+      });
+    else
+      c.run("spgemm_numeric", est_bytes + 4.0 * C.nnz, [&] {
+        k_spgemm_fill<kHtSmall, false><<<nb, 64, 0, c.s>>>(nullptr, 0, A.nrows, A.rowptr.p, A.col.p, nullptr,
+                                                           B.rowptr.p, B.col.p, nullptr, C.rowptr.p, C.col.p, nullptr);
+      });
+    if (hover > 0) {
+      if (numeric)
+        c.run("spgemm_numeric_large", est_bytes, [&] {
+          k_spgemm_fill<kHtLarge, true><<<std::min(hover, 65536), 64, 0, c.s>>>(
+              olist.p, hover, A.nrows, A.rowptr.p, A.col.p, A.val.p, B.rowptr.p, B.col.p, B.val.p, C.rowptr.p, C.col.p,
+              C.val.p);
+        });
+      else
+        c.run("spgemm_numeric_large", est_bytes, [&] {
+          k_spgemm_fill<kHtLarge, false><<<std::min(hover, 65536), 64, 0, c.s>>>(
+              olist.p, hover, A.nrows, A.rowptr.p, A.col.p, nullptr, B.rowptr.p, B.col.p, nullptr, C.rowptr.p, C.col.p,
+              nullptr);
+        });
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// SpMV: LPR lanes per row, shuffle reduction inside the lane group
+// ---------------------------------------------------------------------------
+template <class T, class Acc, int LPR>
+__global__ void __launch_bounds__(256) k_spmv(const int* __restrict__ rp, const int* __restrict__ col,
+                                              const T* __restrict__ val, const T* __restrict__ x, T* __restrict__ y,
+                                              const T* __restrict__ b, int n, int mode) {
+  const int g = (blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+  const int l = threadIdx.x & (LPR - 1);
+  if (g >= n) return;
+  Acc s = 0;
+  const int e = rp[g + 1];
+  for (int q = rp[g] + l; q < e; q += LPR) s += (Acc)val[q] * (Acc)x[col[q]];
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LPR);
+  if (l == 0) {
+    if (mode == 0) y[g] = (T)s;
+    else if (mode == 1) y[g] = (T)((Acc)b[g] - s);
+    else y[g] = (T)((Acc)y[g] + s);
+  }
+}
+
+template <class T, class Acc>
+static void spmv_t(const int* rp, const int* col, const T* val, int n, int64_t nnz, const T* x, T* y, const T* b, int mode,
+                   Ctx& c, const char* tag) {
+  if (n == 0) return;
+  const double avg = (double)nnz / n;
+  const double bytes = (double)nnz * (4 + sizeof(T)) + 4.0 * (n + 1) + sizeof(T) * (2.0 * n + (mode ? n : 0));
+  if (avg <= 6)
+    c.run(tag, bytes, [&] { k_spmv<T, Acc, 4><<<ceil_div((int64_t)n * 4, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
+  else if (avg <= 24)
+    c.run(tag, bytes, [&] { k_spmv<T, Acc, 8><<<ceil_div((int64_t)n * 8, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
+  else if (avg <= 64)
+    c.run(tag, bytes, [&] { k_spmv<T, Acc, 16><<<ceil_div((int64_t)n * 16, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
+  else
+    c.run(tag, bytes, [&] { k_spmv<T, Acc, 64><<<ceil_div((int64_t)n * 64, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
+}
+
+void spmv(const Csr& A, const double* x, double* y, const double* b, int mode, Ctx& c, const char* tag) {
+  spmv_t<double, double>(A.rowptr.p, A.col.p, A.val.p, A.nrows, A.nnz, x, y, b, mode, c, tag);
+}
+void spmv32(const Csr& A, const float* x, float* y, const float* b, int mode, Ctx& c, const char* tag) {
+  spmv_t<float, float>(A.rowptr.p, A.col.p, A.val32.p, A.nrows, A.nnz, x, y, b, mode, c, tag);
+}
+
+// ---------------------------------------------------------------------------
+// deterministic dot products: fixed grid of kRedBlocks blocks, then one block
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(256) k_dot_partial(const T* __restrict__ x, const T* __restrict__ y, int64_t n,
+                                                     double* __restrict__ part) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    s += (double)x[i] * (double)y[i];
+  double r = block_sum256(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+__global__ void __launch_bounds__(256) k_reduce_partials(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) s += part[i];
+  double r = block_sum256(s, sh);
+  if (threadIdx.x == 0) *out = r;
+}
+
+void reduce_partials(int nblocks, int slot, double* out, Ctx& c) {
+  c.run("reduce", 8.0 * nblocks, [&] {
+    k_reduce_partials<<<1, 256, 0, c.s>>>(c.red.p + (size_t)slot * Ctx::kRedBlocks, nblocks, out);
+  });
+}
+
+void dot(const double* x, const double* y, int64_t n, double* out, Ctx& c, int slot) {
+  int nb = (int)std::min<int64_t>(Ctx::kRedBlocks, std::max<int64_t>(1, (n + 255) / 256));
+  c.run("dot", 16.0 * n, [&] { k_dot_partial<double><<<nb, 256, 0, c.s>>>(x, y, n, c.red.p + (size_t)slot * Ctx::kRedBlocks); });
+  reduce_partials(nb, slot, out, c);
+}
+void dot32(const float* x, const float* y, int64_t n, double* out, Ctx& c, int slot) {
+  int nb = (int)std::min<int64_t>(Ctx::kRedBlocks, std::max<int64_t>(1, (n + 255) / 256));
+  c.run("dot32", 8.0 * n, [&] { k_dot_partial<float><<<nb, 256, 0, c.s>>>(x, y, n, c.red.p + (size_t)slot * Ctx::kRedBlocks); });
+  reduce_partials(nb, slot, out, c);
+}
+
+// ---------------------------------------------------------------------------
+// small elementwise kernels
+// ---------------------------------------------------------------------------
+__global__ void k_diag(const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ val, int n,
+                       double* __restrict__ d, int inv) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double v = 0.0;
+  for (int q = rp[i]; q < rp[i + 1]; ++q)
+    if (col[q] == i) v = val[q];
+  d[i] = inv ? 1.0 / v : v;
+}
+void diagonal(const Csr& A, double* d, bool inv, Ctx& c) {
+  if (!A.nrows) return;
+  c.run("diag", 12.0 * A.nnz, [&] { k_diag<<<ceil_div(A.nrows, 256), 256, 0, c.s>>>(A.rowptr.p, A.col.p, A.val.p, A.nrows, d, inv); });
+}
+
+template <class T>
+__global__ void k_fill(T* __restrict__ x, T v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+void fill(double* x, double v, int64_t n, Ctx& c) {
+  if (n) c.run("fill", 8.0 * n, [&] { k_fill<double><<<ceil_div(n, 256), 256, 0, c.s>>>(x, v, n); });
+}
+void fill32(float* x, float v, int64_t n, Ctx& c) {
+  if (n) c.run("fill", 4.0 * n, [&] { k_fill<float><<<ceil_div(n, 256), 256, 0, c.s>>>(x, v, n); });
+}
+void fill_int(int* x, int v, int64_t n, Ctx& c) {
+  if (n) c.run("fill", 4.0 * n, [&] { k_fill<int><<<ceil_div(n, 256), 256, 0, c.s>>>(x, v, n); });
+}
+
+template <class A, class B>
+__global__ void k_cast(const A* __restrict__ x, B* __restrict__ y, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (B)x[i];
+}
+void cast_d2f(const double* x, float* y, int64_t n, Ctx& c) {
+  if (n) c.run("cast", 12.0 * n, [&] { k_cast<double, float><<<ceil_div(n, 256), 256, 0, c.s>>>(x, y, n); });
+}
+void cast_f2d(const float* x, double* y, int64_t n, Ctx& c) {
+  if (n) c.run("cast", 12.0 * n, [&] { k_cast<float, double><<<ceil_div(n, 256), 256, 0, c.s>>>(x, y, n); });
+}
+
+}  // namespace hc

@@ -1,0 +1,842 @@
+// Hierarchy setup (Alg. 3 on every level): nodal operator, smoothed
+// aggregation, coarse gradient, Emin_Setup pattern and local systems (Alg. 2),
+// constrained energy minimisation of P^(e) (Sec. 3, Sec. 4), Galerkin RAP.
+#include <chrono>
+#include <cmath>
+
+#include "amg.hpp"
+
+namespace hc {
+
+// device scalar slots (Ctx::scal)
+enum { S_RHO = 0, S_GAMMA, S_ALPHA, S_RHONEW, S_BETA, S_NX2, S_NY2, S_POWRHO, S_OMEGA, S_ENERGY };
+// device integer flag slots (Ctx::iscal); 0 and 1 are used by the primitives
+enum { F_BAD = 2, F_DISCONNECTED, F_MAXJ, F_MAXNP, F_TOOBIG, F_NOTSPD };
+
+// ---------------------------------------------------------------------------
+// discrete gradient
+// ---------------------------------------------------------------------------
+// Reads a caller CSR gradient: every row exactly one -1 and one +1.
+__global__ void k_grad_from_csr(const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ val,
+                                int n, int m, int* __restrict__ tail, int* __restrict__ head, long long* __restrict__ bad) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int a = rp[i];
+  if (rp[i + 1] - a != 2) { atomicAdd((unsigned long long*)bad, 1ULL); return; }
+  const int c0 = col[a], c1 = col[a + 1];
+  const double v0 = val[a], v1 = val[a + 1];
+  if (c0 < 0 || c1 < 0 || c0 >= m || c1 >= m || c0 == c1) { atomicAdd((unsigned long long*)bad, 1ULL); return; }
+  if (v0 == -1.0 && v1 == 1.0) { tail[i] = c0; head[i] = c1; }
+  else if (v0 == 1.0 && v1 == -1.0) { tail[i] = c1; head[i] = c0; }
+  else atomicAdd((unsigned long long*)bad, 1ULL);
+}
+
+// D as CSR with sorted columns from the endpoint arrays.
+__global__ void k_grad_csr(const int* __restrict__ tail, const int* __restrict__ head, int n, int* __restrict__ rp,
+                           int* __restrict__ col, double* __restrict__ val) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  rp[i] = 2 * i;
+  if (i == n) return;
+  const int t = tail[i], h = head[i];
+  if (t < h) { col[2 * i] = t; col[2 * i + 1] = h; val[2 * i] = -1.0; val[2 * i + 1] = 1.0; }
+  else { col[2 * i] = h; col[2 * i + 1] = t; val[2 * i] = 1.0; val[2 * i + 1] = -1.0; }
+}
+
+static void gradient_csr(Level& L, Ctx& c) {
+  L.D.nrows = L.n; L.D.ncols = L.m; L.D.nnz = 2LL * L.n;
+  L.D.rowptr.alloc(L.n + 1, c.s);
+  L.D.col.alloc(2 * (size_t)L.n, c.s);
+  L.D.val.alloc(2 * (size_t)L.n, c.s);
+  c.run("grad_csr", 24.0 * L.n, [&] {
+    k_grad_csr<<<ceil_div(L.n + 1, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, L.n, L.D.rowptr.p, L.D.col.p, L.D.val.p);
+  });
+  transpose(L.D, L.DT, true, c);
+}
+
+// Diagonal must be positive and finite.
+__global__ void k_check_diag(const double* __restrict__ dinv, int n, long long* __restrict__ bad) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = dinv[i];
+  if (!(v > 0.0) || !isfinite(v)) atomicAdd((unsigned long long*)bad, 1ULL);
+}
+
+static long long read_flag(int slot, Ctx& c) {
+  long long h = 0;
+  d2h(&h, c.iscal.p + slot, 1, c);
+  return h;
+}
+static void clear_flag(int slot, Ctx& c) { HC_HIP(hipMemsetAsync(c.iscal.p + slot, 0, sizeof(long long), c.s)); }
+
+// ---------------------------------------------------------------------------
+// smoothed aggregation
+// ---------------------------------------------------------------------------
+__global__ void k_hash_unit(double* __restrict__ x, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = (double)(splitmix64((uint64_t)i) >> 11) * 0x1.0p-53;
+}
+__global__ void k_mul(double* __restrict__ y, const double* __restrict__ d, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] *= d[i];
+}
+// rho = ||y|| / ||x||, x = y / ||y||
+__global__ void k_power_normalise(double* __restrict__ x, const double* __restrict__ y, int n, const double* __restrict__ nx2,
+                                  const double* __restrict__ ny2, double* __restrict__ rho) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const double ny = sqrt(*ny2);
+  if (i == 0) *rho = ny / sqrt(*nx2);
+  if (i < n) x[i] = y[i] / ny;
+}
+__global__ void k_omega(const double* __restrict__ rho, double* __restrict__ omega) { *omega = 4.0 / (3.0 * *rho); }
+
+__global__ void k_pbar(const int* __restrict__ agg, int m, int* __restrict__ rp, int* __restrict__ col,
+                       double* __restrict__ val) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > m) return;
+  rp[i] = i;
+  if (i < m) { col[i] = agg[i]; val[i] = 1.0; }
+}
+
+// P^(n) = P-bar - omega D^-1 A^(n) P-bar on the pattern of A^(n) P-bar, rows
+// then scaled to sum 1.  On entry val holds (A^(n) P-bar).
+__global__ void k_sa_values(const int* __restrict__ rp, const int* __restrict__ col, double* __restrict__ val,
+                            const int* __restrict__ agg, const double* __restrict__ dinv, const double* __restrict__ omega,
+                            int m) {
+  int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= m) return;
+  const double w = *omega * dinv[u];
+  const int a = agg[u];
+  double s = 0.0;
+  for (int q = rp[u]; q < rp[u + 1]; ++q) {
+    const double v = (col[q] == a ? 1.0 : 0.0) - w * val[q];
+    val[q] = v;
+    s += v;
+  }
+  const double inv = 1.0 / s;
+  for (int q = rp[u]; q < rp[u + 1]; ++q) val[q] *= inv;
+}
+
+// ---------------------------------------------------------------------------
+// coarse gradient by the RS rule on P-bar
+// ---------------------------------------------------------------------------
+__global__ void k_cross_count(const int* __restrict__ tail, const int* __restrict__ head, const int* __restrict__ agg,
+                              int n, int* __restrict__ cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) cnt[i] = agg[tail[i]] != agg[head[i]] ? 2 : 0;
+}
+__global__ void k_cross_fill(const int* __restrict__ tail, const int* __restrict__ head, const int* __restrict__ agg,
+                             int n, const int* __restrict__ rp, int* __restrict__ col) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int I = agg[tail[i]], K = agg[head[i]];
+  if (I == K) return;
+  col[rp[i]] = min(I, K);
+  col[rp[i] + 1] = max(I, K);
+}
+__global__ void k_upper_count(const int* __restrict__ rp, const int* __restrict__ col, int n, int* __restrict__ cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int c = 0;
+  for (int q = rp[i]; q < rp[i + 1]; ++q) c += col[q] > i;
+  cnt[i] = c;
+}
+__global__ void k_upper_fill(const int* __restrict__ rp, const int* __restrict__ col, int n, const int* __restrict__ up,
+                             int* __restrict__ ctail, int* __restrict__ chead) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int o = up[i];
+  for (int q = rp[i]; q < rp[i + 1]; ++q)
+    if (col[q] > i) { ctail[o] = i; chead[o] = col[q]; ++o; }
+}
+
+// ---------------------------------------------------------------------------
+// pattern N of P^(e) (Alg. 2): for fine edge i, the coarse edges whose two end
+// points both lie in T_i (B_ij = 2 with W = 1 for two-node coarse edges).
+// Coarse edges are ordered by (tail, head), so walking T_i in increasing order
+// and each node's outgoing edges yields sorted columns.
+// ---------------------------------------------------------------------------
+static constexpr int kMaxJ = 32;
+
+template <bool FILL>
+__global__ void k_pattern(int n, const int* __restrict__ Trp, const int* __restrict__ Tcol, const int* __restrict__ tptr,
+                          const int* __restrict__ chead, int* __restrict__ cnt, const int* __restrict__ Nrp,
+                          int* __restrict__ Ncol, uint16_t* __restrict__ lpair, long long* __restrict__ flags) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int t0 = Trp[i];
+  const int nJ = Trp[i + 1] - t0;
+  if (nJ > kMaxJ) { atomicAdd((unsigned long long*)&flags[F_TOOBIG], 1ULL); if (!FILL) cnt[i] = 0; return; }
+  unsigned adj[kMaxJ];
+  for (int a = 0; a < nJ; ++a) adj[a] = 0u;
+  int c = 0;
+  const int o = FILL ? Nrp[i] : 0;
+  for (int a = 0; a < nJ; ++a) {
+    const int I = Tcol[t0 + a];
+    for (int e = tptr[I]; e < tptr[I + 1]; ++e) {
+      const int K = chead[e];
+      int lo = a + 1, hi = nJ - 1, b = -1;
+      while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int v = Tcol[t0 + mid];
+        if (v == K) { b = mid; break; }
+        if (v < K) lo = mid + 1; else hi = mid - 1;
+      }
+      if (b >= 0) {
+        if (FILL) {
+          Ncol[o + c] = e;
+          lpair[o + c] = (uint16_t)(a | (b << 8));
+        }
+        adj[a] |= 1u << b;
+        adj[b] |= 1u << a;
+        ++c;
+      }
+    }
+  }
+  if (!FILL) {
+    cnt[i] = c;
+    atomicMax((unsigned long long*)&flags[F_MAXJ], (unsigned long long)nJ);
+    atomicMax((unsigned long long*)&flags[F_MAXNP], (unsigned long long)c);
+    if (nJ >= 2) {
+      unsigned reach = 1u, prev = 0u;
+      while (reach != prev) {
+        prev = reach;
+        for (int a = 0; a < nJ; ++a)
+          if (reach >> a & 1u) reach |= adj[a];
+      }
+      const unsigned all = nJ == 32 ? 0xffffffffu : ((1u << nJ) - 1u);
+      if (reach != all) atomicAdd((unsigned long long*)&flags[F_DISCONNECTED], 1ULL);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// local constraint systems (Sec. 4.2).  For row i with coarse nodes T_i
+// (|J| = nJ) and pattern entries e = (local tail t_e, local head h_e), the
+// transposed sub-matrix G~ keeps all nodes but the last (largest id); its
+// normal matrix L~ = G~^T G~ is the reduced graph Laplacian of the local
+// graph, SPD when the graph is connected (k = nJ - 1 unknowns).
+//   project:     x <- x - G~ L~^-1 G~^T x
+//   affine:      x <- x + G~ L~^-1 (r~ - G~^T x)
+// ---------------------------------------------------------------------------
+template <int MAXJ>
+__device__ __forceinline__ bool local_solve(double* x, const uint16_t* __restrict__ lp, int np, int nJ,
+                                            const double* __restrict__ rrow) {
+  constexpr int MK = MAXJ - 1;
+  constexpr int NL = MK * (MK + 1) / 2;
+  const int k = nJ - 1;
+  if (k <= 0 || np == 0) return true;
+  double L[NL];
+  double y[MK];
+#pragma unroll
+  for (int a = 0; a < NL; ++a) L[a] = 0.0;
+#pragma unroll
+  for (int a = 0; a < MK; ++a) y[a] = 0.0;
+  for (int e = 0; e < np; ++e) {
+    const int t = lp[e] & 255, h = lp[e] >> 8;
+    const double xe = x[e];
+    const int hi = t > h ? t : h, lo = t > h ? h : t;
+#pragma unroll
+    for (int a = 0; a < MK; ++a) {
+      if (a == t) { L[a * (a + 1) / 2 + a] += 1.0; y[a] -= xe; }
+      if (a == h) { L[a * (a + 1) / 2 + a] += 1.0; y[a] += xe; }
+#pragma unroll
+      for (int b = 0; b < a; ++b)
+        if (a == hi && b == lo) L[a * (a + 1) / 2 + b] -= 1.0;
+    }
+  }
+  if (rrow) {
+#pragma unroll
+    for (int a = 0; a < MK; ++a)
+      if (a < k) y[a] = rrow[a] - y[a];
+  }
+  bool ok = true;
+  // Cholesky, packed lower triangle
+#pragma unroll
+  for (int i = 0; i < MK; ++i) {
+    if (i < k) {
+#pragma unroll
+      for (int j = 0; j <= i; ++j) {
+        double s = L[i * (i + 1) / 2 + j];
+#pragma unroll
+        for (int q = 0; q < j; ++q) s -= L[i * (i + 1) / 2 + q] * L[j * (j + 1) / 2 + q];
+        if (i == j) {
+          ok = ok && (s > 0.0);
+          L[i * (i + 1) / 2 + i] = sqrt(s);
+        } else {
+          L[i * (i + 1) / 2 + j] = s / L[j * (j + 1) / 2 + j];
+        }
+      }
+    }
+  }
+  // forward L w = y, backward L^T z = w (in y)
+#pragma unroll
+  for (int i = 0; i < MK; ++i) {
+    if (i < k) {
+      double s = y[i];
+#pragma unroll
+      for (int q = 0; q < i; ++q) s -= L[i * (i + 1) / 2 + q] * y[q];
+      y[i] = s / L[i * (i + 1) / 2 + i];
+    }
+  }
+#pragma unroll
+  for (int i = MK - 1; i >= 0; --i) {
+    if (i < k) {
+      double s = y[i];
+#pragma unroll
+      for (int q = i + 1; q < MK; ++q)
+        if (q < k) s -= L[q * (q + 1) / 2 + i] * y[q];
+      y[i] = s / L[i * (i + 1) / 2 + i];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < MK; ++a)
+    if (a >= k) y[a] = 0.0;
+  for (int e = 0; e < np; ++e) {
+    const int t = lp[e] & 255, h = lp[e] >> 8;
+    double zt = 0.0, zh = 0.0;
+#pragma unroll
+    for (int a = 0; a < MK; ++a) {
+      if (a == t) zt = y[a];
+      if (a == h) zh = y[a];
+    }
+    const double dz = zh - zt;
+    x[e] = rrow ? x[e] + dz : x[e] - dz;
+  }
+  return ok;
+}
+
+// Affine step on every row: x <- x + G~ L~^-1 (r~ - G~^T x).  With `ones` the
+// row is first set to ones (the plain initial guess of Sec. 6.1).
+template <int MAXJ>
+__global__ void k_make_feasible(int n, const int* __restrict__ Prp, double* __restrict__ x, const uint16_t* __restrict__ lp,
+                                const int* __restrict__ Trp, const double* __restrict__ Rval, int ones,
+                                long long* __restrict__ flags) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int p0 = Prp[i], np = Prp[i + 1] - p0;
+  if (ones)
+    for (int e = 0; e < np; ++e) x[p0 + e] = 1.0;
+  const int t0 = Trp[i];
+  if (!local_solve<MAXJ>(x + p0, lp + p0, np, Trp[i + 1] - t0, Rval + t0)) atomicAdd((unsigned long long*)&flags[F_NOTSPD], 1ULL);
+}
+
+// ---------------------------------------------------------------------------
+// masked SpGEMM on P's pattern with fused row projection and inner product:
+//   Out = s * Pi( dscale * mask_N(A X) ),  part[block] = sum X * Out
+// One 64-lane workgroup takes a block of consecutive rows.  The products of
+// the block are flattened over the lanes (prefix sum of the pattern lengths
+// of the A-columns of each chunk of 64 A entries); each product finds its
+// slot in the row's pattern (binary search in LDS) and accumulates there.
+// ---------------------------------------------------------------------------
+static constexpr int kPatCap = 512;
+static constexpr int kRowsCap = 64;
+enum { EM_PROJECT = 1, EM_NEGATE = 2, EM_DOT = 4 };
+
+template <int MAXJ>
+__global__ void __launch_bounds__(64) k_emin_apply(int nrows, int R, const int* __restrict__ Arp,
+                                                   const int* __restrict__ Acol, const double* __restrict__ Aval,
+                                                   const double* __restrict__ dscale, const int* __restrict__ Prp,
+                                                   const int* __restrict__ Pcol, const double* __restrict__ X,
+                                                   const uint16_t* __restrict__ lpair, const int* __restrict__ Trp,
+                                                   double* __restrict__ Out, int flags, double* __restrict__ part,
+                                                   long long* __restrict__ iflags) {
+  __shared__ int pcol[kPatCap];
+  __shared__ double acc[kPatCap];
+  __shared__ int pofs[kRowsCap + 1];
+  __shared__ int arp[kRowsCap + 1];
+  __shared__ int kst[64], pre[64], arow[64];
+  __shared__ double av[64];
+  __shared__ double red[1];
+  const int l = threadIdx.x;
+  const int nbr = (nrows + R - 1) / R;
+  // contiguous row-block ranges per XCD (workgroup b runs on XCD b % 8)
+  const int nw = gridDim.x / 8;
+  const int xcd = blockIdx.x % 8, wi = blockIdx.x / 8;
+  const int chunk = (nbr + 7) / 8;
+  const int rb_end = min(nbr, (xcd + 1) * chunk);
+  double dsum = 0.0;
+  for (int rb = xcd * chunk + wi; rb < rb_end; rb += nw) {
+    const int r0 = rb * R, r1 = min(r0 + R, nrows), nr = r1 - r0;
+    const int p0 = Prp[r0], pn = Prp[r1] - p0;
+    for (int t = l; t < pn; t += 64) { pcol[t] = Pcol[p0 + t]; acc[t] = 0.0; }
+    for (int t = l; t <= nr; t += 64) { pofs[t] = Prp[r0 + t] - p0; arp[t] = Arp[r0 + t]; }
+    __syncthreads();
+    const int a0 = arp[0], a1 = arp[nr];
+    for (int c0 = a0; c0 < a1; c0 += 64) {
+      const int q = c0 + l;
+      int st = 0, len = 0, rl = 0;
+      double a = 0.0;
+      if (q < a1) {
+        int lo = 0, hi = nr - 1;
+        while (lo < hi) {  // largest rl with arp[rl] <= q
+          const int mid = (lo + hi + 1) >> 1;
+          if (arp[mid] <= q) lo = mid; else hi = mid - 1;
+        }
+        rl = lo;
+        if (pofs[rl + 1] > pofs[rl]) {
+          const int k = Acol[q];
+          a = Aval[q];
+          st = Prp[k];
+          len = Prp[k + 1] - st;
+        }
+      }
+      const int incl = wave_incl_scan(len);
+      const int total = __shfl(incl, 63, 64);
+      kst[l] = st; pre[l] = incl - len; arow[l] = rl; av[l] = a;
+      __syncthreads();
+      for (int p = l; p < total; p += 64) {
+        int lo = 0, hi = 63;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (pre[mid] <= p) lo = mid; else hi = mid - 1;
+        }
+        const int pos = kst[lo] + (p - pre[lo]);
+        const int key = Pcol[pos];
+        const int rr = arow[lo];
+        int s = pofs[rr], e = pofs[rr + 1] - 1;
+        while (s < e) {
+          const int mid = (s + e) >> 1;
+          if (pcol[mid] < key) s = mid + 1; else e = mid;
+        }
+        if (s <= e && pcol[s] == key) atomicAdd(&acc[s], av[lo] * X[pos]);
+      }
+      __syncthreads();
+    }
+    if (l < nr) {
+      const int i = r0 + l;
+      double* xr = acc + pofs[l];
+      const int np = pofs[l + 1] - pofs[l];
+      if (dscale) {
+        const double d = dscale[i];
+        for (int e = 0; e < np; ++e) xr[e] *= d;
+      }
+      if (flags & EM_PROJECT) {
+        const int t0 = Trp[i];
+        if (!local_solve<MAXJ>(xr, lpair + p0 + pofs[l], np, Trp[i + 1] - t0, nullptr)) atomicAdd((unsigned long long*)&iflags[F_NOTSPD], 1ULL);
+      }
+    }
+    __syncthreads();
+    for (int t = l; t < pn; t += 64) {
+      double v = acc[t];
+      if (flags & EM_NEGATE) v = -v;
+      Out[p0 + t] = v;
+      if (flags & EM_DOT) dsum += X[p0 + t] * v;
+    }
+    __syncthreads();
+  }
+  dsum = wave_sum(dsum);
+  if (l == 0) part[blockIdx.x] = dsum;
+  (void)red;
+}
+
+// CG vector updates on the pattern values.
+__global__ void __launch_bounds__(256) k_cg_update(int64_t n, double* __restrict__ P, double* __restrict__ R,
+                                                   const double* __restrict__ D, const double* __restrict__ Q,
+                                                   const double* __restrict__ alpha, double* __restrict__ part) {
+  __shared__ double sh[4];
+  const double a = *alpha;
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    P[i] += a * D[i];
+    const double r = R[i] - a * Q[i];
+    R[i] = r;
+    s += r * r;
+  }
+  double t = block_sum256(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+__global__ void k_cg_dir(int64_t n, double* __restrict__ D, const double* __restrict__ R, const double* __restrict__ beta) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) D[i] = R[i] + *beta * D[i];
+}
+// alpha = rho / gamma (0 when rho = 0); flags gamma <= 0 with rho > 0
+__global__ void k_cg_alpha(double* __restrict__ sc, long long* __restrict__ iflags) {
+  const double rho = sc[S_RHO], gamma = sc[S_GAMMA];
+  if (rho > 0.0 && !(gamma > 0.0)) iflags[F_NOTSPD] += 1;
+  sc[S_ALPHA] = (gamma > 0.0) ? rho / gamma : 0.0;
+}
+__global__ void k_cg_beta(double* __restrict__ sc) {
+  const double rho = sc[S_RHO], rn = sc[S_RHONEW];
+  sc[S_BETA] = rho > 0.0 ? rn / rho : 0.0;
+  sc[S_RHO] = rn;
+}
+__global__ void k_axpy_scalar(int64_t n, double* __restrict__ y, const double* __restrict__ x, double a) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += a * x[i];
+}
+
+// ---------------------------------------------------------------------------
+// coarsest level: dense Cholesky and explicit inverse (one workgroup)
+// ---------------------------------------------------------------------------
+__global__ void k_to_dense(const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ val, int n,
+                           double* __restrict__ M) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int q = rp[i]; q < rp[i + 1]; ++q) M[(size_t)i * n + col[q]] = val[q];
+}
+__global__ void __launch_bounds__(1024) k_chol_inverse(double* __restrict__ M, double* __restrict__ inv, int n,
+                                                       long long* __restrict__ iflags) {
+  __shared__ double piv;
+  // right-looking Cholesky, lower triangle of M
+  for (int j = 0; j < n; ++j) {
+    if (threadIdx.x == 0) {
+      double d = M[(size_t)j * n + j];
+      if (!(d > 0.0)) { iflags[F_NOTSPD] += 1; d = 1.0; }
+      piv = sqrt(d);
+      M[(size_t)j * n + j] = piv;
+    }
+    __syncthreads();
+    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) M[(size_t)i * n + j] /= piv;
+    __syncthreads();
+    const int m = n - j - 1;
+    for (int64_t t = threadIdx.x; t < (int64_t)m * m; t += blockDim.x) {
+      const int i = j + 1 + (int)(t / m), k = j + 1 + (int)(t % m);
+      if (k <= i) M[(size_t)i * n + k] -= M[(size_t)i * n + j] * M[(size_t)k * n + j];
+    }
+    __syncthreads();
+  }
+  // columns of the inverse: L L^T x = e_c
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    double* x = inv + (size_t)c;  // column c, stride n
+    for (int i = 0; i < n; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int q = 0; q < i; ++q) s -= M[(size_t)i * n + q] * x[(size_t)q * n];
+      x[(size_t)i * n] = s / M[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = x[(size_t)i * n];
+      for (int q = i + 1; q < n; ++q) s -= M[(size_t)q * n + i] * x[(size_t)q * n];
+      x[(size_t)i * n] = s / M[(size_t)i * n + i];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host orchestration
+// ---------------------------------------------------------------------------
+static int pick_maxj(int maxJ) {
+  if (maxJ <= 8) return 8;
+  if (maxJ <= 16) return 16;
+  return 32;
+}
+
+template <class F>
+static void with_maxj(int maxJ, F&& f) {
+  switch (pick_maxj(maxJ)) {
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    default: f(std::integral_constant<int, 32>{}); break;
+  }
+}
+
+struct EminWork {
+  DBuf<double> P, Rv, Dir, Q, part;
+};
+
+static int emin_grid(int nrows, int R) {
+  const int nbr = (nrows + R - 1) / R;
+  int g = std::min(nbr, 8192);
+  g = std::max(8, (g + 7) / 8 * 8);
+  return g;
+}
+
+// Out = s Pi(dscale mask(A X)); returns the grid used (partials in part).
+static int emin_apply(Level& L, const double* dscale, const double* X, double* Out, int flags, double* part, Ctx& c) {
+  const int R = std::max(1, std::min(kRowsCap, kPatCap / std::max(1, L.maxNp)));
+  const int grid = emin_grid(L.n, R);
+  const double bytes = 12.0 * L.A.nnz + 4.0 * (L.n + 1) * 2 + 12.0 * L.Pe.nnz + 8.0 * L.Pe.nnz + 2.0 * L.Pe.nnz;
+  with_maxj(L.maxJ, [&](auto mj) {
+    c.run("emin_masked_spgemm", bytes, [&] {
+      k_emin_apply<decltype(mj)::value><<<grid, 64, 0, c.s>>>(L.n, R, L.A.rowptr.p, L.A.col.p, L.A.val.p, dscale,
+                                                               L.Pe.rowptr.p, L.Pe.col.p, X, L.lpair.p, L.R.rowptr.p,
+                                                               Out, flags, part, c.iscal.p);
+    });
+  });
+  return grid;
+}
+
+static void make_feasible(Level& L, double* x, bool ones, Ctx& c) {
+  with_maxj(L.maxJ, [&](auto mj) {
+    c.run("emin_affine", 26.0 * L.Pe.nnz, [&] {
+      k_make_feasible<decltype(mj)::value><<<ceil_div(L.n, 128), 128, 0, c.s>>>(
+          L.n, L.Pe.rowptr.p, x, L.lpair.p, L.R.rowptr.p, L.R.val.p, ones ? 1 : 0, c.iscal.p);
+    });
+  });
+}
+
+static double energy_of(Level& L, const double* P, EminWork& w, Ctx& c) {
+  int g = emin_apply(L, nullptr, P, w.Q.p, EM_DOT, w.part.p, c);
+  // sum of partials (g may exceed kRedBlocks: reduce on host deterministically)
+  std::vector<double> h(g);
+  d2h(h.data(), w.part.p, g, c);
+  double s = 0.0;
+  for (double v : h) s += v;
+  return 0.5 * s;
+}
+
+__global__ void k_sum_partials(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) s += part[i];
+  double r = block_sum256(s, sh);
+  if (threadIdx.x == 0) *out = r;
+}
+static void sum_partials(const double* part, int nb, double* out, Ctx& c) {
+  c.run("reduce", 8.0 * nb, [&] { k_sum_partials<<<1, 256, 0, c.s>>>(part, nb, out); });
+}
+
+static void energy_minimisation(Hierarchy& H, Level& L, int iters, bool given_init, const double* init, bool init_dev) {
+  Ctx& c = H.ctx;
+  const int64_t np = L.Pe.nnz;
+  EminWork w;
+  w.P.alloc(np, c.s);
+  w.Rv.alloc(np, c.s);
+  w.Dir.alloc(np, c.s);
+  w.Q.alloc(np, c.s);
+  w.part.alloc(8192, c.s);
+  clear_flag(F_NOTSPD, c);
+  // initial guess
+  if (given_init)
+    HC_HIP(hipMemcpyAsync(w.P.p, init, sizeof(double) * np, init_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c.s));
+  make_feasible(L, w.P.p, !given_init, c);
+  L.p0.alloc(np, c.s);
+  d2d(L.p0.p, w.P.p, np, c);
+  double* sc = c.scal.p;
+  L.energy.clear();
+  const bool rec = H.opts.record_energy != 0;
+  if (rec) L.energy.push_back(energy_of(L, w.P.p, w, c));
+  if (H.opts.emin_method == HCURL_EMIN_JACOBI) {
+    DBuf<double> dinv(L.n, c.s);
+    diagonal(L.A, dinv.p, true, c);
+    for (int it = 0; it < iters; ++it) {
+      emin_apply(L, dinv.p, w.P.p, w.Q.p, EM_PROJECT, w.part.p, c);
+      c.run("emin_axpy", 24.0 * np, [&] { k_axpy_scalar<<<ceil_div(np, 256), 256, 0, c.s>>>(np, w.P.p, w.Q.p, -H.opts.emin_omega); });
+      if (rec) L.energy.push_back(energy_of(L, w.P.p, w, c));
+    }
+  } else {
+    // R = -Pi(mask(A P)), Dir = R, rho = <R, R>
+    emin_apply(L, nullptr, w.P.p, w.Rv.p, EM_PROJECT | EM_NEGATE, w.part.p, c);
+    d2d(w.Dir.p, w.Rv.p, np, c);
+    dot(w.Rv.p, w.Rv.p, np, sc + S_RHO, c, 0);
+    const int ub = Ctx::kRedBlocks;
+    const int nbu = (int)std::min<int64_t>(ub, std::max<int64_t>(1, (np + 255) / 256));
+    for (int it = 0; it < iters; ++it) {
+      int g = emin_apply(L, nullptr, w.Dir.p, w.Q.p, EM_PROJECT | EM_DOT, w.part.p, c);
+      sum_partials(w.part.p, g, sc + S_GAMMA, c);
+      c.run("cg_scalar", 0.0, [&] { k_cg_alpha<<<1, 1, 0, c.s>>>(sc, c.iscal.p); });
+      c.run("emin_cg_update", 48.0 * np, [&] {
+        k_cg_update<<<nbu, 256, 0, c.s>>>(np, w.P.p, w.Rv.p, w.Dir.p, w.Q.p, sc + S_ALPHA, c.red.p);
+      });
+      reduce_partials(nbu, 0, sc + S_RHONEW, c);
+      c.run("cg_scalar", 0.0, [&] { k_cg_beta<<<1, 1, 0, c.s>>>(sc); });
+      c.run("emin_cg_dir", 24.0 * np, [&] { k_cg_dir<<<ceil_div(np, 256), 256, 0, c.s>>>(np, w.Dir.p, w.Rv.p, sc + S_BETA); });
+      if (rec) L.energy.push_back(energy_of(L, w.P.p, w, c));
+    }
+  }
+  // rounding cleanup: re-apply the affine step
+  make_feasible(L, w.P.p, false, c);
+  L.Pe.val = std::move(w.P);
+  if (read_flag(F_NOTSPD, c)) fail(HCURL_ENOTSPD, "non-positive curvature or local Cholesky failure in the energy minimisation");
+}
+
+static void coarsest_factor(Hierarchy& H, Level& L) {
+  Ctx& c = H.ctx;
+  const int n = L.n;
+  if (n > 1024) fail(HCURL_EUNSUPPORTED, "coarsest level has " + std::to_string(n) + " rows (limit 1024): provide more aggregate levels");
+  H.co.n = n;
+  clear_flag(F_NOTSPD, c);
+  DBuf<double> M((size_t)n * n, c.s);
+  H.co.inv.alloc((size_t)n * n, c.s);
+  HC_HIP(hipMemsetAsync(M.p, 0, sizeof(double) * n * n, c.s));
+  c.run("coarse_dense", 12.0 * L.A.nnz, [&] { k_to_dense<<<ceil_div(n, 64), 64, 0, c.s>>>(L.A.rowptr.p, L.A.col.p, L.A.val.p, n, M.p); });
+  c.run("coarse_cholesky", 8.0 * n * n, [&] { k_chol_inverse<<<1, 1024, 0, c.s>>>(M.p, H.co.inv.p, n, c.iscal.p); });
+  if (read_flag(F_NOTSPD, c)) fail(HCURL_ENOTSPD, "coarsest operator is not positive definite");
+}
+
+// nodal operator, diagonals, colourings of one level (all levels)
+static void level_operators(Hierarchy& H, Level& L) {
+  Ctx& c = H.ctx;
+  gradient_csr(L, c);
+  Csr AD;
+  spgemm(L.A, L.D, AD, true, c);
+  spgemm(L.DT, AD, L.An, true, c);
+  L.dinvA.alloc(L.n, c.s);
+  L.dinvAn.alloc(L.m, c.s);
+  diagonal(L.A, L.dinvA.p, true, c);
+  diagonal(L.An, L.dinvAn.p, true, c);
+  clear_flag(F_BAD, c);
+  k_check_diag<<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.dinvA.p, L.n, c.iscal.p + F_BAD);
+  HC_LAUNCH_CHECK();
+  if (read_flag(F_BAD, c)) fail(HCURL_EINVAL, "edge operator has a non-positive or non-finite diagonal entry");
+}
+
+// Everything that builds the transfer from level L to a new level.
+static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg_in, bool level0) {
+  Ctx& c = H.ctx;
+  const bool dev = H.opts.mem_space == HCURL_MEM_DEVICE;
+  // aggregates
+  DBuf<int> agg(L.m, c.s);
+  HC_HIP(hipMemcpyAsync(agg.p, agg_in, sizeof(int) * L.m, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c.s));
+  std::vector<int> hagg(L.m);
+  d2h(hagg.data(), agg.p, L.m, c);
+  int mH = 0;
+  {
+    std::vector<char> seen;
+    for (int v : hagg) {
+      if (v < 0) fail(HCURL_EINVAL, "negative aggregate id");
+      mH = std::max(mH, v + 1);
+    }
+    seen.assign(mH, 0);
+    for (int v : hagg) seen[v] = 1;
+    for (char s : seen)
+      if (!s) fail(HCURL_EINVAL, "aggregate ids are not contiguous (an id is unused)");
+  }
+  // smoothed aggregation P^(n)
+  {
+    DBuf<double> x(L.m, c.s), y(L.m, c.s);
+    c.run("power_init", 8.0 * L.m, [&] { k_hash_unit<<<ceil_div(L.m, 256), 256, 0, c.s>>>(x.p, L.m); });
+    for (int it = 0; it < H.opts.power_iters; ++it) {
+      spmv(L.An, x.p, y.p, nullptr, 0, c, "power_spmv");
+      c.run("power_scale", 24.0 * L.m, [&] { k_mul<<<ceil_div(L.m, 256), 256, 0, c.s>>>(y.p, L.dinvAn.p, L.m); });
+      dot(x.p, x.p, L.m, c.scal.p + S_NX2, c, 1);
+      dot(y.p, y.p, L.m, c.scal.p + S_NY2, c, 2);
+      c.run("power_norm", 16.0 * L.m, [&] {
+        k_power_normalise<<<ceil_div(L.m, 256), 256, 0, c.s>>>(x.p, y.p, L.m, c.scal.p + S_NX2, c.scal.p + S_NY2,
+                                                               c.scal.p + S_POWRHO);
+      });
+    }
+    k_omega<<<1, 1, 0, c.s>>>(c.scal.p + S_POWRHO, c.scal.p + S_OMEGA);
+    HC_LAUNCH_CHECK();
+    double hs[2];
+    d2h(hs, c.scal.p + S_POWRHO, 2, c);
+    L.rho = hs[0];
+    L.omega = hs[1];
+    Csr Pbar;
+    Pbar.nrows = L.m; Pbar.ncols = mH; Pbar.nnz = L.m;
+    Pbar.rowptr.alloc(L.m + 1, c.s); Pbar.col.alloc(L.m, c.s); Pbar.val.alloc(L.m, c.s);
+    k_pbar<<<ceil_div(L.m + 1, 256), 256, 0, c.s>>>(agg.p, L.m, Pbar.rowptr.p, Pbar.col.p, Pbar.val.p);
+    HC_LAUNCH_CHECK();
+    spgemm(L.An, Pbar, L.Pn, true, c);
+    c.run("sa_values", 12.0 * L.Pn.nnz, [&] {
+      k_sa_values<<<ceil_div(L.m, 256), 256, 0, c.s>>>(L.Pn.rowptr.p, L.Pn.col.p, L.Pn.val.p, agg.p, L.dinvAn.p,
+                                                       c.scal.p + S_OMEGA, L.m);
+    });
+  }
+  // coarse gradient: Z = E^T E with E the aggregate pairs of crossing edges
+  auto next = std::make_unique<Level>();
+  DBuf<int> tptr;
+  {
+    Csr E, ET, Z;
+    E.nrows = L.n; E.ncols = mH;
+    E.rowptr.alloc(L.n + 1, c.s);
+    DBuf<int> cnt(L.n + 1, c.s);
+    k_cross_count<<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, agg.p, L.n, cnt.p);
+    HC_LAUNCH_CHECK();
+    E.nnz = exclusive_scan(cnt.p, E.rowptr.p, L.n, c);
+    E.col.alloc(E.nnz, c.s);
+    k_cross_fill<<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, agg.p, L.n, E.rowptr.p, E.col.p);
+    HC_LAUNCH_CHECK();
+    transpose(E, ET, false, c);
+    spgemm(ET, E, Z, false, c);
+    DBuf<int> ucnt(mH + 1, c.s);
+    tptr.alloc(mH + 1, c.s);
+    k_upper_count<<<ceil_div(mH, 256), 256, 0, c.s>>>(Z.rowptr.p, Z.col.p, mH, ucnt.p);
+    HC_LAUNCH_CHECK();
+    const int64_t nH = exclusive_scan(ucnt.p, tptr.p, mH, c);
+    next->n = (int)nH;
+    next->m = mH;
+    next->tail.alloc(nH, c.s);
+    next->head.alloc(nH, c.s);
+    k_upper_fill<<<ceil_div(mH, 256), 256, 0, c.s>>>(Z.rowptr.p, Z.col.p, mH, tptr.p, next->tail.p, next->head.p);
+    HC_LAUNCH_CHECK();
+  }
+  L.n_coarse = next->n;
+  // T and R = D P^(n) on T
+  spgemm(L.D, L.Pn, L.R, true, c);
+  // pattern N
+  {
+    for (int f = F_DISCONNECTED; f <= F_TOOBIG; ++f) clear_flag(f, c);
+    DBuf<int> cnt(L.n + 1, c.s);
+    c.run("pattern", 8.0 * L.R.nnz, [&] {
+      k_pattern<false><<<ceil_div(L.n, 128), 128, 0, c.s>>>(L.n, L.R.rowptr.p, L.R.col.p, tptr.p, next->head.p, cnt.p,
+                                                            nullptr, nullptr, nullptr, c.iscal.p);
+    });
+    long long fl[6];
+    d2h(fl, c.iscal.p, 6, c);
+    if (fl[F_TOOBIG]) fail(HCURL_EUNSUPPORTED, "a fine edge touches more than 32 coarse nodes");
+    if (fl[F_DISCONNECTED])
+      fail(HCURL_EREDUCIBLE, std::to_string(fl[F_DISCONNECTED]) + " rows have a disconnected local coarse-edge graph");
+    L.maxJ = (int)fl[F_MAXJ];
+    L.maxNp = (int)fl[F_MAXNP];
+    if (L.maxNp > kPatCap) fail(HCURL_EUNSUPPORTED, "a row of P^(e) has more than 512 pattern entries");
+    L.Pe.nrows = L.n;
+    L.Pe.ncols = next->n;
+    L.Pe.rowptr.alloc(L.n + 1, c.s);
+    L.Pe.nnz = exclusive_scan(cnt.p, L.Pe.rowptr.p, L.n, c);
+    L.Pe.col.alloc(L.Pe.nnz, c.s);
+    L.lpair.alloc(L.Pe.nnz, c.s);
+    c.run("pattern", 14.0 * L.R.nnz, [&] {
+      k_pattern<true><<<ceil_div(L.n, 128), 128, 0, c.s>>>(L.n, L.R.rowptr.p, L.R.col.p, tptr.p, next->head.p, nullptr,
+                                                           L.Pe.rowptr.p, L.Pe.col.p, L.lpair.p, c.iscal.p);
+    });
+  }
+  // energy minimisation of P^(e)
+  const bool given = level0 && H.opts.init_guess == HCURL_INIT_GIVEN;
+  const int iters = given ? H.opts.emin_iters_given : H.opts.emin_iters;
+  energy_minimisation(H, L, iters, given, H.opts.init_values, dev);
+  transpose(L.Pe, L.PeT, true, c);
+  // Galerkin A_H = P^T A P
+  {
+    Csr AP;
+    spgemm(L.A, L.Pe, AP, true, c);
+    spgemm(L.PeT, AP, next->A, true, c);
+  }
+  L.has_transfer = true;
+  return next;
+}
+
+void build_hierarchy(Hierarchy& H, const hcurl_csr& A, const hcurl_csr& Dh, const int32_t* const* aggs, int nagg) {
+  Ctx& c = H.ctx;
+  const bool dev = H.opts.mem_space == HCURL_MEM_DEVICE;
+  if (A.nrows != A.ncols) fail(HCURL_EINVAL, "A must be square");
+  if (Dh.nrows != A.nrows) fail(HCURL_EINVAL, "D_h must have one row per edge");
+  if (nagg < 0 || (nagg > 0 && !aggs)) fail(HCURL_EINVAL, "aggregates missing");
+  auto L0 = std::make_unique<Level>();
+  L0->n = (int)A.nrows;
+  L0->m = (int)Dh.ncols;
+  upload_csr(A, dev, L0->A, true, c);
+  {
+    Csr Du;
+    upload_csr(Dh, dev, Du, true, c);
+    L0->tail.alloc(L0->n, c.s);
+    L0->head.alloc(L0->n, c.s);
+    clear_flag(F_BAD, c);
+    if (L0->n)
+      k_grad_from_csr<<<ceil_div(L0->n, 256), 256, 0, c.s>>>(Du.rowptr.p, Du.col.p, Du.val.p, L0->n, L0->m, L0->tail.p,
+                                                             L0->head.p, c.iscal.p + F_BAD);
+    HC_LAUNCH_CHECK();
+    if (read_flag(F_BAD, c))
+      fail(HCURL_EINVAL, "every row of D_h must hold exactly one -1 and one +1 (Dirichlet rows are not supported)");
+  }
+  if (H.opts.init_guess == HCURL_INIT_GIVEN && !H.opts.init_values)
+    fail(HCURL_EINVAL, "init_guess = HCURL_INIT_GIVEN needs init_values");
+  H.lv.clear();
+  H.lv.push_back(std::move(L0));
+  const int maxl = H.opts.max_levels > 0 ? H.opts.max_levels : 1 << 20;
+  for (int l = 0;; ++l) {
+    Level& L = *H.lv.back();
+    const bool stop = l >= nagg || (int)H.lv.size() >= maxl ||
+                      (H.opts.coarse_max_rows > 0 && L.n <= H.opts.coarse_max_rows);
+    if (stop) break;
+    level_operators(H, L);
+    color_rows(L.A, L.colorA, L.rowsA, L.cptrA, L.ncolA, c);
+    color_rows(L.An, L.colorAn, L.rowsAn, L.cptrAn, L.ncolAn, c);
+    H.lv.push_back(coarsen(H, L, aggs[l], l == 0));
+  }
+  coarsest_factor(H, *H.lv.back());
+  prepare_solve(H);
+  c.sync();
+}
+
+}  // namespace hc

@@ -258,3 +258,16 @@ def workload(name: str, **kw) -> dict:
     spec = dict(WORKLOADS[name])
     spec.update(kw)
     return problem(**spec)
+
+
+def gradient_csr(tail: np.ndarray, head: np.ndarray):
+    """D_h as CSR arrays (int64 rowptr, int32 col, f64 val): -1 at the tail
+    node and +1 at the head node of every edge, columns sorted."""
+    n = tail.shape[0]
+    lo = np.minimum(tail, head).astype(np.int32)
+    hi = np.maximum(tail, head).astype(np.int32)
+    col = np.stack([lo, hi], axis=1).ravel()
+    up = tail < head
+    val = np.stack([np.where(up, -1.0, 1.0), np.where(up, 1.0, -1.0)], axis=1).ravel()
+    rowptr = np.arange(0, 2 * n + 1, 2, dtype=np.int64)
+    return rowptr, np.ascontiguousarray(col), np.ascontiguousarray(val)

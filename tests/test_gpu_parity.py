@@ -1,0 +1,252 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+the same seeded inputs.  Patterns, aggregates-derived structures, colours and
+local endpoint pairs are compared bit for bit; floating-point results within
+the tolerances stated per check (P^(e): 1e-10 relative, solution residual
+1e-8)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from oracle import hcurl_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    import paper_2506_08284_amd as P
+    return P
+
+
+CASES = {
+    "cube8_const": dict(N=8, sigma=("const", 1.0), f_seed=101),
+    "cube12_jitter_lognormal": dict(N=12, jitter=0.2, jitter_seed=5, sigma=("lognormal", 6, 2.0), f_seed=7),
+    "cube10_inclusions": dict(N=10, sigma=("inclusions", 8, 1.0, 1e-3), f_seed=9),
+    "cube5_const": dict(N=5, sigma=("const", 0.5), f_seed=3),
+    "cube3_width2": dict(N=3, jitter=0.1, jitter_seed=2, sigma=("lognormal", 4, 1.0), f_seed=4, agg_width=2),
+}
+
+_cache = {}
+
+
+def _case(name):
+    if name in _cache:
+        return _cache[name]
+    spec = dict(CASES[name])
+    pr = synth.problem(**spec)
+    m = pr["mesh"]["n"] ** 3
+    levels = O.setup(pr["A"], pr["tail"], pr["head"], m, pr["aggregates"], dict(record_energy=True))
+    P = _lib()
+    Dh = synth.gradient_csr(pr["tail"], pr["head"])
+    H = P.Hierarchy(pr["A"], Dh, pr["aggregates"], n_nodes=m, record_energy=1)
+    _cache[name] = (pr, m, levels, H)
+    return _cache[name]
+
+
+def _sp(t, shape):
+    (rp, col, val), _ = t, None
+    return sp.csr_matrix((val, col, rp), shape=shape)
+
+
+def _export(H, level, which):
+    arrs, shape = H.export_csr(level, which)
+    return sp.csr_matrix((arrs[2], arrs[1], arrs[0]), shape=shape)
+
+
+def _same_pattern(G, R):
+    G, R = O.csr(G), O.csr(R)
+    assert G.shape == R.shape
+    assert np.array_equal(G.indptr, R.indptr)
+    assert np.array_equal(G.indices, R.indices)
+
+
+def _close(G, R, rtol):
+    G, R = O.csr(G), O.csr(R)
+    scale = max(abs(R.data).max(), 1e-300) if R.nnz else 1.0
+    assert np.max(abs(G.data - R.data), initial=0.0) <= rtol * scale
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hierarchy_structure_bit_exact(name):
+    pr, m, levels, H = _case(name)
+    assert H.num_levels() == len(levels)
+    for l, lv in enumerate(levels[:-1]):
+        info = H.level_info(l)
+        assert info["n_edges"] == lv["A"].shape[0]
+        assert info["n_nodes"] == lv["m"]
+        _same_pattern(_export(H, l, "An"), lv["An"])
+        _same_pattern(_export(H, l, "Pn"), lv["Pn"])
+        _same_pattern(_export(H, l, "R"), lv["R"])
+        _same_pattern(_export(H, l, "Pe"), lv["N"])
+        DH = _export(H, l, "DH")
+        ref = O.gradient_matrix(lv["DH_tail"], lv["DH_head"], lv["Pn"].shape[1])
+        _same_pattern(DH, ref)
+        assert np.array_equal(DH.data, O.csr(ref).data)
+        lp = H.export_vec(l, "local_pairs")
+        assert np.array_equal(lp & 255, lv["lt"]) and np.array_equal(lp >> 8, lv["lh"])
+        _same_pattern(_export(H, l + 1, "A"), levels[l + 1]["A"])
+        # colourings are bit-identical (same Jones-Plassmann rule and hash)
+        assert np.array_equal(H.export_vec(l, "colors_A"), lv["colors_A"])
+        assert np.array_equal(H.export_vec(l, "colors_An"), lv["colors_An"])
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hierarchy_values_within_tolerance(name):
+    pr, m, levels, H = _case(name)
+    for l, lv in enumerate(levels[:-1]):
+        info = H.level_info(l)
+        if "rho" in lv["sa"]:
+            assert abs(info["rho"] - lv["sa"]["rho"]) <= 1e-10 * lv["sa"]["rho"]
+        _close(_export(H, l, "An"), lv["An"], 1e-12)
+        _close(_export(H, l, "Pn"), lv["Pn"], 1e-11)
+        _close(_export(H, l, "R"), lv["R"], 1e-11)
+        _close(_export(H, l, "P0"), O.with_values(lv["N"], lv["p0"]), 1e-10)
+        _close(_export(H, l, "Pe"), lv["Pe"], 1e-10)
+        _close(_export(H, l + 1, "A"), levels[l + 1]["A"], 1e-10)
+        E = H.export_vec(l, "energy")
+        Eo = np.array(lv["energies"])
+        assert len(E) == len(Eo)
+        assert np.all(abs(E - Eo) <= 1e-10 * abs(Eo))
+        assert np.all(np.diff(E) <= 0)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_structure_preservation_on_gpu_output(name):
+    """Commuting relation P^(e) D_H = D_h P^(n) and S_H D_H = 0 hold for the
+    GPU's own operators at rounding level."""
+    pr, m, levels, H = _case(name)
+    if H.num_levels() < 2:
+        pytest.skip("single level")
+    Pe = _export(H, 0, "Pe")
+    Pn = _export(H, 0, "Pn")
+    DH = _export(H, 0, "DH")
+    D = O.gradient_matrix(pr["tail"], pr["head"], m)
+    E = Pe @ DH - D @ Pn
+    assert abs(E).max() <= 1e-12 * abs(D @ Pn).max()
+    S = O.csr(synth.assemble(pr["mesh"], pr["sigma"], "S"))
+    SH = Pe.T @ S @ Pe
+    assert abs(SH @ DH).max() <= 1e-11 * abs(SH).max()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_vcycle_and_pcg_parity(name):
+    pr, m, levels, H = _case(name)
+    n = pr["A"][0].shape[0] - 1
+    r = np.random.default_rng(11).standard_normal(n)
+    z = np.empty(n)
+    H.vcycle(r, z)
+    zo = O.vcycle(levels, r)
+    assert np.linalg.norm(z - zo) <= 1e-8 * np.linalg.norm(zo)
+    f = pr["f"]
+    u = np.empty(n)
+    it, rel, rc = H.solve(f, u, 1e-8, 500)
+    uo, ito, relo, _ = O.pcg(levels, f)
+    assert rc == 0 and rel <= 1e-8
+    assert abs(it - ito) <= 1
+    assert np.linalg.norm(u - uo) <= 1e-6 * np.linalg.norm(uo)
+
+
+def test_fp32_vcycle_in_fp64_pcg():
+    pr, m, levels, H64 = _case("cube12_jitter_lognormal")
+    P = _lib()
+    Dh = synth.gradient_csr(pr["tail"], pr["head"])
+    H = P.Hierarchy(pr["A"], Dh, pr["aggregates"], n_nodes=m, vcycle_fp32=1)
+    n = pr["A"][0].shape[0] - 1
+    u = np.empty(n)
+    it, rel, rc = H.solve(pr["f"], u, 1e-8, 500)
+    it64, _, _ = H64.solve(pr["f"], np.empty(n), 1e-8, 500)
+    assert rc == 0 and rel <= 1e-8
+    assert it <= it64 + 3
+    l32 = O.fp32_levels(levels)
+    r = np.random.default_rng(1).standard_normal(n)
+    z = np.empty(n)
+    H.vcycle(r, z)
+    zo = O.vcycle_fp32(l32, r)
+    assert np.linalg.norm(z - zo) <= 2e-4 * np.linalg.norm(zo)
+
+
+def test_projected_jacobi_variant():
+    """One projected Jacobi step with omega = 0.5 (Sec. 3 eq. "emin iteration",
+    the setting of Sec. 6.1)."""
+    pr = synth.problem(8, jitter=0.1, jitter_seed=3, sigma=("lognormal", 2, 1.0))
+    m = 729
+    P = _lib()
+    H = P.Hierarchy(pr["A"], synth.gradient_csr(pr["tail"], pr["head"]), pr["aggregates"], n_nodes=m,
+                    emin_method=1, emin_iters=1, emin_omega=0.5)
+    lvl, _ = O.build_level(O.csr(pr["A"]), pr["tail"], pr["head"], m, pr["aggregates"][0],
+                           dict(emin_method="jacobi", emin_iters=1, emin_omega=0.5))
+    _close(_export(H, 0, "Pe"), lvl["Pe"], 1e-10)
+
+
+def test_given_initial_guess_is_projected_then_refined():
+    """A caller-given level-0 guess is made feasible by the local min-norm
+    correction and refined by 3 CG iterations, like the oracle with p_init."""
+    pr, m, levels, _ = _case("cube8_const")
+    rng = np.random.default_rng(5)
+    guess = levels[0]["Pe"].data + 0.1 * rng.standard_normal(levels[0]["N"].nnz)
+    P = _lib()
+    H = P.Hierarchy(pr["A"], synth.gradient_csr(pr["tail"], pr["head"]), pr["aggregates"], n_nodes=m,
+                    init_guess=1, init_values=guess, emin_iters_given=3, record_energy=1)
+    lvl, _ = O.build_level(O.csr(pr["A"]), pr["tail"], pr["head"], m, pr["aggregates"][0],
+                           dict(p_init=guess, emin_iters=3))
+    _close(_export(H, 0, "P0"), O.with_values(lvl["N"], lvl["p0"]), 1e-10)
+    _close(_export(H, 0, "Pe"), lvl["Pe"], 1e-10)
+    assert len(H.export_vec(0, "energy")) == 4
+
+
+def test_device_pointers_match_host_run():
+    import torch
+    pr, m, levels, Hh = _case("cube10_inclusions")
+    P = _lib()
+    dev = torch.device("cuda:0")
+    Dh = synth.gradient_csr(pr["tail"], pr["head"])
+    A_t = tuple(torch.from_numpy(a).to(dev) for a in pr["A"])
+    D_t = tuple(torch.from_numpy(a).to(dev) for a in Dh)
+    aggs = [torch.from_numpy(a).to(dev) for a in pr["aggregates"]]
+    s = torch.cuda.current_stream()
+    H = P.Hierarchy(A_t, D_t, aggs, n_nodes=m, mem_space="device", stream=s.cuda_stream)
+    f = torch.from_numpy(pr["f"]).to(dev)
+    u = torch.empty_like(f)
+    it, rel, rc = H.solve(f, u)
+    un = np.empty_like(pr["f"])
+    ith, relh, _ = Hh.solve(pr["f"], un)
+    assert it == ith and rel <= 1e-8
+    assert np.linalg.norm(u.cpu().numpy() - un) <= 1e-9 * np.linalg.norm(un)
+
+
+def test_invalid_inputs_rejected():
+    P = _lib()
+    pr = synth.problem(4)
+    m = 125
+    Dh = synth.gradient_csr(pr["tail"], pr["head"])
+    bad = (Dh[0], Dh[1], Dh[2].copy())
+    bad[2][0] = 2.0
+    with pytest.raises(P.HcurlError) as e:
+        P.Hierarchy(pr["A"], bad, pr["aggregates"], n_nodes=m)
+    assert e.value.code == P.HCURL_EINVAL
+    agg = pr["aggregates"][0].copy()
+    agg[agg == 3] = 0  # aggregate 3 left empty
+    with pytest.raises(P.HcurlError) as e:
+        P.Hierarchy(pr["A"], Dh, [agg], n_nodes=m)
+    assert e.value.code == P.HCURL_EINVAL
+    A = (pr["A"][0], pr["A"][1], pr["A"][2].copy())
+    d0 = np.nonzero(A[1][A[0][0]:A[0][1]] == 0)[0][0]
+    A[2][d0] = -1.0
+    with pytest.raises(P.HcurlError) as e:
+        P.Hierarchy(A, Dh, pr["aggregates"], n_nodes=m)
+    assert e.value.code == P.HCURL_EINVAL
+    big = synth.problem(8)
+    with pytest.raises(P.HcurlError) as e:
+        P.Hierarchy(big["A"], synth.gradient_csr(big["tail"], big["head"]), [], n_nodes=729)
+    assert e.value.code == P.HCURL_EUNSUPPORTED
+
+
+def test_single_level_is_direct_solve():
+    pr = synth.problem(2, sigma=("const", 1.0), f_seed=1)
+    P = _lib()
+    H = P.Hierarchy(pr["A"], synth.gradient_csr(pr["tail"], pr["head"]), pr["aggregates"], n_nodes=27)
+    assert H.num_levels() == 1
+    n = pr["A"][0].shape[0] - 1
+    u = np.empty(n)
+    it, rel, rc = H.solve(pr["f"], u)
+    assert it == 1 and rel <= 1e-12
