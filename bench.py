@@ -1,0 +1,190 @@
+"""Benchmark: setup + solve to 1e-8 relative residual on one MI355X.
+
+One step = hcurl_amg_setup (every level: nodal operator, smoothed aggregation,
+coarse gradient, pattern, energy-minimised P^(e), Galerkin RAP, colourings,
+coarsest factor) followed by hcurl_amg_solve (PCG with a Hiptmair V-cycle) to
+||r|| <= 1e-8 ||f||.  Inputs (A, D_h, aggregates, f) are generated on the host,
+copied to HBM before timing, and passed as device pointers.
+
+Prints one JSON line.  `value` is the mean setup+solve seconds of the
+headline form (FP32 V-cycle inside FP64 PCG); the plain all-FP64 form is
+measured the same way and reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def to_device(arrs, torch, dev):
+    return tuple(torch.from_numpy(a).to(dev) for a in arrs)
+
+
+def run_step(P, A_t, D_t, aggs_t, f_t, u_t, m, stream, **opts):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H = P.Hierarchy(A_t, D_t, aggs_t, n_nodes=m, mem_space="device", stream=stream, **opts)
+    t1 = time.perf_counter()
+    it, rel, rc = H.solve(f_t, u_t, 1e-8, 1000)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return H, dict(setup_s=t1 - t0, solve_s=t2 - t1, total_s=t2 - t0, iters=it, relres=rel, rc=rc)
+
+
+def cpu_baseline(spec_name: str, n_full_edges: int, N_sample: int):
+    """Oracle (numpy/scipy FP64, one thread) on a bounded sample of the same
+    workload law, scaled to the full problem by edge count."""
+    import synth
+    from threadpoolctl import threadpool_limits
+    from oracle import hcurl_oracle as O
+    spec = dict(synth.WORKLOADS[spec_name])
+    spec["N"] = N_sample
+    pr = synth.problem(**spec)
+    m = (N_sample + 1) ** 3
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        levels = O.setup(pr["A"], pr["tail"], pr["head"], m, pr["aggregates"])
+        t1 = time.perf_counter()
+        _, it, rel, _ = O.pcg(levels, pr["f"], maxit=1000)
+        t2 = time.perf_counter()
+    ne = pr["A"][0].shape[0] - 1
+    scale = n_full_edges / ne
+    return dict(value=(t2 - t0) * scale, unit="s", cores=1, kind="oracle",
+                sample="oracle setup+solve on the %d^3 cube of the same sigma law (%d edges, %d PCG its, "
+                       "relres %.1e, %.1f s setup + %.1f s solve), scaled by edge count x%.1f"
+                       % (N_sample, ne, it, rel, t1 - t0, t2 - t1, scale))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cube128_contrast")
+    ap.add_argument("--cpu-sample", type=int, default=24, help="edge lattice of the oracle sample (0 = skip)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md on sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_2506_08284_amd as P
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    pr = synth.workload(args.workload)
+    N = synth.WORKLOADS[args.workload]["N"]
+    m = (N + 1) ** 3
+    ne = pr["A"][0].shape[0] - 1
+    log("workload %s: %d edges, nnz(A)=%d, %d aggregate levels, generated in %.1f s"
+        % (args.workload, ne, pr["A"][0][-1], len(pr["aggregates"]), time.perf_counter() - t0))
+    A_t = to_device(pr["A"], torch, dev)
+    D_t = to_device(synth.gradient_csr(pr["tail"], pr["head"]), torch, dev)
+    aggs_t = [torch.from_numpy(a).to(dev) for a in pr["aggregates"]]
+    f_t = torch.from_numpy(pr["f"]).to(dev)
+    u_t = torch.empty_like(f_t)
+    stream = torch.cuda.current_stream().cuda_stream
+    del pr
+    torch.cuda.synchronize()
+
+    head = dict(vcycle_fp32=1)
+    for w in range(args.warmup):
+        H, r = run_step(P, A_t, D_t, aggs_t, f_t, u_t, m, stream, **head)
+        log("warmup fp32-vcycle: %s" % json.dumps(r))
+        H.close()
+
+    # timed region: K steps of the headline form, kernels timed with HIP events
+    results = []
+    kstats = {}
+    torch.cuda.synchronize()
+    tt0 = time.perf_counter()
+    for k in range(args.steps):
+        H, r = run_step(P, A_t, D_t, aggs_t, f_t, u_t, m, stream, profile=1, **head)
+        ks = H.kernel_stats()
+        for name, d in ks.items():
+            acc = kstats.setdefault(name, dict(launches=0, ms=0.0, bytes=0.0))
+            for key in acc:
+                acc[key] += d[key]
+        if k == 0:
+            st = H.stats()
+            info = [H.level_info(l) for l in range(H.num_levels())]
+        H.close()
+        results.append(r)
+        log("step %d fp32-vcycle: %s" % (k, json.dumps(r)))
+    torch.cuda.synchronize()
+    tt1 = time.perf_counter()
+    ms_per_step = (tt1 - tt0) * 1000.0 / args.steps
+
+    fp64 = []
+    if not args.no_fp64:
+        for k in range(max(1, args.steps)):
+            H, r = run_step(P, A_t, D_t, aggs_t, f_t, u_t, m, stream)
+            H.close()
+            fp64.append(r)
+            log("plain fp64: %s" % json.dumps(r))
+
+    top = sorted(kstats.items(), key=lambda kv: -kv[1]["ms"])
+    for name, d in top[:12]:
+        gbs = d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0
+        log("kernel %-22s launches %7d  %9.2f ms  %8.1f GB/s" % (name, d["launches"], d["ms"] / args.steps, gbs))
+    dom_name, dom = top[0]
+    achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
+    mean = lambda key, rs: float(np.mean([x[key] for x in rs])) if rs else None
+    value = mean("total_s", results)
+    out = {
+        "metric": "setup+solve s to 1e-8 resid, HBM GB/s; learned+FP32 vs plain FP64",
+        "value": value,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 setup and PCG, f32 V-cycle",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_edges": ne, "nnz_A": int(A_t[0][-1].item()),
+                   "levels": st["num_levels"], "operator_complexity": st["operator_complexity"],
+                   "form": "fp32 V-cycle in fp64 PCG, plain initial guess + 10 projected-CG emin iterations",
+                   "level_edges": [int(i["n_edges"]) for i in info]},
+        "setup_s": mean("setup_s", results),
+        "solve_s": mean("solve_s", results),
+        "iters": results[-1]["iters"],
+        "relres": results[-1]["relres"],
+        "plain_fp64": ({"setup_s": mean("setup_s", fp64), "solve_s": mean("solve_s", fp64),
+                        "total_s": mean("total_s", fp64), "iters": fp64[-1]["iters"],
+                        "relres": fp64[-1]["relres"]} if fp64 else None),
+        "speedup_vs_plain_fp64": (mean("total_s", fp64) / value) if fp64 else None,
+        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "launches_per_step": dom["launches"] / args.steps,
+                     "bytes_per_launch": dom["bytes"] / dom["launches"],
+                     "avg_launch_us": dom["ms"] * 1e3 / dom["launches"]},
+    }
+    if args.cpu_sample > 0:
+        log("timing the oracle on the %d^3 sample ..." % args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(args.workload, ne, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

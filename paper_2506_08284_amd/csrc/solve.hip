@@ -96,7 +96,7 @@ void color_rows(const Csr& A, DBuf<int>& color, DBuf<int>& rows, std::vector<int
 // Gauss-Seidel on the rows of one colour: x_i += (b_i - A_i x) / a_ii.
 // Rows of one colour are not coupled, so they update in parallel.
 // ---------------------------------------------------------------------------
-template <class T, int LPR>
+template <class T, int LPR, int TAG>
 __global__ void __launch_bounds__(256) k_gs_color(const int* __restrict__ rows, int nr, const int* __restrict__ rp,
                                                   const int* __restrict__ col, const T* __restrict__ val,
                                                   const T* __restrict__ dinv, const T* __restrict__ b, T* __restrict__ x) {
@@ -112,7 +112,10 @@ __global__ void __launch_bounds__(256) k_gs_color(const int* __restrict__ rows, 
   if (l == 0) x[i] += (b[i] - s) * dinv[i];
 }
 
-template <class T>
+// Algorithmic bytes of one colour launch: the rows' CSR data, their b, 1/a_ii
+// and x (read and write), counting every x entry once per sweep (ideal reuse
+// of the gathered neighbours).
+template <class T, int TAG>
 static void sgs_t(const Csr& A, const T* val, const T* dinv, const DBuf<int>& rows, const std::vector<int>& cptr, int ncol,
                   const T* b, T* x, Ctx& c, const char* tag) {
   const double avg = A.nrows ? (double)A.nnz / A.nrows : 0.0;
@@ -120,13 +123,13 @@ static void sgs_t(const Csr& A, const T* val, const T* dinv, const DBuf<int>& ro
     const int nr = cptr[k + 1] - cptr[k];
     if (!nr) return;
     const int* r = rows.p + cptr[k];
-    const double bytes = (double)nr * (avg * (4 + sizeof(T)) + 8 + 4 + 3 * sizeof(T)) + (double)nr * avg * sizeof(T);
+    const double bytes = (double)nr * avg * (4 + sizeof(T)) + (double)nr * (8 + 4 + 4 * sizeof(T));
     if (avg <= 12)
-      c.run(tag, bytes, [&] { k_gs_color<T, 8><<<ceil_div((int64_t)nr * 8, 256), 256, 0, c.s>>>(r, nr, A.rowptr.p, A.col.p, val, dinv, b, x); });
+      c.run(tag, bytes, [&] { k_gs_color<T, 8, TAG><<<ceil_div((int64_t)nr * 8, 256), 256, 0, c.s>>>(r, nr, A.rowptr.p, A.col.p, val, dinv, b, x); });
     else if (avg <= 40)
-      c.run(tag, bytes, [&] { k_gs_color<T, 16><<<ceil_div((int64_t)nr * 16, 256), 256, 0, c.s>>>(r, nr, A.rowptr.p, A.col.p, val, dinv, b, x); });
+      c.run(tag, bytes, [&] { k_gs_color<T, 16, TAG><<<ceil_div((int64_t)nr * 16, 256), 256, 0, c.s>>>(r, nr, A.rowptr.p, A.col.p, val, dinv, b, x); });
     else
-      c.run(tag, bytes, [&] { k_gs_color<T, 64><<<ceil_div((int64_t)nr * 64, 256), 256, 0, c.s>>>(r, nr, A.rowptr.p, A.col.p, val, dinv, b, x); });
+      c.run(tag, bytes, [&] { k_gs_color<T, 64, TAG><<<ceil_div((int64_t)nr * 64, 256), 256, 0, c.s>>>(r, nr, A.rowptr.p, A.col.p, val, dinv, b, x); });
   };
   for (int k = 0; k < ncol; ++k) launch(k);
   for (int k = ncol - 1; k >= 0; --k) launch(k);
@@ -156,24 +159,36 @@ __global__ void __launch_bounds__(256) k_dense_apply(const double* __restrict__ 
 // ---------------------------------------------------------------------------
 // Hiptmair smoother and V-cycle
 // ---------------------------------------------------------------------------
-static void hiptmair64(Level& L, double* x, const double* b, Ctx& c) {
-  sgs_t<double>(L.A, L.A.val.p, L.dinvA.p, L.rowsA, L.cptrA, L.ncolA, b, x, c, "sgs_edge");
-  spmv(L.A, x, L.r.p, b, 1, c, "residual");
+// Level 0 gets its own kernel instances (TAG 1) so that profiles separate the
+// fine-level sweeps from the launch-bound coarse ones.
+static void hiptmair64(Level& L, bool fine, double* x, const double* b, Ctx& c) {
+  auto edge = [&] {
+    if (fine) sgs_t<double, 1>(L.A, L.A.val.p, L.dinvA.p, L.rowsA, L.cptrA, L.ncolA, b, x, c, "sgs_edge_l0");
+    else sgs_t<double, 0>(L.A, L.A.val.p, L.dinvA.p, L.rowsA, L.cptrA, L.ncolA, b, x, c, "sgs_edge");
+  };
+  edge();
+  spmv(L.A, x, L.r.p, b, 1, c, fine ? "residual_l0" : "residual");
   spmv(L.DT, L.r.p, L.rn.p, nullptr, 0, c, "grad_transpose");
   fill(L.cn.p, 0.0, L.m, c);
-  sgs_t<double>(L.An, L.An.val.p, L.dinvAn.p, L.rowsAn, L.cptrAn, L.ncolAn, L.rn.p, L.cn.p, c, "sgs_node");
+  if (fine) sgs_t<double, 2>(L.An, L.An.val.p, L.dinvAn.p, L.rowsAn, L.cptrAn, L.ncolAn, L.rn.p, L.cn.p, c, "sgs_node_l0");
+  else sgs_t<double, 0>(L.An, L.An.val.p, L.dinvAn.p, L.rowsAn, L.cptrAn, L.ncolAn, L.rn.p, L.cn.p, c, "sgs_node");
   c.run("grad_add", 24.0 * L.n, [&] { k_grad_add<double><<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, L.n, L.cn.p, x); });
-  sgs_t<double>(L.A, L.A.val.p, L.dinvA.p, L.rowsA, L.cptrA, L.ncolA, b, x, c, "sgs_edge");
+  edge();
 }
 
-static void hiptmair32(Level& L, float* x, const float* b, Ctx& c) {
-  sgs_t<float>(L.A, L.A.val32.p, L.dinvA32.p, L.rowsA, L.cptrA, L.ncolA, b, x, c, "sgs_edge32");
-  spmv32(L.A, x, L.r32.p, b, 1, c, "residual32");
+static void hiptmair32(Level& L, bool fine, float* x, const float* b, Ctx& c) {
+  auto edge = [&] {
+    if (fine) sgs_t<float, 1>(L.A, L.A.val32.p, L.dinvA32.p, L.rowsA, L.cptrA, L.ncolA, b, x, c, "sgs_edge32_l0");
+    else sgs_t<float, 0>(L.A, L.A.val32.p, L.dinvA32.p, L.rowsA, L.cptrA, L.ncolA, b, x, c, "sgs_edge32");
+  };
+  edge();
+  spmv32(L.A, x, L.r32.p, b, 1, c, fine ? "residual32_l0" : "residual32");
   spmv32(L.DT, L.r32.p, L.rn32.p, nullptr, 0, c, "grad_transpose32");
   fill32(L.cn32.p, 0.0f, L.m, c);
-  sgs_t<float>(L.An, L.An.val32.p, L.dinvAn32.p, L.rowsAn, L.cptrAn, L.ncolAn, L.rn32.p, L.cn32.p, c, "sgs_node32");
+  if (fine) sgs_t<float, 2>(L.An, L.An.val32.p, L.dinvAn32.p, L.rowsAn, L.cptrAn, L.ncolAn, L.rn32.p, L.cn32.p, c, "sgs_node32_l0");
+  else sgs_t<float, 0>(L.An, L.An.val32.p, L.dinvAn32.p, L.rowsAn, L.cptrAn, L.ncolAn, L.rn32.p, L.cn32.p, c, "sgs_node32");
   c.run("grad_add32", 12.0 * L.n, [&] { k_grad_add<float><<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, L.n, L.cn32.p, x); });
-  sgs_t<float>(L.A, L.A.val32.p, L.dinvA32.p, L.rowsA, L.cptrA, L.ncolA, b, x, c, "sgs_edge32");
+  edge();
 }
 
 static void vcycle64(Hierarchy& H, int l, const double* b, double* x) {
@@ -187,12 +202,12 @@ static void vcycle64(Hierarchy& H, int l, const double* b, double* x) {
   Level& L = *H.lv[l];
   Level& N = *H.lv[l + 1];
   fill(x, 0.0, L.n, c);
-  hiptmair64(L, x, b, c);
+  hiptmair64(L, l == 0, x, b, c);
   spmv(L.A, x, L.r.p, b, 1, c, "residual");
   spmv(L.PeT, L.r.p, N.b.p, nullptr, 0, c, "restrict");
   vcycle64(H, l + 1, N.b.p, N.x.p);
   spmv(L.Pe, N.x.p, x, nullptr, 2, c, "prolong");
-  hiptmair64(L, x, b, c);
+  hiptmair64(L, l == 0, x, b, c);
 }
 
 static void vcycle32(Hierarchy& H, int l, const float* b, float* x) {
@@ -206,12 +221,12 @@ static void vcycle32(Hierarchy& H, int l, const float* b, float* x) {
   Level& L = *H.lv[l];
   Level& N = *H.lv[l + 1];
   fill32(x, 0.0f, L.n, c);
-  hiptmair32(L, x, b, c);
+  hiptmair32(L, l == 0, x, b, c);
   spmv32(L.A, x, L.r32.p, b, 1, c, "residual32");
   spmv32(L.PeT, L.r32.p, N.b32.p, nullptr, 0, c, "restrict32");
   vcycle32(H, l + 1, N.b32.p, N.x32.p);
   spmv32(L.Pe, N.x32.p, x, nullptr, 2, c, "prolong32");
-  hiptmair32(L, x, b, c);
+  hiptmair32(L, l == 0, x, b, c);
 }
 
 void apply_vcycle(Hierarchy& H, const double* r, double* z) {
