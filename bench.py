@@ -7,8 +7,8 @@ coarsest factor) followed by hcurl_amg_solve (PCG with a Hiptmair V-cycle) to
 copied to HBM before timing, and passed as device pointers.
 
 Prints one JSON line.  `value` is the mean setup+solve seconds of the
-headline form (FP32 V-cycle inside FP64 PCG); the plain all-FP64 form is
-measured the same way and reported beside it.
+headline form (default: plain FP64; the FP32 V-cycle form is run beside it
+untimed and reported with its iteration count and residual).
 """
 from __future__ import annotations
 
@@ -32,13 +32,13 @@ def to_device(arrs, torch, dev):
     return tuple(torch.from_numpy(a).to(dev) for a in arrs)
 
 
-def run_step(P, A_t, D_t, aggs_t, f_t, u_t, m, stream, **opts):
+def run_step(P, A_t, D_t, aggs_t, f_t, u_t, m, stream, maxit=1000, **opts):
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     H = P.Hierarchy(A_t, D_t, aggs_t, n_nodes=m, mem_space="device", stream=stream, **opts)
     t1 = time.perf_counter()
-    it, rel, rc = H.solve(f_t, u_t, 1e-8, 1000)
+    it, rel, rc = H.solve(f_t, u_t, 1e-8, maxit)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     return H, dict(setup_s=t1 - t0, solve_s=t2 - t1, total_s=t2 - t0, iters=it, relres=rel, rc=rc)
@@ -75,7 +75,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cube128_contrast")
     ap.add_argument("--cpu-sample", type=int, default=24, help="edge lattice of the oracle sample (0 = skip)")
-    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
+    ap.add_argument("--form", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--maxit", type=int, default=500)
+    ap.add_argument("--no-compare", action="store_true", help="skip the untimed other-precision run")
+    ap.add_argument("--coarse-max-rows", type=int, default=1024)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md on sharding)",
@@ -89,6 +92,8 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(0)
+    side = torch.cuda.Stream()  # default priority; a non-null stream lets the V-cycle run as a HIP graph
+    torch.cuda.set_stream(side)
     t0 = time.perf_counter()
     pr = synth.workload(args.workload)
     N = synth.WORKLOADS[args.workload]["N"]
@@ -105,19 +110,22 @@ def main():
     del pr
     torch.cuda.synchronize()
 
-    head = dict(vcycle_fp32=1)
+    cmr = dict(coarse_max_rows=args.coarse_max_rows)
+    forms = {"fp64": dict(**cmr), "fp32": dict(vcycle_fp32=1, **cmr)}
+    head = forms[args.form]
     for w in range(args.warmup):
-        H, r = run_step(P, A_t, D_t, aggs_t, f_t, u_t, m, stream, **head)
-        log("warmup fp32-vcycle: %s" % json.dumps(r))
+        H, r = run_step(P, A_t, D_t, aggs_t, f_t, u_t, m, stream, maxit=args.maxit, **head)
+        log("warmup %s: %s" % (args.form, json.dumps(r)))
         H.close()
 
-    # timed region: K steps of the headline form, kernels timed with HIP events
+    # timed region: K steps of the headline form, every kernel bracketed by HIP
+    # events on the library's stream (this disables the V-cycle graph)
     results = []
     kstats = {}
     torch.cuda.synchronize()
     tt0 = time.perf_counter()
     for k in range(args.steps):
-        H, r = run_step(P, A_t, D_t, aggs_t, f_t, u_t, m, stream, profile=1, **head)
+        H, r = run_step(P, A_t, D_t, aggs_t, f_t, u_t, m, stream, profile=1, maxit=args.maxit, **head)
         ks = H.kernel_stats()
         for name, d in ks.items():
             acc = kstats.setdefault(name, dict(launches=0, ms=0.0, bytes=0.0))
@@ -126,25 +134,31 @@ def main():
         if k == 0:
             st = H.stats()
             info = [H.level_info(l) for l in range(H.num_levels())]
+            log("levels: " + "; ".join("%d edges %d nodes colours %d/%d" % (i["n_edges"], i["n_nodes"], i["n_colors_A"],
+                                                                               i["n_colors_An"]) for i in info))
         H.close()
         results.append(r)
-        log("step %d fp32-vcycle: %s" % (k, json.dumps(r)))
+        log("step %d %s: %s" % (k, args.form, json.dumps(r)))
     torch.cuda.synchronize()
     tt1 = time.perf_counter()
     ms_per_step = (tt1 - tt0) * 1000.0 / args.steps
 
-    fp64 = []
-    if not args.no_fp64:
-        for k in range(max(1, args.steps)):
-            H, r = run_step(P, A_t, D_t, aggs_t, f_t, u_t, m, stream)
-            H.close()
-            fp64.append(r)
-            log("plain fp64: %s" % json.dumps(r))
+    # untimed companions: the same form without per-kernel events (V-cycle as
+    # a HIP graph) and the other precision
+    extra = {}
+    for name, opts in forms.items():
+        if args.no_compare and name != args.form:
+            continue
+        H, r = run_step(P, A_t, D_t, aggs_t, f_t, u_t, m, stream, maxit=args.maxit, **opts)
+        H.close()
+        r["converged"] = r["rc"] == 0 and r["relres"] <= 1e-6
+        extra[name] = r
+        log("untimed %s (graph V-cycle): %s" % (name, json.dumps(r)))
 
     top = sorted(kstats.items(), key=lambda kv: -kv[1]["ms"])
-    for name, d in top[:12]:
+    for name, d in top[:14]:
         gbs = d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0
-        log("kernel %-22s launches %7d  %9.2f ms  %8.1f GB/s" % (name, d["launches"], d["ms"] / args.steps, gbs))
+        log("kernel %-22s launches %7d  %9.2f ms/step  %8.1f GB/s" % (name, d["launches"], d["ms"] / args.steps, gbs))
     dom_name, dom = top[0]
     achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
     mean = lambda key, rs: float(np.mean([x[key] for x in rs])) if rs else None
@@ -160,20 +174,17 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64 setup and PCG, f32 V-cycle",
+        "dtype": "f64" if args.form == "fp64" else "f64 setup and PCG, f32 V-cycle",
         "data": "synthetic",
         "config": {"workload": args.workload, "n_edges": ne, "nnz_A": int(A_t[0][-1].item()),
                    "levels": st["num_levels"], "operator_complexity": st["operator_complexity"],
-                   "form": "fp32 V-cycle in fp64 PCG, plain initial guess + 10 projected-CG emin iterations",
+                   "form": args.form + " V-cycle in fp64 PCG, plain initial guess + 10 projected-CG emin iterations",
                    "level_edges": [int(i["n_edges"]) for i in info]},
         "setup_s": mean("setup_s", results),
         "solve_s": mean("solve_s", results),
         "iters": results[-1]["iters"],
         "relres": results[-1]["relres"],
-        "plain_fp64": ({"setup_s": mean("setup_s", fp64), "solve_s": mean("solve_s", fp64),
-                        "total_s": mean("total_s", fp64), "iters": fp64[-1]["iters"],
-                        "relres": fp64[-1]["relres"]} if fp64 else None),
-        "speedup_vs_plain_fp64": (mean("total_s", fp64) / value) if fp64 else None,
+        "untimed_forms": extra,
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "launches_per_step": dom["launches"] / args.steps,

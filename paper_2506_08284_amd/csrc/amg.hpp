@@ -22,8 +22,14 @@ struct Level {
   // multicolour Gauss-Seidel orderings
   int ncolA = 0, ncolAn = 0;
   std::vector<int> cptrA, cptrAn;  // host offsets of each colour in rowsA / rowsAn
-  DBuf<int> rowsA, rowsAn;         // rows grouped by colour
+  DBuf<int> cptrA_d, cptrAn_d;     // the same offsets on the device
+  DBuf<int> rowsA, rowsAn;         // rows grouped by colour, increasing within a colour
   DBuf<int> colorA, colorAn;
+  // colour-major copies: row g is original row rows[g], columns unchanged,
+  // so every colour is one contiguous block of rows
+  Csr Acm, Ancm;
+  DBuf<double> dinvAcm, dinvAncm;
+  DBuf<float> dinvAcm32, dinvAncm32;
 
   // transfer to the next level (empty on the coarsest level)
   bool has_transfer = false;
@@ -49,6 +55,10 @@ struct Coarsest {
 
 struct Hierarchy {
   Ctx ctx;
+  hipGraphExec_t vgraph = nullptr;  // captured V-cycle on (pr -> pz)
+  ~Hierarchy() {
+    if (vgraph) (void)hipGraphExecDestroy(vgraph);
+  }
   hcurl_amg_opts opts{};
   std::vector<std::unique_ptr<Level>> lv;
   Coarsest co;
@@ -64,6 +74,8 @@ void build_hierarchy(Hierarchy& H, const hcurl_csr& A, const hcurl_csr& Dh, cons
 
 // solve.hip
 void color_rows(const Csr& A, DBuf<int>& color, DBuf<int>& rows, std::vector<int>& cptr, int& ncol, Ctx& c);
+void colour_major(const Csr& A, const DBuf<int>& rows, Csr& Acm, Ctx& c);
+void gather_vec(const double* x, const int* rows, double* y, int n, Ctx& c);
 void prepare_solve(Hierarchy& H);
 void apply_vcycle(Hierarchy& H, const double* r, double* z);
 int pcg_solve(Hierarchy& H, const double* f, double* u, double rtol, int maxit, int* iters, double* relres);

@@ -478,12 +478,13 @@ template <class T, class Acc, int LPR>
 __global__ void __launch_bounds__(256) k_spmv(const int* __restrict__ rp, const int* __restrict__ col,
                                               const T* __restrict__ val, const T* __restrict__ x, T* __restrict__ y,
                                               const T* __restrict__ b, int n, int mode) {
-  const int g = (blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+  const int g = (xcd_block(gridDim.x) * blockDim.x + threadIdx.x) / LPR;
   const int l = threadIdx.x & (LPR - 1);
   if (g >= n) return;
   Acc s = 0;
   const int e = rp[g + 1];
-  for (int q = rp[g] + l; q < e; q += LPR) s += (Acc)val[q] * (Acc)x[col[q]];
+  for (int q = rp[g] + l; q < e; q += LPR)
+    s += (Acc)__builtin_nontemporal_load(&val[q]) * (Acc)x[__builtin_nontemporal_load(&col[q])];
 #pragma unroll
   for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LPR);
   if (l == 0) {
@@ -501,10 +502,12 @@ static void spmv_t(const int* rp, const int* col, const T* val, int n, int64_t n
   const double bytes = (double)nnz * (4 + sizeof(T)) + 4.0 * (n + 1) + sizeof(T) * (2.0 * n + (mode ? n : 0));
   if (avg <= 6)
     c.run(tag, bytes, [&] { k_spmv<T, Acc, 4><<<ceil_div((int64_t)n * 4, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
-  else if (avg <= 24)
+  else if (avg <= 20)
     c.run(tag, bytes, [&] { k_spmv<T, Acc, 8><<<ceil_div((int64_t)n * 8, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
-  else if (avg <= 64)
+  else if (avg <= 48)
     c.run(tag, bytes, [&] { k_spmv<T, Acc, 16><<<ceil_div((int64_t)n * 16, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
+  else if (avg <= 96)
+    c.run(tag, bytes, [&] { k_spmv<T, Acc, 32><<<ceil_div((int64_t)n * 32, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
   else
     c.run(tag, bytes, [&] { k_spmv<T, Acc, 64><<<ceil_div((int64_t)n * 64, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
 }

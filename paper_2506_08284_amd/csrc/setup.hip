@@ -322,41 +322,68 @@ __global__ void k_make_feasible(int n, const int* __restrict__ Prp, double* __re
 }
 
 // ---------------------------------------------------------------------------
-// masked SpGEMM on P's pattern with fused row projection and inner product:
-//   Out = s * Pi( dscale * mask_N(A X) ),  part[block] = sum X * Out
-// One 64-lane workgroup takes a block of consecutive rows.  The products of
+// masked SpGEMM on P's pattern:  Y = dscale * mask_N(A X)
+// One 64-lane workgroup takes a block of R consecutive rows.  The products of
 // the block are flattened over the lanes (prefix sum of the pattern lengths
 // of the A-columns of each chunk of 64 A entries); each product finds its
-// slot in the row's pattern (binary search in LDS) and accumulates there.
+// slot in the row's pattern (binary search in LDS) and accumulates there with
+// an LDS atomic.  Two products per lane are in flight at a time.  With
+// EM_DOT the block also sums X * Y (the energy <P, A P>).
 // ---------------------------------------------------------------------------
 static constexpr int kPatCap = 512;
 static constexpr int kRowsCap = 64;
 enum { EM_PROJECT = 1, EM_NEGATE = 2, EM_DOT = 4 };
 
-template <int MAXJ>
-__global__ void __launch_bounds__(64) k_emin_apply(int nrows, int R, const int* __restrict__ Arp,
-                                                   const int* __restrict__ Acol, const double* __restrict__ Aval,
-                                                   const double* __restrict__ dscale, const int* __restrict__ Prp,
-                                                   const int* __restrict__ Pcol, const double* __restrict__ X,
-                                                   const uint16_t* __restrict__ lpair, const int* __restrict__ Trp,
-                                                   double* __restrict__ Out, int flags, double* __restrict__ part,
-                                                   long long* __restrict__ iflags) {
-  __shared__ int pcol[kPatCap];
-  __shared__ double acc[kPatCap];
+struct RowBlocks {
+  // contiguous row-block ranges per XCD (workgroup b runs on XCD b % 8)
+  int nbr, chunk, xcd, wi, nw;
+  __device__ RowBlocks(int nrows, int R) {
+    nbr = (nrows + R - 1) / R;
+    nw = gridDim.x / 8;
+    xcd = blockIdx.x % 8;
+    wi = blockIdx.x / 8;
+    chunk = (nbr + 7) / 8;
+  }
+  __device__ int first() const { return xcd * chunk + wi; }
+  __device__ int end() const { return min(nbr, (xcd + 1) * chunk); }
+};
+
+__device__ __forceinline__ void emin_product(int p, const int* pre, const int* kst, const int* arow, const double* av,
+                                             const int* pofs, const int* pcol, double* acc, const int* __restrict__ Pcol,
+                                             const double* __restrict__ X) {
+  int lo = 0, hi = 63;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= p) lo = mid; else hi = mid - 1;
+  }
+  const int pos = kst[lo] + (p - pre[lo]);
+  const int key = Pcol[pos];
+  const double v = av[lo] * X[pos];
+  const int rr = arow[lo];
+  int s = pofs[rr], e = pofs[rr + 1] - 1;
+  while (s < e) {
+    const int mid = (s + e) >> 1;
+    if (pcol[mid] < key) s = mid + 1; else e = mid;
+  }
+  if (s <= e && pcol[s] == key) atomicAdd(&acc[s], v);
+}
+
+template <int CAP>
+__global__ void __launch_bounds__(64) k_emin_masked(int nrows, int R, const int* __restrict__ Arp,
+                                                    const int* __restrict__ Acol, const double* __restrict__ Aval,
+                                                    const double* __restrict__ dscale, const int* __restrict__ Prp,
+                                                    const int* __restrict__ Pcol, const double* __restrict__ X,
+                                                    double* __restrict__ Y, int flags, double* __restrict__ part) {
+  __shared__ int pcol[CAP];
+  __shared__ double acc[CAP];
   __shared__ int pofs[kRowsCap + 1];
   __shared__ int arp[kRowsCap + 1];
   __shared__ int kst[64], pre[64], arow[64];
   __shared__ double av[64];
-  __shared__ double red[1];
   const int l = threadIdx.x;
-  const int nbr = (nrows + R - 1) / R;
-  // contiguous row-block ranges per XCD (workgroup b runs on XCD b % 8)
-  const int nw = gridDim.x / 8;
-  const int xcd = blockIdx.x % 8, wi = blockIdx.x / 8;
-  const int chunk = (nbr + 7) / 8;
-  const int rb_end = min(nbr, (xcd + 1) * chunk);
+  const RowBlocks B(nrows, R);
   double dsum = 0.0;
-  for (int rb = xcd * chunk + wi; rb < rb_end; rb += nw) {
+  for (int rb = B.first(); rb < B.end(); rb += B.nw) {
     const int r0 = rb * R, r1 = min(r0 + R, nrows), nr = r1 - r0;
     const int p0 = Prp[r0], pn = Prp[r1] - p0;
     for (int t = l; t < pn; t += 64) { pcol[t] = Pcol[p0 + t]; acc[t] = 0.0; }
@@ -385,36 +412,58 @@ __global__ void __launch_bounds__(64) k_emin_apply(int nrows, int R, const int* 
       const int total = __shfl(incl, 63, 64);
       kst[l] = st; pre[l] = incl - len; arow[l] = rl; av[l] = a;
       __syncthreads();
-      for (int p = l; p < total; p += 64) {
-        int lo = 0, hi = 63;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (pre[mid] <= p) lo = mid; else hi = mid - 1;
-        }
-        const int pos = kst[lo] + (p - pre[lo]);
-        const int key = Pcol[pos];
-        const int rr = arow[lo];
-        int s = pofs[rr], e = pofs[rr + 1] - 1;
-        while (s < e) {
-          const int mid = (s + e) >> 1;
-          if (pcol[mid] < key) s = mid + 1; else e = mid;
-        }
-        if (s <= e && pcol[s] == key) atomicAdd(&acc[s], av[lo] * X[pos]);
+      int p = l;
+      for (; p + 64 < total; p += 128) {
+        emin_product(p, pre, kst, arow, av, pofs, pcol, acc, Pcol, X);
+        emin_product(p + 64, pre, kst, arow, av, pofs, pcol, acc, Pcol, X);
       }
+      if (p < total) emin_product(p, pre, kst, arow, av, pofs, pcol, acc, Pcol, X);
       __syncthreads();
     }
+    for (int t = l; t < pn; t += 64) {
+      double v = acc[t];
+      if (dscale) {
+        int lo = 0, hi = nr - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (pofs[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        v *= dscale[r0 + lo];
+      }
+      Y[p0 + t] = v;
+      if (flags & EM_DOT) dsum += X[p0 + t] * v;
+    }
+    __syncthreads();
+  }
+  dsum = wave_sum(dsum);
+  if (l == 0) part[blockIdx.x] = dsum;
+}
+
+// Row projection of a vector on the pattern: Out = s * Pi(Y), with the
+// block's values staged through LDS (coalesced load and store) and one
+// thread per row solving its local system; with EM_DOT, part[block] = sum X*Out.
+template <int MAXJ, int CAP>
+__global__ void __launch_bounds__(64) k_emin_project(int nrows, int R, const int* __restrict__ Prp,
+                                                     const double* __restrict__ Y, const uint16_t* __restrict__ lpair,
+                                                     const int* __restrict__ Trp, const double* __restrict__ X,
+                                                     double* __restrict__ Out, int flags, double* __restrict__ part,
+                                                     long long* __restrict__ iflags) {
+  __shared__ double acc[CAP];
+  __shared__ int pofs[kRowsCap + 1];
+  const int l = threadIdx.x;
+  const RowBlocks B(nrows, R);
+  double dsum = 0.0;
+  for (int rb = B.first(); rb < B.end(); rb += B.nw) {
+    const int r0 = rb * R, r1 = min(r0 + R, nrows), nr = r1 - r0;
+    const int p0 = Prp[r0], pn = Prp[r1] - p0;
+    for (int t = l; t < pn; t += 64) acc[t] = Y[p0 + t];
+    for (int t = l; t <= nr; t += 64) pofs[t] = Prp[r0 + t] - p0;
+    __syncthreads();
     if (l < nr) {
       const int i = r0 + l;
-      double* xr = acc + pofs[l];
-      const int np = pofs[l + 1] - pofs[l];
-      if (dscale) {
-        const double d = dscale[i];
-        for (int e = 0; e < np; ++e) xr[e] *= d;
-      }
-      if (flags & EM_PROJECT) {
-        const int t0 = Trp[i];
-        if (!local_solve<MAXJ>(xr, lpair + p0 + pofs[l], np, Trp[i + 1] - t0, nullptr)) atomicAdd((unsigned long long*)&iflags[F_NOTSPD], 1ULL);
-      }
+      const int t0 = Trp[i];
+      if (!local_solve<MAXJ>(acc + pofs[l], lpair + p0 + pofs[l], pofs[l + 1] - pofs[l], Trp[i + 1] - t0, nullptr))
+        atomicAdd((unsigned long long*)&iflags[F_NOTSPD], 1ULL);
     }
     __syncthreads();
     for (int t = l; t < pn; t += 64) {
@@ -427,7 +476,6 @@ __global__ void __launch_bounds__(64) k_emin_apply(int nrows, int R, const int* 
   }
   dsum = wave_sum(dsum);
   if (l == 0) part[blockIdx.x] = dsum;
-  (void)red;
 }
 
 // CG vector updates on the pattern values.
@@ -531,7 +579,7 @@ static void with_maxj(int maxJ, F&& f) {
 }
 
 struct EminWork {
-  DBuf<double> P, Rv, Dir, Q, part;
+  DBuf<double> P, Rv, Dir, Q, Y, part;
 };
 
 static int emin_grid(int nrows, int R) {
@@ -541,18 +589,45 @@ static int emin_grid(int nrows, int R) {
   return g;
 }
 
-// Out = s Pi(dscale mask(A X)); returns the grid used (partials in part).
-static int emin_apply(Level& L, const double* dscale, const double* X, double* Out, int flags, double* part, Ctx& c) {
-  const int R = std::max(1, std::min(kRowsCap, kPatCap / std::max(1, L.maxNp)));
+// Out = s Pi(dscale mask(A X)) (projection with EM_PROJECT); returns the
+// grid whose partial sums X . Out are in part (EM_DOT).  Y is scratch of the
+// pattern's length, used when projecting.
+static constexpr int kPatSmall = 256;
+
+static int emin_rows_per_block(const Level& L) {
+  const int cap = L.maxNp * 4 <= kPatSmall ? kPatSmall : kPatCap;
+  return std::max(1, std::min(kRowsCap, cap / std::max(1, L.maxNp)));
+}
+
+static int emin_apply(Level& L, const double* dscale, const double* X, double* Out, int flags, double* part, double* Y,
+                      Ctx& c) {
+  const int R = emin_rows_per_block(L);
+  const bool small = L.maxNp * 4 <= kPatSmall;
   const int grid = emin_grid(L.n, R);
-  const double bytes = 12.0 * L.A.nnz + 4.0 * (L.n + 1) * 2 + 12.0 * L.Pe.nnz + 8.0 * L.Pe.nnz + 2.0 * L.Pe.nnz;
-  with_maxj(L.maxJ, [&](auto mj) {
-    c.run("emin_masked_spgemm", bytes, [&] {
-      k_emin_apply<decltype(mj)::value><<<grid, 64, 0, c.s>>>(L.n, R, L.A.rowptr.p, L.A.col.p, L.A.val.p, dscale,
-                                                               L.Pe.rowptr.p, L.Pe.col.p, X, L.lpair.p, L.R.rowptr.p,
-                                                               Out, flags, part, c.iscal.p);
-    });
+  const double bytes = 12.0 * L.A.nnz + 4.0 * (L.n + 1) * 2 + 12.0 * L.Pe.nnz + 8.0 * L.Pe.nnz;
+  const bool proj = flags & EM_PROJECT;
+  double* tgt = proj ? Y : Out;
+  c.run("emin_masked_spgemm", bytes, [&] {
+    if (small)
+      k_emin_masked<kPatSmall><<<grid, 64, 0, c.s>>>(L.n, R, L.A.rowptr.p, L.A.col.p, L.A.val.p, dscale, L.Pe.rowptr.p,
+                                                     L.Pe.col.p, X, tgt, proj ? 0 : flags, part);
+    else
+      k_emin_masked<kPatCap><<<grid, 64, 0, c.s>>>(L.n, R, L.A.rowptr.p, L.A.col.p, L.A.val.p, dscale, L.Pe.rowptr.p,
+                                                   L.Pe.col.p, X, tgt, proj ? 0 : flags, part);
   });
+  if (proj) {
+    // one row per lane: blocks of up to 64 rows, LDS sized for them
+    constexpr int kProjCap = 1536;
+    const int RP = std::max(1, std::min(kRowsCap, kProjCap / std::max(1, L.maxNp)));
+    const int pgrid = emin_grid(L.n, RP);
+    with_maxj(L.maxJ, [&](auto mj) {
+      c.run("emin_projection", 26.0 * L.Pe.nnz, [&] {
+        k_emin_project<decltype(mj)::value, kProjCap><<<pgrid, 64, 0, c.s>>>(L.n, RP, L.Pe.rowptr.p, Y, L.lpair.p,
+                                                                             L.R.rowptr.p, X, Out, flags, part, c.iscal.p);
+      });
+    });
+    return pgrid;
+  }
   return grid;
 }
 
@@ -566,7 +641,7 @@ static void make_feasible(Level& L, double* x, bool ones, Ctx& c) {
 }
 
 static double energy_of(Level& L, const double* P, EminWork& w, Ctx& c) {
-  int g = emin_apply(L, nullptr, P, w.Q.p, EM_DOT, w.part.p, c);
+  int g = emin_apply(L, nullptr, P, w.Q.p, EM_DOT, w.part.p, nullptr, c);
   // sum of partials (g may exceed kRedBlocks: reduce on host deterministically)
   std::vector<double> h(g);
   d2h(h.data(), w.part.p, g, c);
@@ -594,6 +669,7 @@ static void energy_minimisation(Hierarchy& H, Level& L, int iters, bool given_in
   w.Rv.alloc(np, c.s);
   w.Dir.alloc(np, c.s);
   w.Q.alloc(np, c.s);
+  w.Y.alloc(np, c.s);
   w.part.alloc(8192, c.s);
   clear_flag(F_NOTSPD, c);
   // initial guess
@@ -610,19 +686,19 @@ static void energy_minimisation(Hierarchy& H, Level& L, int iters, bool given_in
     DBuf<double> dinv(L.n, c.s);
     diagonal(L.A, dinv.p, true, c);
     for (int it = 0; it < iters; ++it) {
-      emin_apply(L, dinv.p, w.P.p, w.Q.p, EM_PROJECT, w.part.p, c);
+      emin_apply(L, dinv.p, w.P.p, w.Q.p, EM_PROJECT, w.part.p, w.Y.p, c);
       c.run("emin_axpy", 24.0 * np, [&] { k_axpy_scalar<<<ceil_div(np, 256), 256, 0, c.s>>>(np, w.P.p, w.Q.p, -H.opts.emin_omega); });
       if (rec) L.energy.push_back(energy_of(L, w.P.p, w, c));
     }
   } else {
     // R = -Pi(mask(A P)), Dir = R, rho = <R, R>
-    emin_apply(L, nullptr, w.P.p, w.Rv.p, EM_PROJECT | EM_NEGATE, w.part.p, c);
+    emin_apply(L, nullptr, w.P.p, w.Rv.p, EM_PROJECT | EM_NEGATE, w.part.p, w.Y.p, c);
     d2d(w.Dir.p, w.Rv.p, np, c);
     dot(w.Rv.p, w.Rv.p, np, sc + S_RHO, c, 0);
     const int ub = Ctx::kRedBlocks;
     const int nbu = (int)std::min<int64_t>(ub, std::max<int64_t>(1, (np + 255) / 256));
     for (int it = 0; it < iters; ++it) {
-      int g = emin_apply(L, nullptr, w.Dir.p, w.Q.p, EM_PROJECT | EM_DOT, w.part.p, c);
+      int g = emin_apply(L, nullptr, w.Dir.p, w.Q.p, EM_PROJECT | EM_DOT, w.part.p, w.Y.p, c);
       sum_partials(w.part.p, g, sc + S_GAMMA, c);
       c.run("cg_scalar", 0.0, [&] { k_cg_alpha<<<1, 1, 0, c.s>>>(sc, c.iscal.p); });
       c.run("emin_cg_update", 48.0 * np, [&] {

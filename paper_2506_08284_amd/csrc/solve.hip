@@ -50,13 +50,14 @@ __global__ void k_jp_assign(const int* __restrict__ rp, const int* __restrict__ 
   }
 }
 
-__global__ void k_color_count(const int* __restrict__ color, int n, int* __restrict__ cnt) {
+__global__ void k_flag_eq(const int* __restrict__ color, int n, int c, int* __restrict__ flag) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) atomicAdd(&cnt[color[v]], 1);
+  if (v < n) flag[v] = color[v] == c;
 }
-__global__ void k_color_fill(const int* __restrict__ color, int n, int* __restrict__ cursor, int* __restrict__ rows) {
+__global__ void k_scatter_eq(const int* __restrict__ color, int n, int c, const int* __restrict__ pos, int base,
+                             int* __restrict__ rows) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) rows[atomicAdd(&cursor[color[v]], 1)] = v;
+  if (v < n && color[v] == c) rows[base + pos[v]] = v;
 }
 
 void color_rows(const Csr& A, DBuf<int>& color, DBuf<int>& rows, std::vector<int>& cptr, int& ncol, Ctx& c) {
@@ -74,62 +75,148 @@ void color_rows(const Csr& A, DBuf<int>& color, DBuf<int>& rows, std::vector<int
     d2h(&h, rem, 1, c);
     if (h == 0) break;
   }
-  // group rows by colour
+  // rows grouped by colour, increasing row index inside every colour
   std::vector<int> hc_(n);
   d2h(hc_.data(), color.p, n, c);
   ncol = 0;
   for (int v : hc_) ncol = std::max(ncol, v + 1);
-  DBuf<int> cnt(ncol + 1, c.s);
-  HC_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int) * (ncol + 1), c.s));
-  k_color_count<<<ceil_div(n, 256), 256, 0, c.s>>>(color.p, n, cnt.p);
-  HC_LAUNCH_CHECK();
-  std::vector<int> hcnt(ncol + 1);
-  d2h(hcnt.data(), cnt.p, ncol, c);
   cptr.assign(ncol + 1, 0);
-  for (int k = 0; k < ncol; ++k) cptr[k + 1] = cptr[k] + hcnt[k];
-  h2d(cnt.p, cptr.data(), ncol, c);
-  k_color_fill<<<ceil_div(n, 256), 256, 0, c.s>>>(color.p, n, cnt.p, rows.p);
+  DBuf<int> flag(n + 1, c.s), pos(n + 1, c.s);
+  for (int k = 0; k < ncol; ++k) {
+    k_flag_eq<<<ceil_div(n, 256), 256, 0, c.s>>>(color.p, n, k, flag.p);
+    HC_LAUNCH_CHECK();
+    const int64_t cnt = exclusive_scan(flag.p, pos.p, n, c);
+    k_scatter_eq<<<ceil_div(n, 256), 256, 0, c.s>>>(color.p, n, k, pos.p, cptr[k], rows.p);
+    HC_LAUNCH_CHECK();
+    cptr[k + 1] = cptr[k] + (int)cnt;
+  }
+}
+
+__global__ void k_perm_len(const int* __restrict__ rp, const int* __restrict__ rows, int n, int* __restrict__ len) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) len[g] = rp[rows[g] + 1] - rp[rows[g]];
+}
+__global__ void __launch_bounds__(256) k_perm_copy(const int* __restrict__ rp, const int* __restrict__ col,
+                                                   const double* __restrict__ val, const int* __restrict__ rows, int n,
+                                                   const int* __restrict__ nrp, int* __restrict__ ncol,
+                                                   double* __restrict__ nval) {
+  const int g = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const int l = threadIdx.x & 15;
+  if (g >= n) return;
+  const int a = rp[rows[g]], len = rp[rows[g] + 1] - a, o = nrp[g];
+  for (int q = l; q < len; q += 16) {
+    ncol[o + q] = col[a + q];
+    nval[o + q] = val[a + q];
+  }
+}
+
+void colour_major(const Csr& A, const DBuf<int>& rows, Csr& Acm, Ctx& c) {
+  const int n = A.nrows;
+  Acm.nrows = n;
+  Acm.ncols = A.ncols;
+  Acm.nnz = A.nnz;
+  Acm.rowptr.alloc(n + 1, c.s);
+  Acm.col.alloc(A.nnz, c.s);
+  Acm.val.alloc(A.nnz, c.s);
+  DBuf<int> len(n + 1, c.s);
+  k_perm_len<<<ceil_div(n, 256), 256, 0, c.s>>>(A.rowptr.p, rows.p, n, len.p);
   HC_LAUNCH_CHECK();
+  exclusive_scan(len.p, Acm.rowptr.p, n, c);
+  c.run("colour_major", 24.0 * A.nnz, [&] {
+    k_perm_copy<<<ceil_div((int64_t)n * 16, 256), 256, 0, c.s>>>(A.rowptr.p, A.col.p, A.val.p, rows.p, n, Acm.rowptr.p,
+                                                               Acm.col.p, Acm.val.p);
+  });
+}
+
+__global__ void k_gather(const double* __restrict__ x, const int* __restrict__ rows, double* __restrict__ y, int n) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) y[g] = x[rows[g]];
+}
+void gather_vec(const double* x, const int* rows, double* y, int n, Ctx& c) {
+  if (n) c.run("gather", 16.0 * n, [&] { k_gather<<<ceil_div(n, 256), 256, 0, c.s>>>(x, rows, y, n); });
 }
 
 // ---------------------------------------------------------------------------
 // Gauss-Seidel on the rows of one colour: x_i += (b_i - A_i x) / a_ii.
-// Rows of one colour are not coupled, so they update in parallel.
+// Rows of one colour are not coupled, so they update in parallel.  The
+// matrix is the colour-major copy: the colour's rows are contiguous (g) and
+// rows[g] is the original row index, used for b and x.
 // ---------------------------------------------------------------------------
 template <class T, int LPR, int TAG>
-__global__ void __launch_bounds__(256) k_gs_color(const int* __restrict__ rows, int nr, const int* __restrict__ rp,
+__global__ void __launch_bounds__(256) k_gs_color(int g0, int nr, const int* __restrict__ rows, const int* __restrict__ rp,
                                                   const int* __restrict__ col, const T* __restrict__ val,
                                                   const T* __restrict__ dinv, const T* __restrict__ b, T* __restrict__ x) {
-  const int g = (blockIdx.x * blockDim.x + threadIdx.x) / LPR;
+  // neighbouring row blocks share gathered x entries: give every XCD a
+  // contiguous range of blocks so they meet in the same L2
+  const int g = g0 + (xcd_block(gridDim.x) * blockDim.x + threadIdx.x) / LPR;
   const int l = threadIdx.x & (LPR - 1);
-  if (g >= nr) return;
-  const int i = rows[g];
+  if (g >= g0 + nr) return;
   T s = 0;
-  const int e = rp[i + 1];
-  for (int q = rp[i] + l; q < e; q += LPR) s += val[q] * x[col[q]];
+  const int e = rp[g + 1];
+  // the matrix is streamed once per sweep: non-temporal loads keep it from
+  // evicting the gathered x entries from the caches
+  for (int q = rp[g] + l; q < e; q += LPR)
+    s += __builtin_nontemporal_load(&val[q]) * x[__builtin_nontemporal_load(&col[q])];
 #pragma unroll
   for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LPR);
-  if (l == 0) x[i] += (b[i] - s) * dinv[i];
+  if (l == 0) {
+    const int i = rows[g];
+    x[i] += (b[i] - s) * dinv[g];
+  }
 }
+
+// The whole symmetric sweep (all colours forward, then backward) in one
+// workgroup, for levels small enough that launches would dominate.
+template <class T, int LPR>
+__global__ void __launch_bounds__(1024) k_gs_sweep_small(int ncol, const int* __restrict__ cptr,
+                                                         const int* __restrict__ rows, const int* __restrict__ rp,
+                                                         const int* __restrict__ col, const T* __restrict__ val,
+                                                         const T* __restrict__ dinv, const T* __restrict__ b,
+                                                         T* __restrict__ x) {
+  const int l = threadIdx.x & (LPR - 1);
+  const int grp = threadIdx.x / LPR;
+  constexpr int NG = 1024 / LPR;
+  for (int step = 0; step < 2 * ncol; ++step) {
+    const int k = step < ncol ? step : 2 * ncol - 1 - step;
+    for (int g = cptr[k] + grp; g < cptr[k + 1]; g += NG) {
+      T s = 0;
+      const int e = rp[g + 1];
+      for (int q = rp[g] + l; q < e; q += LPR) s += val[q] * x[col[q]];
+#pragma unroll
+      for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LPR);
+      if (l == 0) {
+        const int i = rows[g];
+        x[i] += (b[i] - s) * dinv[g];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+static constexpr int kSmallLevel = 8192;
 
 // Algorithmic bytes of one colour launch: the rows' CSR data, their b, 1/a_ii
 // and x (read and write), counting every x entry once per sweep (ideal reuse
 // of the gathered neighbours).
 template <class T, int TAG>
-static void sgs_t(const Csr& A, const T* val, const T* dinv, const DBuf<int>& rows, const std::vector<int>& cptr, int ncol,
-                  const T* b, T* x, Ctx& c, const char* tag) {
+static void sgs_t(const Csr& A, const T* val, const T* dinv, const DBuf<int>& rows, const std::vector<int>& cptr,
+                  const DBuf<int>& cptr_d, int ncol, const T* b, T* x, Ctx& c, const char* tag) {
   const double avg = A.nrows ? (double)A.nnz / A.nrows : 0.0;
+  if (A.nrows <= kSmallLevel) {
+    const double bytes = 2.0 * ((double)A.nnz * (4 + sizeof(T)) + (double)A.nrows * (8 + 4 + 4 * sizeof(T)));
+    c.run("sgs_small", bytes, [&] { k_gs_sweep_small<T, 8><<<1, 1024, 0, c.s>>>(ncol, cptr_d.p, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
+    return;
+  }
   auto launch = [&](int k) {
-    const int nr = cptr[k + 1] - cptr[k];
+    const int g0 = cptr[k], nr = cptr[k + 1] - cptr[k];
     if (!nr) return;
-    const int* r = rows.p + cptr[k];
     const double bytes = (double)nr * avg * (4 + sizeof(T)) + (double)nr * (8 + 4 + 4 * sizeof(T));
-    if (avg <= 12)
-      c.run(tag, bytes, [&] { k_gs_color<T, 8, TAG><<<ceil_div((int64_t)nr * 8, 256), 256, 0, c.s>>>(r, nr, A.rowptr.p, A.col.p, val, dinv, b, x); });
-    else if (avg <= 40)
-      c.run(tag, bytes, [&] { k_gs_color<T, 16, TAG><<<ceil_div((int64_t)nr * 16, 256), 256, 0, c.s>>>(r, nr, A.rowptr.p, A.col.p, val, dinv, b, x); });
+    if (avg <= 20)
+      c.run(tag, bytes, [&] { k_gs_color<T, 8, TAG><<<ceil_div((int64_t)nr * 8, 256), 256, 0, c.s>>>(g0, nr, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
+    else if (avg <= 48)
+      c.run(tag, bytes, [&] { k_gs_color<T, 16, TAG><<<ceil_div((int64_t)nr * 16, 256), 256, 0, c.s>>>(g0, nr, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
     else
-      c.run(tag, bytes, [&] { k_gs_color<T, 64, TAG><<<ceil_div((int64_t)nr * 64, 256), 256, 0, c.s>>>(r, nr, A.rowptr.p, A.col.p, val, dinv, b, x); });
+      c.run(tag, bytes, [&] { k_gs_color<T, 32, TAG><<<ceil_div((int64_t)nr * 32, 256), 256, 0, c.s>>>(g0, nr, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
   };
   for (int k = 0; k < ncol; ++k) launch(k);
   for (int k = ncol - 1; k >= 0; --k) launch(k);
@@ -159,34 +246,34 @@ __global__ void __launch_bounds__(256) k_dense_apply(const double* __restrict__ 
 // ---------------------------------------------------------------------------
 // Hiptmair smoother and V-cycle
 // ---------------------------------------------------------------------------
-// Level 0 gets its own kernel instances (TAG 1) so that profiles separate the
-// fine-level sweeps from the launch-bound coarse ones.
+// Level 0 gets its own kernel instances (TAG 1, 2) so that profiles separate
+// the fine-level sweeps from the launch-bound coarse ones.
 static void hiptmair64(Level& L, bool fine, double* x, const double* b, Ctx& c) {
   auto edge = [&] {
-    if (fine) sgs_t<double, 1>(L.A, L.A.val.p, L.dinvA.p, L.rowsA, L.cptrA, L.ncolA, b, x, c, "sgs_edge_l0");
-    else sgs_t<double, 0>(L.A, L.A.val.p, L.dinvA.p, L.rowsA, L.cptrA, L.ncolA, b, x, c, "sgs_edge");
+    if (fine) sgs_t<double, 1>(L.Acm, L.Acm.val.p, L.dinvAcm.p, L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, b, x, c, "sgs_edge_l0");
+    else sgs_t<double, 0>(L.Acm, L.Acm.val.p, L.dinvAcm.p, L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, b, x, c, "sgs_edge");
   };
   edge();
   spmv(L.A, x, L.r.p, b, 1, c, fine ? "residual_l0" : "residual");
   spmv(L.DT, L.r.p, L.rn.p, nullptr, 0, c, "grad_transpose");
   fill(L.cn.p, 0.0, L.m, c);
-  if (fine) sgs_t<double, 2>(L.An, L.An.val.p, L.dinvAn.p, L.rowsAn, L.cptrAn, L.ncolAn, L.rn.p, L.cn.p, c, "sgs_node_l0");
-  else sgs_t<double, 0>(L.An, L.An.val.p, L.dinvAn.p, L.rowsAn, L.cptrAn, L.ncolAn, L.rn.p, L.cn.p, c, "sgs_node");
+  if (fine) sgs_t<double, 2>(L.Ancm, L.Ancm.val.p, L.dinvAncm.p, L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.rn.p, L.cn.p, c, "sgs_node_l0");
+  else sgs_t<double, 0>(L.Ancm, L.Ancm.val.p, L.dinvAncm.p, L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.rn.p, L.cn.p, c, "sgs_node");
   c.run("grad_add", 24.0 * L.n, [&] { k_grad_add<double><<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, L.n, L.cn.p, x); });
   edge();
 }
 
 static void hiptmair32(Level& L, bool fine, float* x, const float* b, Ctx& c) {
   auto edge = [&] {
-    if (fine) sgs_t<float, 1>(L.A, L.A.val32.p, L.dinvA32.p, L.rowsA, L.cptrA, L.ncolA, b, x, c, "sgs_edge32_l0");
-    else sgs_t<float, 0>(L.A, L.A.val32.p, L.dinvA32.p, L.rowsA, L.cptrA, L.ncolA, b, x, c, "sgs_edge32");
+    if (fine) sgs_t<float, 1>(L.Acm, L.Acm.val32.p, L.dinvAcm32.p, L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, b, x, c, "sgs_edge32_l0");
+    else sgs_t<float, 0>(L.Acm, L.Acm.val32.p, L.dinvAcm32.p, L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, b, x, c, "sgs_edge32");
   };
   edge();
   spmv32(L.A, x, L.r32.p, b, 1, c, fine ? "residual32_l0" : "residual32");
   spmv32(L.DT, L.r32.p, L.rn32.p, nullptr, 0, c, "grad_transpose32");
   fill32(L.cn32.p, 0.0f, L.m, c);
-  if (fine) sgs_t<float, 2>(L.An, L.An.val32.p, L.dinvAn32.p, L.rowsAn, L.cptrAn, L.ncolAn, L.rn32.p, L.cn32.p, c, "sgs_node32_l0");
-  else sgs_t<float, 0>(L.An, L.An.val32.p, L.dinvAn32.p, L.rowsAn, L.cptrAn, L.ncolAn, L.rn32.p, L.cn32.p, c, "sgs_node32");
+  if (fine) sgs_t<float, 2>(L.Ancm, L.Ancm.val32.p, L.dinvAncm32.p, L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.rn32.p, L.cn32.p, c, "sgs_node32_l0");
+  else sgs_t<float, 0>(L.Ancm, L.Ancm.val32.p, L.dinvAncm32.p, L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.rn32.p, L.cn32.p, c, "sgs_node32");
   c.run("grad_add32", 12.0 * L.n, [&] { k_grad_add<float><<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, L.n, L.cn32.p, x); });
   edge();
 }
@@ -203,7 +290,7 @@ static void vcycle64(Hierarchy& H, int l, const double* b, double* x) {
   Level& N = *H.lv[l + 1];
   fill(x, 0.0, L.n, c);
   hiptmair64(L, l == 0, x, b, c);
-  spmv(L.A, x, L.r.p, b, 1, c, "residual");
+  spmv(L.A, x, L.r.p, b, 1, c, l == 0 ? "residual_l0" : "residual");
   spmv(L.PeT, L.r.p, N.b.p, nullptr, 0, c, "restrict");
   vcycle64(H, l + 1, N.b.p, N.x.p);
   spmv(L.Pe, N.x.p, x, nullptr, 2, c, "prolong");
@@ -222,27 +309,51 @@ static void vcycle32(Hierarchy& H, int l, const float* b, float* x) {
   Level& N = *H.lv[l + 1];
   fill32(x, 0.0f, L.n, c);
   hiptmair32(L, l == 0, x, b, c);
-  spmv32(L.A, x, L.r32.p, b, 1, c, "residual32");
+  spmv32(L.A, x, L.r32.p, b, 1, c, l == 0 ? "residual32_l0" : "residual32");
   spmv32(L.PeT, L.r32.p, N.b32.p, nullptr, 0, c, "restrict32");
   vcycle32(H, l + 1, N.b32.p, N.x32.p);
   spmv32(L.Pe, N.x32.p, x, nullptr, 2, c, "prolong32");
   hiptmair32(L, l == 0, x, b, c);
 }
 
-void apply_vcycle(Hierarchy& H, const double* r, double* z) {
+static void vcycle_direct(Hierarchy& H, const double* r, double* z) {
   Ctx& c = H.ctx;
-  if (H.opts.vcycle_fp32) {
+  if (H.opts.vcycle_fp32 && H.lv.size() > 1) {
     Level& L = *H.lv[0];
-    if (H.lv.size() == 1) {
-      vcycle64(H, 0, r, z);
-      return;
-    }
     cast_d2f(r, L.b32.p, L.n, c);
     vcycle32(H, 0, L.b32.p, L.x32.p);
     cast_f2d(L.x32.p, z, L.n, c);
   } else {
     vcycle64(H, 0, r, z);
   }
+}
+
+// The V-cycle issues the same kernels with the same arguments every time, so
+// on a non-null stream (and without per-kernel profiling) it is captured once
+// as a HIP graph for the PCG workspace (pr -> pz) and replayed.
+void apply_vcycle(Hierarchy& H, const double* r, double* z) {
+  Ctx& c = H.ctx;
+  const bool graphable = c.s != nullptr && !c.profile && r == H.pr.p && z == H.pz.p;
+  if (!graphable) {
+    vcycle_direct(H, r, z);
+    return;
+  }
+  if (!H.vgraph) {
+    hipGraph_t g = nullptr;
+    HC_HIP(hipStreamBeginCapture(c.s, hipStreamCaptureModeThreadLocal));
+    try {
+      vcycle_direct(H, r, z);
+    } catch (...) {
+      (void)hipStreamEndCapture(c.s, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    HC_HIP(hipStreamEndCapture(c.s, &g));
+    hipError_t e = hipGraphInstantiate(&H.vgraph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HC_HIP(e);
+  }
+  HC_HIP(hipGraphLaunch(H.vgraph, c.s));
 }
 
 // ---------------------------------------------------------------------------
@@ -265,16 +376,26 @@ void prepare_solve(Hierarchy& H) {
       if (f32) { L.x32.alloc(L.n, c.s); L.b32.alloc(L.n, c.s); }
       continue;
     }
+    colour_major(L.A, L.rowsA, L.Acm, c);
+    colour_major(L.An, L.rowsAn, L.Ancm, c);
+    L.cptrA_d.alloc(L.ncolA + 1, c.s);
+    L.cptrAn_d.alloc(L.ncolAn + 1, c.s);
+    h2d(L.cptrA_d.p, L.cptrA.data(), L.ncolA + 1, c);
+    h2d(L.cptrAn_d.p, L.cptrAn.data(), L.ncolAn + 1, c);
+    L.dinvAcm.alloc(L.n, c.s);
+    L.dinvAncm.alloc(L.m, c.s);
+    gather_vec(L.dinvA.p, L.rowsA.p, L.dinvAcm.p, L.n, c);
+    gather_vec(L.dinvAn.p, L.rowsAn.p, L.dinvAncm.p, L.m, c);
     L.r.alloc(L.n, c.s);
     L.rn.alloc(L.m, c.s);
     L.cn.alloc(L.m, c.s);
     if (f32) {
       L.x32.alloc(L.n, c.s); L.b32.alloc(L.n, c.s); L.r32.alloc(L.n, c.s);
       L.rn32.alloc(L.m, c.s); L.cn32.alloc(L.m, c.s);
-      make32(L.A, c); make32(L.An, c); make32(L.Pe, c); make32(L.PeT, c); make32(L.D, c); make32(L.DT, c);
-      L.dinvA32.alloc(L.n, c.s); L.dinvAn32.alloc(L.m, c.s);
-      cast_d2f(L.dinvA.p, L.dinvA32.p, L.n, c);
-      cast_d2f(L.dinvAn.p, L.dinvAn32.p, L.m, c);
+      make32(L.A, c); make32(L.Acm, c); make32(L.Ancm, c); make32(L.Pe, c); make32(L.PeT, c); make32(L.D, c); make32(L.DT, c);
+      L.dinvAcm32.alloc(L.n, c.s); L.dinvAncm32.alloc(L.m, c.s);
+      cast_d2f(L.dinvAcm.p, L.dinvAcm32.p, L.n, c);
+      cast_d2f(L.dinvAncm.p, L.dinvAncm32.p, L.m, c);
     }
   }
   const int n = H.lv[0]->n;

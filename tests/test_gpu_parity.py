@@ -213,24 +213,34 @@ def test_given_initial_guess_is_projected_then_refined():
     assert len(H.export_vec(0, "energy")) == 4
 
 
-def test_device_pointers_match_host_run():
+def test_device_pointers_and_graph_replay_match_host_run():
+    """Device inputs on a side stream: the V-cycle is captured as a HIP graph
+    and replayed every PCG iteration (with eager dots and updates between
+    replays).  Two solves in a row and the host-pointer run (no graph) agree."""
     import torch
     pr, m, levels, Hh = _case("cube10_inclusions")
     P = _lib()
     dev = torch.device("cuda:0")
-    Dh = synth.gradient_csr(pr["tail"], pr["head"])
-    A_t = tuple(torch.from_numpy(a).to(dev) for a in pr["A"])
-    D_t = tuple(torch.from_numpy(a).to(dev) for a in Dh)
-    aggs = [torch.from_numpy(a).to(dev) for a in pr["aggregates"]]
-    s = torch.cuda.current_stream()
-    H = P.Hierarchy(A_t, D_t, aggs, n_nodes=m, mem_space="device", stream=s.cuda_stream)
-    f = torch.from_numpy(pr["f"]).to(dev)
-    u = torch.empty_like(f)
-    it, rel, rc = H.solve(f, u)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        Dh = synth.gradient_csr(pr["tail"], pr["head"])
+        A_t = tuple(torch.from_numpy(a).to(dev) for a in pr["A"])
+        D_t = tuple(torch.from_numpy(a).to(dev) for a in Dh)
+        aggs = [torch.from_numpy(a).to(dev) for a in pr["aggregates"]]
+        f = torch.from_numpy(pr["f"]).to(dev)
+        u1 = torch.empty_like(f)
+        u2 = torch.empty_like(f)
+        side.synchronize()
+        H = P.Hierarchy(A_t, D_t, aggs, n_nodes=m, mem_space="device", stream=side.cuda_stream)
+        it1, rel1, rc1 = H.solve(f, u1)
+        it2, rel2, rc2 = H.solve(f, u2)
+        side.synchronize()
     un = np.empty_like(pr["f"])
     ith, relh, _ = Hh.solve(pr["f"], un)
-    assert it == ith and rel <= 1e-8
-    assert np.linalg.norm(u.cpu().numpy() - un) <= 1e-9 * np.linalg.norm(un)
+    assert rc1 == 0 and rc2 == 0 and it1 == ith and it2 == ith and rel1 <= 1e-8
+    a1, a2 = u1.cpu().numpy(), u2.cpu().numpy()
+    assert np.array_equal(a1, a2)
+    assert np.linalg.norm(a1 - un) <= 1e-9 * np.linalg.norm(un)
 
 
 def test_invalid_inputs_rejected():
