@@ -56,7 +56,7 @@ enum {
 
 enum { HCURL_MEM_HOST = 0, HCURL_MEM_DEVICE = 1 };
 enum { HCURL_EMIN_CG = 0, HCURL_EMIN_JACOBI = 1 };
-enum { HCURL_INIT_ONES = 0, HCURL_INIT_GIVEN = 1 };
+enum { HCURL_INIT_ONES = 0, HCURL_INIT_GIVEN = 1, HCURL_INIT_MPNN = 2 };
 
 /* CSR matrix.  rowptr has nrows+1 entries; column indices sorted per row.
  * val may be NULL where only the pattern is read. */
@@ -73,7 +73,7 @@ typedef struct {
   int max_levels;          /* cap on the number of levels, 0 = aggregates decide */
   int coarse_max_rows;     /* stop coarsening once a level has <= this many edges
                               (0 = never stop early); the coarsest level is solved
-                              by a dense factorisation and may have at most 4096 rows */
+                              by a dense factorisation and may have at most 1024 rows */
   int emin_iters;          /* energy-minimisation iterations per level (default 10) */
   int emin_method;         /* HCURL_EMIN_CG (projected CG, default) or
                               HCURL_EMIN_JACOBI (projected Jacobi, Sec. 3 eq. "emin iteration") */
@@ -81,10 +81,14 @@ typedef struct {
   int init_guess;          /* HCURL_INIT_ONES: ones on the pattern then the local
                               min-norm correction (Sec. 6.1); HCURL_INIT_GIVEN:
                               init_values on the level-0 pattern, then the same
-                              correction (coarser levels use ones) */
+                              correction; HCURL_INIT_MPNN: the plain guess plus
+                              the correction predicted by opts.mpnn (needs
+                              coords), then the same correction.  Coarser levels
+                              always start from ones. */
   const double* init_values; /* nnz(P^(e)_0) values in pattern order (mem_space) */
-  int emin_iters_given;    /* level-0 iterations when init_guess = HCURL_INIT_GIVEN
-                              (default 3) */
+  int emin_iters_given;    /* level-0 iterations when init_guess is
+                              HCURL_INIT_GIVEN or HCURL_INIT_MPNN (default 3) */
+  const struct hcurl_mpnn_s* mpnn; /* network for HCURL_INIT_MPNN */
   int vcycle_fp32;         /* 1: smoother and transfers in FP32 inside FP64 PCG */
   int power_iters;         /* power iterations for rho(D^-1 A^(n)), default 20 */
   int record_energy;       /* 1: measure 1/2 <P, A P> after every emin iteration */
@@ -155,7 +159,8 @@ enum {
   HCURL_EXPORT_PE = 3,   /* P^(e)_l           n x n_H   */
   HCURL_EXPORT_R = 4,    /* D_l P^(n)_l on the pattern T_l, n x m_H */
   HCURL_EXPORT_DH = 5,   /* D_{l+1} as CSR   n_H x m_H (-1 tail, +1 head) */
-  HCURL_EXPORT_P0 = 6    /* initial guess P_0 on the P^(e)_l pattern */
+  HCURL_EXPORT_P0 = 6    /* initial guess actually used (after the min-norm
+                            correction) on the P^(e)_l pattern */
 };
 int hcurl_amg_export_csr(hcurl_amg h, int level, int which, int64_t* rowptr, int32_t* col, double* val);
 
@@ -185,6 +190,47 @@ int hcurl_amg_stats(hcurl_amg h, hcurl_amg_stats_t* s);
 int hcurl_amg_kernel_stats(hcurl_amg h, int max_kernels, char (*names)[48], int64_t* launches,
                            double* ms, double* bytes);
 void hcurl_amg_reset_kernel_stats(hcurl_amg h);
+
+/*
+ * Learned initial guess for P^(e) (level 0).  A message-passing network on the
+ * pattern entries e = (i, j) of P^(e) (fine edge i, coarse edge j): 16 input
+ * features per entry, hidden width 64, 3 layers; each layer averages the
+ * hidden states over the entry's row and column and applies
+ * h <- h + silu([h, mean_row, mean_col] W_l + b_l).  The output head gives a
+ * correction delta_e added to the plain initial value; the result is always
+ * made feasible by the local min-norm correction, so the commuting relation
+ * holds exactly whatever the network predicts.  Dense layers run as BF16
+ * matrix-core products with FP32 accumulation; master weights are FP32.
+ *
+ * Parameters are a flat FP32 array in the order W_in (16x64 row-major), b_in
+ * (64), then for l = 0..2: W_l (192x64), b_l (64), then w_out (64), b_out (1).
+ */
+typedef struct hcurl_mpnn_s* hcurl_mpnn;
+typedef struct hcurl_mpnn_sample_s* hcurl_mpnn_sample;
+
+int64_t hcurl_mpnn_num_params(void);
+/* params: host array of hcurl_mpnn_num_params() floats, copied. */
+int hcurl_mpnn_create(const float* params, void* stream, hcurl_mpnn* out);
+int hcurl_mpnn_get_params(hcurl_mpnn net, float* params);
+void hcurl_mpnn_destroy(hcurl_mpnn net);
+
+/* Training sample from a hierarchy built with HCURL_INIT_ONES and coords:
+ * the level-0 features, the pattern graph, the plain initial values and the
+ * target = the final P^(e)_0 values.  The sample owns device copies. */
+int hcurl_amg_mpnn_sample(hcurl_amg h, hcurl_mpnn_sample* out);
+int64_t hcurl_mpnn_sample_entries(hcurl_mpnn_sample s);
+/* host copies: features (E x 16 floats), p0 and target (E doubles); any may be NULL */
+int hcurl_mpnn_sample_export(hcurl_mpnn_sample s, float* features, double* p0, double* target);
+void hcurl_mpnn_sample_destroy(hcurl_mpnn_sample s);
+
+/* delta (E doubles, host) predicted for the sample */
+int hcurl_mpnn_forward(hcurl_mpnn net, hcurl_mpnn_sample s, double* delta);
+/* loss = mean_e (p0_e + delta_e - target_e)^2 and its gradient (host,
+ * hcurl_mpnn_num_params() floats; grad may be NULL) */
+int hcurl_mpnn_loss_grad(hcurl_mpnn net, hcurl_mpnn_sample s, double* loss, float* grad);
+/* one Adam step (step counts from 1) on the sample; returns the loss before it */
+int hcurl_mpnn_train_step(hcurl_mpnn net, hcurl_mpnn_sample s, float lr, float beta1, float beta2, float eps, int step,
+                          double* loss);
 
 const char* hcurl_last_error(void);
 const char* hcurl_error_string(int code);

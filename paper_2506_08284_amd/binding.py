@@ -27,7 +27,9 @@ EXPORTED_SYMBOLS = [
     "hcurl_amg_default_opts", "hcurl_amg_setup", "hcurl_amg_solve", "hcurl_amg_vcycle", "hcurl_amg_destroy",
     "hcurl_amg_num_levels", "hcurl_amg_level_info", "hcurl_amg_export_csr", "hcurl_amg_export_vec",
     "hcurl_amg_stats", "hcurl_amg_kernel_stats", "hcurl_amg_reset_kernel_stats", "hcurl_last_error",
-    "hcurl_error_string",
+    "hcurl_error_string", "hcurl_mpnn_num_params", "hcurl_mpnn_create", "hcurl_mpnn_get_params", "hcurl_mpnn_destroy",
+    "hcurl_amg_mpnn_sample", "hcurl_mpnn_sample_entries", "hcurl_mpnn_sample_export", "hcurl_mpnn_sample_destroy",
+    "hcurl_mpnn_forward", "hcurl_mpnn_loss_grad", "hcurl_mpnn_train_step",
 ]
 
 
@@ -39,7 +41,8 @@ class hcurl_csr(ctypes.Structure):
 class hcurl_amg_opts(ctypes.Structure):
     _fields_ = [("max_levels", ctypes.c_int), ("coarse_max_rows", ctypes.c_int), ("emin_iters", ctypes.c_int),
                 ("emin_method", ctypes.c_int), ("emin_omega", ctypes.c_double), ("init_guess", ctypes.c_int),
-                ("init_values", ctypes.c_void_p), ("emin_iters_given", ctypes.c_int), ("vcycle_fp32", ctypes.c_int),
+                ("init_values", ctypes.c_void_p), ("emin_iters_given", ctypes.c_int), ("mpnn", ctypes.c_void_p),
+                ("vcycle_fp32", ctypes.c_int),
                 ("power_iters", ctypes.c_int), ("record_energy", ctypes.c_int), ("profile", ctypes.c_int),
                 ("mem_space", ctypes.c_int), ("stream", ctypes.c_void_p)]
 
@@ -105,6 +108,29 @@ def _load():
     L.hcurl_last_error.restype = ctypes.c_char_p
     L.hcurl_error_string.argtypes = [ctypes.c_int]
     L.hcurl_error_string.restype = ctypes.c_char_p
+    L.hcurl_mpnn_num_params.argtypes = []
+    L.hcurl_mpnn_num_params.restype = ctypes.c_int64
+    L.hcurl_mpnn_create.argtypes = [P, P, ctypes.POINTER(P)]
+    L.hcurl_mpnn_create.restype = ctypes.c_int
+    L.hcurl_mpnn_get_params.argtypes = [P, P]
+    L.hcurl_mpnn_get_params.restype = ctypes.c_int
+    L.hcurl_mpnn_destroy.argtypes = [P]
+    L.hcurl_mpnn_destroy.restype = None
+    L.hcurl_amg_mpnn_sample.argtypes = [P, ctypes.POINTER(P)]
+    L.hcurl_amg_mpnn_sample.restype = ctypes.c_int
+    L.hcurl_mpnn_sample_entries.argtypes = [P]
+    L.hcurl_mpnn_sample_entries.restype = ctypes.c_int64
+    L.hcurl_mpnn_sample_export.argtypes = [P, P, P, P]
+    L.hcurl_mpnn_sample_export.restype = ctypes.c_int
+    L.hcurl_mpnn_sample_destroy.argtypes = [P]
+    L.hcurl_mpnn_sample_destroy.restype = None
+    L.hcurl_mpnn_forward.argtypes = [P, P, P]
+    L.hcurl_mpnn_forward.restype = ctypes.c_int
+    L.hcurl_mpnn_loss_grad.argtypes = [P, P, ctypes.POINTER(ctypes.c_double), P]
+    L.hcurl_mpnn_loss_grad.restype = ctypes.c_int
+    L.hcurl_mpnn_train_step.argtypes = [P, P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                        ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    L.hcurl_mpnn_train_step.restype = ctypes.c_int
     return L
 
 
@@ -153,6 +179,8 @@ def hcurl_amg_default_opts(**overrides) -> hcurl_amg_opts:
             v = MEM[v]
         if k == "init_values":
             v = _ptr(v)
+        if k == "mpnn" and v is not None and not isinstance(v, (int, ctypes.c_void_p)):
+            v = v.h  # a Network
         setattr(o, k, v)
     return o
 
@@ -270,12 +298,97 @@ def hcurl_amg_reset_kernel_stats(h):
     lib.hcurl_amg_reset_kernel_stats(h)
 
 
+def hcurl_mpnn_num_params() -> int:
+    return int(lib.hcurl_mpnn_num_params())
+
+
+def hcurl_mpnn_create(params: np.ndarray, stream=None):
+    params = np.ascontiguousarray(params, np.float32)
+    assert params.size == hcurl_mpnn_num_params()
+    h = ctypes.c_void_p()
+    _check(lib.hcurl_mpnn_create(_ptr(params), stream, ctypes.byref(h)))
+    return h
+
+
+def hcurl_mpnn_get_params(net) -> np.ndarray:
+    out = np.empty(hcurl_mpnn_num_params(), np.float32)
+    _check(lib.hcurl_mpnn_get_params(net, _ptr(out)))
+    return out
+
+
+def hcurl_mpnn_destroy(net):
+    lib.hcurl_mpnn_destroy(net)
+
+
+def hcurl_amg_mpnn_sample(h):
+    s = ctypes.c_void_p()
+    _check(lib.hcurl_amg_mpnn_sample(h, ctypes.byref(s)))
+    return s
+
+
+def hcurl_mpnn_sample_entries(s) -> int:
+    return int(lib.hcurl_mpnn_sample_entries(s))
+
+
+def hcurl_mpnn_sample_export(s):
+    E = hcurl_mpnn_sample_entries(s)
+    X = np.empty((E, 16), np.float32)
+    p0 = np.empty(E)
+    tg = np.empty(E)
+    _check(lib.hcurl_mpnn_sample_export(s, _ptr(X), _ptr(p0), _ptr(tg)))
+    return X, p0, tg
+
+
+def hcurl_mpnn_sample_destroy(s):
+    lib.hcurl_mpnn_sample_destroy(s)
+
+
+def hcurl_mpnn_forward(net, s) -> np.ndarray:
+    out = np.empty(hcurl_mpnn_sample_entries(s))
+    _check(lib.hcurl_mpnn_forward(net, s, _ptr(out)))
+    return out
+
+
+def hcurl_mpnn_loss_grad(net, s):
+    loss = ctypes.c_double()
+    g = np.empty(hcurl_mpnn_num_params(), np.float32)
+    _check(lib.hcurl_mpnn_loss_grad(net, s, ctypes.byref(loss), _ptr(g)))
+    return loss.value, g
+
+
+def hcurl_mpnn_train_step(net, s, lr, step, beta1=0.9, beta2=0.999, eps=1e-8) -> float:
+    loss = ctypes.c_double()
+    _check(lib.hcurl_mpnn_train_step(net, s, lr, beta1, beta2, eps, step, ctypes.byref(loss)))
+    return loss.value
+
+
+class Network:
+    """Owns a network handle."""
+
+    def __init__(self, params: np.ndarray, stream=None):
+        self.h = hcurl_mpnn_create(params, stream)
+
+    def params(self):
+        return hcurl_mpnn_get_params(self.h)
+
+    def close(self):
+        if self.h:
+            hcurl_mpnn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Hierarchy:
     """Owns a handle; methods map one to one onto the C calls."""
 
     def __init__(self, A, Dh, aggregates, n_nodes, coords=None, **opts):
         self.opts = hcurl_amg_default_opts(**opts)
-        self._keep = (A, Dh, aggregates, opts.get("init_values"))
+        self._keep = (A, Dh, aggregates, opts.get("init_values"), opts.get("mpnn"), coords)
         self.h = hcurl_amg_setup(A, Dh, aggregates, coords, self.opts, n_nodes=n_nodes)
 
     def solve(self, f, u, rtol=1e-8, maxit=500):
@@ -304,6 +417,9 @@ class Hierarchy:
 
     def reset_kernel_stats(self):
         hcurl_amg_reset_kernel_stats(self.h)
+
+    def mpnn_sample(self):
+        return hcurl_amg_mpnn_sample(self.h)
 
     def close(self):
         if self.h:

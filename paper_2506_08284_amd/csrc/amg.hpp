@@ -33,6 +33,7 @@ struct Level {
 
   // transfer to the next level (empty on the coarsest level)
   bool has_transfer = false;
+  DBuf<int> agg;          // aggregate of every node (the next level's node id)
   Csr Pn;                 // nodal prolongator m x m_H
   Csr R;                  // D P^(n) on the pattern T (n x m_H)
   Csr Pe, PeT;            // edge prolongator n x n_H and its transpose
@@ -65,12 +66,18 @@ struct Hierarchy {
   double setup_ms = 0.0, solve_ms = 0.0;
   int last_iters = 0;
   double last_relres = 0.0;
+  DBuf<double> coords;  // level-0 node coordinates (m x 3) when given
   // PCG workspace (level 0, FP64)
   DBuf<double> px, pr, pz, pp, pq, pzold;
 };
 
 // setup.hip
-void build_hierarchy(Hierarchy& H, const hcurl_csr& A, const hcurl_csr& Dh, const int32_t* const* aggs, int nagg);
+void build_hierarchy(Hierarchy& H, const hcurl_csr& A, const hcurl_csr& Dh, const double* coords, const int32_t* const* aggs,
+                     int nagg);
+
+// the local min-norm correction x <- x + G~ L~^-1 (r~ - G~^T x) on every row
+// (with `ones`, x is first set to ones)
+void emin_make_feasible(Level& L, double* x, bool ones, Ctx& c);
 
 // solve.hip
 void color_rows(const Csr& A, DBuf<int>& color, DBuf<int>& rows, std::vector<int>& cptr, int& ncol, Ctx& c);

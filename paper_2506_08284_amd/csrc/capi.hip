@@ -3,7 +3,7 @@
 #include <chrono>
 #include <cstring>
 
-#include "amg.hpp"
+#include "mpnn.hpp"
 
 struct hcurl_amg_s {
   hc::Hierarchy H;
@@ -66,6 +66,7 @@ void hcurl_amg_default_opts(hcurl_amg_opts* o) {
   o->init_guess = HCURL_INIT_ONES;
   o->init_values = nullptr;
   o->emin_iters_given = 3;
+  o->mpnn = nullptr;
   o->vcycle_fp32 = 0;
   o->power_iters = 20;
   o->record_energy = 0;
@@ -76,7 +77,6 @@ void hcurl_amg_default_opts(hcurl_amg_opts* o) {
 
 int hcurl_amg_setup(const hcurl_csr* A, const hcurl_csr* Dh, const double* coords, const int32_t* const* aggregates,
                     int n_agg_levels, const hcurl_amg_opts* opts, hcurl_amg* out) {
-  (void)coords;
   if (!out) return HCURL_EINVAL;
   *out = nullptr;
   if (!A || !Dh) return HCURL_EINVAL;
@@ -87,7 +87,7 @@ int hcurl_amg_setup(const hcurl_csr* A, const hcurl_csr* Dh, const double* coord
     if (h->H.opts.emin_iters < 0 || h->H.opts.power_iters < 1) hc::fail(HCURL_EINVAL, "bad iteration counts");
     h->H.ctx.init((hipStream_t)h->H.opts.stream, h->H.opts.profile != 0);
     auto t0 = std::chrono::steady_clock::now();
-    hc::build_hierarchy(h->H, *A, *Dh, aggregates, n_agg_levels);
+    hc::build_hierarchy(h->H, *A, *Dh, coords, aggregates, n_agg_levels);
     h->H.setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return HCURL_OK;
   });
@@ -273,6 +273,134 @@ void hcurl_amg_reset_kernel_stats(hcurl_amg h) {
   } catch (...) {
   }
   h->H.ctx.stats.clear();
+}
+
+// ---------------------------------------------------------------------------
+// learned initial guess
+// ---------------------------------------------------------------------------
+int64_t hcurl_mpnn_num_params(void) { return hc::kNParam; }
+
+int hcurl_mpnn_create(const float* params, void* stream, hcurl_mpnn* out) {
+  if (!out || !params) return HCURL_EINVAL;
+  *out = nullptr;
+  auto* n = new (std::nothrow) hcurl_mpnn_s();
+  if (!n) return HCURL_ENOMEM;
+  int rc = guarded([&]() -> int {
+    hc::Net& net = n->net;
+    hc::Ctx& c = net.ctx;
+    c.init((hipStream_t)stream, false);
+    net.w.alloc(hc::kNParam, c.s);
+    net.m.alloc(hc::kNParam, c.s);
+    net.v.alloc(hc::kNParam, c.s);
+    net.g.alloc(hc::kNParam, c.s);
+    HC_HIP(hipMemsetAsync(net.m.p, 0, sizeof(float) * hc::kNParam, c.s));
+    HC_HIP(hipMemsetAsync(net.v.p, 0, sizeof(float) * hc::kNParam, c.s));
+    HC_HIP(hipMemsetAsync(net.g.p, 0, sizeof(float) * hc::kNParam, c.s));
+    hc::h2d(net.w.p, params, hc::kNParam, c);
+    net.wt_in.alloc(hc::kNF * hc::kHD, c.s);
+    for (int l = 0; l < hc::kNL; ++l) {
+      net.wt[l].alloc(hc::kKZ * hc::kHD, c.s);
+      net.wr[l].alloc(hc::kKZ * hc::kHD, c.s);
+    }
+    net.refresh_bf16(c);
+    c.sync();
+    return HCURL_OK;
+  });
+  if (rc != HCURL_OK) { delete n; return rc; }
+  *out = n;
+  return HCURL_OK;
+}
+
+int hcurl_mpnn_get_params(hcurl_mpnn net, float* params) {
+  if (!net || !params) return HCURL_EINVAL;
+  return guarded([&]() -> int {
+    hc::d2h(params, net->net.w.p, hc::kNParam, net->net.ctx);
+    return HCURL_OK;
+  });
+}
+
+void hcurl_mpnn_destroy(hcurl_mpnn net) {
+  if (!net) return;
+  try { (void)hipStreamSynchronize(net->net.ctx.s); } catch (...) {}
+  delete net;
+}
+
+int hcurl_amg_mpnn_sample(hcurl_amg h, hcurl_mpnn_sample* out) {
+  if (!h || !out) return HCURL_EINVAL;
+  *out = nullptr;
+  auto* smp = new (std::nothrow) hcurl_mpnn_sample_s();
+  if (!smp) return HCURL_ENOMEM;
+  int rc = guarded([&]() -> int {
+    auto& H = h->H;
+    if (H.lv.size() < 2) hc::fail(HCURL_EINVAL, "hierarchy has a single level");
+    if (H.opts.init_guess != HCURL_INIT_ONES) hc::fail(HCURL_EINVAL, "samples come from hierarchies with the plain initial guess");
+    hc::Level& L0 = *H.lv[0];
+    const int64_t np = L0.Pe.nnz;
+    hc::DBuf<double> pmin(np, H.ctx.s);
+    hc::fill(pmin.p, 0.0, np, H.ctx);
+    hc::emin_make_feasible(L0, pmin.p, false, H.ctx);
+    hc::mpnn_build_sample(H, L0, *H.lv[1], L0.p0.p, pmin.p, smp->S);
+    smp->S.target.alloc(np, H.ctx.s);
+    hc::d2d(smp->S.target.p, L0.Pe.val.p, np, H.ctx);
+    H.ctx.sync();
+    smp->ctx.init(H.ctx.s, false);
+    return HCURL_OK;
+  });
+  if (rc != HCURL_OK) { delete smp; return rc; }
+  *out = smp;
+  return HCURL_OK;
+}
+
+int64_t hcurl_mpnn_sample_entries(hcurl_mpnn_sample s) { return s ? s->S.E : HCURL_EINVAL; }
+
+int hcurl_mpnn_sample_export(hcurl_mpnn_sample s, float* features, double* p0, double* target) {
+  if (!s) return HCURL_EINVAL;
+  return guarded([&]() -> int {
+    if (features) hc::d2h(features, s->S.X.p, s->S.E * hc::kNF, s->ctx);
+    if (p0) hc::d2h(p0, s->S.p0.p, s->S.E, s->ctx);
+    if (target) hc::d2h(target, s->S.target.p, s->S.E, s->ctx);
+    return HCURL_OK;
+  });
+}
+
+void hcurl_mpnn_sample_destroy(hcurl_mpnn_sample s) {
+  if (!s) return;
+  try { (void)hipStreamSynchronize(s->ctx.s); } catch (...) {}
+  delete s;
+}
+
+int hcurl_mpnn_forward(hcurl_mpnn net, hcurl_mpnn_sample s, double* delta) {
+  if (!net || !s || !delta) return HCURL_EINVAL;
+  return guarded([&]() -> int {
+    net->net.ctx.sync();
+    hc::mpnn_forward(net->net, s->S, s->ctx, false);
+    hc::d2h(delta, s->S.delta.p, s->S.E, s->ctx);
+    return HCURL_OK;
+  });
+}
+
+int hcurl_mpnn_loss_grad(hcurl_mpnn net, hcurl_mpnn_sample s, double* loss, float* grad) {
+  if (!net || !s) return HCURL_EINVAL;
+  return guarded([&]() -> int {
+    net->net.ctx.sync();
+    const double l = hc::mpnn_loss_grad(net->net, s->S, s->ctx);
+    if (loss) *loss = l;
+    if (grad) hc::d2h(grad, net->net.g.p, hc::kNParam, s->ctx);
+    return HCURL_OK;
+  });
+}
+
+int hcurl_mpnn_train_step(hcurl_mpnn net, hcurl_mpnn_sample s, float lr, float beta1, float beta2, float eps, int step,
+                          double* loss) {
+  if (!net || !s || step < 1) return HCURL_EINVAL;
+  return guarded([&]() -> int {
+    net->net.ctx.sync();
+    const double l = hc::mpnn_loss_grad(net->net, s->S, s->ctx);
+    hc::mpnn_adam(net->net, lr, beta1, beta2, eps, step, s->ctx);
+    s->ctx.sync();
+    if (loss) *loss = l;
+    return HCURL_OK;
+  });
 }
 
 const char* hcurl_last_error(void) { return g_last_error.c_str(); }

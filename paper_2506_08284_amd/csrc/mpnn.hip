@@ -1,0 +1,545 @@
+// Message-passing network for the learned P^(e) initial guess: per-entry
+// features, BF16 matrix-core (MFMA 32x32x8) dense layers with FP32
+// accumulation, segment means over pattern rows and columns, MSE loss,
+// backward pass and Adam.
+#include <cmath>
+#include <cstring>
+
+#include "mpnn.hpp"
+
+namespace hc {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float silu_f(float x) { return x / (1.0f + expf(-x)); }
+__device__ __forceinline__ float dsilu_f(float x) {
+  const float s = 1.0f / (1.0f + expf(-x));
+  return s * (1.0f + x * (1.0f - s));
+}
+
+// ---------------------------------------------------------------------------
+// features of pattern entry e = (i, j); see the feature list in the header
+// of the FP64 reference (same definitions)
+// ---------------------------------------------------------------------------
+__global__ void k_expand_rows(const int* __restrict__ rp, int n, int* __restrict__ row_of) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int q = rp[i]; q < rp[i + 1]; ++q) row_of[q] = i;
+}
+__global__ void k_iota_d(double* __restrict__ v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = (double)i;
+}
+__global__ void k_d2i(const double* __restrict__ v, int* __restrict__ o, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) o[i] = (int)v[i];
+}
+__global__ void k_centroid_sum(const double* __restrict__ x, const int* __restrict__ agg, int m, double* __restrict__ cen,
+                               double* __restrict__ cnt) {
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= m) return;
+  const int I = agg[a];
+  atomicAdd(&cen[3 * I + 0], x[3 * a + 0]);
+  atomicAdd(&cen[3 * I + 1], x[3 * a + 1]);
+  atomicAdd(&cen[3 * I + 2], x[3 * a + 2]);
+  atomicAdd(&cnt[I], 1.0);
+}
+__global__ void k_centroid_div(double* __restrict__ cen, const double* __restrict__ cnt, int mH) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= mH) return;
+  for (int d = 0; d < 3; ++d) cen[3 * I + d] /= cnt[I];
+}
+
+__device__ __forceinline__ double r_at(const int* __restrict__ Rrp, const int* __restrict__ Rcol,
+                                       const double* __restrict__ Rval, int i, int I) {
+  int lo = Rrp[i], hi = Rrp[i + 1] - 1;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const int c = Rcol[mid];
+    if (c == I) return Rval[mid];
+    if (c < I) lo = mid + 1; else hi = mid - 1;
+  }
+  return 0.0;
+}
+
+__global__ void k_features(int64_t E, const int* __restrict__ row_of, const int* __restrict__ col_of,
+                           const int* __restrict__ Prp, const int* __restrict__ colptr, const int* __restrict__ tail,
+                           const int* __restrict__ head, const int* __restrict__ ctail, const int* __restrict__ chead,
+                           const double* __restrict__ x, const double* __restrict__ cen, const double* __restrict__ p0,
+                           const double* __restrict__ pmin, const int* __restrict__ Rrp, const int* __restrict__ Rcol,
+                           const double* __restrict__ Rval, const double* __restrict__ dinvA, const int* __restrict__ agg,
+                           float* __restrict__ X) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const int i = row_of[e], j = col_of[e];
+  const int a = tail[i], b = head[i], I = ctail[j], K = chead[j];
+  double t[3], mid[3], T[3], Mid[3];
+  for (int d = 0; d < 3; ++d) {
+    t[d] = x[3 * b + d] - x[3 * a + d];
+    mid[d] = 0.5 * (x[3 * b + d] + x[3 * a + d]);
+    T[d] = cen[3 * K + d] - cen[3 * I + d];
+    Mid[d] = 0.5 * (cen[3 * K + d] + cen[3 * I + d]);
+  }
+  const double lt = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+  const double LT = sqrt(T[0] * T[0] + T[1] * T[1] + T[2] * T[2]);
+  const double dm = sqrt((mid[0] - Mid[0]) * (mid[0] - Mid[0]) + (mid[1] - Mid[1]) * (mid[1] - Mid[1]) +
+                         (mid[2] - Mid[2]) * (mid[2] - Mid[2]));
+  float* f = X + e * kNF;
+  f[0] = (float)p0[e];
+  f[1] = (float)pmin[e];
+  f[2] = (float)((t[0] * T[0] + t[1] * T[1] + t[2] * T[2]) / (lt * LT));
+  f[3] = (float)(lt / LT);
+  f[4] = (float)(dm / LT);
+  f[5] = (float)((Prp[i + 1] - Prp[i]) / 16.0);
+  f[6] = (float)((Rrp[i + 1] - Rrp[i]) / 8.0);
+  f[7] = (float)((colptr[j + 1] - colptr[j]) / 256.0);
+  f[8] = (float)r_at(Rrp, Rcol, Rval, i, I);
+  f[9] = (float)r_at(Rrp, Rcol, Rval, i, K);
+  const int ai = agg[a], bi = agg[b];
+  f[10] = (ai == I || ai == K) ? 1.0f : 0.0f;
+  f[11] = (bi == I || bi == K) ? 1.0f : 0.0f;
+  f[12] = (float)(log10(1.0 / dinvA[i]) / 8.0);
+  f[13] = 0.0f;
+  f[14] = 0.0f;
+  f[15] = 0.0f;
+}
+
+void mpnn_build_sample(Hierarchy& H, Level& L0, const Level& L1, const double* p0plain, const double* pmin, Sample& S) {
+  Ctx& c = H.ctx;
+  if (!H.coords.p) fail(HCURL_EINVAL, "the learned initial guess needs node coordinates at setup");
+  S.s = c.s;
+  S.E = L0.Pe.nnz;
+  S.nrow = L0.n;
+  S.ncol = L0.Pe.ncols;
+  const int64_t E = S.E;
+  S.rowptr.alloc(L0.n + 1, c.s);
+  d2d(S.rowptr.p, L0.Pe.rowptr.p, L0.n + 1, c);
+  S.row_of.alloc(E, c.s);
+  S.col_of.alloc(E, c.s);
+  d2d(S.col_of.p, L0.Pe.col.p, E, c);
+  k_expand_rows<<<ceil_div(L0.n, 256), 256, 0, c.s>>>(L0.Pe.rowptr.p, L0.n, S.row_of.p);
+  HC_LAUNCH_CHECK();
+  {  // entries grouped by column: transpose of the pattern carrying entry ids
+    Csr P, PT;
+    P.nrows = L0.n; P.ncols = S.ncol; P.nnz = E;
+    P.rowptr.alloc(L0.n + 1, c.s); P.col.alloc(E, c.s); P.val.alloc(E, c.s);
+    d2d(P.rowptr.p, L0.Pe.rowptr.p, L0.n + 1, c);
+    d2d(P.col.p, L0.Pe.col.p, E, c);
+    k_iota_d<<<ceil_div(E, 256), 256, 0, c.s>>>(P.val.p, E);
+    HC_LAUNCH_CHECK();
+    transpose(P, PT, true, c);
+    S.colptr = std::move(PT.rowptr);
+    S.colidx.alloc(E, c.s);
+    k_d2i<<<ceil_div(E, 256), 256, 0, c.s>>>(PT.val.p, S.colidx.p, E);
+    HC_LAUNCH_CHECK();
+  }
+  const int mH = L1.m;
+  DBuf<double> cen(3 * (size_t)mH, c.s), cnt(mH, c.s);
+  fill(cen.p, 0.0, 3 * (int64_t)mH, c);
+  fill(cnt.p, 0.0, mH, c);
+  k_centroid_sum<<<ceil_div(L0.m, 256), 256, 0, c.s>>>(H.coords.p, L0.agg.p, L0.m, cen.p, cnt.p);
+  HC_LAUNCH_CHECK();
+  k_centroid_div<<<ceil_div(mH, 256), 256, 0, c.s>>>(cen.p, cnt.p, mH);
+  HC_LAUNCH_CHECK();
+  S.X.alloc(E * kNF, c.s);
+  c.run("mpnn_features", 100.0 * E, [&] {
+    k_features<<<ceil_div(E, 256), 256, 0, c.s>>>(E, S.row_of.p, S.col_of.p, L0.Pe.rowptr.p, S.colptr.p, L0.tail.p,
+                                                  L0.head.p, L1.tail.p, L1.head.p, H.coords.p, cen.p, p0plain, pmin,
+                                                  L0.R.rowptr.p, L0.R.col.p, L0.R.val.p, L0.dinvA.p, L0.agg.p, S.X.p);
+  });
+  S.p0.alloc(E, c.s);
+  d2d(S.p0.p, p0plain, E, c);
+}
+
+// ---------------------------------------------------------------------------
+// dense layers on the matrix cores.  Tiles of 64 entries x 64 outputs, four
+// waves each computing a 32x32 block with v_mfma_f32_32x32x8_bf16: lane l holds
+// A[l%32][4(l/32)+v], B[4(l/32)+v][l%32], and accumulator r is element
+// (8(r/4) + 4(l/32) + r%4, l%32).
+// ---------------------------------------------------------------------------
+// Z row of entry e for layer input: MODE 0 the features, MODE 1 the
+// concatenation [h_e, mean_row(i(e)), mean_col(j(e))].
+template <int K, int MODE>
+__device__ __forceinline__ float z_value(int64_t e, int k, const float* __restrict__ X, const float* __restrict__ hin,
+                                         const float* __restrict__ mr, const float* __restrict__ mc,
+                                         const int* __restrict__ row_of, const int* __restrict__ col_of) {
+  if (MODE == 0) return X[e * K + k];
+  if (k < kHD) return hin[e * kHD + k];
+  if (k < 2 * kHD) return mr[(int64_t)row_of[e] * kHD + (k - kHD)];
+  return mc[(int64_t)col_of[e] * kHD + (k - 2 * kHD)];
+}
+
+template <int K, int MODE>
+__global__ void __launch_bounds__(256) k_mpnn_fwd(int64_t E, const float* __restrict__ X, const float* __restrict__ hin,
+                                                  const float* __restrict__ mr, const float* __restrict__ mc,
+                                                  const int* __restrict__ row_of, const int* __restrict__ col_of,
+                                                  const uint16_t* __restrict__ Wt, const float* __restrict__ bias,
+                                                  float* __restrict__ U, float* __restrict__ hout) {
+  __shared__ __attribute__((aligned(16))) uint16_t Zs[64][K + 8];
+  __shared__ __attribute__((aligned(16))) uint16_t Ws[64][K + 8];
+  const int t = threadIdx.x;
+  const int64_t e0 = (int64_t)blockIdx.x * 64;
+  for (int q = t; q < 64 * K; q += 256) Ws[q / K][q % K] = Wt[q];
+  for (int q = t; q < 64 * K; q += 256) {
+    const int r = q / K, k = q % K;
+    const int64_t e = e0 + r;
+    Zs[r][k] = f2bf(e < E ? z_value<K, MODE>(e, k, X, hin, mr, mc, row_of, col_of) : 0.0f);
+  }
+  __syncthreads();
+  const int w = t >> 6, l = t & 63;
+  const int mt = w >> 1, nt = w & 1;
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+#pragma unroll
+  for (int kk = 0; kk < K; kk += 8) {
+    const bf16x4 a = *(const bf16x4*)&Zs[mt * 32 + (l & 31)][kk + 4 * (l >> 5)];
+    const bf16x4 b = *(const bf16x4*)&Ws[nt * 32 + (l & 31)][kk + 4 * (l >> 5)];
+    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = mt * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+    const int col = nt * 32 + (l & 31);
+    const int64_t e = e0 + row;
+    if (e < E) {
+      const float u = acc[r] + bias[col];
+      if (U) U[e * kHD + col] = u;
+      hout[e * kHD + col] = (MODE ? hin[e * kHD + col] : 0.0f) + silu_f(u);
+    }
+  }
+}
+
+// dZ = du W^T: du (E x 64), W (192 x 64) bf16 row-major, dz (E x 192); grid.y
+// picks the 64-column slice of dz.
+__global__ void __launch_bounds__(256) k_mpnn_dz(int64_t E, const float* __restrict__ du, const uint16_t* __restrict__ Wr,
+                                                 float* __restrict__ dz) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[64][kHD + 8];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[64][kHD + 8];
+  const int t = threadIdx.x;
+  const int64_t e0 = (int64_t)blockIdx.x * 64;
+  const int n0 = blockIdx.y * 64;
+  for (int q = t; q < 64 * kHD; q += 256) {
+    const int r = q / kHD, k = q % kHD;
+    const int64_t e = e0 + r;
+    As[r][k] = f2bf(e < E ? du[e * kHD + k] : 0.0f);
+    Bs[r][k] = Wr[(int64_t)(n0 + r) * kHD + k];
+  }
+  __syncthreads();
+  const int w = t >> 6, l = t & 63;
+  const int mt = w >> 1, nt = w & 1;
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+#pragma unroll
+  for (int kk = 0; kk < kHD; kk += 8) {
+    const bf16x4 a = *(const bf16x4*)&As[mt * 32 + (l & 31)][kk + 4 * (l >> 5)];
+    const bf16x4 b = *(const bf16x4*)&Bs[nt * 32 + (l & 31)][kk + 4 * (l >> 5)];
+    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = mt * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+    const int col = nt * 32 + (l & 31);
+    const int64_t e = e0 + row;
+    if (e < E) dz[e * kKZ + n0 + col] = acc[r];
+  }
+}
+
+// Partial weight gradient over a run of entries: dW (K x 64) += Z^T du,
+// db (64) += sum du.  The entry dimension is the MFMA reduction dimension.
+template <int K, int MODE>
+__global__ void __launch_bounds__(256) k_mpnn_wgrad(int64_t E, int chunks, const float* __restrict__ X,
+                                                    const float* __restrict__ hin, const float* __restrict__ mr,
+                                                    const float* __restrict__ mc, const int* __restrict__ row_of,
+                                                    const int* __restrict__ col_of, const float* __restrict__ du,
+                                                    float* __restrict__ part) {
+  constexpr int MP = (K + 31) / 32 * 32;
+  constexpr int NT = (MP / 32) * 2;  // 32x32 output tiles
+  constexpr int PER = (NT + 3) / 4;  // tiles per wave
+  __shared__ __attribute__((aligned(16))) uint16_t Zt[MP][64 + 8];
+  __shared__ __attribute__((aligned(16))) uint16_t Dt[kHD][64 + 8];
+  const int t = threadIdx.x;
+  const int w = t >> 6, l = t & 63;
+  f32x16 acc[PER];
+#pragma unroll
+  for (int s = 0; s < PER; ++s)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[s][r] = 0.0f;
+  float bsum = 0.0f;
+  for (int cidx = 0; cidx < chunks; ++cidx) {
+    const int64_t e0 = ((int64_t)blockIdx.x * chunks + cidx) * 64;
+    if (e0 >= E) break;
+    for (int q = t; q < 64 * MP; q += 256) {
+      const int el = q / MP, zf = q % MP;
+      const int64_t e = e0 + el;
+      Zt[zf][el] = f2bf((zf < K && e < E) ? z_value<K, MODE>(e, zf, X, hin, mr, mc, row_of, col_of) : 0.0f);
+    }
+    for (int q = t; q < 64 * kHD; q += 256) {
+      const int el = q / kHD, hid = q % kHD;
+      const int64_t e = e0 + el;
+      Dt[hid][el] = f2bf(e < E ? du[e * kHD + hid] : 0.0f);
+    }
+    if (t < kHD)
+      for (int el = 0; el < 64 && e0 + el < E; ++el) bsum += du[(e0 + el) * kHD + t];
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+      const int ti = w + 4 * s;
+      if (ti < NT) {
+        const int tm = ti >> 1, tn = ti & 1;
+#pragma unroll
+        for (int kk = 0; kk < 64; kk += 8) {
+          const bf16x4 a = *(const bf16x4*)&Zt[tm * 32 + (l & 31)][kk + 4 * (l >> 5)];
+          const bf16x4 b = *(const bf16x4*)&Dt[tn * 32 + (l & 31)][kk + 4 * (l >> 5)];
+          acc[s] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[s], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  float* out = part + (int64_t)blockIdx.x * (K * kHD + kHD);
+#pragma unroll
+  for (int s = 0; s < PER; ++s) {
+    const int ti = w + 4 * s;
+    if (ti < NT) {
+      const int tm = ti >> 1, tn = ti & 1;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = tm * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+        const int j = tn * 32 + (l & 31);
+        if (i < K) out[i * kHD + j] = acc[s][r];
+      }
+    }
+  }
+  if (t < kHD) out[K * kHD + t] = bsum;
+}
+
+// out[k] = sum over blocks of part[b * stride + k] (fixed order)
+__global__ void k_sum_blocks(const float* __restrict__ part, int nb, int stride, float* __restrict__ out) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= stride) return;
+  float s = 0.0f;
+  for (int b = 0; b < nb; ++b) s += part[(int64_t)b * stride + k];
+  out[k] = s;
+}
+
+// mean over segments: dst[s][f] = mean of src[e][off + f] over the segment's
+// entries (idx maps positions to entries, NULL = identity); one wave per segment
+__global__ void __launch_bounds__(256) k_seg_mean(int nseg, const int* __restrict__ ptr, const int* __restrict__ idx,
+                                                  const float* __restrict__ src, int stride, int off,
+                                                  float* __restrict__ dst) {
+  const int sgi = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int f = threadIdx.x & 63;
+  if (sgi >= nseg) return;
+  const int a = ptr[sgi], b = ptr[sgi + 1];
+  float acc = 0.0f;
+  for (int q = a; q < b; ++q) {
+    const int64_t e = idx ? idx[q] : q;
+    acc += src[e * stride + off + f];
+  }
+  dst[(int64_t)sgi * kHD + f] = b > a ? acc / (float)(b - a) : 0.0f;
+}
+
+// delta_e = h_e . w_out + b_out; with training: residual, loss, dh = dd w_out,
+// and partial sums of the head gradient (one wave per entry, lane = feature)
+__global__ void __launch_bounds__(256) k_head(int64_t E, const float* __restrict__ h, const float* __restrict__ w,
+                                              const double* __restrict__ p0, const double* __restrict__ target,
+                                              double* __restrict__ delta, float* __restrict__ dh,
+                                              float* __restrict__ part /* per block: 64 gw, gb, loss */) {
+  __shared__ float sg[4][kHD + 2];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const float wf = w[lane];
+  const float bo = w[kHD];
+  float gw = 0.0f, gb = 0.0f, ls = 0.0f;
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  for (int64_t e = (int64_t)blockIdx.x * 4 + wv; e < E; e += nw) {
+    const float hv = h[e * kHD + lane];
+    const float d = wave_sum(hv * wf) + bo;
+    if (lane == 0) delta[e] = (double)d;
+    if (target) {
+      const double res = p0[e] + (double)d - target[e];
+      const float dd = (float)(2.0 * res / (double)E);
+      dh[e * kHD + lane] = dd * wf;
+      gw += dd * hv;
+      gb += dd;
+      ls += (float)(res * res);
+    }
+  }
+  if (!target) return;
+  sg[wv][lane] = gw;
+  if (lane == 0) { sg[wv][kHD] = gb; sg[wv][kHD + 1] = ls; }
+  __syncthreads();
+  if (threadIdx.x < kHD + 2) {
+    const int k = threadIdx.x;
+    part[(int64_t)blockIdx.x * (kHD + 2) + k] = (sg[0][k] + sg[1][k]) + (sg[2][k] + sg[3][k]);
+  }
+}
+
+__global__ void k_du(int64_t n, const float* __restrict__ dh, const float* __restrict__ u, float* __restrict__ du) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) du[i] = dh[i] * dsilu_f(u[i]);
+}
+
+// dh_e += dz_e[0:64] + mdr[i(e)] + mdc[j(e)]
+__global__ void k_dh_combine(int64_t E, float* __restrict__ dh, const float* __restrict__ dz, const float* __restrict__ mdr,
+                             const float* __restrict__ mdc, const int* __restrict__ row_of,
+                             const int* __restrict__ col_of) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= E * kHD) return;
+  const int64_t e = q / kHD;
+  const int f = (int)(q % kHD);
+  dh[q] += dz[e * kKZ + f] + mdr[(int64_t)row_of[e] * kHD + f] + mdc[(int64_t)col_of[e] * kHD + f];
+}
+
+__global__ void k_adam(int64_t n, float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, float lr, float b1, float b2, float eps, float c1, float c2) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// bf16 copies: transposed (out x in) for forward products, plain for dZ
+__global__ void k_to_bf16_t(const float* __restrict__ W, int rows, int cols, uint16_t* __restrict__ Wt) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= rows * cols) return;
+  const int r = q / cols, c = q % cols;
+  Wt[(int64_t)c * rows + r] = f2bf(W[q]);
+}
+__global__ void k_to_bf16(const float* __restrict__ W, int n, uint16_t* __restrict__ Wb) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) Wb[q] = f2bf(W[q]);
+}
+
+void Net::refresh_bf16(Ctx& c) {
+  k_to_bf16_t<<<ceil_div(kNF * kHD, 256), 256, 0, c.s>>>(w.p + kOffWin, kNF, kHD, wt_in.p);
+  for (int l = 0; l < kNL; ++l) {
+    k_to_bf16_t<<<ceil_div(kKZ * kHD, 256), 256, 0, c.s>>>(w.p + off_W(l), kKZ, kHD, wt[l].p);
+    k_to_bf16<<<ceil_div(kKZ * kHD, 256), 256, 0, c.s>>>(w.p + off_W(l), kKZ * kHD, wr[l].p);
+  }
+  HC_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static void row_mean(Sample& S, const float* src, int stride, int off, float* mr, Ctx& c) {
+  c.run("mpnn_segment_mean", 8.0 * S.E * kHD, [&] {
+    k_seg_mean<<<ceil_div((int64_t)S.nrow * 64, 256), 256, 0, c.s>>>(S.nrow, S.rowptr.p, nullptr, src, stride, off, mr);
+  });
+}
+static void col_mean(Sample& S, const float* src, int stride, int off, float* mc, Ctx& c) {
+  c.run("mpnn_segment_mean", 8.0 * S.E * kHD, [&] {
+    k_seg_mean<<<ceil_div((int64_t)S.ncol * 64, 256), 256, 0, c.s>>>(S.ncol, S.colptr.p, S.colidx.p, src, stride, off, mc);
+  });
+}
+
+void mpnn_forward(Net& net, Sample& S, Ctx& c, bool keep) {
+  const int64_t E = S.E;
+  const int nb = ceil_div(E, 64);
+  const int nbuf = keep ? kNL + 1 : 2;
+  for (int k = 0; k < nbuf; ++k) {
+    if (S.h[k].n != (size_t)(E * kHD)) S.h[k].alloc(E * kHD, c.s);
+    if (keep && S.u[k].n != (size_t)(E * kHD)) S.u[k].alloc(E * kHD, c.s);
+  }
+  for (int l = 0; l < (keep ? kNL : 1); ++l) {
+    if (S.mr[l].n != (size_t)S.nrow * kHD) S.mr[l].alloc((size_t)S.nrow * kHD, c.s);
+    if (S.mc[l].n != (size_t)S.ncol * kHD) S.mc[l].alloc((size_t)S.ncol * kHD, c.s);
+  }
+  if (S.delta.n != (size_t)E) S.delta.alloc(E, c.s);
+  c.run("mpnn_dense_in", 2.0 * E * kNF * kHD, [&] {
+    k_mpnn_fwd<kNF, 0><<<nb, 256, 0, c.s>>>(E, S.X.p, nullptr, nullptr, nullptr, nullptr, nullptr, net.wt_in.p,
+                                            net.w.p + kOffBin, keep ? S.u[0].p : nullptr, S.h[0].p);
+  });
+  for (int l = 0; l < kNL; ++l) {
+    float* hin = keep ? S.h[l].p : S.h[l & 1].p;
+    float* hout = keep ? S.h[l + 1].p : S.h[(l + 1) & 1].p;
+    float* mr = keep ? S.mr[l].p : S.mr[0].p;
+    float* mc = keep ? S.mc[l].p : S.mc[0].p;
+    row_mean(S, hin, kHD, 0, mr, c);
+    col_mean(S, hin, kHD, 0, mc, c);
+    c.run("mpnn_dense", 2.0 * E * kKZ * kHD, [&] {
+      k_mpnn_fwd<kKZ, 1><<<nb, 256, 0, c.s>>>(E, nullptr, hin, mr, mc, S.row_of.p, S.col_of.p, net.wt[l].p,
+                                              net.w.p + off_b(l), keep ? S.u[l + 1].p : nullptr, hout);
+    });
+  }
+  const float* hlast = keep ? S.h[kNL].p : S.h[kNL & 1].p;
+  c.run("mpnn_head", 4.0 * E * kHD, [&] {
+    k_head<<<1024, 256, 0, c.s>>>(E, hlast, net.w.p + kOffWout, nullptr, nullptr, S.delta.p, nullptr, nullptr);
+  });
+}
+
+double mpnn_loss_grad(Net& net, Sample& S, Ctx& c) {
+  if (!S.target.p) fail(HCURL_EINVAL, "sample has no target");
+  const int64_t E = S.E;
+  mpnn_forward(net, S, c, true);
+  if (S.dh.n != (size_t)(E * kHD)) { S.dh.alloc(E * kHD, c.s); S.du.alloc(E * kHD, c.s); }
+  if (S.dz.n != (size_t)(E * kKZ)) S.dz.alloc(E * kKZ, c.s);
+  if (S.mdr.n != (size_t)S.nrow * kHD) S.mdr.alloc((size_t)S.nrow * kHD, c.s);
+  if (S.mdc.n != (size_t)S.ncol * kHD) S.mdc.alloc((size_t)S.ncol * kHD, c.s);
+  // head: loss, dh, gradient of w_out and b_out
+  DBuf<float> hpart(1024 * (kHD + 2), c.s), hsum(kHD + 2, c.s);
+  c.run("mpnn_head", 12.0 * E * kHD, [&] {
+    k_head<<<1024, 256, 0, c.s>>>(E, S.h[kNL].p, net.w.p + kOffWout, S.p0.p, S.target.p, S.delta.p, S.dh.p, hpart.p);
+  });
+  k_sum_blocks<<<1, 128, 0, c.s>>>(hpart.p, 1024, kHD + 2, hsum.p);
+  HC_LAUNCH_CHECK();
+  d2d(net.g.p + kOffWout, hsum.p, kHD + 1, c);
+  float hl[kHD + 2];
+  d2h(hl, hsum.p, kHD + 2, c);
+  const double loss = (double)hl[kHD + 1] / (double)E;
+  // message layers, top down
+  const int chunks = 16;
+  const int nbw = ceil_div(E, 64 * chunks);
+  DBuf<float> wpart((size_t)nbw * (kKZ * kHD + kHD), c.s);
+  const int nb = ceil_div(E, 64);
+  for (int l = kNL - 1; l >= 0; --l) {
+    c.run("mpnn_du", 12.0 * E * kHD, [&] { k_du<<<ceil_div(E * kHD, 256), 256, 0, c.s>>>(E * kHD, S.dh.p, S.u[l + 1].p, S.du.p); });
+    c.run("mpnn_dense_wgrad", 2.0 * E * kKZ * kHD, [&] {
+      k_mpnn_wgrad<kKZ, 1><<<nbw, 256, 0, c.s>>>(E, chunks, nullptr, S.h[l].p, S.mr[l].p, S.mc[l].p, S.row_of.p,
+                                                 S.col_of.p, S.du.p, wpart.p);
+    });
+    k_sum_blocks<<<ceil_div(kKZ * kHD + kHD, 256), 256, 0, c.s>>>(wpart.p, nbw, kKZ * kHD + kHD, net.g.p + off_W(l));
+    HC_LAUNCH_CHECK();
+    c.run("mpnn_dense_dz", 2.0 * E * kKZ * kHD, [&] {
+      k_mpnn_dz<<<dim3(nb, 3), 256, 0, c.s>>>(E, S.du.p, net.wr[l].p, S.dz.p);
+    });
+    // adjoints of the gathered means: average the row slice over rows and
+    // the column slice over columns
+    row_mean(S, S.dz.p, kKZ, kHD, S.mdr.p, c);
+    col_mean(S, S.dz.p, kKZ, 2 * kHD, S.mdc.p, c);
+    c.run("mpnn_dh", 16.0 * E * kHD, [&] {
+      k_dh_combine<<<ceil_div(E * kHD, 256), 256, 0, c.s>>>(E, S.dh.p, S.dz.p, S.mdr.p, S.mdc.p, S.row_of.p, S.col_of.p);
+    });
+  }
+  // input layer
+  c.run("mpnn_du", 12.0 * E * kHD, [&] { k_du<<<ceil_div(E * kHD, 256), 256, 0, c.s>>>(E * kHD, S.dh.p, S.u[0].p, S.du.p); });
+  c.run("mpnn_dense_wgrad", 2.0 * E * kNF * kHD, [&] {
+    k_mpnn_wgrad<kNF, 0><<<nbw, 256, 0, c.s>>>(E, chunks, S.X.p, nullptr, nullptr, nullptr, nullptr, nullptr, S.du.p,
+                                               wpart.p);
+  });
+  k_sum_blocks<<<ceil_div(kNF * kHD + kHD, 256), 256, 0, c.s>>>(wpart.p, nbw, kNF * kHD + kHD, net.g.p + kOffWin);
+  HC_LAUNCH_CHECK();
+  c.sync();
+  return loss;
+}
+
+void mpnn_adam(Net& net, float lr, float b1, float b2, float eps, int step, Ctx& c) {
+  const float c1 = 1.0f - std::pow(b1, (float)step), c2 = 1.0f - std::pow(b2, (float)step);
+  k_adam<<<ceil_div(kNParam, 256), 256, 0, c.s>>>(kNParam, net.w.p, net.g.p, net.m.p, net.v.p, lr, b1, b2, eps, c1, c2);
+  HC_LAUNCH_CHECK();
+  net.refresh_bf16(c);
+}
+
+}  // namespace hc

@@ -4,7 +4,7 @@
 #include <chrono>
 #include <cmath>
 
-#include "amg.hpp"
+#include "mpnn.hpp"
 
 namespace hc {
 
@@ -640,6 +640,13 @@ static void make_feasible(Level& L, double* x, bool ones, Ctx& c) {
   });
 }
 
+void emin_make_feasible(Level& L, double* x, bool ones, Ctx& c) { make_feasible(L, x, ones, c); }
+
+__global__ void k_add2(int64_t n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a[i] + b[i];
+}
+
 static double energy_of(Level& L, const double* P, EminWork& w, Ctx& c) {
   int g = emin_apply(L, nullptr, P, w.Q.p, EM_DOT, w.part.p, nullptr, c);
   // sum of partials (g may exceed kRedBlocks: reduce on host deterministically)
@@ -661,7 +668,8 @@ static void sum_partials(const double* part, int nb, double* out, Ctx& c) {
   c.run("reduce", 8.0 * nb, [&] { k_sum_partials<<<1, 256, 0, c.s>>>(part, nb, out); });
 }
 
-static void energy_minimisation(Hierarchy& H, Level& L, int iters, bool given_init, const double* init, bool init_dev) {
+static void energy_minimisation(Hierarchy& H, Level& L, const Level* next, int iters, bool given_init, const double* init,
+                                bool init_dev, bool learned) {
   Ctx& c = H.ctx;
   const int64_t np = L.Pe.nnz;
   EminWork w;
@@ -673,9 +681,24 @@ static void energy_minimisation(Hierarchy& H, Level& L, int iters, bool given_in
   w.part.alloc(8192, c.s);
   clear_flag(F_NOTSPD, c);
   // initial guess
-  if (given_init)
-    HC_HIP(hipMemcpyAsync(w.P.p, init, sizeof(double) * np, init_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c.s));
-  make_feasible(L, w.P.p, !given_init, c);
+  if (learned) {
+    // plain guess plus the network's correction, then the min-norm correction
+    DBuf<double> p0plain(np, c.s), pmin(np, c.s);
+    make_feasible(L, p0plain.p, true, c);
+    fill(pmin.p, 0.0, np, c);
+    make_feasible(L, pmin.p, false, c);
+    Sample S;
+    mpnn_build_sample(H, L, *next, p0plain.p, pmin.p, S);
+    Net& net = ((hcurl_mpnn_s*)H.opts.mpnn)->net;
+    net.ctx.sync();
+    mpnn_forward(net, S, c, false);
+    c.run("mpnn_add", 24.0 * np, [&] { k_add2<<<ceil_div(np, 256), 256, 0, c.s>>>(np, p0plain.p, S.delta.p, w.P.p); });
+    make_feasible(L, w.P.p, false, c);
+  } else {
+    if (given_init)
+      HC_HIP(hipMemcpyAsync(w.P.p, init, sizeof(double) * np, init_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c.s));
+    make_feasible(L, w.P.p, !given_init, c);
+  }
   L.p0.alloc(np, c.s);
   d2d(L.p0.p, w.P.p, np, c);
   double* sc = c.scal.p;
@@ -752,7 +775,8 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
   Ctx& c = H.ctx;
   const bool dev = H.opts.mem_space == HCURL_MEM_DEVICE;
   // aggregates
-  DBuf<int> agg(L.m, c.s);
+  L.agg.alloc(L.m, c.s);
+  DBuf<int>& agg = L.agg;
   HC_HIP(hipMemcpyAsync(agg.p, agg_in, sizeof(int) * L.m, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c.s));
   std::vector<int> hagg(L.m);
   d2h(hagg.data(), agg.p, L.m, c);
@@ -859,8 +883,9 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
   }
   // energy minimisation of P^(e)
   const bool given = level0 && H.opts.init_guess == HCURL_INIT_GIVEN;
-  const int iters = given ? H.opts.emin_iters_given : H.opts.emin_iters;
-  energy_minimisation(H, L, iters, given, H.opts.init_values, dev);
+  const bool learned = level0 && H.opts.init_guess == HCURL_INIT_MPNN;
+  const int iters = (given || learned) ? H.opts.emin_iters_given : H.opts.emin_iters;
+  energy_minimisation(H, L, next.get(), iters, given, H.opts.init_values, dev, learned);
   transpose(L.Pe, L.PeT, true, c);
   // Galerkin A_H = P^T A P
   {
@@ -872,7 +897,8 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
   return next;
 }
 
-void build_hierarchy(Hierarchy& H, const hcurl_csr& A, const hcurl_csr& Dh, const int32_t* const* aggs, int nagg) {
+void build_hierarchy(Hierarchy& H, const hcurl_csr& A, const hcurl_csr& Dh, const double* coords, const int32_t* const* aggs,
+                     int nagg) {
   Ctx& c = H.ctx;
   const bool dev = H.opts.mem_space == HCURL_MEM_DEVICE;
   if (A.nrows != A.ncols) fail(HCURL_EINVAL, "A must be square");
@@ -897,6 +923,13 @@ void build_hierarchy(Hierarchy& H, const hcurl_csr& A, const hcurl_csr& Dh, cons
   }
   if (H.opts.init_guess == HCURL_INIT_GIVEN && !H.opts.init_values)
     fail(HCURL_EINVAL, "init_guess = HCURL_INIT_GIVEN needs init_values");
+  if (H.opts.init_guess == HCURL_INIT_MPNN && (!H.opts.mpnn || !coords))
+    fail(HCURL_EINVAL, "init_guess = HCURL_INIT_MPNN needs opts.mpnn and coords");
+  if (coords) {
+    H.coords.alloc(3 * (size_t)Dh.ncols, c.s);
+    HC_HIP(hipMemcpyAsync(H.coords.p, coords, sizeof(double) * 3 * Dh.ncols,
+                          dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c.s));
+  }
   H.lv.clear();
   H.lv.push_back(std::move(L0));
   const int maxl = H.opts.max_levels > 0 ? H.opts.max_levels : 1 << 20;
