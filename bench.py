@@ -32,11 +32,11 @@ def to_device(arrs, torch, dev):
     return tuple(torch.from_numpy(a).to(dev) for a in arrs)
 
 
-def run_step(P, A_t, D_t, aggs_t, f_t, u_t, m, stream, maxit=1000, **opts):
+def run_step(P, A_t, D_t, aggs_t, f_t, u_t, m, stream, maxit=1000, coords=None, **opts):
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    H = P.Hierarchy(A_t, D_t, aggs_t, n_nodes=m, mem_space="device", stream=stream, **opts)
+    H = P.Hierarchy(A_t, D_t, aggs_t, n_nodes=m, coords=coords, mem_space="device", stream=stream, **opts)
     t1 = time.perf_counter()
     it, rel, rc = H.solve(f_t, u_t, 1e-8, maxit)
     torch.cuda.synchronize()
@@ -75,10 +75,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cube128_contrast")
     ap.add_argument("--cpu-sample", type=int, default=24, help="edge lattice of the oracle sample (0 = skip)")
-    ap.add_argument("--form", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--form", default="learned_fp64",
+                    choices=["plain_fp64", "plain_fp32", "learned_fp64", "learned_fp32"])
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2506_08284_amd", "weights", "mpnn_lognormal_200.npy"))
     ap.add_argument("--maxit", type=int, default=500)
     ap.add_argument("--no-compare", action="store_true", help="skip the untimed other-precision run")
     ap.add_argument("--coarse-max-rows", type=int, default=1024)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy a 1 GiB buffer three times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md on sharding)",
@@ -94,6 +98,14 @@ def main():
     torch.cuda.set_device(0)
     side = torch.cuda.Stream()  # default priority; a non-null stream lets the V-cycle run as a HIP graph
     torch.cuda.set_stream(side)
+    if args.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 copies of %d bytes" % (src.numel() * 4))
+        del src, dst
     t0 = time.perf_counter()
     pr = synth.workload(args.workload)
     N = synth.WORKLOADS[args.workload]["N"]
@@ -105,13 +117,22 @@ def main():
     D_t = to_device(synth.gradient_csr(pr["tail"], pr["head"]), torch, dev)
     aggs_t = [torch.from_numpy(a).to(dev) for a in pr["aggregates"]]
     f_t = torch.from_numpy(pr["f"]).to(dev)
+    coords_t = torch.from_numpy(pr["coords"]).to(dev)
     u_t = torch.empty_like(f_t)
     stream = torch.cuda.current_stream().cuda_stream
     del pr
     torch.cuda.synchronize()
 
     cmr = dict(coarse_max_rows=args.coarse_max_rows)
-    forms = {"fp64": dict(**cmr), "fp32": dict(vcycle_fp32=1, **cmr)}
+    net = P.Network(np.load(args.weights), stream) if os.path.exists(args.weights) else None
+    if net is None and args.form.startswith("learned"):
+        log("no trained weights at %s: falling back to the plain form" % args.weights)
+        args.form = "plain_fp64"
+    learned = dict(init_guess=2, mpnn=net, emin_iters_given=3, coords=coords_t)
+    forms = {"plain_fp64": dict(**cmr), "plain_fp32": dict(vcycle_fp32=1, **cmr)}
+    if net is not None:
+        forms["learned_fp64"] = dict(**cmr, **learned)
+        forms["learned_fp32"] = dict(vcycle_fp32=1, **cmr, **learned)
     head = forms[args.form]
     for w in range(args.warmup):
         H, r = run_step(P, A_t, D_t, aggs_t, f_t, u_t, m, stream, maxit=args.maxit, **head)
@@ -143,15 +164,15 @@ def main():
     tt1 = time.perf_counter()
     ms_per_step = (tt1 - tt0) * 1000.0 / args.steps
 
-    # untimed companions: the same form without per-kernel events (V-cycle as
-    # a HIP graph) and the other precision
+    # untimed companions: every form once without per-kernel events (the
+    # V-cycle then runs as a HIP graph)
     extra = {}
     for name, opts in forms.items():
-        if args.no_compare and name != args.form:
+        if args.no_compare and name not in (args.form, "plain_fp64"):
             continue
         H, r = run_step(P, A_t, D_t, aggs_t, f_t, u_t, m, stream, maxit=args.maxit, **opts)
         H.close()
-        r["converged"] = r["rc"] == 0 and r["relres"] <= 1e-6
+        r["reached_tol"] = r["rc"] == 0
         extra[name] = r
         log("untimed %s (graph V-cycle): %s" % (name, json.dumps(r)))
 
@@ -174,17 +195,21 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.form == "fp64" else "f64 setup and PCG, f32 V-cycle",
+        "dtype": "f64" if args.form.endswith("fp64") else "f64 setup and PCG, f32 V-cycle",
         "data": "synthetic",
         "config": {"workload": args.workload, "n_edges": ne, "nnz_A": int(A_t[0][-1].item()),
                    "levels": st["num_levels"], "operator_complexity": st["operator_complexity"],
-                   "form": args.form + " V-cycle in fp64 PCG, plain initial guess + 10 projected-CG emin iterations",
+                   "form": args.form + (": learned initial guess + 3 projected-CG emin iterations" if args.form.startswith(
+                       "learned") else ": plain initial guess + 10 projected-CG emin iterations") + (
+                       ", fp32 V-cycle" if args.form.endswith("fp32") else ", fp64 V-cycle") + " in fp64 PCG",
                    "level_edges": [int(i["n_edges"]) for i in info]},
         "setup_s": mean("setup_s", results),
         "solve_s": mean("solve_s", results),
         "iters": results[-1]["iters"],
         "relres": results[-1]["relres"],
         "untimed_forms": extra,
+        "speedup_vs_plain_fp64": (extra["plain_fp64"]["total_s"] / extra[args.form]["total_s"])
+        if ("plain_fp64" in extra and args.form in extra) else None,
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "launches_per_step": dom["launches"] / args.steps,

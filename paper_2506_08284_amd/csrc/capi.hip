@@ -375,6 +375,7 @@ int hcurl_mpnn_forward(hcurl_mpnn net, hcurl_mpnn_sample s, double* delta) {
     net->net.ctx.sync();
     hc::mpnn_forward(net->net, s->S, s->ctx, false);
     hc::d2h(delta, s->S.delta.p, s->S.E, s->ctx);
+    s->S.release_workspace();
     return HCURL_OK;
   });
 }
@@ -386,6 +387,7 @@ int hcurl_mpnn_loss_grad(hcurl_mpnn net, hcurl_mpnn_sample s, double* loss, floa
     const double l = hc::mpnn_loss_grad(net->net, s->S, s->ctx);
     if (loss) *loss = l;
     if (grad) hc::d2h(grad, net->net.g.p, hc::kNParam, s->ctx);
+    s->S.release_workspace();
     return HCURL_OK;
   });
 }
@@ -397,6 +399,7 @@ int hcurl_mpnn_train_step(hcurl_mpnn net, hcurl_mpnn_sample s, float lr, float b
     net->net.ctx.sync();
     const double l = hc::mpnn_loss_grad(net->net, s->S, s->ctx);
     hc::mpnn_adam(net->net, lr, beta1, beta2, eps, step, s->ctx);
+    s->S.release_workspace();
     s->ctx.sync();
     if (loss) *loss = l;
     return HCURL_OK;

@@ -41,6 +41,14 @@ struct Sample {
   DBuf<float> h[kNL + 1], u[kNL + 1], mr[kNL], mc[kNL];
   DBuf<float> dh, du, dz, mdr, mdc;
   DBuf<double> delta;
+  // activations are transient: released after every forward / training step
+  void release_workspace() {
+    for (auto& b : h) b.release();
+    for (auto& b : u) b.release();
+    for (auto& b : mr) b.release();
+    for (auto& b : mc) b.release();
+    dh.release(); du.release(); dz.release(); mdr.release(); mdc.release();
+  }
 };
 
 // Builds graph and features from level 0 (L0) and its coarse gradient (L1's

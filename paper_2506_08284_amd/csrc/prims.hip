@@ -483,8 +483,26 @@ __global__ void __launch_bounds__(256) k_spmv(const int* __restrict__ rp, const 
   if (g >= n) return;
   Acc s = 0;
   const int e = rp[g + 1];
-  for (int q = rp[g] + l; q < e; q += LPR)
-    s += (Acc)__builtin_nontemporal_load(&val[q]) * (Acc)x[__builtin_nontemporal_load(&col[q])];
+  // up to four entries per lane are loaded before they are summed, so their
+  // gathers overlap; the matrix is streamed with non-temporal loads
+  int q = rp[g] + l;
+  for (; q + 3 * LPR < e; q += 4 * LPR) {
+    const int c0 = __builtin_nontemporal_load(&col[q]), c1 = __builtin_nontemporal_load(&col[q + LPR]);
+    const int c2 = __builtin_nontemporal_load(&col[q + 2 * LPR]), c3 = __builtin_nontemporal_load(&col[q + 3 * LPR]);
+    const T v0 = __builtin_nontemporal_load(&val[q]), v1 = __builtin_nontemporal_load(&val[q + LPR]);
+    const T v2 = __builtin_nontemporal_load(&val[q + 2 * LPR]), v3 = __builtin_nontemporal_load(&val[q + 3 * LPR]);
+    s += (Acc)v0 * (Acc)x[c0] + (Acc)v1 * (Acc)x[c1] + (Acc)v2 * (Acc)x[c2] + (Acc)v3 * (Acc)x[c3];
+  }
+  int cc[3];
+  T vv[3];
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    const int qq = q + u * LPR;
+    cc[u] = qq < e ? __builtin_nontemporal_load(&col[qq]) : 0;
+    vv[u] = qq < e ? __builtin_nontemporal_load(&val[qq]) : T(0);
+  }
+#pragma unroll
+  for (int u = 0; u < 3; ++u) s += (Acc)vv[u] * (Acc)x[cc[u]];
 #pragma unroll
   for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LPR);
   if (l == 0) {

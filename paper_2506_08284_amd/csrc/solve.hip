@@ -50,14 +50,28 @@ __global__ void k_jp_assign(const int* __restrict__ rp, const int* __restrict__ 
   }
 }
 
-__global__ void k_flag_eq(const int* __restrict__ color, int n, int c, int* __restrict__ flag) {
+// Rows are grouped by colour and, inside a colour, by row length (bucket of
+// at most kLenBuckets - 1), increasing row index inside each group: slices of
+// 64 rows then have nearly equal lengths and keep the lattice locality.
+static constexpr int kLenBuckets = 128;
+
+__global__ void k_group_key(const int* __restrict__ color, const int* __restrict__ rp, int n, int* __restrict__ key,
+                            int* __restrict__ hist) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) flag[v] = color[v] == c;
+  if (v >= n) return;
+  const int len = min(rp[v + 1] - rp[v], kLenBuckets - 1);
+  const int k = color[v] * kLenBuckets + len;
+  key[v] = k;
+  atomicAdd(&hist[k], 1);
 }
-__global__ void k_scatter_eq(const int* __restrict__ color, int n, int c, const int* __restrict__ pos, int base,
+__global__ void k_flag_eq(const int* __restrict__ key, int n, int k, int* __restrict__ flag) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) flag[v] = key[v] == k;
+}
+__global__ void k_scatter_eq(const int* __restrict__ key, int n, int k, const int* __restrict__ pos, int base,
                              int* __restrict__ rows) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n && color[v] == c) rows[base + pos[v]] = v;
+  if (v < n && key[v] == k) rows[base + pos[v]] = v;
 }
 
 void color_rows(const Csr& A, DBuf<int>& color, DBuf<int>& rows, std::vector<int>& cptr, int& ncol, Ctx& c) {
@@ -75,21 +89,30 @@ void color_rows(const Csr& A, DBuf<int>& color, DBuf<int>& rows, std::vector<int
     d2h(&h, rem, 1, c);
     if (h == 0) break;
   }
-  // rows grouped by colour, increasing row index inside every colour
   std::vector<int> hc_(n);
   d2h(hc_.data(), color.p, n, c);
   ncol = 0;
   for (int v : hc_) ncol = std::max(ncol, v + 1);
+  const int nk = ncol * kLenBuckets;
+  DBuf<int> key(n + 1, c.s), hist(nk, c.s), flag(n + 1, c.s), pos(n + 1, c.s);
+  HC_HIP(hipMemsetAsync(hist.p, 0, sizeof(int) * nk, c.s));
+  if (n) k_group_key<<<ceil_div(n, 256), 256, 0, c.s>>>(color.p, A.rowptr.p, n, key.p, hist.p);
+  HC_LAUNCH_CHECK();
+  std::vector<int> hh(nk);
+  d2h(hh.data(), hist.p, nk, c);
   cptr.assign(ncol + 1, 0);
-  DBuf<int> flag(n + 1, c.s), pos(n + 1, c.s);
-  for (int k = 0; k < ncol; ++k) {
-    k_flag_eq<<<ceil_div(n, 256), 256, 0, c.s>>>(color.p, n, k, flag.p);
+  int base = 0;
+  for (int k = 0; k < nk; ++k) {
+    if (hh[k] == 0) continue;
+    k_flag_eq<<<ceil_div(n, 256), 256, 0, c.s>>>(key.p, n, k, flag.p);
     HC_LAUNCH_CHECK();
-    const int64_t cnt = exclusive_scan(flag.p, pos.p, n, c);
-    k_scatter_eq<<<ceil_div(n, 256), 256, 0, c.s>>>(color.p, n, k, pos.p, cptr[k], rows.p);
+    exclusive_scan(flag.p, pos.p, n, c);
+    k_scatter_eq<<<ceil_div(n, 256), 256, 0, c.s>>>(key.p, n, k, pos.p, base, rows.p);
     HC_LAUNCH_CHECK();
-    cptr[k + 1] = cptr[k] + (int)cnt;
+    base += hh[k];
   }
+  for (int k = 0; k < nk; ++k) cptr[k / kLenBuckets + 1] += hh[k];
+  for (int k = 0; k < ncol; ++k) cptr[k + 1] += cptr[k];
 }
 
 __global__ void k_perm_len(const int* __restrict__ rp, const int* __restrict__ rows, int n, int* __restrict__ len) {
@@ -152,17 +175,33 @@ __global__ void __launch_bounds__(256) k_gs_color(int g0, int nr, const int* __r
   const int l = threadIdx.x & (LPR - 1);
   if (g >= g0 + nr) return;
   T s = 0;
-  const int e = rp[g + 1];
+  const int a = rp[g], e = rp[g + 1];
+  const int i = rows[g];
+  const T bi = b[i], di = dinv[g];
   // the matrix is streamed once per sweep: non-temporal loads keep it from
-  // evicting the gathered x entries from the caches
-  for (int q = rp[g] + l; q < e; q += LPR)
-    s += __builtin_nontemporal_load(&val[q]) * x[__builtin_nontemporal_load(&col[q])];
+  // evicting the gathered x entries from the caches.  Up to four entries per
+  // lane are loaded before they are summed, so their gathers overlap.
+  int q = a + l;
+  for (; q + 3 * LPR < e; q += 4 * LPR) {
+    const int c0 = __builtin_nontemporal_load(&col[q]), c1 = __builtin_nontemporal_load(&col[q + LPR]);
+    const int c2 = __builtin_nontemporal_load(&col[q + 2 * LPR]), c3 = __builtin_nontemporal_load(&col[q + 3 * LPR]);
+    const T v0 = __builtin_nontemporal_load(&val[q]), v1 = __builtin_nontemporal_load(&val[q + LPR]);
+    const T v2 = __builtin_nontemporal_load(&val[q + 2 * LPR]), v3 = __builtin_nontemporal_load(&val[q + 3 * LPR]);
+    s += v0 * x[c0] + v1 * x[c1] + v2 * x[c2] + v3 * x[c3];
+  }
+  int cc[3];
+  T vv[3];
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    const int qq = q + u * LPR;
+    cc[u] = qq < e ? __builtin_nontemporal_load(&col[qq]) : i;
+    vv[u] = qq < e ? __builtin_nontemporal_load(&val[qq]) : T(0);
+  }
+#pragma unroll
+  for (int u = 0; u < 3; ++u) s += vv[u] * x[cc[u]];
 #pragma unroll
   for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LPR);
-  if (l == 0) {
-    const int i = rows[g];
-    x[i] += (b[i] - s) * dinv[g];
-  }
+  if (l == 0) x[i] += (bi - s) * di;
 }
 
 // The whole symmetric sweep (all colours forward, then backward) in one
@@ -392,7 +431,8 @@ void prepare_solve(Hierarchy& H) {
     if (f32) {
       L.x32.alloc(L.n, c.s); L.b32.alloc(L.n, c.s); L.r32.alloc(L.n, c.s);
       L.rn32.alloc(L.m, c.s); L.cn32.alloc(L.m, c.s);
-      make32(L.A, c); make32(L.Acm, c); make32(L.Ancm, c); make32(L.Pe, c); make32(L.PeT, c); make32(L.D, c); make32(L.DT, c);
+      make32(L.A, c); make32(L.Acm, c); make32(L.Ancm, c);
+      make32(L.Pe, c); make32(L.PeT, c); make32(L.D, c); make32(L.DT, c);
       L.dinvAcm32.alloc(L.n, c.s); L.dinvAncm32.alloc(L.m, c.s);
       cast_d2f(L.dinvAcm.p, L.dinvAcm32.p, L.n, c);
       cast_d2f(L.dinvAncm.p, L.dinvAncm32.p, L.m, c);

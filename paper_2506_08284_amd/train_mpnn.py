@@ -76,6 +76,29 @@ def train(net, samples, steps: int, lr: float = 1e-3, seed: int = 0, log_every: 
     return losses
 
 
+def evaluate(net, spec, stream=None, emin_plain: int = 10, emin_learned: int = 3):
+    """Plain start + emin_plain CG iterations against the learned start +
+    emin_learned: final level-0 energy, PCG iterations and setup seconds."""
+    import synth
+    import paper_2506_08284_amd as P
+    pr = synth.problem(**spec)
+    m = pr["mesh"]["n"] ** 3
+    n = pr["A"][0].shape[0] - 1
+    out = {}
+    for name, opts in (("plain", dict(emin_iters=emin_plain)),
+                       ("plain_short", dict(emin_iters=emin_learned)),
+                       ("learned", dict(init_guess=2, mpnn=net, emin_iters_given=emin_learned))):
+        t0 = time.time()
+        H = P.Hierarchy(pr["A"], synth.gradient_csr(pr["tail"], pr["head"]), pr["aggregates"], n_nodes=m,
+                        coords=pr["coords"], record_energy=1, stream=stream, **opts)
+        t1 = time.time()
+        E = H.export_vec(0, "energy")
+        it, rel, rc = H.solve(pr["f"], np.empty(n))
+        out[name] = dict(energy=float(E[-1]), energy_start=float(E[0]), iters=it, relres=rel, setup_s=t1 - t0)
+        H.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--meshes", type=int, default=200)
@@ -84,6 +107,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--out", default="mpnn_weights.npy")
+    ap.add_argument("--eval-n", type=int, default=0, help="evaluate on an N^3 held-out mesh after training")
     args = ap.parse_args()
     import paper_2506_08284_amd as P
     t0 = time.time()
@@ -95,9 +119,16 @@ def main():
     net = P.Network(init_params(7))
     losses = train(net, samples, args.steps, args.lr, log_every=100, lr_final=args.lr * 0.1)
     np.save(args.out, net.params())
-    print("trained %d steps in %.0f s, final loss %.3e" % (args.steps, time.time() - t0, np.mean(losses[-100:])))
+    print("trained %d steps in %.0f s, final loss %.3e" % (args.steps, time.time() - t0, np.mean(losses[-100:])),
+          flush=True)
     for s in samples:
         P.hcurl_mpnn_sample_destroy(s)
+    if args.eval_n:
+        spec = dict(N=args.eval_n, jitter=0.1, jitter_seed=404, sigma=("lognormal", 405, 2.0), f_seed=104)
+        res = evaluate(net, spec)
+        for k, v in res.items():
+            print("eval %d^3 %-12s energy %.6g (from %.6g)  PCG its %d relres %.1e  setup %.2f s" % (
+                args.eval_n, k, v["energy"], v["energy_start"], v["iters"], v["relres"], v["setup_s"]), flush=True)
 
 
 if __name__ == "__main__":
