@@ -139,8 +139,9 @@ def main():
         log("warmup %s: %s" % (args.form, json.dumps(r)))
         H.close()
 
-    # timed region: K steps of the headline form, every kernel bracketed by HIP
-    # events on the library's stream (this disables the V-cycle graph)
+    # timed region: K steps of the headline form; every eagerly launched kernel
+    # is bracketed by HIP events on the library's stream (the V-cycle levels
+    # below the finest replay as one graph, timed as a whole)
     results = []
     kstats = {}
     torch.cuda.synchronize()
@@ -174,13 +175,14 @@ def main():
         H.close()
         r["reached_tol"] = r["rc"] == 0
         extra[name] = r
-        log("untimed %s (graph V-cycle): %s" % (name, json.dumps(r)))
+        log("untimed %s (whole V-cycle as a graph): %s" % (name, json.dumps(r)))
 
     top = sorted(kstats.items(), key=lambda kv: -kv[1]["ms"])
     for name, d in top[:14]:
         gbs = d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0
         log("kernel %-22s launches %7d  %9.2f ms/step  %8.1f GB/s" % (name, d["launches"], d["ms"] / args.steps, gbs))
-    dom_name, dom = top[0]
+    # graph replays are booked as one entry; the dominant kernel is a kernel
+    dom_name, dom = next((k, d) for k, d in top if not k.startswith("graph_"))
     achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
     mean = lambda key, rs: float(np.mean([x[key] for x in rs])) if rs else None
     value = mean("total_s", results)

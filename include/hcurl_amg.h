@@ -92,7 +92,10 @@ typedef struct {
   int vcycle_fp32;         /* 1: smoother and transfers in FP32 inside FP64 PCG */
   int power_iters;         /* power iterations for rho(D^-1 A^(n)), default 20 */
   int record_energy;       /* 1: measure 1/2 <P, A P> after every emin iteration */
-  int profile;             /* 1: time kernels with HIP events (hcurl_amg_kernel_stats) */
+  int profile;             /* 0: off.  1: time every eagerly launched kernel with HIP
+                              events (hcurl_amg_kernel_stats); on a non-null stream the
+                              V-cycle levels below the finest replay as one HIP graph,
+                              booked as "graph_coarse_levels".  2: as 1 with no graphs. */
   int mem_space;           /* HCURL_MEM_HOST or HCURL_MEM_DEVICE */
   void* stream;            /* hipStream_t */
 } hcurl_amg_opts;

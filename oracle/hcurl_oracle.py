@@ -590,12 +590,22 @@ def sgs(A: sp.csr_matrix, colors: np.ndarray, x: np.ndarray, b: np.ndarray) -> n
     return x
 
 
+def residual(lvl, x, b):
+    """b - A x.  A level of the FP32 V-cycle carries its FP64 operator as
+    "A_res": the residual is then formed in FP64 and stored in FP32 (see
+    vcycle_fp32)."""
+    A64 = lvl.get("A_res")
+    if A64 is None:
+        return b - lvl["A"] @ x
+    return (b.astype(np.float64) - A64 @ x.astype(np.float64)).astype(b.dtype)
+
+
 def hiptmair(lvl, x, b):
     """Hiptmair sweep (Sec. 6.1): SGS on A; SGS on D^T A D c = D^T r from c = 0;
     x += D c; SGS on A."""
     A, D = lvl["A"], lvl["D"]
     x = sgs(A, lvl["colors_A"], x, b)
-    r = b - A @ x
+    r = residual(lvl, x, b)
     c = sgs(lvl["An"], lvl["colors_An"], np.zeros(D.shape[1], x.dtype), D.T @ r)
     x = x + D @ c
     x = sgs(A, lvl["colors_A"], x, b)
@@ -652,25 +662,37 @@ def pcg(levels, f, tol: float = 1e-8, maxit: int = 500, precond=None, flexible: 
 
 def fp32_levels(levels):
     """FP32 copies of A_l, A^(n)_l, P_l for the single-precision V-cycle; the
-    coarsest Cholesky stays FP64."""
+    FP64 A_l is kept for residuals ("A_res") and the coarsest Cholesky stays
+    FP64."""
     out = []
     for lvl in levels[:-1]:
         l2 = dict(lvl)
         for k in ("A", "An", "Pe", "D"):
             l2[k] = lvl[k].astype(np.float32)
+        l2["A_res"] = lvl["A"]
         out.append(l2)
     out.append(levels[-1])
     return out
 
 
 def vcycle_fp32(levels32, b):
-    """V-cycle with float32 smoother and transfers; FP64 coarsest solve."""
+    """V-cycle with FP32 vectors, smoothers and transfers; FP64 coarsest solve.
+
+    Residuals b - A x are formed with the FP64 operator.  A gradient field
+    x = D phi is nearly free of energy in a low-conductivity region (S D = 0,
+    what remains is the sigma M part, of relative size sigma h^2), while
+    the rounding of an FP32 copy of A breaks S D = 0 at the level of FP32
+    epsilon times |S||x|.  Once sigma h^2 is far below that epsilon, a
+    residual formed with the FP32 copy is dominated by this noise, D^T of it
+    drives the nodal correction, and the cycle diverges.  With the FP64
+    operator the remaining noise comes from storing x in FP32; D^T removes
+    its curl part and the nodal correction stays accurate."""
     def rec(li, bb):
         if li == len(levels32) - 1:
             return sla.cho_solve(levels32[-1]["chol"], bb.astype(np.float64)).astype(np.float32)
         lvl = levels32[li]
         x = hiptmair(lvl, np.zeros_like(bb), bb)
-        r = bb - lvl["A"] @ x
+        r = residual(lvl, x, bb)
         xc = rec(li + 1, (lvl["Pe"].T @ r).astype(np.float32))
         x = x + lvl["Pe"] @ xc
         return hiptmair(lvl, x, bb)

@@ -56,9 +56,12 @@ struct Coarsest {
 
 struct Hierarchy {
   Ctx ctx;
-  hipGraphExec_t vgraph = nullptr;  // captured V-cycle on (pr -> pz)
+  hipGraphExec_t vgraph = nullptr;  // whole V-cycle on (pr -> pz)
+  hipGraphExec_t cgraph = nullptr;  // V-cycle of levels >= 1 on (lv[1].b -> lv[1].x)
+  bool capturing = false;
   ~Hierarchy() {
     if (vgraph) (void)hipGraphExecDestroy(vgraph);
+    if (cgraph) (void)hipGraphExecDestroy(cgraph);
   }
   hcurl_amg_opts opts{};
   std::vector<std::unique_ptr<Level>> lv;

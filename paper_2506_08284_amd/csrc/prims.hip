@@ -474,9 +474,10 @@ void spgemm(const Csr& A, const Csr& B, Csr& C, bool numeric, Ctx& c) {
 // ---------------------------------------------------------------------------
 // SpMV: LPR lanes per row, shuffle reduction inside the lane group
 // ---------------------------------------------------------------------------
-template <class T, class Acc, int LPR>
+// V: matrix value type, T: vector type, Acc: accumulation type
+template <class V, class T, class Acc, int LPR>
 __global__ void __launch_bounds__(256) k_spmv(const int* __restrict__ rp, const int* __restrict__ col,
-                                              const T* __restrict__ val, const T* __restrict__ x, T* __restrict__ y,
+                                              const V* __restrict__ val, const T* __restrict__ x, T* __restrict__ y,
                                               const T* __restrict__ b, int n, int mode) {
   const int g = (xcd_block(gridDim.x) * blockDim.x + threadIdx.x) / LPR;
   const int l = threadIdx.x & (LPR - 1);
@@ -489,17 +490,17 @@ __global__ void __launch_bounds__(256) k_spmv(const int* __restrict__ rp, const 
   for (; q + 3 * LPR < e; q += 4 * LPR) {
     const int c0 = __builtin_nontemporal_load(&col[q]), c1 = __builtin_nontemporal_load(&col[q + LPR]);
     const int c2 = __builtin_nontemporal_load(&col[q + 2 * LPR]), c3 = __builtin_nontemporal_load(&col[q + 3 * LPR]);
-    const T v0 = __builtin_nontemporal_load(&val[q]), v1 = __builtin_nontemporal_load(&val[q + LPR]);
-    const T v2 = __builtin_nontemporal_load(&val[q + 2 * LPR]), v3 = __builtin_nontemporal_load(&val[q + 3 * LPR]);
+    const V v0 = __builtin_nontemporal_load(&val[q]), v1 = __builtin_nontemporal_load(&val[q + LPR]);
+    const V v2 = __builtin_nontemporal_load(&val[q + 2 * LPR]), v3 = __builtin_nontemporal_load(&val[q + 3 * LPR]);
     s += (Acc)v0 * (Acc)x[c0] + (Acc)v1 * (Acc)x[c1] + (Acc)v2 * (Acc)x[c2] + (Acc)v3 * (Acc)x[c3];
   }
   int cc[3];
-  T vv[3];
+  V vv[3];
 #pragma unroll
   for (int u = 0; u < 3; ++u) {
     const int qq = q + u * LPR;
     cc[u] = qq < e ? __builtin_nontemporal_load(&col[qq]) : 0;
-    vv[u] = qq < e ? __builtin_nontemporal_load(&val[qq]) : T(0);
+    vv[u] = qq < e ? __builtin_nontemporal_load(&val[qq]) : V(0);
   }
 #pragma unroll
   for (int u = 0; u < 3; ++u) s += (Acc)vv[u] * (Acc)x[cc[u]];
@@ -512,29 +513,33 @@ __global__ void __launch_bounds__(256) k_spmv(const int* __restrict__ rp, const 
   }
 }
 
-template <class T, class Acc>
-static void spmv_t(const int* rp, const int* col, const T* val, int n, int64_t nnz, const T* x, T* y, const T* b, int mode,
+template <class V, class T, class Acc>
+static void spmv_t(const int* rp, const int* col, const V* val, int n, int64_t nnz, const T* x, T* y, const T* b, int mode,
                    Ctx& c, const char* tag) {
   if (n == 0) return;
   const double avg = (double)nnz / n;
-  const double bytes = (double)nnz * (4 + sizeof(T)) + 4.0 * (n + 1) + sizeof(T) * (2.0 * n + (mode ? n : 0));
+  const double bytes = (double)nnz * (4 + sizeof(V)) + 4.0 * (n + 1) + sizeof(T) * (2.0 * n + (mode ? n : 0));
+  const int64_t nb = n;
   if (avg <= 6)
-    c.run(tag, bytes, [&] { k_spmv<T, Acc, 4><<<ceil_div((int64_t)n * 4, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
+    c.run(tag, bytes, [&] { k_spmv<V, T, Acc, 4><<<ceil_div(nb * 4, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
   else if (avg <= 20)
-    c.run(tag, bytes, [&] { k_spmv<T, Acc, 8><<<ceil_div((int64_t)n * 8, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
+    c.run(tag, bytes, [&] { k_spmv<V, T, Acc, 8><<<ceil_div(nb * 8, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
   else if (avg <= 48)
-    c.run(tag, bytes, [&] { k_spmv<T, Acc, 16><<<ceil_div((int64_t)n * 16, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
+    c.run(tag, bytes, [&] { k_spmv<V, T, Acc, 16><<<ceil_div(nb * 16, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
   else if (avg <= 96)
-    c.run(tag, bytes, [&] { k_spmv<T, Acc, 32><<<ceil_div((int64_t)n * 32, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
+    c.run(tag, bytes, [&] { k_spmv<V, T, Acc, 32><<<ceil_div(nb * 32, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
   else
-    c.run(tag, bytes, [&] { k_spmv<T, Acc, 64><<<ceil_div((int64_t)n * 64, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
+    c.run(tag, bytes, [&] { k_spmv<V, T, Acc, 64><<<ceil_div(nb * 64, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
 }
 
 void spmv(const Csr& A, const double* x, double* y, const double* b, int mode, Ctx& c, const char* tag) {
-  spmv_t<double, double>(A.rowptr.p, A.col.p, A.val.p, A.nrows, A.nnz, x, y, b, mode, c, tag);
+  spmv_t<double, double, double>(A.rowptr.p, A.col.p, A.val.p, A.nrows, A.nnz, x, y, b, mode, c, tag);
 }
 void spmv32(const Csr& A, const float* x, float* y, const float* b, int mode, Ctx& c, const char* tag) {
-  spmv_t<float, float>(A.rowptr.p, A.col.p, A.val32.p, A.nrows, A.nnz, x, y, b, mode, c, tag);
+  spmv_t<float, float, double>(A.rowptr.p, A.col.p, A.val32.p, A.nrows, A.nnz, x, y, b, mode, c, tag);
+}
+void spmv_mixed(const Csr& A, const float* x, float* y, const float* b, int mode, Ctx& c, const char* tag) {
+  spmv_t<double, float, double>(A.rowptr.p, A.col.p, A.val.p, A.nrows, A.nnz, x, y, b, mode, c, tag);
 }
 
 // ---------------------------------------------------------------------------

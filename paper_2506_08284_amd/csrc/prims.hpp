@@ -24,6 +24,10 @@ void copy_csr(const Csr& A, Csr& B, Ctx& c);
 // y = A x   (mode 0), y = b - A x   (mode 1), y += A x (mode 2)
 void spmv(const Csr& A, const double* x, double* y, const double* b, int mode, Ctx& c, const char* tag = "spmv");
 void spmv32(const Csr& A, const float* x, float* y, const float* b, int mode, Ctx& c, const char* tag = "spmv32");
+// FP32 vectors, FP64 matrix values and accumulation: residuals b - A x of the
+// FP32 V-cycle, where A x of a large gradient field cancels (S D = 0) and an
+// FP32 copy of A would leave rounding noise far above the result.
+void spmv_mixed(const Csr& A, const float* x, float* y, const float* b, int mode, Ctx& c, const char* tag = "spmv_mixed");
 
 // Deterministic reductions into device scalars: scal[slot] = sum x*y.
 void dot(const double* x, const double* y, int64_t n, double* out, Ctx& c, int red_slot = 0);

@@ -308,7 +308,7 @@ static void hiptmair32(Level& L, bool fine, float* x, const float* b, Ctx& c) {
     else sgs_t<float, 0>(L.Acm, L.Acm.val32.p, L.dinvAcm32.p, L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, b, x, c, "sgs_edge32");
   };
   edge();
-  spmv32(L.A, x, L.r32.p, b, 1, c, fine ? "residual32_l0" : "residual32");
+  spmv_mixed(L.A, x, L.r32.p, b, 1, c, fine ? "residual32_l0" : "residual32");
   spmv32(L.DT, L.r32.p, L.rn32.p, nullptr, 0, c, "grad_transpose32");
   fill32(L.cn32.p, 0.0f, L.m, c);
   if (fine) sgs_t<float, 2>(L.Ancm, L.Ancm.val32.p, L.dinvAncm32.p, L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.rn32.p, L.cn32.p, c, "sgs_node32_l0");
@@ -316,6 +316,8 @@ static void hiptmair32(Level& L, bool fine, float* x, const float* b, Ctx& c) {
   c.run("grad_add32", 12.0 * L.n, [&] { k_grad_add<float><<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, L.n, L.cn32.p, x); });
   edge();
 }
+
+static void coarse_cycle(Hierarchy& H);
 
 static void vcycle64(Hierarchy& H, int l, const double* b, double* x) {
   Ctx& c = H.ctx;
@@ -331,7 +333,8 @@ static void vcycle64(Hierarchy& H, int l, const double* b, double* x) {
   hiptmair64(L, l == 0, x, b, c);
   spmv(L.A, x, L.r.p, b, 1, c, l == 0 ? "residual_l0" : "residual");
   spmv(L.PeT, L.r.p, N.b.p, nullptr, 0, c, "restrict");
-  vcycle64(H, l + 1, N.b.p, N.x.p);
+  if (l == 0) coarse_cycle(H);
+  else vcycle64(H, l + 1, N.b.p, N.x.p);
   spmv(L.Pe, N.x.p, x, nullptr, 2, c, "prolong");
   hiptmair64(L, l == 0, x, b, c);
 }
@@ -348,9 +351,10 @@ static void vcycle32(Hierarchy& H, int l, const float* b, float* x) {
   Level& N = *H.lv[l + 1];
   fill32(x, 0.0f, L.n, c);
   hiptmair32(L, l == 0, x, b, c);
-  spmv32(L.A, x, L.r32.p, b, 1, c, l == 0 ? "residual32_l0" : "residual32");
+  spmv_mixed(L.A, x, L.r32.p, b, 1, c, l == 0 ? "residual32_l0" : "residual32");
   spmv32(L.PeT, L.r32.p, N.b32.p, nullptr, 0, c, "restrict32");
-  vcycle32(H, l + 1, N.b32.p, N.x32.p);
+  if (l == 0) coarse_cycle(H);
+  else vcycle32(H, l + 1, N.b32.p, N.x32.p);
   spmv32(L.Pe, N.x32.p, x, nullptr, 2, c, "prolong32");
   hiptmair32(L, l == 0, x, b, c);
 }
@@ -367,31 +371,66 @@ static void vcycle_direct(Hierarchy& H, const double* r, double* z) {
   }
 }
 
-// The V-cycle issues the same kernels with the same arguments every time, so
-// on a non-null stream (and without per-kernel profiling) it is captured once
-// as a HIP graph for the PCG workspace (pr -> pz) and replayed.
+// Captures what `body` enqueues on the handle's stream as a graph (no
+// per-kernel events inside a capture).
+template <class F>
+static void capture_graph(Hierarchy& H, hipGraphExec_t* out, F&& body) {
+  Ctx& c = H.ctx;
+  const bool prof = c.profile;
+  hipGraph_t g = nullptr;
+  HC_HIP(hipStreamBeginCapture(c.s, hipStreamCaptureModeThreadLocal));
+  c.profile = false;
+  H.capturing = true;
+  try {
+    body();
+  } catch (...) {
+    c.profile = prof;
+    H.capturing = false;
+    (void)hipStreamEndCapture(c.s, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  c.profile = prof;
+  H.capturing = false;
+  HC_HIP(hipStreamEndCapture(c.s, &g));
+  hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HC_HIP(e);
+}
+
+static bool graphs_allowed(const Hierarchy& H) { return H.ctx.s != nullptr && H.opts.profile != 2; }
+
+// Levels >= 1 of the V-cycle (from lv[1].b into lv[1].x).  The coarse levels
+// are launch-bound (hundreds of short colour sweeps), and their kernels and
+// buffers are the same on every call, so on a non-null stream they are
+// captured once and replayed as one graph; the finest level stays eager.
+static void coarse_cycle(Hierarchy& H) {
+  Level& N = *H.lv[1];
+  const bool f32 = H.opts.vcycle_fp32 != 0;
+  auto body = [&] {
+    if (f32) vcycle32(H, 1, N.b32.p, N.x32.p);
+    else vcycle64(H, 1, N.b.p, N.x.p);
+  };
+  if (H.capturing || !graphs_allowed(H) || H.lv.size() < 3) {
+    body();
+    return;
+  }
+  if (!H.cgraph) capture_graph(H, &H.cgraph, body);
+  Ctx& c = H.ctx;
+  c.run("graph_coarse_levels", 0.0, [&] { HC_HIP(hipGraphLaunch(H.cgraph, c.s)); });
+}
+
+// Without per-kernel profiling on a non-null stream, the whole V-cycle of the
+// PCG workspace (pr -> pz) is captured once and replayed; otherwise level 0
+// runs eagerly and the coarse levels replay as a graph.
 void apply_vcycle(Hierarchy& H, const double* r, double* z) {
   Ctx& c = H.ctx;
-  const bool graphable = c.s != nullptr && !c.profile && r == H.pr.p && z == H.pz.p;
-  if (!graphable) {
+  const bool whole = graphs_allowed(H) && !c.profile && r == H.pr.p && z == H.pz.p;
+  if (!whole) {
     vcycle_direct(H, r, z);
     return;
   }
-  if (!H.vgraph) {
-    hipGraph_t g = nullptr;
-    HC_HIP(hipStreamBeginCapture(c.s, hipStreamCaptureModeThreadLocal));
-    try {
-      vcycle_direct(H, r, z);
-    } catch (...) {
-      (void)hipStreamEndCapture(c.s, &g);
-      if (g) (void)hipGraphDestroy(g);
-      throw;
-    }
-    HC_HIP(hipStreamEndCapture(c.s, &g));
-    hipError_t e = hipGraphInstantiate(&H.vgraph, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    HC_HIP(e);
-  }
+  if (!H.vgraph) capture_graph(H, &H.vgraph, [&] { vcycle_direct(H, r, z); });
   HC_HIP(hipGraphLaunch(H.vgraph, c.s));
 }
 
@@ -431,7 +470,7 @@ void prepare_solve(Hierarchy& H) {
     if (f32) {
       L.x32.alloc(L.n, c.s); L.b32.alloc(L.n, c.s); L.r32.alloc(L.n, c.s);
       L.rn32.alloc(L.m, c.s); L.cn32.alloc(L.m, c.s);
-      make32(L.A, c); make32(L.Acm, c); make32(L.Ancm, c);
+      make32(L.Acm, c); make32(L.Ancm, c);
       make32(L.Pe, c); make32(L.PeT, c); make32(L.D, c); make32(L.DT, c);
       L.dinvAcm32.alloc(L.n, c.s); L.dinvAncm32.alloc(L.m, c.s);
       cast_d2f(L.dinvAcm.p, L.dinvAcm32.p, L.n, c);
