@@ -89,7 +89,15 @@ typedef struct {
   int emin_iters_given;    /* level-0 iterations when init_guess is
                               HCURL_INIT_GIVEN or HCURL_INIT_MPNN (default 3) */
   const struct hcurl_mpnn_s* mpnn; /* network for HCURL_INIT_MPNN */
-  int vcycle_fp32;         /* 1: smoother and transfers in FP32 inside FP64 PCG */
+  int vcycle_fp32;         /* FP32 form of the V-cycle inside FP64 PCG: smoothers and
+                              transfers read FP32 copies of the operators, vectors
+                              are FP64 on level 0 and FP32 below, residuals use the
+                              FP64 operator, the coarsest solve is FP64.
+                              0: off (default).  1: only if FP32 epsilon (2^-23)
+                              times every smoothed level's cancellation_ratio is
+                              at most 10, else the V-cycle stays FP64
+                              (hcurl_amg_stats_t.vcycle_fp32 tells which).
+                              2: unconditionally. */
   int power_iters;         /* power iterations for rho(D^-1 A^(n)), default 20 */
   int record_energy;       /* 1: measure 1/2 <P, A P> after every emin iteration */
   int profile;             /* 0: off.  1: time every eagerly launched kernel with HIP
@@ -149,6 +157,10 @@ typedef struct {
   int64_t nnz_Pe, nnz_Pn, nnz_T, n_coarse_edges;
   int32_t n_colors_A, n_colors_An;
   double rho, omega;       /* power-iteration estimate and SA damping */
+  double cancellation_ratio; /* max over nodes u of (|D|^T|A||D| 1)_u / (D^T A D)_uu:
+                              the relative rounding error of A x for a gradient
+                              field x, in units of the precision of A (0 on the
+                              coarsest level) */
 } hcurl_level_info;
 
 int hcurl_amg_level_info(hcurl_amg h, int level, hcurl_level_info* info);
@@ -171,7 +183,9 @@ enum {
   HCURL_VEC_COLORS_A = 0,   /* int32[n] colour of every edge row            */
   HCURL_VEC_COLORS_AN = 1,  /* int32[m] colour of every node row            */
   HCURL_VEC_ENERGY = 2,     /* double[iters+1] energies (record_energy = 1) */
-  HCURL_VEC_LOCAL_PAIRS = 3 /* uint16[nnz_Pe] local tail | head << 8 in T_i */
+  HCURL_VEC_LOCAL_PAIRS = 3, /* uint16[nnz_Pe] local tail | head << 8 in T_i */
+  HCURL_VEC_PCG_HISTORY = 4  /* double[iters+1] recursive relative residuals of the
+                                last solve (level must be 0) */
 };
 int hcurl_amg_export_vec(hcurl_amg h, int level, int which, void* out, int64_t capacity_bytes);
 
@@ -183,6 +197,7 @@ typedef struct {
   double solve_ms;              /* wall time of the last solve */
   int last_iters;
   double last_relres;
+  int vcycle_fp32;              /* 1 if the FP32 form of the V-cycle is in use */
 } hcurl_amg_stats_t;
 
 int hcurl_amg_stats(hcurl_amg h, hcurl_amg_stats_t* s);

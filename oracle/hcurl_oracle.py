@@ -590,22 +590,12 @@ def sgs(A: sp.csr_matrix, colors: np.ndarray, x: np.ndarray, b: np.ndarray) -> n
     return x
 
 
-def residual(lvl, x, b):
-    """b - A x.  A level of the FP32 V-cycle carries its FP64 operator as
-    "A_res": the residual is then formed in FP64 and stored in FP32 (see
-    vcycle_fp32)."""
-    A64 = lvl.get("A_res")
-    if A64 is None:
-        return b - lvl["A"] @ x
-    return (b.astype(np.float64) - A64 @ x.astype(np.float64)).astype(b.dtype)
-
-
 def hiptmair(lvl, x, b):
     """Hiptmair sweep (Sec. 6.1): SGS on A; SGS on D^T A D c = D^T r from c = 0;
     x += D c; SGS on A."""
     A, D = lvl["A"], lvl["D"]
     x = sgs(A, lvl["colors_A"], x, b)
-    r = residual(lvl, x, b)
+    r = b - A @ x
     c = sgs(lvl["An"], lvl["colors_An"], np.zeros(D.shape[1], x.dtype), D.T @ r)
     x = x + D @ c
     x = sgs(A, lvl["colors_A"], x, b)
@@ -661,39 +651,66 @@ def pcg(levels, f, tol: float = 1e-8, maxit: int = 500, precond=None, flexible: 
 
 
 def fp32_levels(levels):
-    """FP32 copies of A_l, A^(n)_l, P_l for the single-precision V-cycle; the
-    FP64 A_l is kept for residuals ("A_res") and the coarsest Cholesky stays
-    FP64."""
+    """Operators of the FP32 V-cycle: FP32 copies of A_l, A^(n)_l, D_l^T and
+    P^(e)_l for smoothers and transfers, and A_l itself (FP64) for residuals;
+    the coarsest Cholesky stays FP64."""
     out = []
     for lvl in levels[:-1]:
-        l2 = dict(lvl)
-        for k in ("A", "An", "Pe", "D"):
-            l2[k] = lvl[k].astype(np.float32)
-        l2["A_res"] = lvl["A"]
-        out.append(l2)
+        out.append(dict(A=lvl["A"], A32=lvl["A"].astype(np.float32), An32=lvl["An"].astype(np.float32),
+                        DT32=lvl["D"].T.tocsr().astype(np.float32), Pe32=lvl["Pe"].astype(np.float32),
+                        dA=lvl["A"].diagonal(), dAn=lvl["An"].diagonal(),
+                        colors_A=lvl["colors_A"], colors_An=lvl["colors_An"], tail=lvl["tail"], head=lvl["head"]))
     out.append(levels[-1])
     return out
 
 
-def vcycle_fp32(levels32, b):
-    """V-cycle with FP32 vectors, smoothers and transfers; FP64 coarsest solve.
+def _sgs_f32op(A32, d, colors, x, b):
+    """SGS sweep with FP32 operator values; products and sums in the precision
+    of x, the update rounded to it."""
+    x = x.copy()
+    nc = int(colors.max()) + 1 if len(colors) else 0
+    groups = [np.nonzero(colors == c)[0] for c in range(nc)]
+    for rows in groups + groups[::-1]:
+        x[rows] = (x[rows] + (b[rows] - A32[rows] @ x) / d[rows]).astype(x.dtype)
+    return x
 
-    Residuals b - A x are formed with the FP64 operator.  A gradient field
-    x = D phi is nearly free of energy in a low-conductivity region (S D = 0,
-    what remains is the sigma M part, of relative size sigma h^2), while
-    the rounding of an FP32 copy of A breaks S D = 0 at the level of FP32
-    epsilon times |S||x|.  Once sigma h^2 is far below that epsilon, a
-    residual formed with the FP32 copy is dominated by this noise, D^T of it
-    drives the nodal correction, and the cycle diverges.  With the FP64
-    operator the remaining noise comes from storing x in FP32; D^T removes
-    its curl part and the nodal correction stays accurate."""
+
+def _f64_product(M, x, t):
+    """M x with every product and sum in FP64, rounded to type t."""
+    return (M.astype(np.float64) @ x.astype(np.float64)).astype(t)
+
+
+def _hiptmair_fp32(lvl, x, b):
+    t = x.dtype
+    x = _sgs_f32op(lvl["A32"], lvl["dA"], lvl["colors_A"], x, b)
+    r = (b.astype(np.float64) - lvl["A"] @ x.astype(np.float64)).astype(t)
+    rn = _f64_product(lvl["DT32"], r, t)
+    c = _sgs_f32op(lvl["An32"], lvl["dAn"], lvl["colors_An"], np.zeros(len(rn), t), rn)
+    x = x + (c[lvl["head"]] - c[lvl["tail"]])
+    return _sgs_f32op(lvl["A32"], lvl["dA"], lvl["colors_A"], x, b)
+
+
+def vcycle_fp32(levels32, b):
+    """V-cycle of the FP32 form: smoothers and transfers use FP32 operator
+    values; vectors are FP64 on the finest level and FP32 below; the coarsest
+    solve is FP64 and the output is FP64.
+
+    Residuals b - A x are formed with the FP64 operator.  In a region of small
+    conductivity a gradient field x = D phi carries energy of relative size
+    sigma h^2 only (S D = 0 leaves the sigma M part), while an FP32 copy of A
+    breaks S D = 0 at FP32 epsilon times |S||x|.  Once sigma h^2 falls below
+    that epsilon, a residual formed with the FP32 copy is rounding noise, D^T
+    of it drives the nodal correction and the cycle diverges.  Rounding the
+    finest-level vectors to FP32 adds the same kind of noise to the output
+    (slower PCG), so they stay FP64."""
     def rec(li, bb):
         if li == len(levels32) - 1:
             return sla.cho_solve(levels32[-1]["chol"], bb.astype(np.float64)).astype(np.float32)
         lvl = levels32[li]
-        x = hiptmair(lvl, np.zeros_like(bb), bb)
-        r = residual(lvl, x, bb)
-        xc = rec(li + 1, (lvl["Pe"].T @ r).astype(np.float32))
-        x = x + lvl["Pe"] @ xc
-        return hiptmair(lvl, x, bb)
-    return rec(0, b.astype(np.float32)).astype(np.float64)
+        t = bb.dtype
+        x = _hiptmair_fp32(lvl, np.zeros_like(bb), bb)
+        r = (bb.astype(np.float64) - lvl["A"] @ x.astype(np.float64)).astype(t)
+        xc = rec(li + 1, _f64_product(lvl["Pe32"].T.tocsr(), r, np.float32))
+        x = (x.astype(np.float64) + _f64_product(lvl["Pe32"], xc, np.float64)).astype(t)
+        return _hiptmair_fp32(lvl, x, bb)
+    return rec(0, np.asarray(b, dtype=np.float64))

@@ -20,7 +20,7 @@ HCURL_EUNSUPPORTED = -7
 
 MEM = {"host": 0, "device": 1}
 EXPORT = {"A": 0, "An": 1, "Pn": 2, "Pe": 3, "R": 4, "DH": 5, "P0": 6}
-VEC = {"colors_A": 0, "colors_An": 1, "energy": 2, "local_pairs": 3}
+VEC = {"colors_A": 0, "colors_An": 1, "energy": 2, "local_pairs": 3, "pcg_history": 4}
 
 # every function declared in include/hcurl_amg.h
 EXPORTED_SYMBOLS = [
@@ -51,12 +51,14 @@ class hcurl_level_info(ctypes.Structure):
     _fields_ = [("n_edges", ctypes.c_int64), ("n_nodes", ctypes.c_int64), ("nnz_A", ctypes.c_int64),
                 ("nnz_An", ctypes.c_int64), ("nnz_Pe", ctypes.c_int64), ("nnz_Pn", ctypes.c_int64),
                 ("nnz_T", ctypes.c_int64), ("n_coarse_edges", ctypes.c_int64), ("n_colors_A", ctypes.c_int32),
-                ("n_colors_An", ctypes.c_int32), ("rho", ctypes.c_double), ("omega", ctypes.c_double)]
+                ("n_colors_An", ctypes.c_int32), ("rho", ctypes.c_double), ("omega", ctypes.c_double),
+                ("cancellation_ratio", ctypes.c_double)]
 
 
 class hcurl_amg_stats_t(ctypes.Structure):
     _fields_ = [("num_levels", ctypes.c_int), ("operator_complexity", ctypes.c_double), ("setup_ms", ctypes.c_double),
-                ("solve_ms", ctypes.c_double), ("last_iters", ctypes.c_int), ("last_relres", ctypes.c_double)]
+                ("solve_ms", ctypes.c_double), ("last_iters", ctypes.c_int), ("last_relres", ctypes.c_double),
+                ("vcycle_fp32", ctypes.c_int)]
 
 
 class HcurlError(RuntimeError):
@@ -263,12 +265,14 @@ def hcurl_amg_export_vec(h, level: int, which: str, count: int | None = None):
         out = np.empty(count or 1024, np.float64)
     elif which == "local_pairs":
         out = np.empty(info["nnz_Pe"], np.uint16)
+    elif which == "pcg_history":
+        out = np.empty(count or (hcurl_amg_stats(h)["last_iters"] + 1), np.float64)
     else:
         raise ValueError(which)
     rc = lib.hcurl_amg_export_vec(h, level, VEC[which], _ptr(out), out.nbytes)
     if rc < 0:
         _check(rc)
-    if which == "energy":
+    if which in ("energy", "pcg_history"):
         return out[:rc]
     return out
 

@@ -42,6 +42,7 @@ struct Level {
   int maxJ = 0, maxNp = 0;
   int n_coarse = 0;
   double rho = 0.0, omega = 0.0;
+  double cancel = 0.0;  // max over nodes of (|D|^T |A| |D| 1)_u / (D^T A D)_uu
   std::vector<double> energy;
 
   // solve workspace
@@ -59,6 +60,7 @@ struct Hierarchy {
   hipGraphExec_t vgraph = nullptr;  // whole V-cycle on (pr -> pz)
   hipGraphExec_t cgraph = nullptr;  // V-cycle of levels >= 1 on (lv[1].b -> lv[1].x)
   bool capturing = false;
+  bool fp32 = false;  // the FP32 form of the V-cycle is in use
   ~Hierarchy() {
     if (vgraph) (void)hipGraphExecDestroy(vgraph);
     if (cgraph) (void)hipGraphExecDestroy(cgraph);
@@ -68,6 +70,7 @@ struct Hierarchy {
   Coarsest co;
   double setup_ms = 0.0, solve_ms = 0.0;
   int last_iters = 0;
+  std::vector<double> pcg_hist;  // recursive relative residuals of the last solve
   double last_relres = 0.0;
   DBuf<double> coords;  // level-0 node coordinates (m x 3) when given
   // PCG workspace (level 0, FP64)

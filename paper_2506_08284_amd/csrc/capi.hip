@@ -170,6 +170,7 @@ int hcurl_amg_level_info(hcurl_amg h, int level, hcurl_level_info* info) {
     info->n_colors_An = L->ncolAn;
     info->rho = L->rho;
     info->omega = L->omega;
+    info->cancellation_ratio = L->cancel;
     return HCURL_OK;
   });
 }
@@ -227,6 +228,13 @@ int hcurl_amg_export_vec(hcurl_amg h, int level, int which, void* out, int64_t c
         return (int)L->energy.size();
       }
       case HCURL_VEC_LOCAL_PAIRS: need(2LL * L->Pe.nnz); hc::d2h((uint16_t*)out, L->lpair.p, L->Pe.nnz, c); break;
+      case HCURL_VEC_PCG_HISTORY: {
+        if (level != 0) hc::fail(HCURL_EINVAL, "the PCG history belongs to level 0");
+        const auto& v = h->H.pcg_hist;
+        need(8LL * (int64_t)v.size());
+        std::memcpy(out, v.data(), 8 * v.size());
+        return (int)v.size();
+      }
       default: hc::fail(HCURL_EINVAL, "unknown vector");
     }
     return HCURL_OK;
@@ -244,6 +252,7 @@ int hcurl_amg_stats(hcurl_amg h, hcurl_amg_stats_t* s) {
   s->solve_ms = H.solve_ms;
   s->last_iters = H.last_iters;
   s->last_relres = H.last_relres;
+  s->vcycle_fp32 = H.fp32 ? 1 : 0;
   return HCURL_OK;
 }
 

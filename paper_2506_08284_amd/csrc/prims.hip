@@ -474,15 +474,16 @@ void spgemm(const Csr& A, const Csr& B, Csr& C, bool numeric, Ctx& c) {
 // ---------------------------------------------------------------------------
 // SpMV: LPR lanes per row, shuffle reduction inside the lane group
 // ---------------------------------------------------------------------------
-// V: matrix value type, T: vector type, Acc: accumulation type
-template <class V, class T, class Acc, int LPR>
+// V: matrix value type, X: input vector type, Y: output (and b) type; sums in
+// FP64.  mode 0: y = A x, 1: y = b - A x, 2: y += A x.
+template <class V, class X, class Y, int LPR>
 __global__ void __launch_bounds__(256) k_spmv(const int* __restrict__ rp, const int* __restrict__ col,
-                                              const V* __restrict__ val, const T* __restrict__ x, T* __restrict__ y,
-                                              const T* __restrict__ b, int n, int mode) {
+                                              const V* __restrict__ val, const X* __restrict__ x, Y* __restrict__ y,
+                                              const Y* __restrict__ b, int n, int mode) {
   const int g = (xcd_block(gridDim.x) * blockDim.x + threadIdx.x) / LPR;
   const int l = threadIdx.x & (LPR - 1);
   if (g >= n) return;
-  Acc s = 0;
+  double s = 0;
   const int e = rp[g + 1];
   // up to four entries per lane are loaded before they are summed, so their
   // gathers overlap; the matrix is streamed with non-temporal loads
@@ -492,7 +493,8 @@ __global__ void __launch_bounds__(256) k_spmv(const int* __restrict__ rp, const 
     const int c2 = __builtin_nontemporal_load(&col[q + 2 * LPR]), c3 = __builtin_nontemporal_load(&col[q + 3 * LPR]);
     const V v0 = __builtin_nontemporal_load(&val[q]), v1 = __builtin_nontemporal_load(&val[q + LPR]);
     const V v2 = __builtin_nontemporal_load(&val[q + 2 * LPR]), v3 = __builtin_nontemporal_load(&val[q + 3 * LPR]);
-    s += (Acc)v0 * (Acc)x[c0] + (Acc)v1 * (Acc)x[c1] + (Acc)v2 * (Acc)x[c2] + (Acc)v3 * (Acc)x[c3];
+    s += (double)v0 * (double)x[c0] + (double)v1 * (double)x[c1] + (double)v2 * (double)x[c2] +
+         (double)v3 * (double)x[c3];
   }
   int cc[3];
   V vv[3];
@@ -503,43 +505,53 @@ __global__ void __launch_bounds__(256) k_spmv(const int* __restrict__ rp, const 
     vv[u] = qq < e ? __builtin_nontemporal_load(&val[qq]) : V(0);
   }
 #pragma unroll
-  for (int u = 0; u < 3; ++u) s += (Acc)vv[u] * (Acc)x[cc[u]];
+  for (int u = 0; u < 3; ++u) s += (double)vv[u] * (double)x[cc[u]];
 #pragma unroll
   for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LPR);
   if (l == 0) {
-    if (mode == 0) y[g] = (T)s;
-    else if (mode == 1) y[g] = (T)((Acc)b[g] - s);
-    else y[g] = (T)((Acc)y[g] + s);
+    if (mode == 0) y[g] = (Y)s;
+    else if (mode == 1) y[g] = (Y)((double)b[g] - s);
+    else y[g] = (Y)((double)y[g] + s);
   }
 }
 
-template <class V, class T, class Acc>
-static void spmv_t(const int* rp, const int* col, const V* val, int n, int64_t nnz, const T* x, T* y, const T* b, int mode,
+template <class V, class X, class Y>
+static void spmv_t(const int* rp, const int* col, const V* val, int n, int64_t nnz, const X* x, Y* y, const Y* b, int mode,
                    Ctx& c, const char* tag) {
   if (n == 0) return;
   const double avg = (double)nnz / n;
-  const double bytes = (double)nnz * (4 + sizeof(V)) + 4.0 * (n + 1) + sizeof(T) * (2.0 * n + (mode ? n : 0));
+  const double bytes = (double)nnz * (4 + sizeof(V)) + 4.0 * (n + 1) + (double)n * (sizeof(X) + sizeof(Y)) +
+                       (mode ? (double)n * sizeof(Y) : 0.0);
   const int64_t nb = n;
   if (avg <= 6)
-    c.run(tag, bytes, [&] { k_spmv<V, T, Acc, 4><<<ceil_div(nb * 4, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
+    c.run(tag, bytes, [&] { k_spmv<V, X, Y, 4><<<ceil_div(nb * 4, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
   else if (avg <= 20)
-    c.run(tag, bytes, [&] { k_spmv<V, T, Acc, 8><<<ceil_div(nb * 8, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
+    c.run(tag, bytes, [&] { k_spmv<V, X, Y, 8><<<ceil_div(nb * 8, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
   else if (avg <= 48)
-    c.run(tag, bytes, [&] { k_spmv<V, T, Acc, 16><<<ceil_div(nb * 16, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
+    c.run(tag, bytes, [&] { k_spmv<V, X, Y, 16><<<ceil_div(nb * 16, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
   else if (avg <= 96)
-    c.run(tag, bytes, [&] { k_spmv<V, T, Acc, 32><<<ceil_div(nb * 32, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
+    c.run(tag, bytes, [&] { k_spmv<V, X, Y, 32><<<ceil_div(nb * 32, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
   else
-    c.run(tag, bytes, [&] { k_spmv<V, T, Acc, 64><<<ceil_div(nb * 64, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
+    c.run(tag, bytes, [&] { k_spmv<V, X, Y, 64><<<ceil_div(nb * 64, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
 }
 
+template <class X, class Y>
+void spmv_v64(const Csr& A, const X* x, Y* y, const Y* b, int mode, Ctx& c, const char* tag) {
+  spmv_t<double, X, Y>(A.rowptr.p, A.col.p, A.val.p, A.nrows, A.nnz, x, y, b, mode, c, tag);
+}
+template <class X, class Y>
+void spmv_v32(const Csr& A, const X* x, Y* y, const Y* b, int mode, Ctx& c, const char* tag) {
+  spmv_t<float, X, Y>(A.rowptr.p, A.col.p, A.val32.p, A.nrows, A.nnz, x, y, b, mode, c, tag);
+}
+template void spmv_v64<double, double>(const Csr&, const double*, double*, const double*, int, Ctx&, const char*);
+template void spmv_v64<float, float>(const Csr&, const float*, float*, const float*, int, Ctx&, const char*);
+template void spmv_v32<float, float>(const Csr&, const float*, float*, const float*, int, Ctx&, const char*);
+template void spmv_v32<double, float>(const Csr&, const double*, float*, const float*, int, Ctx&, const char*);
+template void spmv_v32<float, double>(const Csr&, const float*, double*, const double*, int, Ctx&, const char*);
+template void spmv_v32<double, double>(const Csr&, const double*, double*, const double*, int, Ctx&, const char*);
+
 void spmv(const Csr& A, const double* x, double* y, const double* b, int mode, Ctx& c, const char* tag) {
-  spmv_t<double, double, double>(A.rowptr.p, A.col.p, A.val.p, A.nrows, A.nnz, x, y, b, mode, c, tag);
-}
-void spmv32(const Csr& A, const float* x, float* y, const float* b, int mode, Ctx& c, const char* tag) {
-  spmv_t<float, float, double>(A.rowptr.p, A.col.p, A.val32.p, A.nrows, A.nnz, x, y, b, mode, c, tag);
-}
-void spmv_mixed(const Csr& A, const float* x, float* y, const float* b, int mode, Ctx& c, const char* tag) {
-  spmv_t<double, float, double>(A.rowptr.p, A.col.p, A.val.p, A.nrows, A.nnz, x, y, b, mode, c, tag);
+  spmv_v64<double, double>(A, x, y, b, mode, c, tag);
 }
 
 // ---------------------------------------------------------------------------

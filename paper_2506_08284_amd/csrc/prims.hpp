@@ -23,11 +23,15 @@ void copy_csr(const Csr& A, Csr& B, Ctx& c);
 
 // y = A x   (mode 0), y = b - A x   (mode 1), y += A x (mode 2)
 void spmv(const Csr& A, const double* x, double* y, const double* b, int mode, Ctx& c, const char* tag = "spmv");
-void spmv32(const Csr& A, const float* x, float* y, const float* b, int mode, Ctx& c, const char* tag = "spmv32");
-// FP32 vectors, FP64 matrix values and accumulation: residuals b - A x of the
-// FP32 V-cycle, where A x of a large gradient field cancels (S D = 0) and an
-// FP32 copy of A would leave rounding noise far above the result.
-void spmv_mixed(const Csr& A, const float* x, float* y, const float* b, int mode, Ctx& c, const char* tag = "spmv_mixed");
+// Mixed-precision forms (sums in FP64): A's FP64 values (spmv_v64) or its FP32
+// copy val32 (spmv_v32); instantiated for the vector types the FP32 V-cycle
+// uses.  The FP32 V-cycle forms residuals with spmv_v64: A x of a large
+// gradient field cancels (S D = 0), and the FP32 copy of A would leave
+// rounding noise far above the result.
+template <class X, class Y>
+void spmv_v64(const Csr& A, const X* x, Y* y, const Y* b, int mode, Ctx& c, const char* tag);
+template <class X, class Y>
+void spmv_v32(const Csr& A, const X* x, Y* y, const Y* b, int mode, Ctx& c, const char* tag);
 
 // Deterministic reductions into device scalars: scal[slot] = sum x*y.
 void dot(const double* x, const double* y, int64_t n, double* out, Ctx& c, int red_slot = 0);

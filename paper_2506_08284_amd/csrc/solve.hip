@@ -2,6 +2,7 @@
 // smoothing, V-cycle with a direct coarsest solve, preconditioned CG.
 #include <chrono>
 #include <cmath>
+#include <cstring>
 
 #include "amg.hpp"
 
@@ -165,9 +166,9 @@ void gather_vec(const double* x, const int* rows, double* y, int n, Ctx& c) {
 // matrix is the colour-major copy: the colour's rows are contiguous (g) and
 // rows[g] is the original row index, used for b and x.
 // ---------------------------------------------------------------------------
-template <class T, int LPR, int TAG>
+template <class V, class T, int LPR, int TAG>
 __global__ void __launch_bounds__(256) k_gs_color(int g0, int nr, const int* __restrict__ rows, const int* __restrict__ rp,
-                                                  const int* __restrict__ col, const T* __restrict__ val,
+                                                  const int* __restrict__ col, const V* __restrict__ val,
                                                   const T* __restrict__ dinv, const T* __restrict__ b, T* __restrict__ x) {
   // neighbouring row blocks share gathered x entries: give every XCD a
   // contiguous range of blocks so they meet in the same L2
@@ -185,20 +186,20 @@ __global__ void __launch_bounds__(256) k_gs_color(int g0, int nr, const int* __r
   for (; q + 3 * LPR < e; q += 4 * LPR) {
     const int c0 = __builtin_nontemporal_load(&col[q]), c1 = __builtin_nontemporal_load(&col[q + LPR]);
     const int c2 = __builtin_nontemporal_load(&col[q + 2 * LPR]), c3 = __builtin_nontemporal_load(&col[q + 3 * LPR]);
-    const T v0 = __builtin_nontemporal_load(&val[q]), v1 = __builtin_nontemporal_load(&val[q + LPR]);
-    const T v2 = __builtin_nontemporal_load(&val[q + 2 * LPR]), v3 = __builtin_nontemporal_load(&val[q + 3 * LPR]);
-    s += v0 * x[c0] + v1 * x[c1] + v2 * x[c2] + v3 * x[c3];
+    const V v0 = __builtin_nontemporal_load(&val[q]), v1 = __builtin_nontemporal_load(&val[q + LPR]);
+    const V v2 = __builtin_nontemporal_load(&val[q + 2 * LPR]), v3 = __builtin_nontemporal_load(&val[q + 3 * LPR]);
+    s += (T)v0 * x[c0] + (T)v1 * x[c1] + (T)v2 * x[c2] + (T)v3 * x[c3];
   }
   int cc[3];
-  T vv[3];
+  V vv[3];
 #pragma unroll
   for (int u = 0; u < 3; ++u) {
     const int qq = q + u * LPR;
     cc[u] = qq < e ? __builtin_nontemporal_load(&col[qq]) : i;
-    vv[u] = qq < e ? __builtin_nontemporal_load(&val[qq]) : T(0);
+    vv[u] = qq < e ? __builtin_nontemporal_load(&val[qq]) : V(0);
   }
 #pragma unroll
-  for (int u = 0; u < 3; ++u) s += vv[u] * x[cc[u]];
+  for (int u = 0; u < 3; ++u) s += (T)vv[u] * x[cc[u]];
 #pragma unroll
   for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LPR);
   if (l == 0) x[i] += (bi - s) * di;
@@ -206,10 +207,10 @@ __global__ void __launch_bounds__(256) k_gs_color(int g0, int nr, const int* __r
 
 // The whole symmetric sweep (all colours forward, then backward) in one
 // workgroup, for levels small enough that launches would dominate.
-template <class T, int LPR>
+template <class V, class T, int LPR>
 __global__ void __launch_bounds__(1024) k_gs_sweep_small(int ncol, const int* __restrict__ cptr,
                                                          const int* __restrict__ rows, const int* __restrict__ rp,
-                                                         const int* __restrict__ col, const T* __restrict__ val,
+                                                         const int* __restrict__ col, const V* __restrict__ val,
                                                          const T* __restrict__ dinv, const T* __restrict__ b,
                                                          T* __restrict__ x) {
   const int l = threadIdx.x & (LPR - 1);
@@ -220,7 +221,7 @@ __global__ void __launch_bounds__(1024) k_gs_sweep_small(int ncol, const int* __
     for (int g = cptr[k] + grp; g < cptr[k + 1]; g += NG) {
       T s = 0;
       const int e = rp[g + 1];
-      for (int q = rp[g] + l; q < e; q += LPR) s += val[q] * x[col[q]];
+      for (int q = rp[g] + l; q < e; q += LPR) s += (T)val[q] * x[col[q]];
 #pragma unroll
       for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LPR);
       if (l == 0) {
@@ -234,28 +235,29 @@ __global__ void __launch_bounds__(1024) k_gs_sweep_small(int ncol, const int* __
 
 static constexpr int kSmallLevel = 8192;
 
-// Algorithmic bytes of one colour launch: the rows' CSR data, their b, 1/a_ii
-// and x (read and write), counting every x entry once per sweep (ideal reuse
-// of the gathered neighbours).
-template <class T, int TAG>
-static void sgs_t(const Csr& A, const T* val, const T* dinv, const DBuf<int>& rows, const std::vector<int>& cptr,
+// Algorithmic bytes of one colour launch: the rows' CSR data (column and
+// value per entry, row pointer and original row index per row), their b,
+// 1/a_ii and x written, and every x entry gathered once per sweep (ideal reuse
+// of the gathered neighbours): nnz_c (4 + sizeof V) + rows_c (8 + 4 sizeof T).
+template <class V, class T, int TAG>
+static void sgs_t(const Csr& A, const V* val, const T* dinv, const DBuf<int>& rows, const std::vector<int>& cptr,
                   const DBuf<int>& cptr_d, int ncol, const T* b, T* x, Ctx& c, const char* tag) {
   const double avg = A.nrows ? (double)A.nnz / A.nrows : 0.0;
   if (A.nrows <= kSmallLevel) {
-    const double bytes = 2.0 * ((double)A.nnz * (4 + sizeof(T)) + (double)A.nrows * (8 + 4 + 4 * sizeof(T)));
-    c.run("sgs_small", bytes, [&] { k_gs_sweep_small<T, 8><<<1, 1024, 0, c.s>>>(ncol, cptr_d.p, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
+    const double bytes = 2.0 * ((double)A.nnz * (4 + sizeof(V)) + (double)A.nrows * (8 + 4 * sizeof(T)));
+    c.run("sgs_small", bytes, [&] { k_gs_sweep_small<V, T, 8><<<1, 1024, 0, c.s>>>(ncol, cptr_d.p, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
     return;
   }
   auto launch = [&](int k) {
     const int g0 = cptr[k], nr = cptr[k + 1] - cptr[k];
     if (!nr) return;
-    const double bytes = (double)nr * avg * (4 + sizeof(T)) + (double)nr * (8 + 4 + 4 * sizeof(T));
+    const double bytes = (double)nr * avg * (4 + sizeof(V)) + (double)nr * (8 + 4 * sizeof(T));
     if (avg <= 20)
-      c.run(tag, bytes, [&] { k_gs_color<T, 8, TAG><<<ceil_div((int64_t)nr * 8, 256), 256, 0, c.s>>>(g0, nr, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
+      c.run(tag, bytes, [&] { k_gs_color<V, T, 8, TAG><<<ceil_div((int64_t)nr * 8, 256), 256, 0, c.s>>>(g0, nr, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
     else if (avg <= 48)
-      c.run(tag, bytes, [&] { k_gs_color<T, 16, TAG><<<ceil_div((int64_t)nr * 16, 256), 256, 0, c.s>>>(g0, nr, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
+      c.run(tag, bytes, [&] { k_gs_color<V, T, 16, TAG><<<ceil_div((int64_t)nr * 16, 256), 256, 0, c.s>>>(g0, nr, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
     else
-      c.run(tag, bytes, [&] { k_gs_color<T, 32, TAG><<<ceil_div((int64_t)nr * 32, 256), 256, 0, c.s>>>(g0, nr, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
+      c.run(tag, bytes, [&] { k_gs_color<V, T, 32, TAG><<<ceil_div((int64_t)nr * 32, 256), 256, 0, c.s>>>(g0, nr, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
   };
   for (int k = 0; k < ncol; ++k) launch(k);
   for (int k = ncol - 1; k >= 0; --k) launch(k);
@@ -289,31 +291,60 @@ __global__ void __launch_bounds__(256) k_dense_apply(const double* __restrict__ 
 // the fine-level sweeps from the launch-bound coarse ones.
 static void hiptmair64(Level& L, bool fine, double* x, const double* b, Ctx& c) {
   auto edge = [&] {
-    if (fine) sgs_t<double, 1>(L.Acm, L.Acm.val.p, L.dinvAcm.p, L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, b, x, c, "sgs_edge_l0");
-    else sgs_t<double, 0>(L.Acm, L.Acm.val.p, L.dinvAcm.p, L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, b, x, c, "sgs_edge");
+    if (fine) sgs_t<double, double, 1>(L.Acm, L.Acm.val.p, L.dinvAcm.p, L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, b, x, c, "sgs_edge_l0");
+    else sgs_t<double, double, 0>(L.Acm, L.Acm.val.p, L.dinvAcm.p, L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, b, x, c, "sgs_edge");
   };
   edge();
   spmv(L.A, x, L.r.p, b, 1, c, fine ? "residual_l0" : "residual");
   spmv(L.DT, L.r.p, L.rn.p, nullptr, 0, c, "grad_transpose");
   fill(L.cn.p, 0.0, L.m, c);
-  if (fine) sgs_t<double, 2>(L.Ancm, L.Ancm.val.p, L.dinvAncm.p, L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.rn.p, L.cn.p, c, "sgs_node_l0");
-  else sgs_t<double, 0>(L.Ancm, L.Ancm.val.p, L.dinvAncm.p, L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.rn.p, L.cn.p, c, "sgs_node");
+  if (fine) sgs_t<double, double, 2>(L.Ancm, L.Ancm.val.p, L.dinvAncm.p, L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.rn.p, L.cn.p, c, "sgs_node_l0");
+  else sgs_t<double, double, 0>(L.Ancm, L.Ancm.val.p, L.dinvAncm.p, L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.rn.p, L.cn.p, c, "sgs_node");
   c.run("grad_add", 24.0 * L.n, [&] { k_grad_add<double><<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, L.n, L.cn.p, x); });
   edge();
 }
 
-static void hiptmair32(Level& L, bool fine, float* x, const float* b, Ctx& c) {
+// FP32 form of the V-cycle: smoothers and transfers read the FP32 copies of
+// the operators; vectors are FP64 on level 0 (T = double) and FP32 below
+// (T = float); residuals are formed with the FP64 operator (spmv_v64), since
+// the FP32 copy of A breaks S D = 0 by more than sigma M in low-conductivity
+// regions.  The V-cycle's output stays FP64.
+static inline void fill_t(double* x, double v, int64_t n, Ctx& c) { fill(x, v, n, c); }
+static inline void fill_t(float* x, float v, int64_t n, Ctx& c) { fill32(x, v, n, c); }
+
+template <class T>
+struct Vec32Form;
+template <>
+struct Vec32Form<double> {
+  static double* r(Level& L) { return L.r.p; }
+  static double* rn(Level& L) { return L.rn.p; }
+  static double* cn(Level& L) { return L.cn.p; }
+  static const double* dA(Level& L) { return L.dinvAcm.p; }
+  static const double* dAn(Level& L) { return L.dinvAncm.p; }
+};
+template <>
+struct Vec32Form<float> {
+  static float* r(Level& L) { return L.r32.p; }
+  static float* rn(Level& L) { return L.rn32.p; }
+  static float* cn(Level& L) { return L.cn32.p; }
+  static const float* dA(Level& L) { return L.dinvAcm32.p; }
+  static const float* dAn(Level& L) { return L.dinvAncm32.p; }
+};
+
+template <class T>
+static void hiptmair32(Level& L, bool fine, T* x, const T* b, Ctx& c) {
+  using F = Vec32Form<T>;
   auto edge = [&] {
-    if (fine) sgs_t<float, 1>(L.Acm, L.Acm.val32.p, L.dinvAcm32.p, L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, b, x, c, "sgs_edge32_l0");
-    else sgs_t<float, 0>(L.Acm, L.Acm.val32.p, L.dinvAcm32.p, L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, b, x, c, "sgs_edge32");
+    if (fine) sgs_t<float, T, 1>(L.Acm, L.Acm.val32.p, F::dA(L), L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, b, x, c, "sgs_edge32_l0");
+    else sgs_t<float, T, 0>(L.Acm, L.Acm.val32.p, F::dA(L), L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, b, x, c, "sgs_edge32");
   };
   edge();
-  spmv_mixed(L.A, x, L.r32.p, b, 1, c, fine ? "residual32_l0" : "residual32");
-  spmv32(L.DT, L.r32.p, L.rn32.p, nullptr, 0, c, "grad_transpose32");
-  fill32(L.cn32.p, 0.0f, L.m, c);
-  if (fine) sgs_t<float, 2>(L.Ancm, L.Ancm.val32.p, L.dinvAncm32.p, L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.rn32.p, L.cn32.p, c, "sgs_node32_l0");
-  else sgs_t<float, 0>(L.Ancm, L.Ancm.val32.p, L.dinvAncm32.p, L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.rn32.p, L.cn32.p, c, "sgs_node32");
-  c.run("grad_add32", 12.0 * L.n, [&] { k_grad_add<float><<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, L.n, L.cn32.p, x); });
+  spmv_v64<T, T>(L.A, x, F::r(L), b, 1, c, fine ? "residual32_l0" : "residual32");
+  spmv_v32<T, T>(L.DT, F::r(L), F::rn(L), nullptr, 0, c, "grad_transpose32");
+  fill_t(F::cn(L), T(0), L.m, c);
+  if (fine) sgs_t<float, T, 2>(L.Ancm, L.Ancm.val32.p, F::dAn(L), L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, F::rn(L), F::cn(L), c, "sgs_node32_l0");
+  else sgs_t<float, T, 0>(L.Ancm, L.Ancm.val32.p, F::dAn(L), L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, F::rn(L), F::cn(L), c, "sgs_node32");
+  c.run("grad_add32", (8.0 + 3.0 * sizeof(T)) * L.n, [&] { k_grad_add<T><<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, L.n, F::cn(L), x); });
   edge();
 }
 
@@ -339,33 +370,33 @@ static void vcycle64(Hierarchy& H, int l, const double* b, double* x) {
   hiptmair64(L, l == 0, x, b, c);
 }
 
-static void vcycle32(Hierarchy& H, int l, const float* b, float* x) {
+// Level l of the FP32 form (T = double on level 0, float below).
+template <class T>
+static void vcycle32(Hierarchy& H, int l, const T* b, T* x) {
   Ctx& c = H.ctx;
   if (l == (int)H.lv.size() - 1) {
     c.run("coarse_solve32", 8.0 * H.co.n * H.co.n, [&] {
-      k_dense_apply<float><<<ceil_div((int64_t)H.co.n * 64, 256), 256, 0, c.s>>>(H.co.inv.p, H.co.n, b, x);
+      k_dense_apply<T><<<ceil_div((int64_t)H.co.n * 64, 256), 256, 0, c.s>>>(H.co.inv.p, H.co.n, b, x);
     });
     return;
   }
   Level& L = *H.lv[l];
   Level& N = *H.lv[l + 1];
-  fill32(x, 0.0f, L.n, c);
-  hiptmair32(L, l == 0, x, b, c);
-  spmv_mixed(L.A, x, L.r32.p, b, 1, c, l == 0 ? "residual32_l0" : "residual32");
-  spmv32(L.PeT, L.r32.p, N.b32.p, nullptr, 0, c, "restrict32");
+  using F = Vec32Form<T>;
+  fill_t(x, T(0), L.n, c);
+  hiptmair32<T>(L, l == 0, x, b, c);
+  spmv_v64<T, T>(L.A, x, F::r(L), b, 1, c, l == 0 ? "residual32_l0" : "residual32");
+  spmv_v32<T, float>(L.PeT, F::r(L), N.b32.p, nullptr, 0, c, "restrict32");
   if (l == 0) coarse_cycle(H);
-  else vcycle32(H, l + 1, N.b32.p, N.x32.p);
-  spmv32(L.Pe, N.x32.p, x, nullptr, 2, c, "prolong32");
-  hiptmair32(L, l == 0, x, b, c);
+  else vcycle32<float>(H, l + 1, N.b32.p, N.x32.p);
+  spmv_v32<float, T>(L.Pe, N.x32.p, x, nullptr, 2, c, "prolong32");
+  hiptmair32<T>(L, l == 0, x, b, c);
 }
 
 static void vcycle_direct(Hierarchy& H, const double* r, double* z) {
   Ctx& c = H.ctx;
-  if (H.opts.vcycle_fp32 && H.lv.size() > 1) {
-    Level& L = *H.lv[0];
-    cast_d2f(r, L.b32.p, L.n, c);
-    vcycle32(H, 0, L.b32.p, L.x32.p);
-    cast_f2d(L.x32.p, z, L.n, c);
+  if (H.fp32 && H.lv.size() > 1) {
+    vcycle32<double>(H, 0, r, z);
   } else {
     vcycle64(H, 0, r, z);
   }
@@ -406,9 +437,9 @@ static bool graphs_allowed(const Hierarchy& H) { return H.ctx.s != nullptr && H.
 // captured once and replayed as one graph; the finest level stays eager.
 static void coarse_cycle(Hierarchy& H) {
   Level& N = *H.lv[1];
-  const bool f32 = H.opts.vcycle_fp32 != 0;
+  const bool f32 = H.fp32;
   auto body = [&] {
-    if (f32) vcycle32(H, 1, N.b32.p, N.x32.p);
+    if (f32) vcycle32<float>(H, 1, N.b32.p, N.x32.p);
     else vcycle64(H, 1, N.b.p, N.x.p);
   };
   if (H.capturing || !graphs_allowed(H) || H.lv.size() < 3) {
@@ -443,9 +474,72 @@ static void make32(Csr& A, Ctx& c) {
   cast_d2f(A.val.p, A.val32.p, A.nnz, c);
 }
 
+// Cancellation ratio of D^T A D at node u: (|D|^T |A| |D| 1)_u / (D^T A D)_uu
+// = 2 sum over the edges e at u of sum_j |a_ej|, over A^(n)_uu.  For a
+// gradient field x, A x = sigma M x while the terms summed are of size
+// |S||x|: an operator rounded with relative error u leaves an error of about
+// u times this ratio relative to the result.
+__global__ void k_abs_rowsum(const int* __restrict__ rp, const double* __restrict__ val, int n, double* __restrict__ s) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double t = 0.0;
+  for (int q = rp[i]; q < rp[i + 1]; ++q) t += fabs(val[q]);
+  s[i] = t;
+}
+__global__ void __launch_bounds__(256) k_cancel_max(const int* __restrict__ rp, const int* __restrict__ col, int m,
+                                                    const double* __restrict__ s, const double* __restrict__ dinv,
+                                                    unsigned long long* __restrict__ out) {
+  __shared__ double sh[4];
+  const int u = blockIdx.x * 256 + threadIdx.x;
+  double r = 0.0;
+  if (u < m) {
+    double t = 0.0;
+    for (int q = rp[u]; q < rp[u + 1]; ++q) t += s[col[q]];
+    const double d = dinv[u];
+    if (d > 0.0) r = 2.0 * t * d;
+  }
+  for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double b = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    // non-negative doubles order like their bit patterns
+    atomicMax(out, (unsigned long long)__double_as_longlong(b));
+  }
+}
+
+static double cancellation_ratio(Level& L, Ctx& c) {
+  if (L.n == 0 || L.m == 0) return 0.0;
+  constexpr int kSlot = 10;
+  unsigned long long* out = (unsigned long long*)(c.iscal.p + kSlot);
+  DBuf<double> s;
+  s.alloc(L.n, c.s);
+  HC_HIP(hipMemsetAsync(out, 0, sizeof(unsigned long long), c.s));
+  c.run("cancel_rowsum", 12.0 * L.A.nnz, [&] { k_abs_rowsum<<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.A.rowptr.p, L.A.val.p, L.n, s.p); });
+  c.run("cancel_max", 12.0 * L.DT.nnz, [&] {
+    k_cancel_max<<<ceil_div(L.m, 256), 256, 0, c.s>>>(L.DT.rowptr.p, L.DT.col.p, L.m, s.p, L.dinvAn.p, out);
+  });
+  unsigned long long bits = 0;
+  d2h(&bits, out, 1, c);
+  double r;
+  std::memcpy(&r, &bits, sizeof r);
+  s.release();
+  return r;
+}
+
+// The FP32 form rounds every operator of the smoothers to FP32; it is used
+// (opts.vcycle_fp32 = 1) only if FP32 machine epsilon (2^-23) times the
+// cancellation ratio stays at most kFp32Guard on every smoothed level, else
+// the V-cycle stays FP64.  opts.vcycle_fp32 = 2 uses it unconditionally.
+static constexpr double kFp32Guard = 10.0;
+
 void prepare_solve(Hierarchy& H) {
   Ctx& c = H.ctx;
-  const bool f32 = H.opts.vcycle_fp32 != 0;
+  for (size_t l = 0; l + 1 < H.lv.size(); ++l) H.lv[l]->cancel = cancellation_ratio(*H.lv[l], c);
+  bool ok = H.lv.size() > 1;
+  for (size_t l = 0; l + 1 < H.lv.size(); ++l) ok = ok && 0x1p-23 * H.lv[l]->cancel <= kFp32Guard;
+  H.fp32 = H.opts.vcycle_fp32 == 2 || (H.opts.vcycle_fp32 == 1 && ok);
+  const bool f32 = H.fp32;
   for (size_t l = 0; l < H.lv.size(); ++l) {
     Level& L = *H.lv[l];
     L.x.alloc(L.n, c.s);
@@ -468,13 +562,16 @@ void prepare_solve(Hierarchy& H) {
     L.rn.alloc(L.m, c.s);
     L.cn.alloc(L.m, c.s);
     if (f32) {
-      L.x32.alloc(L.n, c.s); L.b32.alloc(L.n, c.s); L.r32.alloc(L.n, c.s);
-      L.rn32.alloc(L.m, c.s); L.cn32.alloc(L.m, c.s);
+      // FP32 operator copies on every level; FP32 vectors below level 0
       make32(L.Acm, c); make32(L.Ancm, c);
-      make32(L.Pe, c); make32(L.PeT, c); make32(L.D, c); make32(L.DT, c);
-      L.dinvAcm32.alloc(L.n, c.s); L.dinvAncm32.alloc(L.m, c.s);
-      cast_d2f(L.dinvAcm.p, L.dinvAcm32.p, L.n, c);
-      cast_d2f(L.dinvAncm.p, L.dinvAncm32.p, L.m, c);
+      make32(L.Pe, c); make32(L.PeT, c); make32(L.DT, c);
+      if (l > 0) {
+        L.x32.alloc(L.n, c.s); L.b32.alloc(L.n, c.s); L.r32.alloc(L.n, c.s);
+        L.rn32.alloc(L.m, c.s); L.cn32.alloc(L.m, c.s);
+        L.dinvAcm32.alloc(L.n, c.s); L.dinvAncm32.alloc(L.m, c.s);
+        cast_d2f(L.dinvAcm.p, L.dinvAcm32.p, L.n, c);
+        cast_d2f(L.dinvAncm.p, L.dinvAncm32.p, L.m, c);
+      }
     }
   }
   const int n = H.lv[0]->n;
@@ -524,7 +621,7 @@ int pcg_solve(Hierarchy& H, const double* f, double* u, double rtol, int maxit, 
   Ctx& c = H.ctx;
   Level& L = *H.lv[0];
   const int64_t n = L.n;
-  const bool flex = H.opts.vcycle_fp32 != 0;
+  const bool flex = H.fp32;
   double* sc = c.scal.p;
   unsigned long long* bad = (unsigned long long*)(c.iscal.p + 9);
   HC_HIP(hipMemsetAsync(bad, 0, sizeof(unsigned long long), c.s));
@@ -538,6 +635,7 @@ int pcg_solve(Hierarchy& H, const double* f, double* u, double rtol, int maxit, 
   const double nf = std::sqrt(ff);
   int it = 0;
   double rel = 1.0;
+  H.pcg_hist.assign(1, nf == 0.0 ? 0.0 : 1.0);
   if (nf == 0.0) {
     d2d(u, H.px.p, n, c);
     if (iters) *iters = 0;
@@ -563,6 +661,7 @@ int pcg_solve(Hierarchy& H, const double* f, double* u, double rtol, int maxit, 
     d2h(&hb, bad, 1, c);
     if (hb) fail(HCURL_ENOTSPD, "PCG breakdown: <p, A p> <= 0");
     rel = std::sqrt(rr[0]) / nf;
+    H.pcg_hist.push_back(rel);
     if (rel <= rtol) break;
     if (flex) d2d(H.pzold.p, H.pz.p, n, c);
     apply_vcycle(H, H.pr.p, H.pz.p);

@@ -170,18 +170,58 @@ def test_fp32_vcycle_in_fp64_pcg():
     P = _lib()
     Dh = synth.gradient_csr(pr["tail"], pr["head"])
     H = P.Hierarchy(pr["A"], Dh, pr["aggregates"], n_nodes=m, vcycle_fp32=1)
+    assert H.stats()["vcycle_fp32"] == 1  # lognormal sigma: the guard admits FP32
     n = pr["A"][0].shape[0] - 1
     u = np.empty(n)
     it, rel, rc = H.solve(pr["f"], u, 1e-8, 500)
     it64, _, _ = H64.solve(pr["f"], np.empty(n), 1e-8, 500)
     assert rc == 0 and rel <= 1e-8
-    assert it <= it64 + 3
+    assert it <= it64 + 1
     l32 = O.fp32_levels(levels)
     r = np.random.default_rng(1).standard_normal(n)
     z = np.empty(n)
     H.vcycle(r, z)
     zo = O.vcycle_fp32(l32, r)
-    assert np.linalg.norm(z - zo) <= 2e-4 * np.linalg.norm(zo)
+    err = np.linalg.norm(z - zo) / np.linalg.norm(zo)
+    # FP32 sums of the coarse-level smoothers run in different orders on the
+    # two sides; level-0 vectors and all residuals are FP64
+    assert err <= 1e-5, err
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_cancellation_ratio(name):
+    """The per-level cancellation ratio that guards the FP32 form matches its
+    definition evaluated on the oracle's operators."""
+    pr, m, levels, H = _case(name)
+    for l, lv in enumerate(levels[:-1]):
+        k = H.level_info(l)["cancellation_ratio"]
+        ko = _cancellation_ratio(lv)
+        assert abs(k - ko) <= 1e-10 * ko, (l, k, ko)
+    assert H.level_info(len(levels) - 1)["cancellation_ratio"] == 0.0
+
+
+def test_fp32_guard_keeps_fp64_at_high_contrast():
+    """Contrast 1e6 on an 8^3 mesh: FP32 epsilon times the cancellation ratio
+    is far above 10, so vcycle_fp32 = 1 keeps the FP64 V-cycle (same
+    iterations and solution as the FP64 form), while vcycle_fp32 = 2 forces
+    the FP32 form, which still converges through the FP64 residuals."""
+    pr = synth.problem(8, sigma=("inclusions", 8, 1.0, 1e-6), f_seed=3)
+    m = 9 ** 3
+    P = _lib()
+    Dh = synth.gradient_csr(pr["tail"], pr["head"])
+    n = pr["A"][0].shape[0] - 1
+    H64 = P.Hierarchy(pr["A"], Dh, pr["aggregates"], n_nodes=m)
+    H1 = P.Hierarchy(pr["A"], Dh, pr["aggregates"], n_nodes=m, vcycle_fp32=1)
+    H2 = P.Hierarchy(pr["A"], Dh, pr["aggregates"], n_nodes=m, vcycle_fp32=2)
+    assert 2.0 ** -23 * H1.level_info(0)["cancellation_ratio"] > 10
+    assert H1.stats()["vcycle_fp32"] == 0 and H2.stats()["vcycle_fp32"] == 1
+    u64, u1, u2 = np.empty(n), np.empty(n), np.empty(n)
+    it64, _, rc64 = H64.solve(pr["f"], u64, 1e-8, 500)
+    it1, _, rc1 = H1.solve(pr["f"], u1, 1e-8, 500)
+    it2, _, rc2 = H2.solve(pr["f"], u2, 1e-8, 500)
+    assert rc64 == 0 and rc1 == 0 and rc2 == 0
+    assert it1 == it64 and np.array_equal(u1, u64)
+    assert it2 > it64
 
 
 def test_projected_jacobi_variant():
