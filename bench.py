@@ -47,6 +47,52 @@ def run_step(P, A_t, D_t, aggs_t, f_t, u_t, m, stream, maxit=1000, coords=None, 
                    vcycle_fp32=bool(H.stats()["vcycle_fp32"]))
 
 
+# The HBM traffic of the dominant kernel comes from rocprofv3 counter runs
+# (FETCH_SIZE and WRITE_SIZE, scaled by what the same counters read for a
+# 1 GiB device copy), stored in a profile summary together with a fingerprint
+# of the code that decides that kernel's traffic.  It is reported only while
+# that code is unchanged.
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "sgs_edge_l0_cube128_contrast_pmc.txt")
+TRAFFIC_CODE = [("paper_2506_08284_amd/csrc/solve.hip", "__global__ void __launch_bounds__(256) k_gs_color("),
+                ("paper_2506_08284_amd/csrc/solve.hip", "static void sgs_t("),
+                ("paper_2506_08284_amd/csrc/solve.hip", "void color_rows("),
+                ("paper_2506_08284_amd/csrc/solve.hip", "__global__ void k_group_key(")]
+
+
+def code_fingerprint() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for path, sig in TRAFFIC_CODE:
+        src = open(os.path.join(ROOT, path)).read()
+        a = src.index(sig)
+        depth, end = 0, None
+        for j in range(src.index("{", a), len(src)):
+            if src[j] == "{":
+                depth += 1
+            elif src[j] == "}":
+                depth -= 1
+                if depth == 0:
+                    end = j + 1
+                    break
+        h.update(src[a:end].encode())
+    return h.hexdigest()[:16]
+
+
+def pmc_traffic(kernel_tag: str, workload: str):
+    """Bytes per launch from the stored counter summary, or None when it does
+    not cover this kernel and workload or the code has changed since."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    kv = {}
+    for line in open(PMC_SUMMARY):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("tag") != kernel_tag or kv.get("workload") != workload or kv.get("code_fingerprint") != code_fingerprint():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(spec_name: str, n_full_edges: int, N_sample: int):
     """Oracle (numpy/scipy FP64, one thread) on a bounded sample of the same
     workload law, scaled to the full problem by edge count."""
@@ -225,7 +271,8 @@ def main():
         "speedup_vs_plain_fp64": (extra["plain_fp64"]["total_s"] / extra[args.form]["total_s"])
         if ("plain_fp64" in extra and args.form in extra) else None,
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": pmc_traffic(dom_name, args.workload),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)",
                      "launches_per_step": dom["launches"] / args.steps,
                      "bytes_per_launch": dom["bytes"] / dom["launches"],
                      "avg_launch_us": dom["ms"] * 1e3 / dom["launches"]},

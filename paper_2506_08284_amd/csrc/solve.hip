@@ -51,19 +51,16 @@ __global__ void k_jp_assign(const int* __restrict__ rp, const int* __restrict__ 
   }
 }
 
-// Rows are grouped by colour and, inside a colour, by row length (bucket of
-// at most kLenBuckets - 1), increasing row index inside each group: slices of
-// 64 rows then have nearly equal lengths and keep the lattice locality.
-static constexpr int kLenBuckets = 128;
-
-__global__ void k_group_key(const int* __restrict__ color, const int* __restrict__ rp, int n, int* __restrict__ key,
-                            int* __restrict__ hist) {
+// Rows are grouped by colour, in increasing row index inside a colour: the
+// rows of one launch then follow the lattice order, so neighbouring waves
+// gather overlapping parts of x (grouping by row length as well was measured
+// 20% slower on the finest level, because every length class sweeps the whole
+// domain again).
+__global__ void k_group_key(const int* __restrict__ color, int n, int* __restrict__ key, int* __restrict__ hist) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  const int len = min(rp[v + 1] - rp[v], kLenBuckets - 1);
-  const int k = color[v] * kLenBuckets + len;
-  key[v] = k;
-  atomicAdd(&hist[k], 1);
+  key[v] = color[v];
+  atomicAdd(&hist[color[v]], 1);
 }
 __global__ void k_flag_eq(const int* __restrict__ key, int n, int k, int* __restrict__ flag) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -94,10 +91,10 @@ void color_rows(const Csr& A, DBuf<int>& color, DBuf<int>& rows, std::vector<int
   d2h(hc_.data(), color.p, n, c);
   ncol = 0;
   for (int v : hc_) ncol = std::max(ncol, v + 1);
-  const int nk = ncol * kLenBuckets;
+  const int nk = ncol;
   DBuf<int> key(n + 1, c.s), hist(nk, c.s), flag(n + 1, c.s), pos(n + 1, c.s);
   HC_HIP(hipMemsetAsync(hist.p, 0, sizeof(int) * nk, c.s));
-  if (n) k_group_key<<<ceil_div(n, 256), 256, 0, c.s>>>(color.p, A.rowptr.p, n, key.p, hist.p);
+  if (n) k_group_key<<<ceil_div(n, 256), 256, 0, c.s>>>(color.p, n, key.p, hist.p);
   HC_LAUNCH_CHECK();
   std::vector<int> hh(nk);
   d2h(hh.data(), hist.p, nk, c);
@@ -112,7 +109,7 @@ void color_rows(const Csr& A, DBuf<int>& color, DBuf<int>& rows, std::vector<int
     HC_LAUNCH_CHECK();
     base += hh[k];
   }
-  for (int k = 0; k < nk; ++k) cptr[k / kLenBuckets + 1] += hh[k];
+  for (int k = 0; k < nk; ++k) cptr[k + 1] += hh[k];
   for (int k = 0; k < ncol; ++k) cptr[k + 1] += cptr[k];
 }
 
