@@ -55,8 +55,7 @@ def run_step(P, A_t, D_t, aggs_t, f_t, u_t, m, stream, maxit=1000, coords=None, 
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "sgs_edge_l0_cube128_contrast_pmc.txt")
 TRAFFIC_CODE = [("paper_2506_08284_amd/csrc/solve.hip", "__global__ void __launch_bounds__(256) k_gs_color("),
                 ("paper_2506_08284_amd/csrc/solve.hip", "static void sgs_t("),
-                ("paper_2506_08284_amd/csrc/solve.hip", "void color_rows("),
-                ("paper_2506_08284_amd/csrc/solve.hip", "__global__ void k_group_key(")]
+                ("paper_2506_08284_amd/csrc/solve.hip", "void color_rows(")]
 
 
 def code_fingerprint() -> str:
@@ -64,7 +63,9 @@ def code_fingerprint() -> str:
     h = hashlib.sha256()
     for path, sig in TRAFFIC_CODE:
         src = open(os.path.join(ROOT, path)).read()
-        a = src.index(sig)
+        a = src.find(sig)
+        if a < 0:
+            return "missing"
         depth, end = 0, None
         for j in range(src.index("{", a), len(src)):
             if src[j] == "{":

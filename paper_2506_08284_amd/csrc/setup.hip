@@ -515,7 +515,7 @@ __global__ void k_axpy_scalar(int64_t n, double* __restrict__ y, const double* _
 }
 
 // ---------------------------------------------------------------------------
-// coarsest level: dense Cholesky and explicit inverse (one workgroup)
+// coarsest level: explicit dense inverse
 // ---------------------------------------------------------------------------
 __global__ void k_to_dense(const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ val, int n,
                            double* __restrict__ M) {
@@ -523,41 +523,34 @@ __global__ void k_to_dense(const int* __restrict__ rp, const int* __restrict__ c
   if (i >= n) return;
   for (int q = rp[i]; q < rp[i + 1]; ++q) M[(size_t)i * n + col[q]] = val[q];
 }
-__global__ void __launch_bounds__(1024) k_chol_inverse(double* __restrict__ M, double* __restrict__ inv, int n,
-                                                       long long* __restrict__ iflags) {
-  __shared__ double piv;
-  // right-looking Cholesky, lower triangle of M
-  for (int j = 0; j < n; ++j) {
-    if (threadIdx.x == 0) {
-      double d = M[(size_t)j * n + j];
-      if (!(d > 0.0)) { iflags[F_NOTSPD] += 1; d = 1.0; }
-      piv = sqrt(d);
-      M[(size_t)j * n + j] = piv;
-    }
-    __syncthreads();
-    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) M[(size_t)i * n + j] /= piv;
-    __syncthreads();
-    const int m = n - j - 1;
-    for (int64_t t = threadIdx.x; t < (int64_t)m * m; t += blockDim.x) {
-      const int i = j + 1 + (int)(t / m), k = j + 1 + (int)(t % m);
-      if (k <= i) M[(size_t)i * n + k] -= M[(size_t)i * n + j] * M[(size_t)k * n + j];
-    }
-    __syncthreads();
+// In-place Gauss-Jordan inversion of the dense SPD matrix (no pivoting: the
+// pivots are the diagonals of successive Schur complements, positive for an
+// SPD matrix).  Step k: save column k, scale row k by 1/a_kk (with a_kk
+// replaced by 1), then a_ij -= a_ik a_kj for i != k (with a_ik replaced by 0).
+// After the n steps the matrix holds its inverse.
+__global__ void __launch_bounds__(1024) k_gj_pivot(double* __restrict__ M, int n, int k, double* __restrict__ colk,
+                                                   long long* __restrict__ iflags) {
+  const int t = threadIdx.x;
+  const double p = M[(size_t)k * n + k];
+  double rowv = 0.0, colv = 0.0;
+  if (t < n) {
+    colv = M[(size_t)t * n + k];
+    rowv = M[(size_t)k * n + t];
   }
-  // columns of the inverse: L L^T x = e_c
-  for (int c = threadIdx.x; c < n; c += blockDim.x) {
-    double* x = inv + (size_t)c;  // column c, stride n
-    for (int i = 0; i < n; ++i) {
-      double s = (i == c) ? 1.0 : 0.0;
-      for (int q = 0; q < i; ++q) s -= M[(size_t)i * n + q] * x[(size_t)q * n];
-      x[(size_t)i * n] = s / M[(size_t)i * n + i];
-    }
-    for (int i = n - 1; i >= 0; --i) {
-      double s = x[(size_t)i * n];
-      for (int q = i + 1; q < n; ++q) s -= M[(size_t)q * n + i] * x[(size_t)q * n];
-      x[(size_t)i * n] = s / M[(size_t)i * n + i];
-    }
+  __syncthreads();  // row and column k are read before either is written
+  const bool ok = p > 0.0;
+  if (t < n) {
+    colk[t] = colv;
+    M[(size_t)k * n + t] = (t == k ? 1.0 : rowv) / (ok ? p : 1.0);
   }
+  if (t == 0 && !ok) iflags[F_NOTSPD] += 1;
+}
+__global__ void __launch_bounds__(256) k_gj_eliminate(double* __restrict__ M, int n, int k, const double* __restrict__ colk) {
+  const int i = blockIdx.y;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (i == k || j >= n) return;
+  const size_t t = (size_t)i * n + j;
+  M[t] = (j == k ? 0.0 : M[t]) - colk[i] * M[(size_t)k * n + j];
 }
 
 // ---------------------------------------------------------------------------
@@ -744,12 +737,19 @@ static void coarsest_factor(Hierarchy& H, Level& L) {
   const int n = L.n;
   if (n > 1024) fail(HCURL_EUNSUPPORTED, "coarsest level has " + std::to_string(n) + " rows (limit 1024): provide more aggregate levels");
   H.co.n = n;
+  if (n == 0) return;
   clear_flag(F_NOTSPD, c);
-  DBuf<double> M((size_t)n * n, c.s);
   H.co.inv.alloc((size_t)n * n, c.s);
-  HC_HIP(hipMemsetAsync(M.p, 0, sizeof(double) * n * n, c.s));
-  c.run("coarse_dense", 12.0 * L.A.nnz, [&] { k_to_dense<<<ceil_div(n, 64), 64, 0, c.s>>>(L.A.rowptr.p, L.A.col.p, L.A.val.p, n, M.p); });
-  c.run("coarse_cholesky", 8.0 * n * n, [&] { k_chol_inverse<<<1, 1024, 0, c.s>>>(M.p, H.co.inv.p, n, c.iscal.p); });
+  DBuf<double> colk(n, c.s);
+  double* M = H.co.inv.p;
+  HC_HIP(hipMemsetAsync(M, 0, sizeof(double) * n * n, c.s));
+  c.run("coarse_dense", 12.0 * L.A.nnz, [&] { k_to_dense<<<ceil_div(n, 64), 64, 0, c.s>>>(L.A.rowptr.p, L.A.col.p, L.A.val.p, n, M); });
+  c.run("coarse_inverse", 16.0 * n * n * n, [&] {
+    for (int k = 0; k < n; ++k) {
+      k_gj_pivot<<<1, 1024, 0, c.s>>>(M, n, k, colk.p, c.iscal.p);
+      k_gj_eliminate<<<dim3(ceil_div(n, 256), n), 256, 0, c.s>>>(M, n, k, colk.p);
+    }
+  });
   if (read_flag(F_NOTSPD, c)) fail(HCURL_ENOTSPD, "coarsest operator is not positive definite");
 }
 

@@ -56,11 +56,26 @@ __global__ void k_jp_assign(const int* __restrict__ rp, const int* __restrict__ 
 // gather overlapping parts of x (grouping by row length as well was measured
 // 20% slower on the finest level, because every length class sweeps the whole
 // domain again).
-__global__ void k_group_key(const int* __restrict__ color, int n, int* __restrict__ key, int* __restrict__ hist) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  key[v] = color[v];
-  atomicAdd(&hist[color[v]], 1);
+// Rows per colour: a histogram in LDS per block (few colours would make
+// global atomics contend), added to the global counts once per block.
+static constexpr int kHistLds = 4096;
+__global__ void __launch_bounds__(256) k_group_key(const int* __restrict__ color, int n, int ncol, int* __restrict__ key,
+                                                   int* __restrict__ hist) {
+  __shared__ int h[kHistLds];
+  const bool lds = ncol <= kHistLds;
+  if (lds)
+    for (int k = threadIdx.x; k < ncol; k += 256) h[k] = 0;
+  __syncthreads();
+  for (int v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256) {
+    const int k = color[v];
+    key[v] = k;
+    if (lds) atomicAdd(&h[k], 1);
+    else atomicAdd(&hist[k], 1);
+  }
+  __syncthreads();
+  if (lds)
+    for (int k = threadIdx.x; k < ncol; k += 256)
+      if (h[k]) atomicAdd(&hist[k], h[k]);
 }
 __global__ void k_flag_eq(const int* __restrict__ key, int n, int k, int* __restrict__ flag) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -94,7 +109,7 @@ void color_rows(const Csr& A, DBuf<int>& color, DBuf<int>& rows, std::vector<int
   const int nk = ncol;
   DBuf<int> key(n + 1, c.s), hist(nk, c.s), flag(n + 1, c.s), pos(n + 1, c.s);
   HC_HIP(hipMemsetAsync(hist.p, 0, sizeof(int) * nk, c.s));
-  if (n) k_group_key<<<ceil_div(n, 256), 256, 0, c.s>>>(color.p, n, key.p, hist.p);
+  if (n) k_group_key<<<(int)std::min<int64_t>(ceil_div(n, 256), 2048), 256, 0, c.s>>>(color.p, n, ncol, key.p, hist.p);
   HC_LAUNCH_CHECK();
   std::vector<int> hh(nk);
   d2h(hh.data(), hist.p, nk, c);
