@@ -404,20 +404,148 @@ __global__ void k_collect_overflow(const int* __restrict__ cnt, int n, int* __re
   if (i < n && cnt[i] < 0) list[atomicAdd(nlist, 1)] = i;
 }
 
+// Short rows: when every row of A has at most 64 entries and at most 64
+// products, one wave handles a row with one product per lane.  The (column,
+// value) pairs are sorted over the wave by a bitonic network of lane
+// exchanges and equal columns are summed by a segmented scan, so no LDS table
+// is cleared or compacted per row and the sums run in a fixed order.
+__global__ void k_row_products(int nrows, const int* __restrict__ Arp, const int* __restrict__ Acol,
+                               const int* __restrict__ Brp, unsigned long long* __restrict__ maxes) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int prod = 0, len = 0;
+  if (i < nrows) {
+    const int a = Arp[i], e = Arp[i + 1];
+    len = e - a;
+    for (int q = a; q < e; ++q) {
+      const int k = Acol[q];
+      prod += Brp[k + 1] - Brp[k];
+    }
+  }
+  const int m = max(prod, len);
+  // one atomic per wave
+  int w = m;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) w = max(w, __shfl_xor(w, o, 64));
+  if ((threadIdx.x & 63) == 0 && w > 0) atomicMax(maxes, (unsigned long long)w);
+}
+
+template <bool FILL, bool NUMERIC>
+__global__ void __launch_bounds__(256) k_spgemm_wave(int nrows, const int* __restrict__ Arp, const int* __restrict__ Acol,
+                                                     const double* __restrict__ Aval, const int* __restrict__ Brp,
+                                                     const int* __restrict__ Bcol, const double* __restrict__ Bval,
+                                                     int* __restrict__ cnt, const int* __restrict__ Crp,
+                                                     int* __restrict__ Ccol, double* __restrict__ Cval) {
+  const int l = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= nrows) return;  // whole waves leave together
+  const int a0 = Arp[i], na = Arp[i + 1] - a0;  // na <= 64
+  int st = 0, len = 0;
+  double av = 0.0;
+  if (l < na) {
+    const int k = Acol[a0 + l];
+    if (NUMERIC) av = Aval[a0 + l];
+    st = Brp[k];
+    len = Brp[k + 1] - st;
+  }
+  const int incl = wave_incl_scan(len);
+  const int total = __shfl(incl, 63, 64);  // <= 64
+  const int pre = incl - len;
+  // owner of product l: the last lane q with pre[q] <= l (six halvings of 0..63)
+  int lo = 0, hi = 63;
+#pragma unroll
+  for (int it = 0; it < 6; ++it) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int pm = __shfl(pre, mid, 64);
+    if (pm <= l) lo = mid; else hi = mid - 1;
+  }
+  const int stq = __shfl(st, lo, 64), preq = __shfl(pre, lo, 64);
+  const double aq = __shfl(av, lo, 64);
+  int key = 0x7fffffff;
+  double v = 0.0;
+  if (l < total) {
+    const int pos = stq + (l - preq);
+    key = Bcol[pos];
+    if (NUMERIC) v = aq * Bval[pos];
+  }
+  // bitonic sort of (key, v) ascending over the 64 lanes
+#pragma unroll
+  for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const int pk = __shfl_xor(key, stride, 64);
+      const double pv = NUMERIC ? __shfl_xor(v, stride, 64) : 0.0;
+      const bool asc = (l & size) == 0;
+      const bool lower = (l & stride) == 0;
+      const bool take = (lower == asc) ? (pk < key) : (pk > key);
+      if (take) { key = pk; v = pv; }
+    }
+  }
+  // sum equal keys (contiguous after the sort): segmented inclusive scan
+  if (NUMERIC) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int pk = __shfl_up(key, o, 64);
+      const double pv = __shfl_up(v, o, 64);
+      if (l >= o && pk == key) v += pv;
+    }
+  }
+  const int nk = __shfl_down(key, 1, 64);
+  const bool tail = key != 0x7fffffff && (l == 63 || nk != key);
+  const unsigned long long tails = __ballot(tail);
+  if (!FILL) {
+    if (l == 0) cnt[i] = __popcll(tails);
+    return;
+  }
+  if (tail) {
+    const int r = Crp[i] + __popcll(tails & ((1ull << l) - 1ull));
+    Ccol[r] = key;
+    if (NUMERIC) Cval[r] = v;
+  }
+}
+
 static constexpr int kHtSmall = 512;
 static constexpr int kHtLarge = 2048;
 
-void spgemm(const Csr& A, const Csr& B, Csr& C, bool numeric, Ctx& c) {
+void spgemm(const Csr& A, const Csr& B, Csr& C, bool numeric, Ctx& c, const char* tag) {
   if (A.ncols != B.nrows) fail(HCURL_EINVAL, "spgemm: inner dimensions differ");
   numeric = numeric && A.val.p && B.val.p;
   C.nrows = A.nrows;
   C.ncols = B.ncols;
   C.rowptr.alloc(C.nrows + 1, c.s);
   DBuf<int> cnt(C.nrows + 1, c.s);
+  if (C.nrows) {
+    // short rows everywhere: the wave-sort path
+    unsigned long long* mx = (unsigned long long*)(c.iscal.p + 11);
+    HC_HIP(hipMemsetAsync(mx, 0, sizeof(unsigned long long), c.s));
+    k_row_products<<<ceil_div(A.nrows, 256), 256, 0, c.s>>>(A.nrows, A.rowptr.p, A.col.p, B.rowptr.p, mx);
+    HC_LAUNCH_CHECK();
+    unsigned long long hmax = 0;
+    d2h(&hmax, mx, 1, c);
+    if (hmax <= 64) {
+      const int nb = ceil_div(C.nrows, 4);
+      const std::string t = tag ? std::string(tag) : std::string("spgemm");
+      c.run((t + "_sym").c_str(), 12.0 * A.nnz, [&] {
+        k_spgemm_wave<false, false><<<nb, 256, 0, c.s>>>(C.nrows, A.rowptr.p, A.col.p, nullptr, B.rowptr.p, B.col.p, nullptr,
+                                                         cnt.p, nullptr, nullptr, nullptr);
+      });
+      C.nnz = exclusive_scan(cnt.p, C.rowptr.p, C.nrows, c);
+      C.col.alloc(C.nnz, c.s);
+      if (numeric) C.val.alloc(C.nnz, c.s); else C.val.release();
+      c.run((t + "_num").c_str(), 12.0 * A.nnz + 12.0 * C.nnz, [&] {
+        if (numeric)
+          k_spgemm_wave<true, true><<<nb, 256, 0, c.s>>>(C.nrows, A.rowptr.p, A.col.p, A.val.p, B.rowptr.p, B.col.p, B.val.p,
+                                                         nullptr, C.rowptr.p, C.col.p, C.val.p);
+        else
+          k_spgemm_wave<true, false><<<nb, 256, 0, c.s>>>(C.nrows, A.rowptr.p, A.col.p, nullptr, B.rowptr.p, B.col.p, nullptr,
+                                                          nullptr, C.rowptr.p, C.col.p, nullptr);
+      });
+      return;
+    }
+  }
   const int nb = std::max(1, std::min(C.nrows, 1 << 17));
   const double est_bytes = 12.0 * A.nnz + 8.0 * B.nnz;
   if (C.nrows)
-    c.run("spgemm_symbolic", est_bytes, [&] {
+    c.run(tag ? (std::string(tag) + "_sym").c_str() : "spgemm_symbolic", est_bytes, [&] {
       k_spgemm_count<kHtSmall><<<nb, 64, 0, c.s>>>(nullptr, 0, A.nrows, A.rowptr.p, A.col.p, B.rowptr.p, B.col.p, cnt.p);
     });
   // rows that overflowed the small table
@@ -445,7 +573,7 @@ void spgemm(const Csr& A, const Csr& B, Csr& C, bool numeric, Ctx& c) {
   if (numeric) C.val.alloc(C.nnz, c.s); else C.val.release();
   if (C.nrows) {
     if (numeric)
-      c.run("spgemm_numeric", est_bytes + 12.0 * C.nnz, [&] {
+      c.run(tag ? (std::string(tag) + "_num").c_str() : "spgemm_numeric", est_bytes + 12.0 * C.nnz, [&] {
         k_spgemm_fill<kHtSmall, true><<<nb, 64, 0, c.s>>>(nullptr, 0, A.nrows, A.rowptr.p, A.col.p, A.val.p, B.rowptr.p,
                                                           B.col.p, B.val.p, C.rowptr.p, C.col.p, C.val.p);
       });
@@ -484,15 +612,16 @@ __global__ void __launch_bounds__(256) k_spmv(const int* __restrict__ rp, const 
   const int l = threadIdx.x & (LPR - 1);
   if (g >= n) return;
   double s = 0;
-  const int e = rp[g + 1];
+  const int a = rp[g], e = rp[g + 1];
+  // padding slots gather x at the row's first column (a cached, local line);
+  // a fixed column would make one address hot for every wave of the grid
+  const int cpad = a < e ? col[a] : 0;
   // up to four entries per lane are loaded before they are summed, so their
-  // gathers overlap; the matrix is streamed with non-temporal loads
-  int q = rp[g] + l;
+  // gathers overlap (plain loads measured faster than non-temporal ones here)
+  int q = a + l;
   for (; q + 3 * LPR < e; q += 4 * LPR) {
-    const int c0 = __builtin_nontemporal_load(&col[q]), c1 = __builtin_nontemporal_load(&col[q + LPR]);
-    const int c2 = __builtin_nontemporal_load(&col[q + 2 * LPR]), c3 = __builtin_nontemporal_load(&col[q + 3 * LPR]);
-    const V v0 = __builtin_nontemporal_load(&val[q]), v1 = __builtin_nontemporal_load(&val[q + LPR]);
-    const V v2 = __builtin_nontemporal_load(&val[q + 2 * LPR]), v3 = __builtin_nontemporal_load(&val[q + 3 * LPR]);
+    const int c0 = col[q], c1 = col[q + LPR], c2 = col[q + 2 * LPR], c3 = col[q + 3 * LPR];
+    const V v0 = val[q], v1 = val[q + LPR], v2 = val[q + 2 * LPR], v3 = val[q + 3 * LPR];
     s += (double)v0 * (double)x[c0] + (double)v1 * (double)x[c1] + (double)v2 * (double)x[c2] +
          (double)v3 * (double)x[c3];
   }
@@ -501,8 +630,8 @@ __global__ void __launch_bounds__(256) k_spmv(const int* __restrict__ rp, const 
 #pragma unroll
   for (int u = 0; u < 3; ++u) {
     const int qq = q + u * LPR;
-    cc[u] = qq < e ? __builtin_nontemporal_load(&col[qq]) : 0;
-    vv[u] = qq < e ? __builtin_nontemporal_load(&val[qq]) : V(0);
+    cc[u] = qq < e ? col[qq] : cpad;
+    vv[u] = qq < e ? val[qq] : V(0);
   }
 #pragma unroll
   for (int u = 0; u < 3; ++u) s += (double)vv[u] * (double)x[cc[u]];

@@ -10,7 +10,7 @@ int64_t exclusive_scan(const int* in, int* out, int64_t n, Ctx& c);
 
 // C = A B on the symbolic pattern of |A||B| (structural zeros kept, columns
 // sorted).  numeric: also the values (A and B must carry values).
-void spgemm(const Csr& A, const Csr& B, Csr& C, bool numeric, Ctx& c);
+void spgemm(const Csr& A, const Csr& B, Csr& C, bool numeric, Ctx& c, const char* tag = nullptr);
 
 // AT = A^T with sorted columns; values copied when A has them and `values`.
 void transpose(const Csr& A, Csr& AT, bool values, Ctx& c);

@@ -758,8 +758,8 @@ static void level_operators(Hierarchy& H, Level& L) {
   Ctx& c = H.ctx;
   gradient_csr(L, c);
   Csr AD;
-  spgemm(L.A, L.D, AD, true, c);
-  spgemm(L.DT, AD, L.An, true, c);
+  spgemm(L.A, L.D, AD, true, c, "spgemm_AD");
+  spgemm(L.DT, AD, L.An, true, c, "spgemm_DtAD");
   L.dinvA.alloc(L.n, c.s);
   L.dinvAn.alloc(L.m, c.s);
   diagonal(L.A, L.dinvA.p, true, c);
@@ -817,7 +817,7 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
     Pbar.rowptr.alloc(L.m + 1, c.s); Pbar.col.alloc(L.m, c.s); Pbar.val.alloc(L.m, c.s);
     k_pbar<<<ceil_div(L.m + 1, 256), 256, 0, c.s>>>(agg.p, L.m, Pbar.rowptr.p, Pbar.col.p, Pbar.val.p);
     HC_LAUNCH_CHECK();
-    spgemm(L.An, Pbar, L.Pn, true, c);
+    spgemm(L.An, Pbar, L.Pn, true, c, "spgemm_AnPbar");
     c.run("sa_values", 12.0 * L.Pn.nnz, [&] {
       k_sa_values<<<ceil_div(L.m, 256), 256, 0, c.s>>>(L.Pn.rowptr.p, L.Pn.col.p, L.Pn.val.p, agg.p, L.dinvAn.p,
                                                        c.scal.p + S_OMEGA, L.m);
@@ -838,7 +838,7 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
     k_cross_fill<<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, agg.p, L.n, E.rowptr.p, E.col.p);
     HC_LAUNCH_CHECK();
     transpose(E, ET, false, c);
-    spgemm(ET, E, Z, false, c);
+    spgemm(ET, E, Z, false, c, "spgemm_EtE");
     DBuf<int> ucnt(mH + 1, c.s);
     tptr.alloc(mH + 1, c.s);
     k_upper_count<<<ceil_div(mH, 256), 256, 0, c.s>>>(Z.rowptr.p, Z.col.p, mH, ucnt.p);
@@ -853,7 +853,7 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
   }
   L.n_coarse = next->n;
   // T and R = D P^(n) on T
-  spgemm(L.D, L.Pn, L.R, true, c);
+  spgemm(L.D, L.Pn, L.R, true, c, "spgemm_DPn");
   // pattern N
   {
     for (int f = F_DISCONNECTED; f <= F_TOOBIG; ++f) clear_flag(f, c);
@@ -890,8 +890,8 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
   // Galerkin A_H = P^T A P
   {
     Csr AP;
-    spgemm(L.A, L.Pe, AP, true, c);
-    spgemm(L.PeT, AP, next->A, true, c);
+    spgemm(L.A, L.Pe, AP, true, c, "spgemm_AP");
+    spgemm(L.PeT, AP, next->A, true, c, "spgemm_PtAP");
   }
   L.has_transfer = true;
   return next;

@@ -34,9 +34,9 @@ __global__ void k_jp_select(const int* __restrict__ rp, const int* __restrict__ 
 __global__ void k_jp_assign(const int* __restrict__ rp, const int* __restrict__ col, int n, int* __restrict__ color,
                             unsigned long long* __restrict__ remaining) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  const int cv = color[v];
-  if (cv == -1) { atomicAdd(remaining, 1ULL); return; }
+  const int cv = v < n ? color[v] : 0;
+  // only "any vertex left" matters: one store per wave that has one
+  if (__any(cv == -1) && (threadIdx.x & 63) == 0) *remaining = 1ULL;
   if (cv != -2) return;
   for (int base = 0;; base += 64) {
     unsigned long long used = 0ull;
@@ -191,15 +191,13 @@ __global__ void __launch_bounds__(256) k_gs_color(int g0, int nr, const int* __r
   const int a = rp[g], e = rp[g + 1];
   const int i = rows[g];
   const T bi = b[i], di = dinv[g];
-  // the matrix is streamed once per sweep: non-temporal loads keep it from
-  // evicting the gathered x entries from the caches.  Up to four entries per
-  // lane are loaded before they are summed, so their gathers overlap.
+  // Up to four entries per lane are loaded before they are summed, so their
+  // gathers overlap; padding slots gather the row's own x entry (a local
+  // line).  Plain loads: non-temporal ones measured no faster here.
   int q = a + l;
   for (; q + 3 * LPR < e; q += 4 * LPR) {
-    const int c0 = __builtin_nontemporal_load(&col[q]), c1 = __builtin_nontemporal_load(&col[q + LPR]);
-    const int c2 = __builtin_nontemporal_load(&col[q + 2 * LPR]), c3 = __builtin_nontemporal_load(&col[q + 3 * LPR]);
-    const V v0 = __builtin_nontemporal_load(&val[q]), v1 = __builtin_nontemporal_load(&val[q + LPR]);
-    const V v2 = __builtin_nontemporal_load(&val[q + 2 * LPR]), v3 = __builtin_nontemporal_load(&val[q + 3 * LPR]);
+    const int c0 = col[q], c1 = col[q + LPR], c2 = col[q + 2 * LPR], c3 = col[q + 3 * LPR];
+    const V v0 = val[q], v1 = val[q + LPR], v2 = val[q + 2 * LPR], v3 = val[q + 3 * LPR];
     s += (T)v0 * x[c0] + (T)v1 * x[c1] + (T)v2 * x[c2] + (T)v3 * x[c3];
   }
   int cc[3];
@@ -207,8 +205,8 @@ __global__ void __launch_bounds__(256) k_gs_color(int g0, int nr, const int* __r
 #pragma unroll
   for (int u = 0; u < 3; ++u) {
     const int qq = q + u * LPR;
-    cc[u] = qq < e ? __builtin_nontemporal_load(&col[qq]) : i;
-    vv[u] = qq < e ? __builtin_nontemporal_load(&val[qq]) : V(0);
+    cc[u] = qq < e ? col[qq] : i;
+    vv[u] = qq < e ? val[qq] : V(0);
   }
 #pragma unroll
   for (int u = 0; u < 3; ++u) s += (T)vv[u] * x[cc[u]];
