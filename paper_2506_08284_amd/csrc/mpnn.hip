@@ -175,45 +175,131 @@ __device__ __forceinline__ float z_value(int64_t e, int k, const float* __restri
   return mc[(int64_t)col_of[e] * kHD + (k - 2 * kHD)];
 }
 
+// Persistent form of the dense layer: every block loads W^T once and then
+// takes 64-entry tiles in turn.  Each thread stages whole float4 pieces of
+// the Z rows (the h row, the row mean and the column mean are 16 float4 each),
+// all loaded before any is converted, so the tile costs one round of loads.
+// MODE 0: Z = features (K = 16).  MODE 1: Z = [h, mean_row, mean_col]
+// (K = 192), output h + silu(Z W + b).  MODE 2: as MODE 1, and the head
+// delta = h_out . w_out + b_out is formed in place of writing h_out.
 template <int K, int MODE>
-__global__ void __launch_bounds__(256) k_mpnn_fwd(int64_t E, const float* __restrict__ X, const float* __restrict__ hin,
-                                                  const float* __restrict__ mr, const float* __restrict__ mc,
-                                                  const int* __restrict__ row_of, const int* __restrict__ col_of,
-                                                  const uint16_t* __restrict__ Wt, const float* __restrict__ bias,
-                                                  float* __restrict__ U, float* __restrict__ hout) {
-  __shared__ __attribute__((aligned(16))) uint16_t Zs[64][K + 8];
-  __shared__ __attribute__((aligned(16))) uint16_t Ws[64][K + 8];
-  const int t = threadIdx.x;
-  const int64_t e0 = (int64_t)blockIdx.x * 64;
-  for (int q = t; q < 64 * K; q += 256) Ws[q / K][q % K] = Wt[q];
-  for (int q = t; q < 64 * K; q += 256) {
-    const int r = q / K, k = q % K;
+__device__ __forceinline__ void layer_load(int64_t E, int64_t e0, int t, const float* __restrict__ X,
+                                           const float* __restrict__ hin, const float* __restrict__ mr,
+                                           const float* __restrict__ mc, const int* __restrict__ row_of,
+                                           const int* __restrict__ col_of, float4* v) {
+  constexpr int F4 = K / 4;
+  constexpr int PER = 64 * F4 / 256;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int j = t + 256 * u;
+    const int r = j / F4, c4 = j - r * F4;
     const int64_t e = e0 + r;
-    Zs[r][k] = f2bf(e < E ? z_value<K, MODE>(e, k, X, hin, mr, mc, row_of, col_of) : 0.0f);
-  }
-  __syncthreads();
-  const int w = t >> 6, l = t & 63;
-  const int mt = w >> 1, nt = w & 1;
-  f32x16 acc;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-#pragma unroll
-  for (int kk = 0; kk < K; kk += 8) {
-    const bf16x4 a = *(const bf16x4*)&Zs[mt * 32 + (l & 31)][kk + 4 * (l >> 5)];
-    const bf16x4 b = *(const bf16x4*)&Ws[nt * 32 + (l & 31)][kk + 4 * (l >> 5)];
-    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
-  }
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int row = mt * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
-    const int col = nt * 32 + (l & 31);
-    const int64_t e = e0 + row;
+    v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (e < E) {
-      const float u = acc[r] + bias[col];
-      if (U) U[e * kHD + col] = u;
-      hout[e * kHD + col] = (MODE ? hin[e * kHD + col] : 0.0f) + silu_f(u);
+      const float* src;
+      if (MODE == 0) {
+        src = X + e * K + c4 * 4;
+      } else {
+        const int seg = c4 >> 4, f = (c4 & 15) * 4;
+        src = seg == 0 ? hin + e * kHD + f
+                       : seg == 1 ? mr + (int64_t)row_of[e] * kHD + f : mc + (int64_t)col_of[e] * kHD + f;
+      }
+      v[u] = *(const float4*)src;
     }
   }
+}
+
+// Persistent form of the dense layer: every block loads W^T once and then
+// takes 64-entry tiles in turn.  Each thread stages whole float4 pieces of
+// the Z rows (the h row, the row mean and the column mean are 16 float4 each);
+// the pieces of the next tile are loaded while the current one is multiplied,
+// and the FP32 h rows of the tile stay in LDS for the residual term.
+// MODE 0: Z = features (K = 16).  MODE 1: Z = [h, mean_row, mean_col]
+// (K = 192), output h + silu(Z W + b).  MODE 2: as MODE 1, and the head
+// delta = h_out . w_out + b_out is formed in place of writing h_out.
+template <int K, int MODE>
+__global__ void __launch_bounds__(256) k_mpnn_layer(int64_t E, const float* __restrict__ X, const float* __restrict__ hin,
+                                                    const float* __restrict__ mr, const float* __restrict__ mc,
+                                                    const int* __restrict__ row_of, const int* __restrict__ col_of,
+                                                    const uint16_t* __restrict__ Wt, const float* __restrict__ bias,
+                                                    const float* __restrict__ wout, float* __restrict__ U,
+                                                    float* __restrict__ hout, double* __restrict__ delta) {
+  constexpr int KP = K + 8;
+  constexpr int F4 = K / 4;
+  constexpr int PER = 64 * F4 / 256;
+  static_assert((64 * F4) % 256 == 0, "tile staging");
+  constexpr int HR = MODE ? 64 : 1;
+  __shared__ __attribute__((aligned(16))) uint16_t Zs[64][KP];
+  __shared__ __attribute__((aligned(16))) uint16_t Ws[64][KP];
+  __shared__ __attribute__((aligned(16))) float Hs[HR][kHD + 4];
+  __shared__ float red[64][2];
+  const int t = threadIdx.x;
+  for (int q = t; q < 64 * K; q += 256) Ws[q / K][q % K] = Wt[q];
+  const int w = t >> 6, l = t & 63;
+  const int mt = w >> 1, nt = w & 1;
+  const int col = nt * 32 + (l & 31);
+  const float bcol = bias[col];
+  const float wcol = MODE == 2 ? wout[col] : 0.0f;
+  const float bout = MODE == 2 ? wout[kHD] : 0.0f;
+  const int64_t ntiles = (E + 63) / 64;
+  float4 v[PER];
+  int64_t tile = blockIdx.x;
+  if (tile < ntiles) layer_load<K, MODE>(E, tile * 64, t, X, hin, mr, mc, row_of, col_of, v);
+  for (; tile < ntiles; tile += gridDim.x) {
+    const int64_t e0 = tile * 64;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int j = t + 256 * u;
+      const int r = j / F4, c4 = j - r * F4;
+      bf16x4 b;
+      b[0] = (short)f2bf(v[u].x);
+      b[1] = (short)f2bf(v[u].y);
+      b[2] = (short)f2bf(v[u].z);
+      b[3] = (short)f2bf(v[u].w);
+      *(bf16x4*)&Zs[r][c4 * 4] = b;
+      if (MODE && c4 < 16) *(float4*)&Hs[r][c4 * 4] = v[u];
+    }
+    __syncthreads();
+    // next tile's pieces are in flight during the products and the epilogue
+    const int64_t next = tile + gridDim.x;
+    if (next < ntiles) layer_load<K, MODE>(E, next * 64, t, X, hin, mr, mc, row_of, col_of, v);
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+#pragma unroll
+    for (int kk = 0; kk < K; kk += 8) {
+      const bf16x4 a = *(const bf16x4*)&Zs[mt * 32 + (l & 31)][kk + 4 * (l >> 5)];
+      const bf16x4 b = *(const bf16x4*)&Ws[nt * 32 + (l & 31)][kk + 4 * (l >> 5)];
+      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = mt * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+      const int64_t e = e0 + row;
+      const bool ok = e < E;
+      const float u = acc[r] + bcol;
+      const float hv = (MODE ? Hs[MODE ? row : 0][col] : 0.0f) + silu_f(u);
+      if (MODE == 2) {
+        float d = ok ? hv * wcol : 0.0f;
+#pragma unroll
+        for (int o = 16; o > 0; o >>= 1) d += __shfl_xor(d, o, 32);
+        if ((l & 31) == 0) red[row][nt] = d;
+      } else if (ok) {
+        if (U) U[e * kHD + col] = u;
+        hout[e * kHD + col] = hv;
+      }
+    }
+    if (MODE == 2) {
+      __syncthreads();
+      if (t < 64 && e0 + t < E) delta[e0 + t] = (double)(red[t][0] + red[t][1] + bout);
+    }
+    __syncthreads();
+  }
+}
+
+static int layer_grid(int64_t E) {
+  const int64_t tiles = (E + 63) / 64;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, 256 * 2));
 }
 
 // dZ = du W^T: du (E x 64), W (192 x 64) bf16 row-major, dz (E x 192); grid.y
@@ -339,11 +425,19 @@ __global__ void __launch_bounds__(256) k_seg_mean(int nseg, const int* __restric
   const int f = threadIdx.x & 63;
   if (sgi >= nseg) return;
   const int a = ptr[sgi], b = ptr[sgi + 1];
-  float acc = 0.0f;
-  for (int q = a; q < b; ++q) {
-    const int64_t e = idx ? idx[q] : q;
-    acc += src[e * stride + off + f];
+  // four entries in flight per lane; partial sums combined in a fixed order
+  float acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f, acc3 = 0.0f;
+  int q = a;
+  for (; q + 3 < b; q += 4) {
+    const int64_t e0 = idx ? idx[q] : q, e1 = idx ? idx[q + 1] : q + 1;
+    const int64_t e2 = idx ? idx[q + 2] : q + 2, e3 = idx ? idx[q + 3] : q + 3;
+    acc0 += src[e0 * stride + off + f];
+    acc1 += src[e1 * stride + off + f];
+    acc2 += src[e2 * stride + off + f];
+    acc3 += src[e3 * stride + off + f];
   }
+  for (; q < b; ++q) acc0 += src[(idx ? idx[q] : q) * (int64_t)stride + off + f];
+  const float acc = (acc0 + acc1) + (acc2 + acc3);
   dst[(int64_t)sgi * kHD + f] = b > a ? acc / (float)(b - a) : 0.0f;
 }
 
@@ -447,7 +541,6 @@ static void col_mean(Sample& S, const float* src, int stride, int off, float* mc
 
 void mpnn_forward(Net& net, Sample& S, Ctx& c, bool keep) {
   const int64_t E = S.E;
-  const int nb = ceil_div(E, 64);
   const int nbuf = keep ? kNL + 1 : 2;
   for (int k = 0; k < nbuf; ++k) {
     if (S.h[k].n != (size_t)(E * kHD)) S.h[k].alloc(E * kHD, c.s);
@@ -458,9 +551,10 @@ void mpnn_forward(Net& net, Sample& S, Ctx& c, bool keep) {
     if (S.mc[l].n != (size_t)S.ncol * kHD) S.mc[l].alloc((size_t)S.ncol * kHD, c.s);
   }
   if (S.delta.n != (size_t)E) S.delta.alloc(E, c.s);
+  const int lg = layer_grid(E);
   c.run("mpnn_dense_in", 2.0 * E * kNF * kHD, [&] {
-    k_mpnn_fwd<kNF, 0><<<nb, 256, 0, c.s>>>(E, S.X.p, nullptr, nullptr, nullptr, nullptr, nullptr, net.wt_in.p,
-                                            net.w.p + kOffBin, keep ? S.u[0].p : nullptr, S.h[0].p);
+    k_mpnn_layer<kNF, 0><<<lg, 256, 0, c.s>>>(E, S.X.p, nullptr, nullptr, nullptr, nullptr, nullptr, net.wt_in.p,
+                                              net.w.p + kOffBin, nullptr, keep ? S.u[0].p : nullptr, S.h[0].p, nullptr);
   });
   for (int l = 0; l < kNL; ++l) {
     float* hin = keep ? S.h[l].p : S.h[l & 1].p;
@@ -469,15 +563,21 @@ void mpnn_forward(Net& net, Sample& S, Ctx& c, bool keep) {
     float* mc = keep ? S.mc[l].p : S.mc[0].p;
     row_mean(S, hin, kHD, 0, mr, c);
     col_mean(S, hin, kHD, 0, mc, c);
+    const bool last_fused = !keep && l == kNL - 1;  // inference: the head is formed in the last layer
     c.run("mpnn_dense", 2.0 * E * kKZ * kHD, [&] {
-      k_mpnn_fwd<kKZ, 1><<<nb, 256, 0, c.s>>>(E, nullptr, hin, mr, mc, S.row_of.p, S.col_of.p, net.wt[l].p,
-                                              net.w.p + off_b(l), keep ? S.u[l + 1].p : nullptr, hout);
+      if (last_fused)
+        k_mpnn_layer<kKZ, 2><<<lg, 256, 0, c.s>>>(E, nullptr, hin, mr, mc, S.row_of.p, S.col_of.p, net.wt[l].p,
+                                                  net.w.p + off_b(l), net.w.p + kOffWout, nullptr, nullptr, S.delta.p);
+      else
+        k_mpnn_layer<kKZ, 1><<<lg, 256, 0, c.s>>>(E, nullptr, hin, mr, mc, S.row_of.p, S.col_of.p, net.wt[l].p,
+                                                  net.w.p + off_b(l), nullptr, keep ? S.u[l + 1].p : nullptr, hout, nullptr);
     });
   }
-  const float* hlast = keep ? S.h[kNL].p : S.h[kNL & 1].p;
-  c.run("mpnn_head", 4.0 * E * kHD, [&] {
-    k_head<<<1024, 256, 0, c.s>>>(E, hlast, net.w.p + kOffWout, nullptr, nullptr, S.delta.p, nullptr, nullptr);
-  });
+  if (keep) {
+    c.run("mpnn_head", 4.0 * E * kHD, [&] {
+      k_head<<<1024, 256, 0, c.s>>>(E, S.h[kNL].p, net.w.p + kOffWout, nullptr, nullptr, S.delta.p, nullptr, nullptr);
+    });
+  }
 }
 
 double mpnn_loss_grad(Net& net, Sample& S, Ctx& c) {
