@@ -652,7 +652,11 @@ static void spmv_t(const int* rp, const int* col, const V* val, int n, int64_t n
   const double bytes = (double)nnz * (4 + sizeof(V)) + 4.0 * (n + 1) + (double)n * (sizeof(X) + sizeof(Y)) +
                        (mode ? (double)n * sizeof(Y) : 0.0);
   const int64_t nb = n;
-  if (avg <= 6)
+  // lanes per row: about two or more entries per lane, so each lane has
+  // independent gathers in flight
+  if (avg <= 3)
+    c.run(tag, bytes, [&] { k_spmv<V, X, Y, 2><<<ceil_div(nb * 2, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
+  else if (avg <= 12)
     c.run(tag, bytes, [&] { k_spmv<V, X, Y, 4><<<ceil_div(nb * 4, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
   else if (avg <= 20)
     c.run(tag, bytes, [&] { k_spmv<V, X, Y, 8><<<ceil_div(nb * 8, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
