@@ -16,6 +16,8 @@ struct Level {
   DBuf<int> tail, head;  // endpoints of every edge: D row = -1 at tail, +1 at head
   Csr D, DT;             // D as CSR (+-1 values) and its transpose
   Csr An;                // nodal operator D^T A D
+  Csr DTA;               // (A D)^T = D^T A (A symmetric): the Hiptmair nodal right-hand
+                         // side D^T (b - A x) is formed as D^T b - DTA x
   DBuf<double> dinvA, dinvAn;
   DBuf<float> dinvA32, dinvAn32;
 
@@ -46,8 +48,8 @@ struct Level {
   std::vector<double> energy;
 
   // solve workspace
-  DBuf<double> x, b, r, rn, cn;
-  DBuf<float> x32, b32, r32, rn32, cn32;
+  DBuf<double> x, b, r, rn, cn, dtb;
+  DBuf<float> x32, b32, r32, rn32, cn32, dtb32;
 };
 
 struct Coarsest {

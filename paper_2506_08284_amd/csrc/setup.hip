@@ -760,6 +760,7 @@ static void level_operators(Hierarchy& H, Level& L) {
   Csr AD;
   spgemm(L.A, L.D, AD, true, c, "spgemm_AD");
   spgemm(L.DT, AD, L.An, true, c, "spgemm_DtAD");
+  transpose(AD, L.DTA, true, c);
   L.dinvA.alloc(L.n, c.s);
   L.dinvAn.alloc(L.m, c.s);
   diagonal(L.A, L.dinvA.p, true, c);

@@ -299,14 +299,14 @@ __global__ void __launch_bounds__(256) k_dense_apply(const double* __restrict__ 
 // ---------------------------------------------------------------------------
 // Level 0 gets its own kernel instances (TAG 1, 2) so that profiles separate
 // the fine-level sweeps from the launch-bound coarse ones.
-static void hiptmair64(Level& L, bool fine, double* x, const double* b, Ctx& c) {
+static void hiptmair64(Level& L, bool fine, double* x, const double* b, const double* dtb, Ctx& c) {
   auto edge = [&] {
     if (fine) sgs_t<double, double, 1>(L.Acm, L.Acm.val.p, L.dinvAcm.p, L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, b, x, c, "sgs_edge_l0");
     else sgs_t<double, double, 0>(L.Acm, L.Acm.val.p, L.dinvAcm.p, L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, b, x, c, "sgs_edge");
   };
   edge();
-  spmv(L.A, x, L.r.p, b, 1, c, fine ? "residual_l0" : "residual");
-  spmv(L.DT, L.r.p, L.rn.p, nullptr, 0, c, "grad_transpose");
+  // nodal right-hand side D^T (b - A x) = D^T b - (D^T A) x
+  spmv(L.DTA, x, L.rn.p, dtb, 1, c, fine ? "nodal_residual_l0" : "nodal_residual");
   fill(L.cn.p, 0.0, L.m, c);
   if (fine) sgs_t<double, double, 2>(L.Ancm, L.Ancm.val.p, L.dinvAncm.p, L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.rn.p, L.cn.p, c, "sgs_node_l0");
   else sgs_t<double, double, 0>(L.Ancm, L.Ancm.val.p, L.dinvAncm.p, L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.rn.p, L.cn.p, c, "sgs_node");
@@ -329,6 +329,7 @@ struct Vec32Form<double> {
   static double* r(Level& L) { return L.r.p; }
   static double* rn(Level& L) { return L.rn.p; }
   static double* cn(Level& L) { return L.cn.p; }
+  static double* dtb(Level& L) { return L.dtb.p; }
   static const double* dA(Level& L) { return L.dinvAcm.p; }
   static const double* dAn(Level& L) { return L.dinvAncm.p; }
 };
@@ -337,20 +338,21 @@ struct Vec32Form<float> {
   static float* r(Level& L) { return L.r32.p; }
   static float* rn(Level& L) { return L.rn32.p; }
   static float* cn(Level& L) { return L.cn32.p; }
+  static float* dtb(Level& L) { return L.dtb32.p; }
   static const float* dA(Level& L) { return L.dinvAcm32.p; }
   static const float* dAn(Level& L) { return L.dinvAncm32.p; }
 };
 
 template <class T>
-static void hiptmair32(Level& L, bool fine, T* x, const T* b, Ctx& c) {
+static void hiptmair32(Level& L, bool fine, T* x, const T* b, const T* dtb, Ctx& c) {
   using F = Vec32Form<T>;
   auto edge = [&] {
     if (fine) sgs_t<float, T, 1>(L.Acm, L.Acm.val32.p, F::dA(L), L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, b, x, c, "sgs_edge32_l0");
     else sgs_t<float, T, 0>(L.Acm, L.Acm.val32.p, F::dA(L), L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, b, x, c, "sgs_edge32");
   };
   edge();
-  spmv_v64<T, T>(L.A, x, F::r(L), b, 1, c, fine ? "residual32_l0" : "residual32");
-  spmv_v32<T, T>(L.DT, F::r(L), F::rn(L), nullptr, 0, c, "grad_transpose32");
+  // nodal right-hand side D^T b - (D^T A) x with the FP64 operator
+  spmv_v64<T, T>(L.DTA, x, F::rn(L), dtb, 1, c, fine ? "nodal_residual32_l0" : "nodal_residual32");
   fill_t(F::cn(L), T(0), L.m, c);
   if (fine) sgs_t<float, T, 2>(L.Ancm, L.Ancm.val32.p, F::dAn(L), L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, F::rn(L), F::cn(L), c, "sgs_node32_l0");
   else sgs_t<float, T, 0>(L.Ancm, L.Ancm.val32.p, F::dAn(L), L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, F::rn(L), F::cn(L), c, "sgs_node32");
@@ -371,13 +373,14 @@ static void vcycle64(Hierarchy& H, int l, const double* b, double* x) {
   Level& L = *H.lv[l];
   Level& N = *H.lv[l + 1];
   fill(x, 0.0, L.n, c);
-  hiptmair64(L, l == 0, x, b, c);
+  spmv(L.DT, b, L.dtb.p, nullptr, 0, c, "grad_transpose");
+  hiptmair64(L, l == 0, x, b, L.dtb.p, c);
   spmv(L.A, x, L.r.p, b, 1, c, l == 0 ? "residual_l0" : "residual");
   spmv(L.PeT, L.r.p, N.b.p, nullptr, 0, c, "restrict");
   if (l == 0) coarse_cycle(H);
   else vcycle64(H, l + 1, N.b.p, N.x.p);
   spmv(L.Pe, N.x.p, x, nullptr, 2, c, "prolong");
-  hiptmair64(L, l == 0, x, b, c);
+  hiptmair64(L, l == 0, x, b, L.dtb.p, c);
 }
 
 // Level l of the FP32 form (T = double on level 0, float below).
@@ -394,13 +397,14 @@ static void vcycle32(Hierarchy& H, int l, const T* b, T* x) {
   Level& N = *H.lv[l + 1];
   using F = Vec32Form<T>;
   fill_t(x, T(0), L.n, c);
-  hiptmair32<T>(L, l == 0, x, b, c);
+  spmv_v32<T, T>(L.DT, b, F::dtb(L), nullptr, 0, c, "grad_transpose32");
+  hiptmair32<T>(L, l == 0, x, b, F::dtb(L), c);
   spmv_v64<T, T>(L.A, x, F::r(L), b, 1, c, l == 0 ? "residual32_l0" : "residual32");
   spmv_v32<T, float>(L.PeT, F::r(L), N.b32.p, nullptr, 0, c, "restrict32");
   if (l == 0) coarse_cycle(H);
   else vcycle32<float>(H, l + 1, N.b32.p, N.x32.p);
   spmv_v32<float, T>(L.Pe, N.x32.p, x, nullptr, 2, c, "prolong32");
-  hiptmair32<T>(L, l == 0, x, b, c);
+  hiptmair32<T>(L, l == 0, x, b, F::dtb(L), c);
 }
 
 static void vcycle_direct(Hierarchy& H, const double* r, double* z) {
@@ -571,13 +575,14 @@ void prepare_solve(Hierarchy& H) {
     L.r.alloc(L.n, c.s);
     L.rn.alloc(L.m, c.s);
     L.cn.alloc(L.m, c.s);
+    L.dtb.alloc(L.m, c.s);
     if (f32) {
       // FP32 operator copies on every level; FP32 vectors below level 0
       make32(L.Acm, c); make32(L.Ancm, c);
       make32(L.Pe, c); make32(L.PeT, c); make32(L.DT, c);
       if (l > 0) {
         L.x32.alloc(L.n, c.s); L.b32.alloc(L.n, c.s); L.r32.alloc(L.n, c.s);
-        L.rn32.alloc(L.m, c.s); L.cn32.alloc(L.m, c.s);
+        L.rn32.alloc(L.m, c.s); L.cn32.alloc(L.m, c.s); L.dtb32.alloc(L.m, c.s);
         L.dinvAcm32.alloc(L.n, c.s); L.dinvAncm32.alloc(L.m, c.s);
         cast_d2f(L.dinvAcm.p, L.dinvAcm32.p, L.n, c);
         cast_d2f(L.dinvAncm.p, L.dinvAncm32.p, L.m, c);
