@@ -226,18 +226,35 @@ __global__ void __launch_bounds__(1024) k_gs_sweep_small(int ncol, const int* __
   const int l = threadIdx.x & (LPR - 1);
   const int grp = threadIdx.x / LPR;
   constexpr int NG = 1024 / LPR;
-  for (int step = 0; step < 2 * ncol; ++step) {
-    const int k = step < ncol ? step : 2 * ncol - 1 - step;
+  // forward over the colours, then backward from the second-to-last: the
+  // last colour's rows already solve their equations after the forward pass
+  // (rows of one colour do not couple), so repeating it changes nothing
+  for (int step = 0; step < 2 * ncol - 1; ++step) {
+    const int k = step < ncol ? step : 2 * ncol - 2 - step;
     for (int g = cptr[k] + grp; g < cptr[k + 1]; g += NG) {
       T s = 0;
       const int e = rp[g + 1];
-      for (int q = rp[g] + l; q < e; q += LPR) s += (T)val[q] * x[col[q]];
+      const int i = rows[g];
+      // up to four entries per lane loaded before they are summed
+      int q = rp[g] + l;
+      for (; q + 3 * LPR < e; q += 4 * LPR) {
+        const int c0 = col[q], c1 = col[q + LPR], c2 = col[q + 2 * LPR], c3 = col[q + 3 * LPR];
+        const V v0 = val[q], v1 = val[q + LPR], v2 = val[q + 2 * LPR], v3 = val[q + 3 * LPR];
+        s += (T)v0 * x[c0] + (T)v1 * x[c1] + (T)v2 * x[c2] + (T)v3 * x[c3];
+      }
+      int cc[3];
+      V vv[3];
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        const int qq = q + u * LPR;
+        cc[u] = qq < e ? col[qq] : i;
+        vv[u] = qq < e ? val[qq] : V(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 3; ++u) s += (T)vv[u] * x[cc[u]];
 #pragma unroll
       for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LPR);
-      if (l == 0) {
-        const int i = rows[g];
-        x[i] += (b[i] - s) * dinv[g];
-      }
+      if (l == 0) x[i] += (b[i] - s) * dinv[g];
     }
     __syncthreads();
   }
@@ -270,7 +287,9 @@ static void sgs_t(const Csr& A, const V* val, const T* dinv, const DBuf<int>& ro
       c.run(tag, bytes, [&] { k_gs_color<V, T, 32, TAG><<<ceil_div((int64_t)nr * 32, 256), 256, 0, c.s>>>(g0, nr, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
   };
   for (int k = 0; k < ncol; ++k) launch(k);
-  for (int k = ncol - 1; k >= 0; --k) launch(k);
+  // backward from the second-to-last colour: the last colour's rows already
+  // solve their equations after the forward pass, so repeating it is a no-op
+  for (int k = ncol - 2; k >= 0; --k) launch(k);
 }
 
 // x += D c  with D given by its endpoints: x_e += c[head] - c[tail]
