@@ -7,6 +7,7 @@
  * A^(e) u = f (Sec. 1, eq. "discrete eddy") the setup builds, on every level,
  *   - the nodal operator A^(n) = D_h^T A^(e) D_h and a smoothed-aggregation
  *     nodal prolongator P^(n) from caller-given aggregates (Sec. 2, Sec. 3),
+ *     or on level 0 a caller-given P^(n) whose aggregates come from Alg. 1,
  *   - the coarse gradient D_H by the Reitzinger-Schoeberl rule on the
  *     piecewise-constant prolongator (Sec. 2 and Sec. 4.1, eq. "revised RS DH"),
  *   - the pattern of P^(e) and its local constraint systems (Alg. 2),
@@ -98,6 +99,30 @@ typedef struct {
                               at most 10, else the V-cycle stays FP64
                               (hcurl_amg_stats_t.vcycle_fp32 tells which).
                               2: unconditionally. */
+  const hcurl_csr* nodal_prolongator; /* NULL (default), or a level-0 nodal prolongator
+                              P^(n), m_h x m_1 with values, in mem_space, used in
+                              place of smoothed aggregation (the method takes
+                              "P^(n) or aggregates", Sec. 4.1).  Every row is
+                              divided by its sum (summed in column order) so that
+                              P^(n) keeps constants; an empty row, a zero or
+                              non-finite row sum is HCURL_EINVAL.  If aggregates[0]
+                              is NULL the level-0 aggregates (the piecewise-constant
+                              P-bar behind D_H) come from Alg. 1 in the parallel
+                              form below; otherwise aggregates[0] must map onto
+                              exactly the m_1 columns.  level_info reports rho and
+                              omega as 0 for that level. */
+  int alg1_passes;         /* passes of the parallel Alg. 1 (default 2, >= 1).  Column j
+                              gets the target t_j = ceil(nnz(P_:j) m_h / nnz(P)); in
+                              each pass every column proposes its ceil(t_j / passes)
+                              unassigned rows of largest |p_ij| (ties: smaller row) and
+                              a row proposed by several columns takes the largest
+                              |p_ij| (ties: smaller column); rows left over take the
+                              column of their largest |p_ij| (ties: smaller column).
+                              A column left without rows is HCURL_EINVAL. */
+  int pbar_alg1;           /* 0 (default): P-bar behind D_H is the piecewise-constant
+                              prolongator of the aggregates.  1: P-bar comes from
+                              Alg. 1 applied to the smoothed P^(n) of every level, as
+                              in the paper's own runs (Sec. 4.1); P^(n) is unchanged. */
   int power_iters;         /* power iterations for rho(D^-1 A^(n)), default 20 */
   int record_energy;       /* 1: measure 1/2 <P, A P> after every emin iteration */
   int profile;             /* 0: off.  1: time every eagerly launched kernel with HIP
@@ -123,6 +148,8 @@ void hcurl_amg_default_opts(hcurl_amg_opts* opts);
  *   aggregates[l]  for l < n_agg_levels: int32 map from the nodes of level l to
  *           aggregate ids 0..m_{l+1}-1, every id used (the non-overlapping
  *           aggregates of Sec. 2).  Level l+1's nodes are level l's aggregates.
+ *           aggregates[0] may be NULL when opts.nodal_prolongator is given
+ *           (n_agg_levels still counts level 0).
  *   out     receives the handle.
  * Errors: HCURL_EINVAL (shapes, D_h rows, non-positive diagonal, aggregate ids),
  * HCURL_EREDUCIBLE, HCURL_ENOTSPD, HCURL_EUNSUPPORTED, HCURL_EHIP, HCURL_ENOMEM.
@@ -184,8 +211,11 @@ enum {
   HCURL_VEC_COLORS_AN = 1,  /* int32[m] colour of every node row            */
   HCURL_VEC_ENERGY = 2,     /* double[iters+1] energies (record_energy = 1) */
   HCURL_VEC_LOCAL_PAIRS = 3, /* uint16[nnz_Pe] local tail | head << 8 in T_i */
-  HCURL_VEC_PCG_HISTORY = 4  /* double[iters+1] recursive relative residuals of the
+  HCURL_VEC_PCG_HISTORY = 4, /* double[iters+1] recursive relative residuals of the
                                 last solve (level must be 0) */
+  HCURL_VEC_AGGREGATES = 5   /* int32[m] map of P-bar (the coarse node of every node
+                                that D_H is built from): the caller's aggregates, or
+                                Alg. 1's (l < levels-1) */
 };
 int hcurl_amg_export_vec(hcurl_amg h, int level, int which, void* out, int64_t capacity_bytes);
 

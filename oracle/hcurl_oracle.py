@@ -17,6 +17,16 @@ Readings where the paper is silent or garbled (each is listed in the design doc):
   R3  the weight of Alg. 2 is W = Diag(3 - |D_H| 1) over coarse edges (the
       printed |D_h| has the wrong dimension for B = |T| |D_H|^T W).
   R4  Alg. 2 loops over fine edges (rows of P^(e)).
+  R5  Alg. 1 (piecewise-constant interpolation from a given P^(n)): column
+      target t_j = ceil(nnz(P_:j) m_h / nnz(P)); in each pass the columns in
+      order take their ceil(t_j / passes) unassigned rows of largest |p_ij|
+      (ties: smaller row); a row left over goes to the column of its largest
+      |p_ij| (ties: smaller column); the unstated safeguard: an empty column,
+      in column order, takes its row of largest |p_ij| (ties: smaller row)
+      among rows whose column keeps another row, else it is an error.  A given
+      P^(n) is scaled to row sums one first (sums in column order).  P-bar
+      comes from the aggregates unless ``pbar_alg1`` asks for Alg. 1 on the
+      smoothed P^(n), as in the paper's runs (Sec. 4.1).
   R6  Reduce_Dimension drops the column of the largest coarse node id of T_i.
   R8  sparsity patterns are symbolic: products of absolute values, structural
       zeros kept (Alg. 2 uses |.|).
@@ -35,8 +45,8 @@ Readings where the paper is silent or garbled (each is listed in the design doc):
   R19 PCG stops on the recursive residual, ||r|| <= tol ||b||; the FP32 V-cycle
       uses the flexible (Polak-Ribiere) beta.
 
-Parity pins that do not exist: the FP32 V-cycle form (parity unpinned by the
-paper; checked by the true residual only).
+The FP32 V-cycle form is not in the paper: its precision layout is pinned by
+a high-contrast test against the plausible simplification (FP32 residuals).
 """
 from __future__ import annotations
 
@@ -182,6 +192,68 @@ def sa_prolongator(An: sp.csr_matrix, agg: np.ndarray, m_coarse: int, power_iter
     rs = np.asarray(P.sum(axis=1)).ravel()
     P.data = P.data / np.repeat(rs, np.diff(P.indptr))  # in place: keeps structural zeros
     return P, dict(rho=rho, omega=omega, row_sums_before=rs)
+
+
+def scale_rows_to_one(P: sp.csr_matrix) -> sp.csr_matrix:
+    """Each row of a nodal prolongator scaled to sum one, structural zeros
+    kept (Sec. 4.2: constants must be preserved for the commuting relation)."""
+    P = csr(P).copy()
+    lens = np.diff(P.indptr)
+    rs = np.zeros(P.shape[0])
+    for k in range(int(lens.max(initial=0))):      # in index order, one term at a time
+        on = lens > k
+        rs[on] += P.data[P.indptr[:-1][on] + k]
+    if np.any(rs == 0) or not np.all(np.isfinite(rs)):
+        raise ValueError("a row of P^(n) is empty or sums to zero")
+    P.data = P.data / np.repeat(rs, lens)
+    return P
+
+
+def piecewise_constant_assignment(P: sp.csr_matrix, passes: int = 2) -> np.ndarray:
+    """Alg. 1 (Gen_Piecewise_Const) with the details of reading R5: assigns
+    every fine node (row of P^(n)) to one coarse node (column); the map is the
+    piecewise-constant P-bar that the coarse gradient is built from
+    (Sec. 4.1).  Steps in the order of Alg. 1: per-column targets; ``passes``
+    sweeps over the columns in order, each column taking its
+    ceil(target / passes) unassigned rows of largest |p_ij|; greedy
+    assignment of the rows left; then the safeguard for empty columns."""
+    P = csr(P)
+    mh, mH = P.shape
+    C = P.tocsc()
+    C.sort_indices()
+    ncol = np.diff(C.indptr)
+    target = -(-ncol * mh // max(P.nnz, 1))            # ceil(nnz_j m_h / nnz)
+    n_assign = -(-target // passes)                     # ceil(target_j / passes)
+    assign = np.full(mh, -1, np.int64)
+    for _ in range(passes):
+        for j in range(mH):
+            rows = C.indices[C.indptr[j]:C.indptr[j + 1]]
+            mag = np.abs(C.data[C.indptr[j]:C.indptr[j + 1]])
+            free = assign[rows] < 0
+            r, v = rows[free], mag[free]
+            take = r[np.lexsort((r, -v))][:n_assign[j]]   # largest |p| first, ties: smaller row
+            assign[take] = j
+    # greedy: a row left over goes to the column of its largest |p| (ties: smaller column)
+    for i in np.nonzero(assign < 0)[0]:
+        cols = P.indices[P.indptr[i]:P.indptr[i + 1]]
+        if len(cols) == 0:
+            raise ValueError("a fine node has no coarse node in P^(n)")
+        assign[i] = cols[np.argmax(np.abs(P.data[P.indptr[i]:P.indptr[i + 1]]))]
+    # safeguard, columns in order: an empty column takes its row of largest |p|
+    # (ties: smaller row) among rows whose column keeps at least one other row
+    cnt = np.bincount(assign, minlength=mH)
+    for j in np.nonzero(cnt == 0)[0]:
+        rows = C.indices[C.indptr[j]:C.indptr[j + 1]]
+        mag = np.abs(C.data[C.indptr[j]:C.indptr[j + 1]])
+        ok = cnt[assign[rows]] >= 2
+        if not np.any(ok):
+            raise ValueError("Alg. 1 left a coarse node without fine nodes and no row can move to it")
+        r, v = rows[ok], mag[ok]
+        pick = r[np.lexsort((r, -v))][0]
+        cnt[assign[pick]] -= 1
+        assign[pick] = j
+        cnt[j] += 1
+    return assign.astype(np.int32)
 
 
 def coarse_gradient(D: sp.csr_matrix, agg: np.ndarray, m_coarse: int):
@@ -463,15 +535,24 @@ def galerkin(P: sp.csr_matrix, A: sp.csr_matrix) -> sp.csr_matrix:
 
 def build_level(A, tail, head, m, agg, opts):
     """One coarsening step of Alg. 3 with smoothed aggregation from the given
-    aggregates; returns the level record and the coarse (A, tail, head, m)."""
+    aggregates (or a given P^(n)); returns the level record and the coarse
+    (A, tail, head, m).  ``agg`` in the record is the map of P-bar, the one
+    the coarse gradient is built from."""
     D = gradient_matrix(tail, head, m)
     An = nodal_operator(A, D)
-    mH = int(agg.max()) + 1
     if opts.get("Pn") is not None:
-        Pn = csr(opts["Pn"])
+        Pn = scale_rows_to_one(opts["Pn"])
         sa = {}
+        if agg is None:
+            agg = piecewise_constant_assignment(Pn, opts.get("alg1_passes", 2))
+        mH = Pn.shape[1]
     else:
+        mH = int(agg.max()) + 1
         Pn, sa = sa_prolongator(An, agg, mH, opts.get("power_iters", 20))
+        if opts.get("pbar_alg1"):
+            # Sec. 4.1: the paper's own runs take P-bar from Alg. 1 applied to
+            # the smoothed P^(n), not from the aggregates
+            agg = piecewise_constant_assignment(Pn, opts.get("alg1_passes", 2))
     cth, chd = coarse_gradient(D, agg, mH)
     DH = gradient_matrix(cth, chd, mH)
     N, T, R = emin_pattern(D, Pn, DH)
@@ -496,7 +577,7 @@ def build_level(A, tail, head, m, agg, opts):
         energies, info = [energy(A, N, p0), energy(A, N, p)], {}
     Pe = with_values(N, p)
     AH = galerkin(Pe, A)
-    lvl = dict(A=A, D=D, An=An, tail=np.asarray(tail), head=np.asarray(head), m=m, Pn=Pn, sa=sa, Pe=Pe, N=N, T=T,
+    lvl = dict(A=A, D=D, An=An, tail=np.asarray(tail), head=np.asarray(head), m=m, agg=agg, Pn=Pn, sa=sa, Pe=Pe, N=N, T=T,
                R=R, lt=lt, lh=lh, loc=loc, p0=p0, energies=energies, cg=info, DH_tail=cth, DH_head=chd,
                irreducible_added=added)
     return lvl, (AH, cth, chd, mH)
@@ -515,7 +596,7 @@ def setup(A, tail, head, m: int, aggregates, opts=None):
         if li > 0:
             lopts.pop("Pn", None)
             lopts.pop("p_init", None)
-        lvl, (A, tail, head, m) = build_level(A, tail, head, m, np.asarray(agg), lopts)
+        lvl, (A, tail, head, m) = build_level(A, tail, head, m, None if agg is None else np.asarray(agg), lopts)
         levels.append(lvl)
     D = gradient_matrix(tail, head, m)
     coarse = dict(A=A, D=D, An=nodal_operator(A, D), tail=np.asarray(tail), head=np.asarray(head), m=m,

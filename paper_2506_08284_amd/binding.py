@@ -20,7 +20,7 @@ HCURL_EUNSUPPORTED = -7
 
 MEM = {"host": 0, "device": 1}
 EXPORT = {"A": 0, "An": 1, "Pn": 2, "Pe": 3, "R": 4, "DH": 5, "P0": 6}
-VEC = {"colors_A": 0, "colors_An": 1, "energy": 2, "local_pairs": 3, "pcg_history": 4}
+VEC = {"colors_A": 0, "colors_An": 1, "energy": 2, "local_pairs": 3, "pcg_history": 4, "aggregates": 5}
 
 # every function declared in include/hcurl_amg.h
 EXPORTED_SYMBOLS = [
@@ -42,7 +42,8 @@ class hcurl_amg_opts(ctypes.Structure):
     _fields_ = [("max_levels", ctypes.c_int), ("coarse_max_rows", ctypes.c_int), ("emin_iters", ctypes.c_int),
                 ("emin_method", ctypes.c_int), ("emin_omega", ctypes.c_double), ("init_guess", ctypes.c_int),
                 ("init_values", ctypes.c_void_p), ("emin_iters_given", ctypes.c_int), ("mpnn", ctypes.c_void_p),
-                ("vcycle_fp32", ctypes.c_int),
+                ("vcycle_fp32", ctypes.c_int), ("nodal_prolongator", ctypes.c_void_p), ("alg1_passes", ctypes.c_int),
+                ("pbar_alg1", ctypes.c_int),
                 ("power_iters", ctypes.c_int), ("record_energy", ctypes.c_int), ("profile", ctypes.c_int),
                 ("mem_space", ctypes.c_int), ("stream", ctypes.c_void_p)]
 
@@ -183,6 +184,11 @@ def hcurl_amg_default_opts(**overrides) -> hcurl_amg_opts:
             v = _ptr(v)
         if k == "mpnn" and v is not None and not isinstance(v, (int, ctypes.c_void_p)):
             v = v.h  # a Network
+        if k == "nodal_prolongator" and v is not None:
+            # (rowptr int64, col int32, val f64, ncols): the struct lives as long as the opts
+            rowptr, col, val, ncols = v
+            o._nodal_prolongator = _csr(rowptr, col, val, int(rowptr.shape[0]) - 1, int(ncols))
+            v = ctypes.addressof(o._nodal_prolongator)
         setattr(o, k, v)
     return o
 
@@ -192,7 +198,7 @@ def hcurl_amg_setup(A, Dh, aggregates, coords=None, opts: hcurl_amg_opts | None 
     aggregates: list of int32 maps (host or device arrays per opts.mem_space)."""
     opts = opts or hcurl_amg_default_opts()
     n = int(A[0].shape[0]) - 1
-    m = int(n_nodes) if n_nodes is not None else int(max(int(agg.shape[0]) for agg in aggregates[:1]) if aggregates else 0)
+    m = int(n_nodes) if n_nodes is not None else int(aggregates[0].shape[0])
     cA = _csr(*A, n, n)
     cD = _csr(*Dh, n, m)
     arr = (ctypes.c_void_p * max(1, len(aggregates)))(*[_ptr(a) for a in aggregates])
@@ -265,6 +271,8 @@ def hcurl_amg_export_vec(h, level: int, which: str, count: int | None = None):
         out = np.empty(count or 1024, np.float64)
     elif which == "local_pairs":
         out = np.empty(info["nnz_Pe"], np.uint16)
+    elif which == "aggregates":
+        out = np.empty(info["n_nodes"], np.int32)
     elif which == "pcg_history":
         out = np.empty(count or (hcurl_amg_stats(h)["last_iters"] + 1), np.float64)
     else:
@@ -392,7 +400,7 @@ class Hierarchy:
 
     def __init__(self, A, Dh, aggregates, n_nodes, coords=None, **opts):
         self.opts = hcurl_amg_default_opts(**opts)
-        self._keep = (A, Dh, aggregates, opts.get("init_values"), opts.get("mpnn"), coords)
+        self._keep = (A, Dh, aggregates, opts.get("init_values"), opts.get("mpnn"), opts.get("nodal_prolongator"), coords)
         self.h = hcurl_amg_setup(A, Dh, aggregates, coords, self.opts, n_nodes=n_nodes)
 
     def solve(self, f, u, rtol=1e-8, maxit=500):

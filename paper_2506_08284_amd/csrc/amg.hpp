@@ -36,6 +36,7 @@ struct Level {
   // transfer to the next level (empty on the coarsest level)
   bool has_transfer = false;
   DBuf<int> agg;          // aggregate of every node (the next level's node id)
+  DBuf<int> pbar;         // map of P-bar when it comes from Alg. 1 on the smoothed P^(n)
   Csr Pn;                 // nodal prolongator m x m_H
   Csr R;                  // D P^(n) on the pattern T (n x m_H)
   Csr Pe, PeT;            // edge prolongator n x n_H and its transpose

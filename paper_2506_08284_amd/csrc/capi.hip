@@ -68,6 +68,9 @@ void hcurl_amg_default_opts(hcurl_amg_opts* o) {
   o->emin_iters_given = 3;
   o->mpnn = nullptr;
   o->vcycle_fp32 = 0;
+  o->nodal_prolongator = nullptr;
+  o->alg1_passes = 2;
+  o->pbar_alg1 = 0;
   o->power_iters = 20;
   o->record_energy = 0;
   o->profile = 0;
@@ -85,6 +88,8 @@ int hcurl_amg_setup(const hcurl_csr* A, const hcurl_csr* Dh, const double* coord
   int rc = guarded([&]() -> int {
     if (opts) h->H.opts = *opts; else hcurl_amg_default_opts(&h->H.opts);
     if (h->H.opts.emin_iters < 0 || h->H.opts.power_iters < 1) hc::fail(HCURL_EINVAL, "bad iteration counts");
+    if ((h->H.opts.nodal_prolongator || h->H.opts.pbar_alg1) && h->H.opts.alg1_passes < 1)
+      hc::fail(HCURL_EINVAL, "alg1_passes must be >= 1");
     h->H.ctx.init((hipStream_t)h->H.opts.stream, h->H.opts.profile != 0);
     auto t0 = std::chrono::steady_clock::now();
     hc::build_hierarchy(h->H, *A, *Dh, coords, aggregates, n_agg_levels);
@@ -235,6 +240,11 @@ int hcurl_amg_export_vec(hcurl_amg h, int level, int which, void* out, int64_t c
         std::memcpy(out, v.data(), 8 * v.size());
         return (int)v.size();
       }
+      case HCURL_VEC_AGGREGATES:
+        if (!L->agg.p) hc::fail(HCURL_EINVAL, "the coarsest level has no aggregates");
+        need(4LL * L->m);
+        hc::d2h((int*)out, L->pbar.p ? L->pbar.p : L->agg.p, L->m, c);
+        break;
       default: hc::fail(HCURL_EINVAL, "unknown vector");
     }
     return HCURL_OK;

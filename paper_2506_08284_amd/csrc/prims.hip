@@ -123,6 +123,23 @@ __global__ void k_i64_to_i32(const int64_t* __restrict__ a, int* __restrict__ b,
   if (i < n) b[i] = (int)a[i];
 }
 
+// Caller CSR check: row pointers rise from 0 to nnz, columns lie in range and
+// increase strictly within a row.
+__global__ void k_check_csr(const int64_t* __restrict__ rp, const int* __restrict__ col, int64_t n, int64_t ncols,
+                            int64_t nnz, int* __restrict__ bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0 && (rp[0] != 0 || rp[n] != nnz)) atomicOr(bad, 1);
+  if (i >= n) return;
+  const int64_t a = rp[i], b = rp[i + 1];
+  if (a < 0 || b < a || b > nnz) { atomicOr(bad, 1); return; }
+  int prev = -1;
+  for (int64_t k = a; k < b; ++k) {
+    const int j = col[k];
+    if (j <= prev || j >= ncols) { atomicOr(bad, 1); return; }
+    prev = j;
+  }
+}
+
 void upload_csr(const hcurl_csr& in, bool device_ptrs, Csr& out, bool values, Ctx& c) {
   if (in.nrows < 0 || in.ncols < 0 || in.nnz < 0 || in.nnz > 0x7fffffffLL || in.nrows > 0x7fffffffLL)
     fail(HCURL_EINVAL, "CSR sizes out of range");
@@ -138,6 +155,17 @@ void upload_csr(const hcurl_csr& in, bool device_ptrs, Csr& out, bool values, Ct
   HC_HIP(hipMemcpyAsync(rp.p, in.rowptr, (in.nrows + 1) * sizeof(int64_t), kind, c.s));
   if (in.nnz) HC_HIP(hipMemcpyAsync(out.col.p, in.col, in.nnz * sizeof(int), kind, c.s));
   if (values && in.nnz) HC_HIP(hipMemcpyAsync(out.val.p, in.val, in.nnz * sizeof(double), kind, c.s));
+  {
+    DBuf<int> bad(1, c.s);
+    HC_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), c.s));
+    k_check_csr<<<ceil_div(in.nrows + 1, 256), 256, 0, c.s>>>(rp.p, out.col.p, in.nrows, in.ncols, in.nnz, bad.p);
+    HC_LAUNCH_CHECK();
+    int hb = 0;
+    d2h(&hb, bad.p, 1, c);
+    if (hb)
+      fail(HCURL_EINVAL, "malformed CSR: row pointers must rise from 0 to nnz and column indices must lie in "
+                         "[0, ncols) and increase within each row");
+  }
   int64_t n1 = in.nrows + 1;
   k_i64_to_i32<<<ceil_div(n1, 256), 256, 0, c.s>>>(rp.p, out.rowptr.p, n1);
   HC_LAUNCH_CHECK();

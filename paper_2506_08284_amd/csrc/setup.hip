@@ -118,6 +118,135 @@ __global__ void k_sa_values(const int* __restrict__ rp, const int* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// caller-given P^(n): rows scaled to sum one, aggregates by Alg. 1
+// ---------------------------------------------------------------------------
+// Row sums in index order, one term at a time; every value divided by its
+// row's sum.  Empty rows, zero or non-finite sums and non-finite values are
+// flagged.
+__global__ void k_scale_rows(const int* __restrict__ rp, double* __restrict__ val, int m, long long* __restrict__ bad) {
+  int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= m) return;
+  double s = 0.0;
+  bool fin = true;
+  for (int q = rp[u]; q < rp[u + 1]; ++q) {
+    s += val[q];
+    fin = fin && isfinite(val[q]);
+  }
+  if (!(s != 0.0) || !isfinite(s) || !fin) { atomicAdd((unsigned long long*)bad, 1ULL); return; }
+  for (int q = rp[u]; q < rp[u + 1]; ++q) val[q] = val[q] / s;
+}
+
+// Order key of |p|: the bit pattern of a non-negative finite double orders
+// like its value; +1 keeps 0 free for "no proposal".
+__device__ __forceinline__ unsigned long long mag_key(double v) {
+  return (unsigned long long)__double_as_longlong(fabs(v)) + 1ULL;
+}
+
+// Alg. 1 passes in the order of the algorithm: one workgroup walks the
+// columns (rows of P^(n)T, fine nodes increasing) in order; for each column
+// its unassigned rows are gathered in LDS and those ranking below the
+// column's quota (larger |p| first, then smaller fine node) are assigned to
+// it before the next column starts.  Columns hold at most kAlg1Cap entries
+// (checked on the host).
+constexpr int kAlg1Cap = 4096;
+__global__ void __launch_bounds__(1024) k_alg1_passes(const int* __restrict__ tp, const int* __restrict__ trow,
+                                                      const double* __restrict__ tval, int mH, int64_t mh, int64_t nnz,
+                                                      int passes, int* __restrict__ assign) {
+  __shared__ unsigned long long sk[kAlg1Cap];
+  __shared__ int sr[kAlg1Cap];
+  __shared__ int nfree;
+  for (int pass = 0; pass < passes; ++pass) {
+    for (int j = 0; j < mH; ++j) {
+      const int a = tp[j], b = tp[j + 1];
+      const int64_t target = ((int64_t)(b - a) * mh + nnz - 1) / nnz;
+      const int64_t quota = (target + passes - 1) / passes;
+      if (threadIdx.x == 0) nfree = 0;
+      __syncthreads();
+      for (int e = a + (int)threadIdx.x; e < b; e += blockDim.x) {
+        const int r = trow[e];
+        if (assign[r] < 0) {
+          const int s = atomicAdd(&nfree, 1);
+          sk[s] = mag_key(tval[e]);
+          sr[s] = r;
+        }
+      }
+      __syncthreads();
+      const int nf = nfree;
+      for (int s = threadIdx.x; s < nf; s += blockDim.x) {
+        const unsigned long long k = sk[s];
+        const int r = sr[s];
+        int64_t better = 0;
+        for (int t = 0; t < nf && better < quota; ++t) better += (sk[t] > k) || (sk[t] == k && sr[t] < r);
+        if (better < quota) assign[r] = j;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void k_alg1_count(const int* __restrict__ assign, int m, int* __restrict__ cnt) {
+  int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < m) atomicAdd(&cnt[assign[u]], 1);
+}
+
+// Safeguard for empty columns, in column order: the column takes its row of
+// largest |p| (ties: smaller fine node) among rows whose column keeps another
+// row; a column with no such row is flagged.  Moves never empty a column, so
+// the empty set is known before the walk; only the order matters.
+__global__ void __launch_bounds__(1024) k_alg1_safeguard(const int* __restrict__ tp, const int* __restrict__ trow,
+                                                         const double* __restrict__ tval, int mH,
+                                                         int* __restrict__ assign, int* __restrict__ cnt,
+                                                         long long* __restrict__ bad) {
+  __shared__ unsigned char empty[1024];
+  __shared__ unsigned long long bk;
+  __shared__ int br;
+  for (int c0 = 0; c0 < mH; c0 += 1024) {
+    const int jt = c0 + (int)threadIdx.x;
+    empty[threadIdx.x] = jt < mH && cnt[jt] == 0;
+    __syncthreads();
+    const int nt = min(1024, mH - c0);
+    for (int t = 0; t < nt; ++t) {
+      if (!empty[t]) continue;  // uniform across the workgroup
+      const int j = c0 + t;
+      if (threadIdx.x == 0) { bk = 0ULL; br = 0x7fffffff; }
+      __syncthreads();
+      for (int e = tp[j] + (int)threadIdx.x; e < tp[j + 1]; e += blockDim.x)
+        if (cnt[assign[trow[e]]] >= 2) atomicMax(&bk, mag_key(tval[e]));
+      __syncthreads();
+      for (int e = tp[j] + (int)threadIdx.x; e < tp[j + 1]; e += blockDim.x)
+        if (cnt[assign[trow[e]]] >= 2 && mag_key(tval[e]) == bk) atomicMin(&br, trow[e]);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        if (bk == 0ULL) {
+          atomicAdd((unsigned long long*)bad, 1ULL);
+        } else {
+          cnt[assign[br]] -= 1;
+          assign[br] = j;
+          cnt[j] += 1;
+        }
+      }
+      __syncthreads();
+    }
+    __syncthreads();
+  }
+}
+
+// Fine nodes no pass assigned: the coarse node of the row's largest |p|
+// (columns increase along the row, so the first maximum is the smallest).
+__global__ void k_alg1_leftover(const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ val,
+                                int m, int* __restrict__ assign) {
+  int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= m || assign[u] >= 0) return;
+  unsigned long long bk = 0ULL;
+  int bc = -1;
+  for (int q = rp[u]; q < rp[u + 1]; ++q) {
+    const unsigned long long k = mag_key(val[q]);
+    if (k > bk) { bk = k; bc = col[q]; }
+  }
+  assign[u] = bc;
+}
+
+// ---------------------------------------------------------------------------
 // coarse gradient by the RS rule on P-bar
 // ---------------------------------------------------------------------------
 __global__ void k_cross_count(const int* __restrict__ tail, const int* __restrict__ head, const int* __restrict__ agg,
@@ -771,14 +900,64 @@ static void level_operators(Hierarchy& H, Level& L) {
   if (read_flag(F_BAD, c)) fail(HCURL_EINVAL, "edge operator has a non-positive or non-finite diagonal entry");
 }
 
+// Alg. 1: every fine node of the (row-scaled) P^(n) is assigned to one
+// coarse node, which defines the piecewise-constant P-bar.
+static void alg1_aggregates(Hierarchy& H, Level& L, DBuf<int>& assign) {
+  Ctx& c = H.ctx;
+  const int mH = L.Pn.ncols;
+  Csr PT;
+  transpose(L.Pn, PT, true, c);
+  {
+    std::vector<int> hp(mH + 1);
+    d2h(hp.data(), PT.rowptr.p, mH + 1, c);
+    for (int j = 0; j < mH; ++j)
+      if (hp[j + 1] - hp[j] > kAlg1Cap) fail(HCURL_EUNSUPPORTED, "a column of P^(n) has more than 4096 entries (Alg. 1)");
+  }
+  HC_HIP(hipMemsetAsync(assign.p, 0xff, sizeof(int) * L.m, c.s));  // every node unassigned (-1)
+  c.run("alg1_passes", 12.0 * PT.nnz * H.opts.alg1_passes, [&] {
+    k_alg1_passes<<<1, 1024, 0, c.s>>>(PT.rowptr.p, PT.col.p, PT.val.p, mH, L.m, L.Pn.nnz, H.opts.alg1_passes,
+                                       assign.p);
+  });
+  c.run("alg1_leftover", 16.0 * L.Pn.nnz, [&] {
+    k_alg1_leftover<<<ceil_div(L.m, 256), 256, 0, c.s>>>(L.Pn.rowptr.p, L.Pn.col.p, L.Pn.val.p, L.m, assign.p);
+  });
+  DBuf<int> cnt(mH, c.s);
+  HC_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int) * mH, c.s));
+  k_alg1_count<<<ceil_div(L.m, 256), 256, 0, c.s>>>(assign.p, L.m, cnt.p);
+  HC_LAUNCH_CHECK();
+  clear_flag(F_BAD, c);
+  c.run("alg1_safeguard", 4.0 * mH, [&] {
+    k_alg1_safeguard<<<1, 1024, 0, c.s>>>(PT.rowptr.p, PT.col.p, PT.val.p, mH, assign.p, cnt.p, c.iscal.p + F_BAD);
+  });
+  if (read_flag(F_BAD, c))
+    fail(HCURL_EINVAL, "Alg. 1 left a coarse node without fine nodes and no row can move to it");
+}
+
 // Everything that builds the transfer from level L to a new level.
 static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg_in, bool level0) {
   Ctx& c = H.ctx;
   const bool dev = H.opts.mem_space == HCURL_MEM_DEVICE;
-  // aggregates
+  // a caller-given nodal prolongator replaces smoothed aggregation on level 0
+  const hcurl_csr* Pgiven = level0 ? H.opts.nodal_prolongator : nullptr;
+  if (Pgiven) {
+    if (Pgiven->nrows != L.m || Pgiven->ncols < 1)
+      fail(HCURL_EINVAL, "the given P^(n) must have one row per level-0 node and at least one column");
+    upload_csr(*Pgiven, dev, L.Pn, true, c);
+    clear_flag(F_BAD, c);
+    k_scale_rows<<<ceil_div(L.m, 256), 256, 0, c.s>>>(L.Pn.rowptr.p, L.Pn.val.p, L.m, c.iscal.p + F_BAD);
+    HC_LAUNCH_CHECK();
+    if (read_flag(F_BAD, c))
+      fail(HCURL_EINVAL, "a row of the given P^(n) is empty, sums to zero or holds a non-finite value");
+  } else if (!agg_in) {
+    fail(HCURL_EINVAL, "aggregates missing for a level");
+  }
+  // aggregates: the caller's, or Alg. 1 on the given P^(n)
   L.agg.alloc(L.m, c.s);
   DBuf<int>& agg = L.agg;
-  HC_HIP(hipMemcpyAsync(agg.p, agg_in, sizeof(int) * L.m, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c.s));
+  if (agg_in)
+    HC_HIP(hipMemcpyAsync(agg.p, agg_in, sizeof(int) * L.m, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c.s));
+  else
+    alg1_aggregates(H, L, agg);
   std::vector<int> hagg(L.m);
   d2h(hagg.data(), agg.p, L.m, c);
   int mH = 0;
@@ -788,13 +967,17 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
       if (v < 0) fail(HCURL_EINVAL, "negative aggregate id");
       mH = std::max(mH, v + 1);
     }
+    if (Pgiven && mH > L.Pn.ncols) fail(HCURL_EINVAL, "an aggregate id exceeds the columns of the given P^(n)");
+    if (Pgiven) mH = L.Pn.ncols;
     seen.assign(mH, 0);
     for (int v : hagg) seen[v] = 1;
     for (char s : seen)
-      if (!s) fail(HCURL_EINVAL, "aggregate ids are not contiguous (an id is unused)");
+      if (!s)
+        fail(HCURL_EINVAL, agg_in ? "aggregate ids are not contiguous (an id is unused)"
+                                  : "Alg. 1 left a coarse node of the given P^(n) without fine nodes");
   }
   // smoothed aggregation P^(n)
-  {
+  if (!Pgiven) {
     DBuf<double> x(L.m, c.s), y(L.m, c.s);
     c.run("power_init", 8.0 * L.m, [&] { k_hash_unit<<<ceil_div(L.m, 256), 256, 0, c.s>>>(x.p, L.m); });
     for (int it = 0; it < H.opts.power_iters; ++it) {
@@ -824,6 +1007,18 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
                                                        c.scal.p + S_OMEGA, L.m);
     });
   }
+  // P-bar from Alg. 1 on the smoothed P^(n) instead of the aggregates
+  if (!Pgiven && H.opts.pbar_alg1) {
+    L.pbar.alloc(L.m, c.s);
+    alg1_aggregates(H, L, L.pbar);
+    std::vector<int> hp(L.m);
+    d2h(hp.data(), L.pbar.p, L.m, c);
+    std::vector<char> seen(mH, 0);
+    for (int v : hp) seen[v] = 1;
+    for (char s : seen)
+      if (!s) fail(HCURL_EINVAL, "Alg. 1 left a coarse node of the smoothed P^(n) without fine nodes");
+  }
+  const int* pbar = L.pbar.p ? L.pbar.p : agg.p;
   // coarse gradient: Z = E^T E with E the aggregate pairs of crossing edges
   auto next = std::make_unique<Level>();
   DBuf<int> tptr;
@@ -832,11 +1027,11 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
     E.nrows = L.n; E.ncols = mH;
     E.rowptr.alloc(L.n + 1, c.s);
     DBuf<int> cnt(L.n + 1, c.s);
-    k_cross_count<<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, agg.p, L.n, cnt.p);
+    k_cross_count<<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, pbar, L.n, cnt.p);
     HC_LAUNCH_CHECK();
     E.nnz = exclusive_scan(cnt.p, E.rowptr.p, L.n, c);
     E.col.alloc(E.nnz, c.s);
-    k_cross_fill<<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, agg.p, L.n, E.rowptr.p, E.col.p);
+    k_cross_fill<<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, pbar, L.n, E.rowptr.p, E.col.p);
     HC_LAUNCH_CHECK();
     transpose(E, ET, false, c);
     spgemm(ET, E, Z, false, c, "spgemm_EtE");

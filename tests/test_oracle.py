@@ -440,3 +440,111 @@ def test_make_irreducible_restores_feasibility():
     assert len(lvl["DH_tail"]) == len(th) + lvl["irreducible_added"]
     assert len(O.disconnected_rows(lvl["N"], lvl["T"], lvl["lt"], lvl["lh"])) == 0
     assert O.commuting_residual(lvl) <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Alg. 1: piecewise-constant interpolation from a given P^(n) (reading R5)
+# ---------------------------------------------------------------------------
+def test_alg1_recovers_piecewise_constant_prolongator():
+    """A P^(n) that is already piecewise constant (one unit entry per row) is
+    mapped back to exactly its aggregates, whatever the number of passes."""
+    agg = synth.box_aggregates(9)[0][0]
+    mH = int(agg.max()) + 1
+    Pbar = O.tentative_prolongator(agg, mH)
+    for passes in (1, 2, 3):
+        assert np.array_equal(O.piecewise_constant_assignment(Pbar, passes), agg)
+
+
+def test_alg1_on_smoothed_aggregation_prolongator():
+    """On a smoothed P^(n) the assignment is a partition that uses every
+    coarse node, takes only columns where the row of P^(n) is non-zero, and
+    returns most rows to the aggregate they came from (smoothing only adds
+    smaller entries around each aggregate)."""
+    p = synth.problem(8, sigma=("const", 1.0))
+    A = O.csr(p["A"])
+    D = O.gradient_matrix(p["tail"], p["head"], 9 ** 3)
+    agg = p["aggregates"][0]
+    mH = int(agg.max()) + 1
+    Pn, _ = O.sa_prolongator(O.nodal_operator(A, D), agg, mH)
+    a = O.piecewise_constant_assignment(Pn, 2)
+    assert a.shape == agg.shape and a.min() >= 0 and np.all(np.bincount(a, minlength=mH) > 0)
+    Pn = O.csr(Pn)
+    for i in range(Pn.shape[0]):
+        assert a[i] in Pn.indices[Pn.indptr[i]:Pn.indptr[i + 1]]
+    assert np.mean(a == agg) > 0.8
+
+
+def test_hierarchy_from_given_nodal_prolongator():
+    """Setup from a given level-0 P^(n) instead of aggregates (the boundary
+    takes either): aggregates for P-bar and D_H come from Alg. 1, the
+    commuting relation holds and PCG converges like the aggregate path."""
+    p = synth.problem(8, sigma=("const", 1.0), f_seed=5)
+    m = 9 ** 3
+    A = O.csr(p["A"])
+    D = O.gradient_matrix(p["tail"], p["head"], m)
+    agg = p["aggregates"][0]
+    Pn, _ = O.sa_prolongator(O.nodal_operator(A, D), agg, int(agg.max()) + 1)
+    ref = O.setup(p["A"], p["tail"], p["head"], m, p["aggregates"])
+    lv = O.setup(p["A"], p["tail"], p["head"], m, [None] + list(p["aggregates"][1:]), dict(Pn=Pn))
+    assert np.array_equal(lv[0]["agg"], O.piecewise_constant_assignment(O.scale_rows_to_one(Pn), 2))
+    assert O.commuting_residual(lv[0]) <= 1e-12
+    _, it_ref, _, _ = O.pcg(ref, p["f"])
+    _, it, rel, _ = O.pcg(lv, p["f"])
+    assert rel <= 1e-8 and abs(it - it_ref) <= 3
+
+
+def _dense_csr(rows):
+    return sp.csr_matrix(np.array(rows, dtype=float))
+
+
+def test_alg1_rules_on_hand_worked_example():
+    """Worked by hand from Alg. 1 with reading R5 (4 fine nodes, 2 coarse).
+    nnz = 8, so both targets are ceil(4 * 4 / 8) = 2.  One pass (2 rows per
+    column): column 0 ranks rows 2 (0.9), 0, 1 (0.5, tie -> row 0) and takes
+    {2, 0}; column 1 then takes the free rows {3, 1}.  Two passes (1 row per
+    column per pass): 2, 3, then 0 (tie -> smaller row), then 1."""
+    P = _dense_csr([[0.5, 0.5], [0.5, 0.5], [0.9, 0.1], [0.1, 0.9]])
+    for passes in (1, 2):
+        assert np.array_equal(O.piecewise_constant_assignment(P, passes), [0, 1, 0, 1])
+    # rows scaled by positive factors: the same assignment once rows sum to one
+    Q = sp.diags([4.0, 0.25, 3.0, 7.0]) @ P
+    assert np.array_equal(O.piecewise_constant_assignment(O.scale_rows_to_one(Q), 1), [0, 1, 0, 1])
+    assert np.allclose(O.scale_rows_to_one(Q).toarray(), P.toarray(), rtol=1e-15, atol=0)
+
+
+def test_alg1_passes_greedy_and_safeguard_by_hand():
+    """Rows [1.2, -0.2], [1.2, -0.2], [1.0, 0]: nnz = 5, targets ceil(9/5) = 2
+    and ceil(6/5) = 2.  One pass: column 0 takes rows 0 and 1 (1.2), column 1
+    finds no free row; row 2 is left over and goes to column 0; column 1 is
+    empty, rows 0 and 1 may move (column 0 keeps 3), |-0.2| ties -> row 0.
+    Two passes: column 0 takes row 0, column 1 row 1, then column 0 row 2."""
+    P = _dense_csr([[1.2, -0.2], [1.2, -0.2], [1.0, 0.0]])
+    assert np.array_equal(O.piecewise_constant_assignment(P, 1), [1, 0, 0])
+    assert np.array_equal(O.piecewise_constant_assignment(P, 2), [0, 1, 0])
+
+
+def test_alg1_empty_column_without_movable_row_is_an_error():
+    """Column 1 meets only row 0, which column 0 takes first and which is
+    column 0's only row: the safeguard cannot fill column 1."""
+    P = _dense_csr([[1.2, -0.2, 0.0], [0.0, 0.0, 1.0]])
+    with pytest.raises(ValueError):
+        O.piecewise_constant_assignment(P, 1)
+    with pytest.raises(ValueError):
+        O.scale_rows_to_one(_dense_csr([[1.0, -1.0], [0.5, 0.5]]))
+
+
+def test_pbar_from_alg1_on_smoothed_prolongator():
+    """P-bar from Alg. 1 on the smoothed P^(n) (the paper's own configuration,
+    Sec. 4.1): the hierarchy keeps the commuting relation and converges like
+    the aggregate-P-bar one; P^(n) itself is unchanged."""
+    p = synth.problem(8, jitter=0.2, jitter_seed=3, sigma=("lognormal", 4, 1.0), f_seed=5)
+    m = 9 ** 3
+    ref = O.setup(p["A"], p["tail"], p["head"], m, p["aggregates"])
+    lv = O.setup(p["A"], p["tail"], p["head"], m, p["aggregates"], dict(pbar_alg1=True))
+    assert abs(lv[0]["Pn"] - ref[0]["Pn"]).max() == 0.0
+    assert np.array_equal(lv[0]["agg"], O.piecewise_constant_assignment(ref[0]["Pn"], 2))
+    for l in lv[:-1]:
+        assert O.commuting_residual(l) <= 1e-12
+    _, it_ref, _, _ = O.pcg(ref, p["f"])
+    _, it, rel, _ = O.pcg(lv, p["f"])
+    assert rel <= 1e-8 and abs(it - it_ref) <= 3
