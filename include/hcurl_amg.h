@@ -128,7 +128,10 @@ typedef struct {
   int profile;             /* 0: off.  1: time every eagerly launched kernel with HIP
                               events (hcurl_amg_kernel_stats); on a non-null stream the
                               V-cycle levels below the finest replay as one HIP graph,
-                              booked as "graph_coarse_levels".  2: as 1 with no graphs. */
+                              booked as "graph_coarse_levels".  2: as 1 with no graphs.
+                              3: as 1 in the setup and on every 16th PCG iteration
+                              (0, 16, ...); the other iterations run as with 0, so
+                              the solve time carries little event overhead. */
   int mem_space;           /* HCURL_MEM_HOST or HCURL_MEM_DEVICE */
   void* stream;            /* hipStream_t */
 } hcurl_amg_opts;

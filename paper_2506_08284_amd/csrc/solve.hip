@@ -677,10 +677,21 @@ int pcg_solve(Hierarchy& H, const double* f, double* u, double rtol, int maxit, 
     c.sync();
     return HCURL_OK;
   }
+  // profile 3: per-kernel events on every kSampleEvery-th iteration only; the
+  // others run like an unprofiled solve (whole V-cycle graph, no events)
+  const bool prof = c.profile;
+  const bool sampled = prof && H.opts.profile == 3;
+  constexpr int kSampleEvery = 16;
+  struct Restore {
+    Ctx& c;
+    bool v;
+    ~Restore() { c.profile = v; }
+  } restore{c, prof};
   apply_vcycle(H, H.pr.p, H.pz.p);
   d2d(H.pp.p, H.pz.p, n, c);
   dot(H.pr.p, H.pz.p, n, sc + P_RZ, c, 3);
   while (it < maxit) {
+    if (sampled) c.profile = it % kSampleEvery == 0;
     spmv(L.A, H.pp.p, H.pq.p, nullptr, 0, c, "pcg_spmv");
     dot(H.pp.p, H.pq.p, n, sc + P_PQ, c, 3);
     c.run("pcg_scalar", 0.0, [&] { k_pcg_alpha<<<1, 1, 0, c.s>>>(sc, bad); });
@@ -704,6 +715,7 @@ int pcg_solve(Hierarchy& H, const double* f, double* u, double rtol, int maxit, 
     c.run("pcg_scalar", 0.0, [&] { k_pcg_beta<<<1, 1, 0, c.s>>>(sc, flex ? 1 : 0); });
     c.run("pcg_dir", 24.0 * n, [&] { k_pcg_dir<<<ceil_div(n, 256), 256, 0, c.s>>>(n, H.pp.p, H.pz.p, sc + P_BETA); });
   }
+  c.profile = prof;
   // true residual
   spmv(L.A, H.px.p, H.pq.p, f, 1, c, "pcg_spmv");
   dot(H.pq.p, H.pq.p, n, sc + P_RR, c, 3);

@@ -283,6 +283,41 @@ def test_device_pointers_and_graph_replay_match_host_run():
     assert np.linalg.norm(a1 - un) <= 1e-9 * np.linalg.norm(un)
 
 
+def test_profiled_solves_match_unprofiled():
+    """Per-kernel events (profile 1), no graphs (2) and sampled events (3) do
+    not change the arithmetic: the same solution on a stream, up to the setup's
+    unordered LDS atomics (1e-9).  Profile 3 books events only on PCG
+    iterations 0, 16, ... (and the setup)."""
+    import torch
+    pr, m, levels, Hh = _case("cube12_jitter_lognormal")
+    P = _lib()
+    dev = torch.device("cuda:0")
+    side = torch.cuda.Stream()
+    out = {}
+    with torch.cuda.stream(side):
+        Dh = synth.gradient_csr(pr["tail"], pr["head"])
+        A_t = tuple(torch.from_numpy(a).to(dev) for a in pr["A"])
+        D_t = tuple(torch.from_numpy(a).to(dev) for a in Dh)
+        aggs = [torch.from_numpy(a).to(dev) for a in pr["aggregates"]]
+        f = torch.from_numpy(pr["f"]).to(dev)
+        for prof in (0, 1, 2, 3):
+            u = torch.empty_like(f)
+            side.synchronize()
+            H = P.Hierarchy(A_t, D_t, aggs, n_nodes=m, mem_space="device", stream=side.cuda_stream, profile=prof)
+            it, rel, rc = H.solve(f, u)
+            side.synchronize()
+            out[prof] = (it, u.cpu().numpy(), H.kernel_stats() if prof else {})
+            H.close()
+    it0, u0, _ = out[0]
+    for prof in (1, 2, 3):
+        assert abs(out[prof][0] - it0) <= 1, prof
+        assert np.linalg.norm(out[prof][1] - u0) <= 1e-9 * np.linalg.norm(u0), prof
+    # the PCG SpMV runs once per iteration plus the final residual
+    it1, it3 = out[1][0], out[3][0]
+    assert out[1][2]["pcg_spmv"]["launches"] == it1 + 1
+    assert out[3][2]["pcg_spmv"]["launches"] == (it3 - 1) // 16 + 1 + 1
+
+
 def test_invalid_inputs_rejected():
     P = _lib()
     pr = synth.problem(4)
