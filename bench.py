@@ -133,6 +133,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="untimed companions: only plain_fp64")
     ap.add_argument("--forced", action="store_true", help="also run the forced FP32 form untimed")
     ap.add_argument("--coarse-max-rows", type=int, default=1024)
+    ap.add_argument("--no-sequence", action="store_true",
+                    help="skip the untimed setup-reuse runs on a second system of the same mesh")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 1 GiB buffer three times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -236,6 +238,38 @@ def main():
         extra[name] = r
         log("untimed %s (whole V-cycle as a graph): %s" % (name, json.dumps(r)))
 
+    # untimed setup reuse: a second system on the same mesh (the background
+    # conductivity doubled), solved after a fresh setup, after re-projecting
+    # the first system's transfers, and after a warm-started re-minimisation
+    sequence = None
+    spec = synth.WORKLOADS[args.workload]
+    if not args.no_sequence and spec["sigma"][0] == "inclusions":
+        kind, seed, s_in, s_bg = spec["sigma"]
+        pr2 = synth.workload(args.workload, sigma=(kind, seed, s_in, 2.0 * s_bg))
+        A2_t = (A_t[0], A_t[1], torch.from_numpy(pr2["A"][2]).to(dev))
+        f2_t = torch.from_numpy(pr2["f"]).to(dev)
+        del pr2
+        torch.cuda.synchronize()
+        sequence = {"second_system": "sigma background %g (first: %g), same mesh and pattern" % (2.0 * s_bg, s_bg)}
+        H, r = run_step(P, A2_t, D_t, aggs_t, f2_t, u_t, m, stream, maxit=args.maxit, **forms["plain_fp64"])
+        H.close()
+        sequence["fresh_setup"] = dict(update_s=r["setup_s"], solve_s=r["solve_s"], total_s=r["total_s"],
+                                       iters=r["iters"], relres=r["relres"])
+        for mode, iters in (("transfers", -1), ("warm", 3)):
+            H = P.Hierarchy(A_t, D_t, aggs_t, n_nodes=m, mem_space="device", stream=stream, **forms["plain_fp64"])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            H.update(A2_t, mode, iters)
+            t1 = time.perf_counter()
+            it, rel, rc = H.solve(f2_t, u_t, 1e-8, args.maxit)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            H.close()
+            key = "reuse_transfers" if mode == "transfers" else "reuse_warm_3_iterations"
+            sequence[key] = dict(update_s=t1 - t0, solve_s=t2 - t1, total_s=t2 - t0, iters=it, relres=rel)
+        log("setup reuse (untimed): %s" % json.dumps(sequence))
+        del A2_t, f2_t
+
     top = sorted(kstats.items(), key=lambda kv: -kv[1]["ms"])
     for name, d in top[:14]:
         gbs = d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0
@@ -275,6 +309,7 @@ def main():
         "iters": results[-1]["iters"],
         "relres": results[-1]["relres"],
         "untimed_forms": extra,
+        "setup_reuse": sequence,
         "speedup_vs_plain_fp64": (extra["plain_fp64"]["total_s"] / extra[args.form]["total_s"])
         if ("plain_fp64" in extra and args.form in extra) else None,
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -222,6 +222,32 @@ enum {
 };
 int hcurl_amg_export_vec(hcurl_amg h, int level, int which, void* out, int64_t capacity_bytes);
 
+/*
+ * hcurl_amg_update -- setup reuse for a sequence of related systems: a new edge
+ * matrix with the sparsity pattern of the setup's (a time step, a Newton step).
+ * The paper suggests both forms: keeping the transfers across solves while
+ * re-projecting the matrix (remarks after Table 4), and starting the energy
+ * minimisation from the previous prolongator (Sec. 3).  Every pattern (T, the
+ * P^(e) pattern, D_H, local graphs) and every colouring is kept.
+ *   A      the new matrix, n_h x n_h with the setup's row pointers and columns
+ *          (HCURL_EINVAL otherwise), in opts.mem_space; read during the call.
+ *   mode   HCURL_REUSE_TRANSFERS: P^(n)_l, P^(e)_l and D_H are kept; A^(n)_l,
+ *          A_{l+1} = P^(e)T A_l P^(e), the diagonals, the FP32 copies and their
+ *          guard, and the coarsest inverse are recomputed (energies cleared).
+ *          HCURL_REUSE_WARM: as above, and on every level the smoothed-
+ *          aggregation P^(n) is rebuilt from the new A^(n) (a caller-given
+ *          level-0 P^(n) is kept), R = D P^(n) on T follows it, and P^(e)
+ *          starts from its previous values, corrected onto the new constraints,
+ *          for `iters` projected-CG (or Jacobi, per opts.emin_method) iterations.
+ *   iters  iterations for HCURL_REUSE_WARM; < 0 takes opts.emin_iters.
+ * Errors: HCURL_EINVAL (pattern, mode, single-level hierarchy), and those of
+ * setup.  After a failure part of the hierarchy may already hold the new
+ * operators: the handle then refuses solve, vcycle and update (HCURL_EINVAL)
+ * and must be destroyed.
+ */
+enum { HCURL_REUSE_TRANSFERS = 0, HCURL_REUSE_WARM = 1 };
+int hcurl_amg_update(hcurl_amg h, const hcurl_csr* A, int mode, int iters);
+
 /* Whole-hierarchy statistics. */
 typedef struct {
   int num_levels;
@@ -231,6 +257,7 @@ typedef struct {
   int last_iters;
   double last_relres;
   int vcycle_fp32;              /* 1 if the FP32 form of the V-cycle is in use */
+  double update_ms;             /* wall time of the last hcurl_amg_update */
 } hcurl_amg_stats_t;
 
 int hcurl_amg_stats(hcurl_amg h, hcurl_amg_stats_t* s);

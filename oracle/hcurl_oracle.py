@@ -28,6 +28,7 @@ Readings where the paper is silent or garbled (each is listed in the design doc):
       comes from the aggregates unless ``pbar_alg1`` asks for Alg. 1 on the
       smoothed P^(n), as in the paper's runs (Sec. 4.1).
   R6  Reduce_Dimension drops the column of the largest coarse node id of T_i.
+  R25 setup reuse (suggested in Sec. 3 and after Table 4): see ``update``.
   R8  sparsity patterns are symbolic: products of absolute values, structural
       zeros kept (Alg. 2 uses |.|).
   R9  the energy is measured in A^(e) (footnote to eq. min2_hcurl allows it).
@@ -549,6 +550,7 @@ def build_level(A, tail, head, m, agg, opts):
     else:
         mH = int(agg.max()) + 1
         Pn, sa = sa_prolongator(An, agg, mH, opts.get("power_iters", 20))
+        sa["agg"] = agg
         if opts.get("pbar_alg1"):
             # Sec. 4.1: the paper's own runs take P-bar from Alg. 1 applied to
             # the smoothed P^(n), not from the aggregates
@@ -606,6 +608,54 @@ def setup(A, tail, head, m: int, aggregates, opts=None):
         lvl["colors_A"] = color_graph(lvl["A"])
         lvl["colors_An"] = color_graph(lvl["An"])
     return levels
+
+
+def update(levels, A_new, mode: str, iters: int = 10, power_iters: int = 20):
+    """Setup reuse for a sequence of related systems whose edge matrix keeps
+    its sparsity pattern (the shortcuts the paper suggests in Sec. 3 and in
+    the remarks after Table 4).  Every pattern (T, N, D_H, the local graphs)
+    and every colouring is kept.
+      mode "transfers": P^(n), P^(e) and D_H are kept; the new matrix is
+        re-projected, A_{l+1} = P^(e)T A_l P^(e), with A^(n)_l = D_l^T A_l D_l.
+      mode "warm": on every level the smoothed-aggregation P^(n) is rebuilt
+        from the new A^(n) (a caller-given P^(n) is kept), the constraint rows
+        R = D P^(n) on T follow it, and the previous P^(e) values, corrected
+        onto the new constraints, start ``iters`` projected-CG iterations.
+    Returns a new list of levels; the given one is left unchanged."""
+    A = csr(A_new)
+    old = csr(levels[0]["A"])
+    if not (np.array_equal(A.indptr, old.indptr) and np.array_equal(A.indices, old.indices)):
+        raise ValueError("the new matrix must keep the sparsity pattern")
+    out = []
+    for lvl in levels[:-1]:
+        new = dict(lvl)
+        D = lvl["D"]
+        new["A"] = A
+        new["An"] = nodal_operator(A, D)
+        if mode == "transfers":
+            new["energies"] = []
+        elif mode == "warm":
+            mH = lvl["Pn"].shape[1]
+            if lvl["sa"]:
+                Pn, sa = sa_prolongator(new["An"], lvl["sa"]["agg"], mH, power_iters)
+                sa["agg"] = lvl["sa"]["agg"]
+                new["Pn"], new["sa"] = Pn, sa
+            DH = gradient_matrix(lvl["DH_tail"], lvl["DH_head"], mH)
+            N, T, R = emin_pattern(D, new["Pn"], DH)
+            loc = LocalSystems(N, T, R, lvl["lt"], lvl["lh"])
+            p0 = loc.make_feasible(lvl["Pe"].data.copy())
+            p, energies, info = projected_cg(A, N, loc, p0, iters)
+            new.update(N=N, T=T, R=R, loc=loc, p0=p0, energies=energies, cg=info, Pe=with_values(N, p))
+        else:
+            raise ValueError(mode)
+        out.append(new)
+        A = galerkin(new["Pe"], A)
+    coarse = dict(levels[-1])
+    coarse["A"] = A
+    coarse["An"] = nodal_operator(A, coarse["D"])
+    coarse["chol"] = sla.cho_factor(A.toarray(), lower=True)
+    out.append(coarse)
+    return out
 
 
 def commuting_residual(lvl) -> float:

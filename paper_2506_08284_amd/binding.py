@@ -24,8 +24,8 @@ VEC = {"colors_A": 0, "colors_An": 1, "energy": 2, "local_pairs": 3, "pcg_histor
 
 # every function declared in include/hcurl_amg.h
 EXPORTED_SYMBOLS = [
-    "hcurl_amg_default_opts", "hcurl_amg_setup", "hcurl_amg_solve", "hcurl_amg_vcycle", "hcurl_amg_destroy",
-    "hcurl_amg_num_levels", "hcurl_amg_level_info", "hcurl_amg_export_csr", "hcurl_amg_export_vec",
+    "hcurl_amg_default_opts", "hcurl_amg_setup", "hcurl_amg_solve", "hcurl_amg_vcycle", "hcurl_amg_update",
+    "hcurl_amg_destroy", "hcurl_amg_num_levels", "hcurl_amg_level_info", "hcurl_amg_export_csr", "hcurl_amg_export_vec",
     "hcurl_amg_stats", "hcurl_amg_kernel_stats", "hcurl_amg_reset_kernel_stats", "hcurl_last_error",
     "hcurl_error_string", "hcurl_mpnn_num_params", "hcurl_mpnn_create", "hcurl_mpnn_get_params", "hcurl_mpnn_destroy",
     "hcurl_amg_mpnn_sample", "hcurl_mpnn_sample_entries", "hcurl_mpnn_sample_export", "hcurl_mpnn_sample_destroy",
@@ -59,7 +59,7 @@ class hcurl_level_info(ctypes.Structure):
 class hcurl_amg_stats_t(ctypes.Structure):
     _fields_ = [("num_levels", ctypes.c_int), ("operator_complexity", ctypes.c_double), ("setup_ms", ctypes.c_double),
                 ("solve_ms", ctypes.c_double), ("last_iters", ctypes.c_int), ("last_relres", ctypes.c_double),
-                ("vcycle_fp32", ctypes.c_int)]
+                ("vcycle_fp32", ctypes.c_int), ("update_ms", ctypes.c_double)]
 
 
 class HcurlError(RuntimeError):
@@ -91,6 +91,8 @@ def _load():
     L.hcurl_amg_solve.restype = ctypes.c_int
     L.hcurl_amg_vcycle.argtypes = [P, P, P]
     L.hcurl_amg_vcycle.restype = ctypes.c_int
+    L.hcurl_amg_update.argtypes = [P, ctypes.POINTER(hcurl_csr), ctypes.c_int, ctypes.c_int]
+    L.hcurl_amg_update.restype = ctypes.c_int
     L.hcurl_amg_destroy.argtypes = [P]
     L.hcurl_amg_destroy.restype = None
     L.hcurl_amg_num_levels.argtypes = [P]
@@ -218,6 +220,16 @@ def hcurl_amg_solve(h, f, u, rtol: float = 1e-8, maxit: int = 500):
 
 def hcurl_amg_vcycle(h, r, z):
     _check(lib.hcurl_amg_vcycle(h, _ptr(r), _ptr(z)))
+
+
+REUSE = {"transfers": 0, "warm": 1}
+
+
+def hcurl_amg_update(h, A, mode="transfers", iters: int = -1):
+    """A = (rowptr int64, col int32, val f64) with the setup's pattern."""
+    n = int(A[0].shape[0]) - 1
+    cA = _csr(*A, n, n)
+    _check(lib.hcurl_amg_update(h, ctypes.byref(cA), REUSE[mode] if isinstance(mode, str) else int(mode), int(iters)))
 
 
 def hcurl_amg_destroy(h):
@@ -408,6 +420,9 @@ class Hierarchy:
 
     def vcycle(self, r, z):
         hcurl_amg_vcycle(self.h, r, z)
+
+    def update(self, A, mode="transfers", iters=-1):
+        hcurl_amg_update(self.h, A, mode, iters)
 
     def num_levels(self):
         return hcurl_amg_num_levels(self.h)

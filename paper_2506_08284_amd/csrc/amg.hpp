@@ -63,7 +63,10 @@ struct Hierarchy {
   hipGraphExec_t vgraph = nullptr;  // whole V-cycle on (pr -> pz)
   hipGraphExec_t cgraph = nullptr;  // V-cycle of levels >= 1 on (lv[1].b -> lv[1].x)
   bool capturing = false;
-  bool fp32 = false;  // the FP32 form of the V-cycle is in use
+  bool fp32 = false;      // the FP32 form of the V-cycle is in use
+  bool pn_given = false;  // level 0's P^(n) came from the caller
+  bool valid = true;      // false after a failed update: the levels are mixed
+  double update_ms = 0.0;
   ~Hierarchy() {
     if (vgraph) (void)hipGraphExecDestroy(vgraph);
     if (cgraph) (void)hipGraphExecDestroy(cgraph);
@@ -83,6 +86,9 @@ struct Hierarchy {
 // setup.hip
 void build_hierarchy(Hierarchy& H, const hcurl_csr& A, const hcurl_csr& Dh, const double* coords, const int32_t* const* aggs,
                      int nagg);
+
+// setup reuse for a new edge matrix with the same pattern (HCURL_REUSE_*)
+void update_hierarchy(Hierarchy& H, const hcurl_csr& A, int mode, int iters);
 
 // the local min-norm correction x <- x + G~ L~^-1 (r~ - G~^T x) on every row
 // (with `ones`, x is first set to ones)

@@ -113,6 +113,7 @@ int hcurl_amg_solve(hcurl_amg h, const double* f, double* u, double rtol, int ma
   return guarded([&]() -> int {
     auto& H = h->H;
     auto& c = H.ctx;
+    if (!H.valid) hc::fail(HCURL_EINVAL, "the handle is unusable after a failed hcurl_amg_update");
     const int64_t n = H.lv[0]->n;
     auto t0 = std::chrono::steady_clock::now();
     int rc;
@@ -134,6 +135,7 @@ int hcurl_amg_vcycle(hcurl_amg h, const double* r, double* z) {
   return guarded([&]() -> int {
     auto& H = h->H;
     auto& c = H.ctx;
+    if (!H.valid) hc::fail(HCURL_EINVAL, "the handle is unusable after a failed hcurl_amg_update");
     const int64_t n = H.lv[0]->n;
     if (H.opts.mem_space == HCURL_MEM_DEVICE) {
       hc::apply_vcycle(H, r, z);
@@ -252,6 +254,20 @@ int hcurl_amg_export_vec(hcurl_amg h, int level, int which, void* out, int64_t c
   });
 }
 
+int hcurl_amg_update(hcurl_amg h, const hcurl_csr* A, int mode, int iters) {
+  if (!h || !A) return HCURL_EINVAL;
+  if (mode != HCURL_REUSE_TRANSFERS && mode != HCURL_REUSE_WARM) return HCURL_EINVAL;
+  return guarded([&]() -> int {
+    auto& H = h->H;
+    if (!H.valid) hc::fail(HCURL_EINVAL, "the handle is unusable after a failed hcurl_amg_update");
+    if (H.lv.size() < 2) hc::fail(HCURL_EINVAL, "a single-level hierarchy has no transfers to reuse");
+    auto t0 = std::chrono::steady_clock::now();
+    hc::update_hierarchy(H, *A, mode, iters);
+    H.update_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return HCURL_OK;
+  });
+}
+
 int hcurl_amg_stats(hcurl_amg h, hcurl_amg_stats_t* s) {
   if (!h || !s) return HCURL_EINVAL;
   auto& H = h->H;
@@ -264,6 +280,7 @@ int hcurl_amg_stats(hcurl_amg h, hcurl_amg_stats_t* s) {
   s->last_iters = H.last_iters;
   s->last_relres = H.last_relres;
   s->vcycle_fp32 = H.fp32 ? 1 : 0;
+  s->update_ms = H.update_ms;
   return HCURL_OK;
 }
 

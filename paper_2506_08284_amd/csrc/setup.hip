@@ -883,9 +883,9 @@ static void coarsest_factor(Hierarchy& H, Level& L) {
 }
 
 // nodal operator, diagonals, colourings of one level (all levels)
-static void level_operators(Hierarchy& H, Level& L) {
+// A^(n) = D^T A D, (A D)^T and the diagonals, from the level's current A
+static void nodal_operators(Hierarchy& H, Level& L) {
   Ctx& c = H.ctx;
-  gradient_csr(L, c);
   Csr AD;
   spgemm(L.A, L.D, AD, true, c, "spgemm_AD");
   spgemm(L.DT, AD, L.An, true, c, "spgemm_DtAD");
@@ -898,6 +898,45 @@ static void level_operators(Hierarchy& H, Level& L) {
   k_check_diag<<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.dinvA.p, L.n, c.iscal.p + F_BAD);
   HC_LAUNCH_CHECK();
   if (read_flag(F_BAD, c)) fail(HCURL_EINVAL, "edge operator has a non-positive or non-finite diagonal entry");
+}
+
+static void level_operators(Hierarchy& H, Level& L) {
+  gradient_csr(L, H.ctx);
+  nodal_operators(H, L);
+}
+
+// Smoothed aggregation P^(n) = (I - omega D^-1 A^(n)) P-bar on the symbolic
+// pattern, rows scaled to sum one; omega = 4 / (3 rho(D^-1 A^(n))).
+static void smoothed_aggregation(Hierarchy& H, Level& L, const int* agg, int mH) {
+  Ctx& c = H.ctx;
+  DBuf<double> x(L.m, c.s), y(L.m, c.s);
+  c.run("power_init", 8.0 * L.m, [&] { k_hash_unit<<<ceil_div(L.m, 256), 256, 0, c.s>>>(x.p, L.m); });
+  for (int it = 0; it < H.opts.power_iters; ++it) {
+    spmv(L.An, x.p, y.p, nullptr, 0, c, "power_spmv");
+    c.run("power_scale", 24.0 * L.m, [&] { k_mul<<<ceil_div(L.m, 256), 256, 0, c.s>>>(y.p, L.dinvAn.p, L.m); });
+    dot(x.p, x.p, L.m, c.scal.p + S_NX2, c, 1);
+    dot(y.p, y.p, L.m, c.scal.p + S_NY2, c, 2);
+    c.run("power_norm", 16.0 * L.m, [&] {
+      k_power_normalise<<<ceil_div(L.m, 256), 256, 0, c.s>>>(x.p, y.p, L.m, c.scal.p + S_NX2, c.scal.p + S_NY2,
+                                                             c.scal.p + S_POWRHO);
+    });
+  }
+  k_omega<<<1, 1, 0, c.s>>>(c.scal.p + S_POWRHO, c.scal.p + S_OMEGA);
+  HC_LAUNCH_CHECK();
+  double hs[2];
+  d2h(hs, c.scal.p + S_POWRHO, 2, c);
+  L.rho = hs[0];
+  L.omega = hs[1];
+  Csr Pbar;
+  Pbar.nrows = L.m; Pbar.ncols = mH; Pbar.nnz = L.m;
+  Pbar.rowptr.alloc(L.m + 1, c.s); Pbar.col.alloc(L.m, c.s); Pbar.val.alloc(L.m, c.s);
+  k_pbar<<<ceil_div(L.m + 1, 256), 256, 0, c.s>>>(agg, L.m, Pbar.rowptr.p, Pbar.col.p, Pbar.val.p);
+  HC_LAUNCH_CHECK();
+  spgemm(L.An, Pbar, L.Pn, true, c, "spgemm_AnPbar");
+  c.run("sa_values", 12.0 * L.Pn.nnz, [&] {
+    k_sa_values<<<ceil_div(L.m, 256), 256, 0, c.s>>>(L.Pn.rowptr.p, L.Pn.col.p, L.Pn.val.p, agg, L.dinvAn.p,
+                                                     c.scal.p + S_OMEGA, L.m);
+  });
 }
 
 // Alg. 1: every fine node of the (row-scaled) P^(n) is assigned to one
@@ -977,36 +1016,7 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
                                   : "Alg. 1 left a coarse node of the given P^(n) without fine nodes");
   }
   // smoothed aggregation P^(n)
-  if (!Pgiven) {
-    DBuf<double> x(L.m, c.s), y(L.m, c.s);
-    c.run("power_init", 8.0 * L.m, [&] { k_hash_unit<<<ceil_div(L.m, 256), 256, 0, c.s>>>(x.p, L.m); });
-    for (int it = 0; it < H.opts.power_iters; ++it) {
-      spmv(L.An, x.p, y.p, nullptr, 0, c, "power_spmv");
-      c.run("power_scale", 24.0 * L.m, [&] { k_mul<<<ceil_div(L.m, 256), 256, 0, c.s>>>(y.p, L.dinvAn.p, L.m); });
-      dot(x.p, x.p, L.m, c.scal.p + S_NX2, c, 1);
-      dot(y.p, y.p, L.m, c.scal.p + S_NY2, c, 2);
-      c.run("power_norm", 16.0 * L.m, [&] {
-        k_power_normalise<<<ceil_div(L.m, 256), 256, 0, c.s>>>(x.p, y.p, L.m, c.scal.p + S_NX2, c.scal.p + S_NY2,
-                                                               c.scal.p + S_POWRHO);
-      });
-    }
-    k_omega<<<1, 1, 0, c.s>>>(c.scal.p + S_POWRHO, c.scal.p + S_OMEGA);
-    HC_LAUNCH_CHECK();
-    double hs[2];
-    d2h(hs, c.scal.p + S_POWRHO, 2, c);
-    L.rho = hs[0];
-    L.omega = hs[1];
-    Csr Pbar;
-    Pbar.nrows = L.m; Pbar.ncols = mH; Pbar.nnz = L.m;
-    Pbar.rowptr.alloc(L.m + 1, c.s); Pbar.col.alloc(L.m, c.s); Pbar.val.alloc(L.m, c.s);
-    k_pbar<<<ceil_div(L.m + 1, 256), 256, 0, c.s>>>(agg.p, L.m, Pbar.rowptr.p, Pbar.col.p, Pbar.val.p);
-    HC_LAUNCH_CHECK();
-    spgemm(L.An, Pbar, L.Pn, true, c, "spgemm_AnPbar");
-    c.run("sa_values", 12.0 * L.Pn.nnz, [&] {
-      k_sa_values<<<ceil_div(L.m, 256), 256, 0, c.s>>>(L.Pn.rowptr.p, L.Pn.col.p, L.Pn.val.p, agg.p, L.dinvAn.p,
-                                                       c.scal.p + S_OMEGA, L.m);
-    });
-  }
+  if (!Pgiven) smoothed_aggregation(H, L, agg.p, mH);
   // P-bar from Alg. 1 on the smoothed P^(n) instead of the aggregates
   if (!Pgiven && H.opts.pbar_alg1) {
     L.pbar.alloc(L.m, c.s);
@@ -1139,9 +1149,62 @@ void build_hierarchy(Hierarchy& H, const hcurl_csr& A, const hcurl_csr& Dh, cons
     color_rows(L.An, L.colorAn, L.rowsAn, L.cptrAn, L.ncolAn, c);
     H.lv.push_back(coarsen(H, L, aggs[l], l == 0));
   }
+  H.pn_given = H.opts.nodal_prolongator != nullptr;
   coarsest_factor(H, *H.lv.back());
   prepare_solve(H);
   c.sync();
+}
+
+// Same row pointers and columns as the stored pattern.
+__global__ void k_same_pattern(const int* __restrict__ rp0, const int* __restrict__ col0, const int* __restrict__ rp1,
+                               const int* __restrict__ col1, int n, long long* __restrict__ bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  if (rp0[i] != rp1[i]) { atomicAdd((unsigned long long*)bad, 1ULL); return; }
+  if (i == n) return;
+  for (int q = rp0[i]; q < rp0[i + 1]; ++q)
+    if (col0[q] != col1[q]) { atomicAdd((unsigned long long*)bad, 1ULL); return; }
+}
+
+void update_hierarchy(Hierarchy& H, const hcurl_csr& A, int mode, int iters) {
+  Ctx& c = H.ctx;
+  const bool dev = H.opts.mem_space == HCURL_MEM_DEVICE;
+  Level& L0 = *H.lv[0];
+  if (A.nrows != L0.n || A.ncols != L0.n || A.nnz != L0.A.nnz)
+    fail(HCURL_EINVAL, "the new matrix must keep the sparsity pattern of the setup's");
+  Csr Anew;
+  upload_csr(A, dev, Anew, true, c);
+  clear_flag(F_BAD, c);
+  k_same_pattern<<<ceil_div(L0.n + 1, 256), 256, 0, c.s>>>(L0.A.rowptr.p, L0.A.col.p, Anew.rowptr.p, Anew.col.p, L0.n,
+                                                          c.iscal.p + F_BAD);
+  HC_LAUNCH_CHECK();
+  if (read_flag(F_BAD, c)) fail(HCURL_EINVAL, "the new matrix must keep the sparsity pattern of the setup's");
+  // captured graphs hold the addresses of buffers rebuilt below
+  if (H.vgraph) { HC_HIP(hipGraphExecDestroy(H.vgraph)); H.vgraph = nullptr; }
+  if (H.cgraph) { HC_HIP(hipGraphExecDestroy(H.cgraph)); H.cgraph = nullptr; }
+  H.valid = false;
+  L0.A.val = std::move(Anew.val);
+  const int K = iters < 0 ? H.opts.emin_iters : iters;
+  for (size_t l = 0; l + 1 < H.lv.size(); ++l) {
+    Level& L = *H.lv[l];
+    Level& N = *H.lv[l + 1];
+    nodal_operators(H, L);
+    if (mode == HCURL_REUSE_WARM) {
+      if (!(l == 0 && H.pn_given)) smoothed_aggregation(H, L, L.agg.p, L.Pn.ncols);
+      spgemm(L.D, L.Pn, L.R, true, c, "spgemm_DPn");
+      energy_minimisation(H, L, &N, K, true, L.Pe.val.p, true, false);
+      transpose(L.Pe, L.PeT, true, c);
+    } else {
+      L.energy.clear();
+    }
+    Csr AP;
+    spgemm(L.A, L.Pe, AP, true, c, "spgemm_AP");
+    spgemm(L.PeT, AP, N.A, true, c, "spgemm_PtAP");
+  }
+  coarsest_factor(H, *H.lv.back());
+  prepare_solve(H);
+  c.sync();
+  H.valid = true;
 }
 
 }  // namespace hc

@@ -548,3 +548,63 @@ def test_pbar_from_alg1_on_smoothed_prolongator():
     _, it_ref, _, _ = O.pcg(ref, p["f"])
     _, it, rel, _ = O.pcg(lv, p["f"])
     assert rel <= 1e-8 and abs(it - it_ref) <= 3
+
+
+# ---------------------------------------------------------------------------
+# setup reuse for a sequence of systems (Sec. 3; remarks after Table 4)
+# ---------------------------------------------------------------------------
+def _sequence_pair():
+    """Two systems on one mesh: lognormal sigma from two seeds (same pattern)."""
+    p1 = synth.problem(8, jitter=0.1, jitter_seed=2, sigma=("lognormal", 4, 1.0), f_seed=5)
+    p2 = synth.problem(8, jitter=0.1, jitter_seed=2, sigma=("lognormal", 9, 1.0), f_seed=5)
+    return p1, p2, 9 ** 3
+
+
+def test_update_with_the_same_matrix_reproduces_the_setup():
+    p1, _, m = _sequence_pair()
+    lv = O.setup(p1["A"], p1["tail"], p1["head"], m, p1["aggregates"])
+    u = O.update(lv, p1["A"], "transfers")
+    for a, b in zip(lv, u):
+        assert np.array_equal(O.csr(a["A"]).data, O.csr(b["A"]).data)
+        assert np.array_equal(O.csr(a["An"]).data, O.csr(b["An"]).data)
+    # a feasible P^(e) is a fixed point of the min-norm correction, and CG
+    # continued from the minimiser cannot raise the energy
+    w = O.update(lv, p1["A"], "warm", iters=4)
+    for a, b in zip(lv[:-1], w[:-1]):
+        assert abs(b["p0"] - a["Pe"].data).max() <= 1e-13 * abs(a["Pe"].data).max()
+        assert abs(b["energies"][0] - a["energies"][-1]) <= 1e-12 * a["energies"][-1]
+        assert b["energies"][-1] <= b["energies"][0] * (1 + 1e-14)
+
+
+def test_update_transfers_keeps_the_nodal_galerkin_identity():
+    """With P^(e) D_H = D_h P^(n), re-projecting any matrix gives
+    D_H^T (P^T A P) D_H = P^(n)T (D_h^T A D_h) P^(n): the kept transfers stay
+    structure preserving for the new sigma on every level."""
+    p1, p2, m = _sequence_pair()
+    lv = O.setup(p1["A"], p1["tail"], p1["head"], m, p1["aggregates"])
+    u = O.update(lv, p2["A"], "transfers")
+    assert abs(O.csr(u[0]["A"]) - O.csr(p2["A"])).max() == 0.0
+    for l, lvl in enumerate(u[:-1]):
+        DH = O.gradient_matrix(lvl["DH_tail"], lvl["DH_head"], lvl["Pn"].shape[1])
+        left = DH.T @ u[l + 1]["A"] @ DH
+        right = lvl["Pn"].T @ lvl["An"] @ lvl["Pn"]
+        assert abs(left - right).max() <= 1e-10 * abs(right).max(), l
+    _, it, rel, _ = O.pcg(u, p2["f"])
+    assert rel <= 1e-8
+
+
+def test_update_warm_start_meets_the_new_constraints():
+    """Warm mode: P^(n) rebuilt from the new A^(n), the previous P^(e) moved
+    onto the new constraints, then projected CG; the commuting relation holds,
+    energies decrease, and the solve converges like a fresh setup."""
+    p1, p2, m = _sequence_pair()
+    lv = O.setup(p1["A"], p1["tail"], p1["head"], m, p1["aggregates"])
+    fresh = O.setup(p2["A"], p2["tail"], p2["head"], m, p2["aggregates"])
+    w = O.update(lv, p2["A"], "warm", iters=10)
+    for a, b in zip(fresh[:-1], w[:-1]):
+        assert abs(O.csr(a["Pn"]) - O.csr(b["Pn"])).max() <= 1e-13
+        assert O.commuting_residual(b) <= 1e-12
+        assert np.all(np.diff(b["energies"]) <= 1e-12 * b["energies"][0])
+    _, it_f, _, _ = O.pcg(fresh, p2["f"])
+    _, it_w, rel, _ = O.pcg(w, p2["f"])
+    assert rel <= 1e-8 and it_w <= it_f + 2
