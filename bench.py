@@ -270,6 +270,16 @@ def main():
         log("setup reuse (untimed): %s" % json.dumps(sequence))
         del A2_t, f2_t
 
+    # untimed: the same system with MIS-2 aggregates from the nodal graphs in
+    # place of the box aggregates
+    if not args.no_compare:
+        H, r = run_step(P, A_t, D_t, [], f_t, u_t, m, stream, maxit=args.maxit, aggregation="mis2", **cmr)
+        r["level_edges"] = [int(H.level_info(l)["n_edges"]) for l in range(H.num_levels())]
+        H.close()
+        r["reached_tol"] = r["rc"] == 0
+        extra["plain_fp64_mis2_aggregates"] = r
+        log("untimed plain_fp64 with MIS-2 aggregates: %s" % json.dumps(r))
+
     top = sorted(kstats.items(), key=lambda kv: -kv[1]["ms"])
     for name, d in top[:14]:
         gbs = d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0

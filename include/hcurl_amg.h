@@ -58,6 +58,7 @@ enum {
 enum { HCURL_MEM_HOST = 0, HCURL_MEM_DEVICE = 1 };
 enum { HCURL_EMIN_CG = 0, HCURL_EMIN_JACOBI = 1 };
 enum { HCURL_INIT_ONES = 0, HCURL_INIT_GIVEN = 1, HCURL_INIT_MPNN = 2 };
+enum { HCURL_AGG_GIVEN = 0, HCURL_AGG_MIS2 = 1 };
 
 /* CSR matrix.  rowptr has nrows+1 entries; column indices sorted per row.
  * val may be NULL where only the pattern is read. */
@@ -123,6 +124,18 @@ typedef struct {
                               prolongator of the aggregates.  1: P-bar comes from
                               Alg. 1 applied to the smoothed P^(n) of every level, as
                               in the paper's own runs (Sec. 4.1); P^(n) is unchanged. */
+  int aggregation;         /* HCURL_AGG_GIVEN (default): levels with a caller map only.
+                              HCURL_AGG_MIS2: a level with no map (aggregates[l] NULL,
+                              or l >= n_agg_levels) is aggregated on the graph of its
+                              A^(n) (not in the paper, which takes aggregates from an
+                              SA package): roots form a distance-2 maximal independent
+                              set chosen in Luby rounds with priority (bits 30..63 of
+                              splitmix64(i), i); every other node joins the root next
+                              to it or, two steps away, the aggregate of its neighbour
+                              of largest priority among those next to a root; ids
+                              follow the roots' order.  Coarsening then stops at
+                              coarse_max_rows, max_levels, or a level the aggregation
+                              does not reduce. */
   int power_iters;         /* power iterations for rho(D^-1 A^(n)), default 20 */
   int record_energy;       /* 1: measure 1/2 <P, A P> after every emin iteration */
   int profile;             /* 0: off.  1: time every eagerly launched kernel with HIP
@@ -152,7 +165,8 @@ void hcurl_amg_default_opts(hcurl_amg_opts* opts);
  *           aggregate ids 0..m_{l+1}-1, every id used (the non-overlapping
  *           aggregates of Sec. 2).  Level l+1's nodes are level l's aggregates.
  *           aggregates[0] may be NULL when opts.nodal_prolongator is given
- *           (n_agg_levels still counts level 0).
+ *           (n_agg_levels still counts level 0); with opts.aggregation =
+ *           HCURL_AGG_MIS2 any map may be NULL and n_agg_levels may be 0.
  *   out     receives the handle.
  * Errors: HCURL_EINVAL (shapes, D_h rows, non-positive diagonal, aggregate ids),
  * HCURL_EREDUCIBLE, HCURL_ENOTSPD, HCURL_EUNSUPPORTED, HCURL_EHIP, HCURL_ENOMEM.

@@ -29,6 +29,7 @@ Readings where the paper is silent or garbled (each is listed in the design doc):
       smoothed P^(n), as in the paper's runs (Sec. 4.1).
   R6  Reduce_Dimension drops the column of the largest coarse node id of T_i.
   R25 setup reuse (suggested in Sec. 3 and after Table 4): see ``update``.
+  R26 aggregates when the caller gives none: see ``mis2_aggregates``.
   R8  sparsity patterns are symbolic: products of absolute values, structural
       zeros kept (Alg. 2 uses |.|).
   R9  the energy is measured in A^(e) (footnote to eq. min2_hcurl allows it).
@@ -160,6 +161,58 @@ def tentative_prolongator(agg: np.ndarray, m_coarse: int) -> sp.csr_matrix:
     aggregate (Sec. 2)."""
     m = len(agg)
     return csr(sp.csr_matrix((np.ones(m), (np.arange(m), np.asarray(agg, np.int64))), shape=(m, m_coarse)))
+
+
+def mis2_aggregates(An: sp.csr_matrix) -> np.ndarray:
+    """Aggregates of the nodes of a level from its nodal graph (the pattern of
+    A^(n), diagonal aside) when the caller gives none -- not in the paper,
+    which takes aggregates from its smoothed-aggregation package (Sec. 6.1);
+    reading R26.  Roots form a distance-2 maximal independent set chosen in
+    Luby rounds with priority key(i) = (bits 30..63 of splitmix64(i), i); every
+    other node joins the root next to it, or, two steps away, the aggregate of
+    its neighbour of largest key among those next to a root.  Aggregate ids
+    follow the roots' node order."""
+    A = csr(An)
+    n = A.shape[0]
+    rows = np.repeat(np.arange(n), np.diff(A.indptr))
+    cols = A.indices.astype(np.int64)
+    key = ((splitmix64(np.arange(n)) >> np.uint64(34)) << np.uint64(32)) | np.arange(n, dtype=np.uint64)
+    UND, IN, OUT = 1, 2, 0
+    state = np.full(n, UND, np.int64)
+
+    def closed_max(v):
+        # max over i and its neighbours
+        m = v.copy()
+        np.maximum.at(m, rows, v[cols])
+        return m
+
+    while np.any(state == UND):
+        t = (state.astype(np.uint64) << np.uint64(62)) | key
+        m2 = closed_max(closed_max(t))
+        und = state == UND
+        win = und & (m2 == t)
+        lose = und & ~win & ((m2 >> np.uint64(62)) == np.uint64(IN))
+        state[win] = IN
+        state[lose] = OUT
+    roots = np.nonzero(state == IN)[0]
+    agg = np.full(n, -1, np.int64)
+    agg[roots] = np.arange(len(roots))
+    # next to a root (roots are at least three steps apart: one root each)
+    adj_root = (state[cols] == IN) & (rows != cols)
+    first = agg.copy()
+    first[rows[adj_root]] = agg[cols[adj_root]]
+    # two steps away: the neighbour of largest key among those next to a root
+    near = (first >= 0) & (agg < 0)  # assigned in the first step, not roots
+    cand = (first[rows] < 0) & near[cols]
+    best = np.zeros(n, np.uint64)
+    np.maximum.at(best, rows[cand], key[cols[cand]] + np.uint64(1))
+    second = first.copy()
+    todo = (first < 0) & (best > 0)
+    owner = (best[todo] - np.uint64(1)) & np.uint64(0xFFFFFFFF)
+    second[np.nonzero(todo)[0]] = first[owner.astype(np.int64)]
+    if np.any(second < 0):
+        raise ValueError("a node is more than two steps from every root (isolated node?)")
+    return second.astype(np.int32)
 
 
 def power_rho(An: sp.csr_matrix, iters: int = 20) -> float:
@@ -591,11 +644,26 @@ def setup(A, tail, head, m: int, aggregates, opts=None):
     opts = dict(opts or {})
     levels = []
     A = csr(A)
-    for li, agg in enumerate(aggregates):
+    li = 0
+    while True:
         if opts.get("max_levels") and li + 1 >= opts["max_levels"]:
             break
+        if opts.get("coarse_max_rows") and A.shape[0] <= opts["coarse_max_rows"]:
+            break
+        agg = aggregates[li] if li < len(aggregates) else None
+        if agg is None and not (li == 0 and opts.get("Pn") is not None):
+            if opts.get("aggregation") != "mis2":
+                if li < len(aggregates):
+                    raise ValueError("aggregates missing for a level")
+                break
+            # reading R26: aggregates from the level's nodal graph; a level
+            # whose aggregation does not reduce it stays the coarsest
+            agg = mis2_aggregates(nodal_operator(A, gradient_matrix(tail, head, m)))
+            if int(agg.max()) + 1 >= m:
+                break
+        li += 1
         lopts = dict(opts)
-        if li > 0:
+        if li > 1:
             lopts.pop("Pn", None)
             lopts.pop("p_init", None)
         lvl, (A, tail, head, m) = build_level(A, tail, head, m, None if agg is None else np.asarray(agg), lopts)

@@ -43,7 +43,7 @@ class hcurl_amg_opts(ctypes.Structure):
                 ("emin_method", ctypes.c_int), ("emin_omega", ctypes.c_double), ("init_guess", ctypes.c_int),
                 ("init_values", ctypes.c_void_p), ("emin_iters_given", ctypes.c_int), ("mpnn", ctypes.c_void_p),
                 ("vcycle_fp32", ctypes.c_int), ("nodal_prolongator", ctypes.c_void_p), ("alg1_passes", ctypes.c_int),
-                ("pbar_alg1", ctypes.c_int),
+                ("pbar_alg1", ctypes.c_int), ("aggregation", ctypes.c_int),
                 ("power_iters", ctypes.c_int), ("record_energy", ctypes.c_int), ("profile", ctypes.c_int),
                 ("mem_space", ctypes.c_int), ("stream", ctypes.c_void_p)]
 
@@ -184,6 +184,8 @@ def hcurl_amg_default_opts(**overrides) -> hcurl_amg_opts:
             v = MEM[v]
         if k == "init_values":
             v = _ptr(v)
+        if k == "aggregation" and isinstance(v, str):
+            v = {"given": 0, "mis2": 1}[v]
         if k == "mpnn" and v is not None and not isinstance(v, (int, ctypes.c_void_p)):
             v = v.h  # a Network
         if k == "nodal_prolongator" and v is not None:

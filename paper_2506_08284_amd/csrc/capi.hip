@@ -71,6 +71,7 @@ void hcurl_amg_default_opts(hcurl_amg_opts* o) {
   o->nodal_prolongator = nullptr;
   o->alg1_passes = 2;
   o->pbar_alg1 = 0;
+  o->aggregation = HCURL_AGG_GIVEN;
   o->power_iters = 20;
   o->record_energy = 0;
   o->profile = 0;
@@ -89,6 +90,8 @@ int hcurl_amg_setup(const hcurl_csr* A, const hcurl_csr* Dh, const double* coord
     if (opts) h->H.opts = *opts; else hcurl_amg_default_opts(&h->H.opts);
     if (h->H.opts.emin_iters < 0 || h->H.opts.power_iters < 1) hc::fail(HCURL_EINVAL, "bad iteration counts");
     if (h->H.opts.profile < 0 || h->H.opts.profile > 3) hc::fail(HCURL_EINVAL, "profile must be 0, 1, 2 or 3");
+    if (h->H.opts.aggregation != HCURL_AGG_GIVEN && h->H.opts.aggregation != HCURL_AGG_MIS2)
+      hc::fail(HCURL_EINVAL, "unknown aggregation");
     if ((h->H.opts.nodal_prolongator || h->H.opts.pbar_alg1) && h->H.opts.alg1_passes < 1)
       hc::fail(HCURL_EINVAL, "alg1_passes must be >= 1");
     h->H.ctx.init((hipStream_t)h->H.opts.stream, h->H.opts.profile != 0);

@@ -973,7 +973,107 @@ static void alg1_aggregates(Hierarchy& H, Level& L, DBuf<int>& assign) {
 }
 
 // Everything that builds the transfer from level L to a new level.
-static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg_in, bool level0) {
+// ---------------------------------------------------------------------------
+// MIS-2 aggregation from the nodal graph when the caller gives no aggregates
+// (not in the paper; reading R26).  Roots: distance-2 maximal independent set
+// in Luby rounds on tuples (state, key); every other node joins the root next
+// to it, or, two steps away, the aggregate of its neighbour of largest key
+// among those next to a root.  Aggregate ids follow the roots' node order.
+// ---------------------------------------------------------------------------
+enum { MIS_OUT = 0, MIS_UND = 1, MIS_IN = 2 };
+__device__ __forceinline__ unsigned long long mis_key(int i) {
+  return ((splitmix64((uint64_t)i) >> 34) << 32) | (unsigned long long)(unsigned)i;
+}
+__global__ void k_mis_tuple(const int* __restrict__ state, int n, unsigned long long* __restrict__ t) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) t[i] = ((unsigned long long)state[i] << 62) | mis_key(i);
+}
+// out_i = max over i and its neighbours of in
+__global__ void k_closed_max(const int* __restrict__ rp, const int* __restrict__ col, int n,
+                             const unsigned long long* __restrict__ in, unsigned long long* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  unsigned long long m = in[i];
+  for (int q = rp[i]; q < rp[i + 1]; ++q) {
+    const unsigned long long v = in[col[q]];
+    m = v > m ? v : m;
+  }
+  out[i] = m;
+}
+__global__ void k_mis_update(int n, const unsigned long long* __restrict__ t, const unsigned long long* __restrict__ m2,
+                             int* __restrict__ state, long long* __restrict__ undecided) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || state[i] != MIS_UND) return;
+  if (m2[i] == t[i]) state[i] = MIS_IN;
+  else if ((m2[i] >> 62) == (unsigned long long)MIS_IN) state[i] = MIS_OUT;
+  else atomicAdd((unsigned long long*)undecided, 1ULL);
+}
+__global__ void k_mis_rootflag(const int* __restrict__ state, int n, int* __restrict__ flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flag[i] = state[i] == MIS_IN;
+}
+__global__ void k_mis_first(const int* __restrict__ rp, const int* __restrict__ col, int n, const int* __restrict__ state,
+                            const int* __restrict__ rid, int* __restrict__ first) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (state[i] == MIS_IN) { first[i] = rid[i]; return; }
+  int a = -1;
+  for (int q = rp[i]; q < rp[i + 1]; ++q) {
+    const int j = col[q];
+    if (j != i && state[j] == MIS_IN) a = rid[j];  // roots are three or more steps apart: at most one
+  }
+  first[i] = a;
+}
+__global__ void k_mis_second(const int* __restrict__ rp, const int* __restrict__ col, int n, const int* __restrict__ state,
+                             const int* __restrict__ first, int* __restrict__ agg, long long* __restrict__ bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (first[i] >= 0) { agg[i] = first[i]; return; }
+  unsigned long long best = 0ULL;
+  int a = -1;
+  for (int q = rp[i]; q < rp[i + 1]; ++q) {
+    const int j = col[q];
+    if (j == i || first[j] < 0 || state[j] == MIS_IN) continue;
+    const unsigned long long k = mis_key(j) + 1ULL;
+    if (k > best) { best = k; a = first[j]; }
+  }
+  agg[i] = a;
+  if (a < 0) atomicAdd((unsigned long long*)bad, 1ULL);
+}
+
+// Writes L.agg from the graph of L.An; returns the number of aggregates.
+static int mis2_aggregates(Hierarchy& H, Level& L) {
+  Ctx& c = H.ctx;
+  const int n = L.m;
+  const Csr& G = L.An;
+  DBuf<int> state(n, c.s), flag(n + 1, c.s), rid(n + 1, c.s), first(n, c.s);
+  DBuf<unsigned long long> t(n, c.s), m1(n, c.s), m2(n, c.s);
+  fill_int(state.p, MIS_UND, n, c);
+  for (int round = 0;; ++round) {
+    if (round > n + 1) fail(HCURL_EHIP, "MIS-2 rounds did not terminate");
+    clear_flag(F_BAD, c);
+    c.run("mis2_round", 8.0 * n + 24.0 * G.nnz, [&] {
+      k_mis_tuple<<<ceil_div(n, 256), 256, 0, c.s>>>(state.p, n, t.p);
+      k_closed_max<<<ceil_div(n, 256), 256, 0, c.s>>>(G.rowptr.p, G.col.p, n, t.p, m1.p);
+      k_closed_max<<<ceil_div(n, 256), 256, 0, c.s>>>(G.rowptr.p, G.col.p, n, m1.p, m2.p);
+      k_mis_update<<<ceil_div(n, 256), 256, 0, c.s>>>(n, t.p, m2.p, state.p, c.iscal.p + F_BAD);
+    });
+    if (read_flag(F_BAD, c) == 0) break;
+  }
+  k_mis_rootflag<<<ceil_div(n, 256), 256, 0, c.s>>>(state.p, n, flag.p);
+  HC_LAUNCH_CHECK();
+  const int nroots = (int)exclusive_scan(flag.p, rid.p, n, c);
+  L.agg.alloc(n, c.s);
+  clear_flag(F_BAD, c);
+  c.run("mis2_attach", 16.0 * G.nnz, [&] {
+    k_mis_first<<<ceil_div(n, 256), 256, 0, c.s>>>(G.rowptr.p, G.col.p, n, state.p, rid.p, first.p);
+    k_mis_second<<<ceil_div(n, 256), 256, 0, c.s>>>(G.rowptr.p, G.col.p, n, state.p, first.p, L.agg.p, c.iscal.p + F_BAD);
+  });
+  if (read_flag(F_BAD, c)) fail(HCURL_EHIP, "MIS-2 aggregation left a node unassigned");
+  return nroots;
+}
+
+static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg_in, bool level0, bool agg_ready) {
   Ctx& c = H.ctx;
   const bool dev = H.opts.mem_space == HCURL_MEM_DEVICE;
   // a caller-given nodal prolongator replaces smoothed aggregation on level 0
@@ -987,16 +1087,18 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
     HC_LAUNCH_CHECK();
     if (read_flag(F_BAD, c))
       fail(HCURL_EINVAL, "a row of the given P^(n) is empty, sums to zero or holds a non-finite value");
-  } else if (!agg_in) {
+  } else if (!agg_in && !agg_ready) {
     fail(HCURL_EINVAL, "aggregates missing for a level");
   }
-  // aggregates: the caller's, or Alg. 1 on the given P^(n)
-  L.agg.alloc(L.m, c.s);
+  // aggregates: the caller's, MIS-2's (already in L.agg), or Alg. 1 on the given P^(n)
   DBuf<int>& agg = L.agg;
-  if (agg_in)
-    HC_HIP(hipMemcpyAsync(agg.p, agg_in, sizeof(int) * L.m, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c.s));
-  else
-    alg1_aggregates(H, L, agg);
+  if (!agg_ready) {
+    L.agg.alloc(L.m, c.s);
+    if (agg_in)
+      HC_HIP(hipMemcpyAsync(agg.p, agg_in, sizeof(int) * L.m, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c.s));
+    else
+      alg1_aggregates(H, L, agg);
+  }
   std::vector<int> hagg(L.m);
   d2h(hagg.data(), agg.p, L.m, c);
   int mH = 0;
@@ -1012,8 +1114,8 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
     for (int v : hagg) seen[v] = 1;
     for (char s : seen)
       if (!s)
-        fail(HCURL_EINVAL, agg_in ? "aggregate ids are not contiguous (an id is unused)"
-                                  : "Alg. 1 left a coarse node of the given P^(n) without fine nodes");
+        fail(HCURL_EINVAL, agg_in || agg_ready ? "aggregate ids are not contiguous (an id is unused)"
+                                               : "Alg. 1 left a coarse node of the given P^(n) without fine nodes");
   }
   // smoothed aggregation P^(n)
   if (!Pgiven) smoothed_aggregation(H, L, agg.p, mH);
@@ -1141,13 +1243,21 @@ void build_hierarchy(Hierarchy& H, const hcurl_csr& A, const hcurl_csr& Dh, cons
   const int maxl = H.opts.max_levels > 0 ? H.opts.max_levels : 1 << 20;
   for (int l = 0;; ++l) {
     Level& L = *H.lv.back();
-    const bool stop = l >= nagg || (int)H.lv.size() >= maxl ||
+    const int32_t* amap = l < nagg ? aggs[l] : nullptr;
+    const bool given_pn = l == 0 && H.opts.nodal_prolongator != nullptr;
+    const bool auto_agg = !amap && !given_pn && H.opts.aggregation == HCURL_AGG_MIS2;
+    const bool stop = (l >= nagg && !auto_agg) || (int)H.lv.size() >= maxl ||
                       (H.opts.coarse_max_rows > 0 && L.n <= H.opts.coarse_max_rows);
     if (stop) break;
     level_operators(H, L);
+    // a level whose MIS-2 aggregation does not reduce it stays the coarsest
+    if (auto_agg && mis2_aggregates(H, L) >= L.m) {
+      L.agg.release();
+      break;
+    }
     color_rows(L.A, L.colorA, L.rowsA, L.cptrA, L.ncolA, c);
     color_rows(L.An, L.colorAn, L.rowsAn, L.cptrAn, L.ncolAn, c);
-    H.lv.push_back(coarsen(H, L, aggs[l], l == 0));
+    H.lv.push_back(coarsen(H, L, amap, l == 0, auto_agg));
   }
   H.pn_given = H.opts.nodal_prolongator != nullptr;
   coarsest_factor(H, *H.lv.back());

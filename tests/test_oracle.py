@@ -12,6 +12,7 @@ import pytest
 import scipy.linalg as sla
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
+from scipy.sparse.csgraph import connected_components
 
 import synth
 from oracle import hcurl_oracle as O
@@ -608,3 +609,84 @@ def test_update_warm_start_meets_the_new_constraints():
     _, it_f, _, _ = O.pcg(fresh, p2["f"])
     _, it_w, rel, _ = O.pcg(w, p2["f"])
     assert rel <= 1e-8 and it_w <= it_f + 2
+
+
+# ---------------------------------------------------------------------------
+# MIS-2 aggregation when the caller gives no aggregates (reading R26)
+# ---------------------------------------------------------------------------
+def _graph_lists(An):
+    An = O.csr(An)
+    return [[int(j) for j in An.indices[An.indptr[i]:An.indptr[i + 1]] if j != i] for i in range(An.shape[0])]
+
+
+def _mis2_by_hand(An):
+    """Sequential definition: nodes in decreasing key order, a node becomes a
+    root unless a root lies within two steps; then the two attachment rules."""
+    nb = _graph_lists(An)
+    n = len(nb)
+    key = [((int(O.splitmix64(np.array([i]))[0]) >> 34) << 32) | i for i in range(n)]
+    dist2 = [set(nb[i]) | {k for j in nb[i] for k in nb[j]} for i in range(n)]
+    roots = []
+    taken = set()
+    for i in sorted(range(n), key=lambda v: -key[v]):
+        if not (dist2[i] & taken):
+            taken.add(i)
+    roots = sorted(taken)
+    rid = {r: a for a, r in enumerate(roots)}
+    agg = [-1] * n
+    for r in roots:
+        agg[r] = rid[r]
+    first = list(agg)
+    for i in range(n):
+        if agg[i] < 0:
+            near = [j for j in nb[i] if j in rid]
+            if near:
+                assert len(near) == 1
+                first[i] = rid[near[0]]
+    out = list(first)
+    for i in range(n):
+        if first[i] < 0:
+            cand = [j for j in nb[i] if first[j] >= 0 and j not in rid]
+            out[i] = first[max(cand, key=lambda j: key[j])]
+    return np.array(out), roots
+
+
+@pytest.mark.parametrize("N,jit", [(4, 0.0), (6, 0.2)])
+def test_mis2_aggregates_match_the_sequential_definition(N, jit):
+    """The Luby rounds choose the roots a sequential sweep in decreasing key
+    order chooses (distance-2 greedy); both attachment steps by hand."""
+    p = synth.problem(N, jitter=jit, jitter_seed=3, sigma=("lognormal", 2, 1.0))
+    m = (N + 1) ** 3
+    An = O.nodal_operator(O.csr(p["A"]), O.gradient_matrix(p["tail"], p["head"], m))
+    ref, roots = _mis2_by_hand(An)
+    got = O.mis2_aggregates(An)
+    assert np.array_equal(got, ref)
+    # roots three or more steps apart, every node within two steps of one
+    nb = _graph_lists(An)
+    rs = set(roots)
+    for r in roots:
+        assert not ((set(nb[r]) | {k for j in nb[r] for k in nb[j]}) - {r}) & rs
+    for i in range(m):
+        assert i in rs or (set(nb[i]) | {k for j in nb[i] for k in nb[j]}) & rs
+
+
+def test_mis2_hierarchy_converges():
+    """Setup with no aggregates at all: MIS-2 on every level's nodal graph
+    down to coarse_max_rows; aggregates are connected in the nodal graph, the
+    commuting relation holds and PCG converges."""
+    p = synth.problem(12, jitter=0.2, jitter_seed=5, sigma=("lognormal", 6, 2.0), f_seed=7)
+    m = 13 ** 3
+    lv = O.setup(p["A"], p["tail"], p["head"], m, [], dict(aggregation="mis2", coarse_max_rows=200))
+    assert len(lv) >= 3 and lv[-1]["A"].shape[0] <= 200
+    for l in lv[:-1]:
+        assert O.commuting_residual(l) <= 1e-12
+        assert l["irreducible_added"] == 0
+        a = l["agg"]
+        G = O.csr(l["An"])
+        same = a[np.repeat(np.arange(len(a)), np.diff(G.indptr))] == a[G.indices]
+        sub = sp.csr_matrix((same.astype(float), G.indices, G.indptr), shape=G.shape)
+        sub.eliminate_zeros()
+        ncomp, lab = connected_components(sub, directed=False)
+        assert ncomp == a.max() + 1
+    _, it, rel, _ = O.pcg(lv, p["f"])
+    assert rel <= 1e-8 and it < 60
