@@ -46,8 +46,8 @@ enum {
   HCURL_EINVAL = -1,       /* malformed input (shapes, D_h rows, diagonal, sizes) */
   HCURL_EHIP = -2,         /* HIP runtime error */
   HCURL_ENOMEM = -3,       /* device allocation failed */
-  HCURL_EREDUCIBLE = -4,   /* a local coarse-edge graph is disconnected (Sec. 4.2);
-                              the edge-adding repair is not implemented on the GPU */
+  HCURL_EREDUCIBLE = -4,   /* a local coarse-edge graph stayed disconnected (Sec. 4.2)
+                              after 64 rounds of the edge-adding repair */
   HCURL_ENOTSPD = -5,      /* non-positive curvature in projected CG or a failed
                               Cholesky of a local or coarsest system */
   HCURL_EMAXIT = -6,       /* PCG stopped at maxit above the tolerance */
@@ -205,6 +205,9 @@ typedef struct {
                               the relative rounding error of A x for a gradient
                               field x, in units of the precision of A (0 on the
                               coarsest level) */
+  int64_t irreducible_added; /* coarse edges that make_irreducible (Alg. 2) added to
+                              D_{l+1} beyond the RS edges; they are merged into the
+                              lexicographic edge order */
 } hcurl_level_info;
 
 int hcurl_amg_level_info(hcurl_amg h, int level, hcurl_level_info* info);

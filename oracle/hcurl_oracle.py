@@ -41,7 +41,8 @@ Readings where the paper is silent or garbled (each is listed in the design doc):
       in Sec. 6.1).
   R13 the nodal operator is A^(n) = D_h^T A^(e) D_h (the Hiptmair smoother of
       Sec. 6.1 applies exactly this product).
-  R15 make_irreducible: two-phase, see ``make_irreducible``.
+  R15 make_irreducible: two-phase, new edges merged into the order of R1;
+      see ``make_irreducible``.
   R18 Gauss-Seidel runs in a multicolour order (Jones-Plassmann, hashed
       priorities) shared with the GPU path.
   R19 PCG stops on the recursive residual, ||r|| <= tol ||b||; the FP32 V-cycle
@@ -476,8 +477,9 @@ def make_irreducible(D, Pn, DH_tail, DH_head, mH):
     """Reading R15 of make_irreducible (Alg. 2): while some row's local graph is
     disconnected, collect for every such row one new coarse edge (I, K), I in
     the component holding the row's smallest coarse node, K outside it, chosen
-    by the largest |(P^T D^T D P)_IK| (ties: smallest (min, max) pair); append
-    the deduplicated new edges, sorted, after the existing ones; rebuild N."""
+    by the largest |(P^T D^T D P)_IK| (ties: smallest (min, max) pair); merge
+    the deduplicated new edges into the lexicographic edge order of reading R1;
+    rebuild N."""
     tail = np.asarray(DH_tail, np.int32)
     head = np.asarray(DH_head, np.int32)
     added_total = 0
@@ -507,9 +509,9 @@ def make_irreducible(D, Pn, DH_tail, DH_head, mH):
                     if best is None or cand < best:
                         best = cand
             new.add((best[1], best[2]))
-        new = sorted(new)
-        tail = np.r_[tail, np.array([e[0] for e in new], np.int32)]
-        head = np.r_[head, np.array([e[1] for e in new], np.int32)]
+        edges = sorted(set(zip(tail.tolist(), head.tolist())) | new)
+        tail = np.array([e[0] for e in edges], np.int32)
+        head = np.array([e[1] for e in edges], np.int32)
         added_total += len(new)
     raise RuntimeError("make_irreducible did not converge")
 

@@ -53,7 +53,7 @@ class hcurl_level_info(ctypes.Structure):
                 ("nnz_An", ctypes.c_int64), ("nnz_Pe", ctypes.c_int64), ("nnz_Pn", ctypes.c_int64),
                 ("nnz_T", ctypes.c_int64), ("n_coarse_edges", ctypes.c_int64), ("n_colors_A", ctypes.c_int32),
                 ("n_colors_An", ctypes.c_int32), ("rho", ctypes.c_double), ("omega", ctypes.c_double),
-                ("cancellation_ratio", ctypes.c_double)]
+                ("cancellation_ratio", ctypes.c_double), ("irreducible_added", ctypes.c_int64)]
 
 
 class hcurl_amg_stats_t(ctypes.Structure):

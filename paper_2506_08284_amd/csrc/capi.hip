@@ -177,6 +177,7 @@ int hcurl_amg_level_info(hcurl_amg h, int level, hcurl_level_info* info) {
     info->nnz_Pn = L->Pn.nnz;
     info->nnz_T = L->R.nnz;
     info->n_coarse_edges = L->n_coarse;
+    info->irreducible_added = L->irreducible_added;
     info->n_colors_A = L->ncolA;
     info->n_colors_An = L->ncolAn;
     info->rho = L->rho;

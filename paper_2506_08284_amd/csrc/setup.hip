@@ -9,7 +9,7 @@
 namespace hc {
 
 // device scalar slots (Ctx::scal)
-enum { S_RHO = 0, S_GAMMA, S_ALPHA, S_RHONEW, S_BETA, S_NX2, S_NY2, S_POWRHO, S_OMEGA, S_ENERGY };
+enum { S_RHO = 0, S_GAMMA, S_ALPHA, S_RHONEW, S_BETA, S_NX2, S_NY2, S_POWRHO, S_OMEGA, S_ENERGY, S_RHO0 };
 // device integer flag slots (Ctx::iscal); 0 and 1 are used by the primitives
 enum { F_BAD = 2, F_DISCONNECTED, F_MAXJ, F_MAXNP, F_TOOBIG, F_NOTSPD };
 
@@ -340,6 +340,110 @@ __global__ void k_pattern(int n, const int* __restrict__ Trp, const int* __restr
 }
 
 // ---------------------------------------------------------------------------
+// make_irreducible (Alg. 2; reading R15).  For every fine edge whose local
+// graph is disconnected: the component of the row's smallest coarse node is
+// joined to the rest by the pair (I, K), I inside, K outside, of largest
+// |(P^(n)T D^T D P^(n))_IK| (ties: smallest (min, max) pair).  The new coarse
+// edges are merged into the lexicographic edge order, and the pattern is
+// rebuilt until every row is connected.
+// ---------------------------------------------------------------------------
+__global__ void k_irreducible_pick(int n, const int* __restrict__ Trp, const int* __restrict__ Tcol,
+                                   const int* __restrict__ tptr, const int* __restrict__ chead,
+                                   const int* __restrict__ Zrp, const int* __restrict__ Zcol,
+                                   const double* __restrict__ Zval, unsigned long long* __restrict__ cand) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  cand[i] = ~0ULL;
+  const int t0 = Trp[i];
+  const int nJ = Trp[i + 1] - t0;
+  if (nJ < 2 || nJ > kMaxJ) return;
+  unsigned adj[kMaxJ];
+  for (int a = 0; a < nJ; ++a) adj[a] = 0u;
+  for (int a = 0; a < nJ; ++a) {
+    const int I = Tcol[t0 + a];
+    for (int e = tptr[I]; e < tptr[I + 1]; ++e) {
+      const int K = chead[e];
+      int lo = a + 1, hi = nJ - 1;
+      while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int v = Tcol[t0 + mid];
+        if (v == K) { adj[a] |= 1u << mid; adj[mid] |= 1u << a; break; }
+        if (v < K) lo = mid + 1; else hi = mid - 1;
+      }
+    }
+  }
+  unsigned reach = 1u, prev = 0u;
+  while (reach != prev) {
+    prev = reach;
+    for (int a = 0; a < nJ; ++a)
+      if (reach >> a & 1u) reach |= adj[a];
+  }
+  const unsigned all = nJ == 32 ? 0xffffffffu : ((1u << nJ) - 1u);
+  if (reach == all) return;
+  double bw = -1.0;
+  int blo = 0, bhi = 0;
+  for (int p = 0; p < nJ; ++p) {
+    if (!(reach >> p & 1u)) continue;
+    for (int q = 0; q < nJ; ++q) {
+      if (reach >> q & 1u) continue;
+      const int I = Tcol[t0 + p], K = Tcol[t0 + q];
+      const int lo = I < K ? I : K, hi = I < K ? K : I;
+      double w = 0.0;
+      int l = Zrp[lo], h = Zrp[lo + 1] - 1;
+      while (l <= h) {
+        const int mid = (l + h) >> 1;
+        const int v = Zcol[mid];
+        if (v == hi) { w = fabs(Zval[mid]); break; }
+        if (v < hi) l = mid + 1; else h = mid - 1;
+      }
+      const bool better = w > bw || (w == bw && (lo < blo || (lo == blo && hi < bhi)));
+      if (better) { bw = w; blo = lo; bhi = hi; }
+    }
+  }
+  cand[i] = ((unsigned long long)(unsigned)blo << 32) | (unsigned)bhi;
+}
+__global__ void k_cand_count(int n, const unsigned long long* __restrict__ cand, int* __restrict__ cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && cand[i] != ~0ULL) atomicAdd(&cnt[(int)(cand[i] >> 32)], 1);
+}
+__global__ void k_cand_fill(int n, const unsigned long long* __restrict__ cand, int* __restrict__ cursor,
+                            int* __restrict__ xcol) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && cand[i] != ~0ULL) xcol[atomicAdd(&cursor[(int)(cand[i] >> 32)], 1)] = (int)(cand[i] & 0xffffffffu);
+}
+// Per coarse node I: the union of its present upper neighbours (sorted) and
+// the new ones (sorted here, duplicates dropped); FILL writes the merged edges.
+template <bool FILL>
+__global__ void k_edge_union(int mH, const int* __restrict__ tptr, const int* __restrict__ chead,
+                             const int* __restrict__ xptr, int* __restrict__ xcol, int* __restrict__ cnt,
+                             const int* __restrict__ nptr, int* __restrict__ ntail, int* __restrict__ nhead) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= mH) return;
+  const int xa = xptr[I], xb = xptr[I + 1];
+  if (!FILL)
+    for (int q = xa + 1; q < xb; ++q) {
+      const int key = xcol[q];
+      int r = q - 1;
+      while (r >= xa && xcol[r] > key) { xcol[r + 1] = xcol[r]; --r; }
+      xcol[r + 1] = key;
+    }
+  int a = tptr[I];
+  const int b = tptr[I + 1];
+  int x = xa, c = 0, last = -1;
+  const int o = FILL ? nptr[I] : 0;
+  while (a < b || x < xb) {
+    int v;
+    if (x >= xb || (a < b && chead[a] <= xcol[x])) v = chead[a++];
+    else v = xcol[x++];
+    if (v == last) continue;
+    last = v;
+    if (FILL) { ntail[o + c] = I; nhead[o + c] = v; }
+    ++c;
+  }
+  if (!FILL) cnt[I] = c;
+}
+
+// ---------------------------------------------------------------------------
 // local constraint systems (Sec. 4.2).  For row i with coarse nodes T_i
 // (|J| = nJ) and pattern entries e = (local tail t_e, local head h_e), the
 // transposed sub-matrix G~ keeps all nodes but the last (largest id); its
@@ -628,11 +732,16 @@ __global__ void k_cg_dir(int64_t n, double* __restrict__ D, const double* __rest
   if (i < n) D[i] = R[i] + *beta * D[i];
 }
 // alpha = rho / gamma (0 when rho = 0); flags gamma <= 0 with rho > 0
+// Once the projected gradient has fallen to 1e-12 of its first norm the
+// minimiser is reached to rounding: the curvature is then rounding noise
+// (either sign) and the iterate is left as it is.
 __global__ void k_cg_alpha(double* __restrict__ sc, long long* __restrict__ iflags) {
   const double rho = sc[S_RHO], gamma = sc[S_GAMMA];
-  if (rho > 0.0 && !(gamma > 0.0)) iflags[F_NOTSPD] += 1;
-  sc[S_ALPHA] = (gamma > 0.0) ? rho / gamma : 0.0;
+  const bool converged = rho <= 1e-24 * sc[S_RHO0];
+  if (rho > 0.0 && !converged && !(gamma > 0.0)) iflags[F_NOTSPD] += 1;
+  sc[S_ALPHA] = (gamma > 0.0 && !converged) ? rho / gamma : 0.0;
 }
+__global__ void k_copy_scalar(const double* __restrict__ a, double* __restrict__ b) { *b = *a; }
 __global__ void k_cg_beta(double* __restrict__ sc) {
   const double rho = sc[S_RHO], rn = sc[S_RHONEW];
   sc[S_BETA] = rho > 0.0 ? rn / rho : 0.0;
@@ -840,6 +949,7 @@ static void energy_minimisation(Hierarchy& H, Level& L, const Level* next, int i
     emin_apply(L, nullptr, w.P.p, w.Rv.p, EM_PROJECT | EM_NEGATE, w.part.p, w.Y.p, c);
     d2d(w.Dir.p, w.Rv.p, np, c);
     dot(w.Rv.p, w.Rv.p, np, sc + S_RHO, c, 0);
+    c.run("cg_scalar", 0.0, [&] { k_copy_scalar<<<1, 1, 0, c.s>>>(sc + S_RHO, sc + S_RHO0); });
     const int ub = Ctx::kRedBlocks;
     const int nbu = (int)std::min<int64_t>(ub, std::max<int64_t>(1, (np + 255) / 256));
     for (int it = 0; it < iters; ++it) {
@@ -1162,19 +1272,58 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
   L.n_coarse = next->n;
   // T and R = D P^(n) on T
   spgemm(L.D, L.Pn, L.R, true, c, "spgemm_DPn");
-  // pattern N
+  // pattern N, with make_irreducible while a local graph is disconnected
   {
-    for (int f = F_DISCONNECTED; f <= F_TOOBIG; ++f) clear_flag(f, c);
     DBuf<int> cnt(L.n + 1, c.s);
-    c.run("pattern", 8.0 * L.R.nnz, [&] {
-      k_pattern<false><<<ceil_div(L.n, 128), 128, 0, c.s>>>(L.n, L.R.rowptr.p, L.R.col.p, tptr.p, next->head.p, cnt.p,
-                                                            nullptr, nullptr, nullptr, c.iscal.p);
-    });
     long long fl[6];
-    d2h(fl, c.iscal.p, 6, c);
-    if (fl[F_TOOBIG]) fail(HCURL_EUNSUPPORTED, "a fine edge touches more than 32 coarse nodes");
-    if (fl[F_DISCONNECTED])
-      fail(HCURL_EREDUCIBLE, std::to_string(fl[F_DISCONNECTED]) + " rows have a disconnected local coarse-edge graph");
+    Csr Zw;  // P^(n)T D^T D P^(n) = R^T R, formed on the first repair
+    L.irreducible_added = 0;
+    for (int round = 0;; ++round) {
+      for (int f = F_DISCONNECTED; f <= F_TOOBIG; ++f) clear_flag(f, c);
+      c.run("pattern", 8.0 * L.R.nnz, [&] {
+        k_pattern<false><<<ceil_div(L.n, 128), 128, 0, c.s>>>(L.n, L.R.rowptr.p, L.R.col.p, tptr.p, next->head.p,
+                                                              cnt.p, nullptr, nullptr, nullptr, c.iscal.p);
+      });
+      d2h(fl, c.iscal.p, 6, c);
+      if (fl[F_TOOBIG]) fail(HCURL_EUNSUPPORTED, "a fine edge touches more than 32 coarse nodes");
+      if (!fl[F_DISCONNECTED]) break;
+      if (round == 64)
+        fail(HCURL_EREDUCIBLE, std::to_string(fl[F_DISCONNECTED]) + " rows stay disconnected after 64 repair rounds");
+      if (!Zw.rowptr.p) {
+        Csr RT;
+        transpose(L.R, RT, true, c);
+        spgemm(RT, L.R, Zw, true, c, "spgemm_RtR");
+      }
+      DBuf<unsigned long long> cand(L.n, c.s);
+      DBuf<int> xcnt(mH + 1, c.s), xptr(mH + 1, c.s), cursor(mH + 1, c.s), ucnt(mH + 1, c.s);
+      c.run("irreducible_pick", 8.0 * L.R.nnz, [&] {
+        k_irreducible_pick<<<ceil_div(L.n, 128), 128, 0, c.s>>>(L.n, L.R.rowptr.p, L.R.col.p, tptr.p, next->head.p,
+                                                               Zw.rowptr.p, Zw.col.p, Zw.val.p, cand.p);
+      });
+      HC_HIP(hipMemsetAsync(xcnt.p, 0, sizeof(int) * (mH + 1), c.s));
+      k_cand_count<<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.n, cand.p, xcnt.p);
+      HC_LAUNCH_CHECK();
+      const int64_t nx = exclusive_scan(xcnt.p, xptr.p, mH, c);
+      DBuf<int> xcol(std::max<int64_t>(nx, 1), c.s);
+      d2d(cursor.p, xptr.p, mH + 1, c);
+      k_cand_fill<<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.n, cand.p, cursor.p, xcol.p);
+      HC_LAUNCH_CHECK();
+      k_edge_union<false><<<ceil_div(mH, 256), 256, 0, c.s>>>(mH, tptr.p, next->head.p, xptr.p, xcol.p, ucnt.p,
+                                                              nullptr, nullptr, nullptr);
+      HC_LAUNCH_CHECK();
+      DBuf<int> nptr(mH + 1, c.s);
+      const int64_t nH = exclusive_scan(ucnt.p, nptr.p, mH, c);
+      DBuf<int> ntail(nH, c.s), nhead(nH, c.s);
+      k_edge_union<true><<<ceil_div(mH, 256), 256, 0, c.s>>>(mH, tptr.p, next->head.p, xptr.p, xcol.p, nullptr, nptr.p,
+                                                             ntail.p, nhead.p);
+      HC_LAUNCH_CHECK();
+      L.irreducible_added += nH - next->n;
+      next->n = (int)nH;
+      next->tail = std::move(ntail);
+      next->head = std::move(nhead);
+      tptr = std::move(nptr);
+    }
+    L.n_coarse = next->n;
     L.maxJ = (int)fl[F_MAXJ];
     L.maxNp = (int)fl[F_MAXNP];
     if (L.maxNp > kPatCap) fail(HCURL_EUNSUPPORTED, "a row of P^(e) has more than 512 pattern entries");
