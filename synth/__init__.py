@@ -271,3 +271,116 @@ def gradient_csr(tail: np.ndarray, head: np.ndarray):
     val = np.stack([np.where(up, -1.0, 1.0), np.where(up, 1.0, -1.0)], axis=1).ravel()
     rowptr = np.arange(0, 2 * n + 1, 2, dtype=np.int64)
     return rowptr, np.ascontiguousarray(col), np.ascontiguousarray(val)
+
+
+# ---------------------------------------------------------------------------
+# Hexahedral meshes with lowest-order Nedelec (first kind) edge elements: the
+# hex column of the 3D model problems (Sec. 6.1, Table 3).  Unit cube, N^3
+# axis-aligned cubes of side h = 1/N, natural boundary conditions.
+# ---------------------------------------------------------------------------
+def hex_mesh(N: int) -> dict:
+    """Lattice nodes (id = i + n j + n^2 k, n = N+1) and the axis edges,
+    oriented low -> high id and sorted by (tail, head); hex_edges[h, e] is the
+    global edge of local edge e of hex h (local order: x-edges at (y, z) =
+    (0,0), (1,0), (0,1), (1,1), then y-edges at (x, z), then z-edges at (x, y))."""
+    n = N + 1
+    v = np.arange(n ** 3, dtype=np.int64)
+    i, j, k = v % n, (v // n) % n, v // (n * n)
+    tails, dirs = [], []
+    for d, (ok, step) in enumerate(((i < N, 1), (j < N, n), (k < N, n * n))):
+        tails.append(v[ok])
+        dirs.append(np.full(int(ok.sum()), d, np.int64))
+    tail = np.concatenate(tails)
+    dirv = np.concatenate(dirs)
+    key = tail * 3 + dirv  # for one tail, +1 < +n < +n^2
+    order = np.argsort(key, kind="stable")
+    tail, dirv, key = tail[order], dirv[order], key[order]
+    head = tail + np.array([1, n, n * n])[dirv]
+    c = np.arange(N, dtype=np.int64)
+    hk, hj, hi = np.meshgrid(c, c, c, indexing="ij")
+    base = (hi + n * hj + n * n * hk).ravel()
+    loc = []
+    for d, step in ((0, 1), (1, n), (2, n * n)):
+        others = [s for s in (1, n, n * n) if s != step]
+        for c2 in (0, 1):
+            for c1 in (0, 1):
+                loc.append(base * 3 + d * 1 + 3 * (c1 * others[0] + c2 * others[1]))
+    hex_edges = np.searchsorted(key, np.stack(loc, axis=1)).astype(np.int32)
+    ax = np.arange(n, dtype=np.float64) / N
+    kk, jj, ii = np.meshgrid(ax, ax, ax, indexing="ij")
+    coords = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1).copy()
+    return dict(N=N, n=n, coords=coords, hex_edges=hex_edges, tail=tail.astype(np.int32), head=head.astype(np.int32))
+
+
+def hex_reference_matrices():
+    """12 x 12 mass and curl-curl matrices of the unit cube.  Basis of the
+    x-edge at (y, z) = (b, c): phi_b(y) phi_c(z) e_x with phi_0 = 1 - t,
+    phi_1 = t (tangential moment one along +x); y- and z-edges alike.  Exact
+    3-point Gauss quadrature per direction (the integrands are quadratic)."""
+    g = np.array([-np.sqrt(0.6), 0.0, np.sqrt(0.6)]) * 0.5 + 0.5
+    w = np.array([5.0, 8.0, 5.0]) / 18.0
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    W = (w[:, None, None] * w[None, :, None] * w[None, None, :]).ravel()
+    P = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    phi = lambda b, t: t if b else 1.0 - t
+    dphi = lambda b: 1.0 if b else -1.0
+    vals, curls = [], []
+    for d in range(3):
+        o1, o2 = [a for a in range(3) if a != d]
+        for c2 in (0, 1):
+            for c1 in (0, 1):
+                u = np.zeros((len(W), 3))
+                u[:, d] = phi(c1, P[:, o1]) * phi(c2, P[:, o2])
+                # curl of f(x_o1, x_o2) e_d: component o2 gets d f / d x_o1 with
+                # the sign of the cyclic order, o1 gets -d f / d x_o2
+                df1 = dphi(c1) * phi(c2, P[:, o2])
+                df2 = phi(c1, P[:, o1]) * dphi(c2)
+                cu = np.zeros((len(W), 3))
+                eps = lambda a, b, cc: np.linalg.det(np.eye(3)[[a, b, cc]])
+                # (curl F)_i = sum_jk eps_ijk d_j F_k with F_k = f delta_kd
+                cu[:, o2] += eps(o2, o1, d) * df1
+                cu[:, o1] += eps(o1, o2, d) * df2
+                vals.append(u)
+                curls.append(cu)
+    V = np.stack(vals)   # 12 x q x 3
+    C = np.stack(curls)
+    M = np.einsum("iqa,jqa,q->ij", V, V, W)
+    S = np.einsum("iqa,jqa,q->ij", C, C, W)
+    return M, S
+
+
+def assemble_hex(mesh: dict, sigma: np.ndarray, which: str = "A"):
+    """Nedelec hex operator in CSR: S / h + sigma_h h M per cube (which = "A",
+    "S" or "M")."""
+    import scipy.sparse as sp
+    N = mesh["N"]
+    h = 1.0 / N
+    M, S = hex_reference_matrices()
+    ne = mesh["tail"].shape[0]
+    E = mesh["hex_edges"].astype(np.int64)
+    sig = np.asarray(sigma, np.float64)
+    rows = np.repeat(E, 12, axis=1).ravel()
+    cols = np.tile(E, (1, 12)).ravel()
+    parts = []
+    if which in ("A", "S"):
+        parts.append(np.broadcast_to((S / h).ravel(), (E.shape[0], 144)))
+    if which in ("A", "M"):
+        parts.append((sig * h)[:, None] * M.ravel()[None, :])
+    vals = sum(parts).ravel()
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(ne, ne))
+    A.sum_duplicates()
+    A.sort_indices()
+    return A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data.astype(np.float64)
+
+
+def hex_problem(N: int, sigma: float = 1.0, f_seed: int = 0, agg_width: int = 3) -> dict:
+    """The hexahedral constant-sigma model problem on N^3 cubes."""
+    mesh = hex_mesh(N)
+    sig = np.full(N ** 3, float(sigma))
+    out = dict(mesh=mesh, sigma=sig, A=assemble_hex(mesh, sig, "A"), tail=mesh["tail"], head=mesh["head"],
+               coords=mesh["coords"])
+    maps, sides = box_aggregates(mesh["n"], agg_width)
+    out["aggregates"] = maps
+    out["sides"] = sides
+    out["f"] = rhs(mesh["tail"].shape[0], f_seed)
+    return out

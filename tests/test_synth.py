@@ -30,6 +30,8 @@ def test_edge_counts_table3(n, kind, count):
         assert synth._lib().synth_edge_ptr(N, synth._p(eptr)) == count
     else:
         assert 3 * N * (N + 1) ** 2 == count
+        if n <= 28:
+            assert len(synth.hex_mesh(N)["tail"]) == count
 
 
 def _grad(tail, head, m):
@@ -108,3 +110,50 @@ def test_box_aggregates_levels():
     for agg, nc in zip(maps, sides[1:]):
         assert agg.max() + 1 == nc ** 3
         assert np.all(np.bincount(agg) > 0)
+
+
+# ---------------------------------------------------------------------------
+# hexahedral Nedelec elements (the hex column of Table 3)
+# ---------------------------------------------------------------------------
+def _q1_stiffness(N):
+    """Trilinear (Q1) stiffness of N^3 cubes, by its own quadrature: the
+    gradients of the Q1 basis lie in the Nedelec space, so D^T M D equals it."""
+    g = np.array([-np.sqrt(0.6), 0.0, np.sqrt(0.6)]) * 0.5 + 0.5
+    w = np.array([5.0, 8.0, 5.0]) / 18.0
+    K = np.zeros((8, 8))
+    corners = [(a, b, c) for c in (0, 1) for b in (0, 1) for a in (0, 1)]
+    f = lambda s, t: t if s else 1.0 - t
+    df = lambda s: 1.0 if s else -1.0
+    for x, wx in zip(g, w):
+        for y, wy in zip(g, w):
+            for z, wz in zip(g, w):
+                G = np.array([[df(a) * f(b, y) * f(c, z), f(a, x) * df(b) * f(c, z), f(a, x) * f(b, y) * df(c)]
+                              for a, b, c in corners])
+                K += wx * wy * wz * G @ G.T
+    n = N + 1
+    h = 1.0 / N
+    rows, cols, vals = [], [], []
+    for k in range(N):
+        for j in range(N):
+            for i in range(N):
+                ids = [(i + a) + n * (j + b) + n * n * (k + c) for a, b, c in corners]
+                for p_, u in enumerate(ids):
+                    for q_, v in enumerate(ids):
+                        rows.append(u); cols.append(v); vals.append(h * K[p_, q_])
+    return sp.csr_matrix((vals, (rows, cols)), shape=(n ** 3, n ** 3))
+
+
+@pytest.mark.parametrize("N", [2, 4])
+def test_hex_elements_null_space_and_gradient_mass(N):
+    """S_h D_h = 0 (the curl of a gradient) and D^T M D = sigma K_Q1."""
+    p = synth.hex_problem(N, sigma=0.7)
+    n = N + 1
+    D = _grad(p["tail"], p["head"], n ** 3)
+    S = _mat(synth.assemble_hex(p["mesh"], p["sigma"], "S"))
+    M = _mat(synth.assemble_hex(p["mesh"], p["sigma"], "M"))
+    assert abs(S @ D).max() <= 1e-13 * abs(S).max()
+    K = _q1_stiffness(N)
+    assert abs(D.T @ M @ D - 0.7 * K).max() <= 1e-13 * abs(K).max()
+    A = _mat(p["A"])
+    assert abs(A - A.T).max() == 0.0
+    assert np.linalg.eigvalsh(A.toarray()).min() > 0
