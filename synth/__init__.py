@@ -384,3 +384,177 @@ def hex_problem(N: int, sigma: float = 1.0, f_seed: int = 0, agg_width: int = 3)
     out["sides"] = sides
     out["f"] = rhs(mesh["tail"].shape[0], f_seed)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Two-dimensional model problems (Sec. 6.1, Tables 1 and 2): the unit square
+# with N^2 squares, each split into two triangles along (i, j) -> (i+1, j+1)
+# (lowest-order Whitney elements) or kept as squares (lowest-order Nedelec
+# elements); natural boundary conditions.  Node id = i + n j, n = N + 1.
+# ---------------------------------------------------------------------------
+def _edges_2d(N: int, diagonals: bool):
+    n = N + 1
+    v = np.arange(n * n, dtype=np.int64)
+    i, j = v % n, v // n
+    steps = [(i < N, 1, 0), (j < N, n, 1)]
+    if diagonals:
+        steps.append(((i < N) & (j < N), n + 1, 2))
+    tail = np.concatenate([v[ok] for ok, _, _ in steps])
+    dirv = np.concatenate([np.full(int(ok.sum()), d, np.int64) for ok, _, d in steps])
+    key = tail * 3 + dirv  # for one tail: +1 < +n < +n+1
+    order = np.argsort(key, kind="stable")
+    tail, dirv, key = tail[order], dirv[order], key[order]
+    head = tail + np.array([1, n, n + 1])[dirv]
+    ax = np.arange(n, dtype=np.float64) / N
+    jj, ii = np.meshgrid(ax, ax, indexing="ij")
+    coords = np.stack([ii.ravel(), jj.ravel()], axis=1).copy()
+    return tail, head, key, coords
+
+
+def tri_mesh(N: int) -> dict:
+    n = N + 1
+    tail, head, key, coords = _edges_2d(N, True)
+    c = np.arange(N, dtype=np.int64)
+    cj, ci = np.meshgrid(c, c, indexing="ij")
+    v = (ci + n * cj).ravel()
+    tris = np.concatenate([np.stack([v, v + 1, v + n + 1], 1), np.stack([v, v + n, v + n + 1], 1)])
+    return dict(N=N, n=n, coords=coords, tris=tris, tail=tail.astype(np.int32), head=head.astype(np.int32), key=key)
+
+
+def _edge_id(mesh, a, b):
+    """Global id of the edge between nodes a and b (any order)."""
+    n = mesh["n"]
+    lo, hi = np.minimum(a, b), np.maximum(a, b)
+    d = hi - lo
+    dirv = np.where(d == 1, 0, np.where(d == n, 1, 2))
+    return np.searchsorted(mesh["key"], lo * 3 + dirv)
+
+
+def assemble_tri(mesh: dict, sigma: np.ndarray, which: str = "A"):
+    """Whitney triangle operator in CSR.  With g_a the gradient of lambda_a and
+    local edge (a, b) oriented a -> b: curl N_ab = 2 g_a x g_b (a scalar in 2D),
+    S[(ab),(cd)] = |T| curl N_ab curl N_cd,
+    M[(ab),(cd)] = sigma_T [(g_b.g_d) m_ac - (g_b.g_c) m_ad - (g_a.g_d) m_bc + (g_a.g_c) m_bd],
+    m_xy = |T| (1 + delta_xy) / 12."""
+    import scipy.sparse as sp
+    X = mesh["coords"][mesh["tris"]]                        # t x 3 x 2
+    e1, e2 = X[:, 1] - X[:, 0], X[:, 2] - X[:, 0]
+    det = e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0]
+    area = 0.5 * np.abs(det)
+    # gradients of the barycentric coordinates
+    inv = np.stack([np.stack([e2[:, 1], -e2[:, 0]], 1), np.stack([-e1[:, 1], e1[:, 0]], 1)], 1) / det[:, None, None]
+    g1, g2 = inv[:, 0], inv[:, 1]
+    G = np.stack([-(g1 + g2), g1, g2], 1)                  # t x 3 x 2
+    T = mesh["tris"].astype(np.int64)
+    pairs = [(0, 1), (0, 2), (1, 2)]
+    ids, loc = [], []
+    for a, b in pairs:
+        swap = T[:, a] > T[:, b]
+        la = np.where(swap, b, a)
+        lb = np.where(swap, a, b)
+        ids.append(_edge_id(mesh, T[:, a], T[:, b]))
+        loc.append((la, lb))
+    t = np.arange(T.shape[0])
+    g = lambda l: G[t, l]
+    sig = np.asarray(sigma, np.float64)
+    blocks_r, blocks_c, blocks_v = [], [], []
+    for p, (a, b) in enumerate(loc):
+        cab = 2.0 * (g(a)[:, 0] * g(b)[:, 1] - g(a)[:, 1] * g(b)[:, 0])
+        for q, (cc, d) in enumerate(loc):
+            ccd = 2.0 * (g(cc)[:, 0] * g(d)[:, 1] - g(cc)[:, 1] * g(d)[:, 0])
+            v = np.zeros(T.shape[0])
+            if which in ("A", "S"):
+                v = v + area * cab * ccd
+            if which in ("A", "M"):
+                m = lambda x, y: area * (1.0 + (x == y)) / 12.0
+                dot = lambda x, y: (g(x) * g(y)).sum(1)
+                v = v + sig * (dot(b, d) * m(a, cc) - dot(b, cc) * m(a, d) - dot(a, d) * m(b, cc) + dot(a, cc) * m(b, d))
+            blocks_r.append(ids[p]); blocks_c.append(ids[q]); blocks_v.append(v)
+    ne = mesh["tail"].shape[0]
+    A = sp.csr_matrix((np.concatenate(blocks_v), (np.concatenate(blocks_r), np.concatenate(blocks_c))), shape=(ne, ne))
+    A.sum_duplicates()
+    A.sort_indices()
+    return A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data.astype(np.float64)
+
+
+def quad_mesh(N: int) -> dict:
+    n = N + 1
+    tail, head, key, coords = _edges_2d(N, False)
+    c = np.arange(N, dtype=np.int64)
+    cj, ci = np.meshgrid(c, c, indexing="ij")
+    v = (ci + n * cj).ravel()
+    # local edges: x-edges at y = 0, 1, then y-edges at x = 0, 1
+    quad_edges = np.stack([np.searchsorted(key, v * 3), np.searchsorted(key, (v + n) * 3),
+                           np.searchsorted(key, v * 3 + 1), np.searchsorted(key, (v + 1) * 3 + 1)], 1)
+    return dict(N=N, n=n, coords=coords, quad_edges=quad_edges.astype(np.int32), tail=tail.astype(np.int32),
+                head=head.astype(np.int32), key=key)
+
+
+def quad_reference_matrices():
+    """4 x 4 mass and curl-curl matrices of the unit square for the basis
+    phi_c(y) e_x (x-edge at y = c) and phi_c(x) e_y (y-edge at x = c); curl
+    = d(u_y)/dx - d(u_x)/dy.  Exact 3-point Gauss quadrature per direction."""
+    g = np.array([-np.sqrt(0.6), 0.0, np.sqrt(0.6)]) * 0.5 + 0.5
+    w = np.array([5.0, 8.0, 5.0]) / 18.0
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    W = (w[:, None] * w[None, :]).ravel()
+    x, y = X.ravel(), Y.ravel()
+    phi = lambda c, t: t if c else 1.0 - t
+    dphi = lambda c: 1.0 if c else -1.0
+    U, C = [], []
+    for c in (0, 1):
+        U.append(np.stack([phi(c, y), 0 * y], 1)); C.append(-dphi(c) + 0 * y)
+    for c in (0, 1):
+        U.append(np.stack([0 * x, phi(c, x)], 1)); C.append(dphi(c) + 0 * x)
+    U, C = np.stack(U), np.stack(C)
+    M = np.einsum("iqa,jqa,q->ij", U, U, W)
+    S = np.einsum("iq,jq,q->ij", C, C, W)
+    return M, S
+
+
+def assemble_quad(mesh: dict, sigma: np.ndarray, which: str = "A"):
+    """Nedelec square operator in CSR: S / h^2 + sigma M per square."""
+    import scipy.sparse as sp
+    h = 1.0 / mesh["N"]
+    M, S = quad_reference_matrices()
+    E = mesh["quad_edges"].astype(np.int64)
+    sig = np.asarray(sigma, np.float64)
+    vals = np.zeros((E.shape[0], 16))
+    if which in ("A", "S"):
+        vals = vals + (S / h ** 2).ravel()[None, :]
+    if which in ("A", "M"):
+        vals = vals + sig[:, None] * M.ravel()[None, :]
+    ne = mesh["tail"].shape[0]
+    A = sp.csr_matrix((vals.ravel(), (np.repeat(E, 4, axis=1).ravel(), np.tile(E, (1, 4)).ravel())), shape=(ne, ne))
+    A.sum_duplicates()
+    A.sort_indices()
+    return A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data.astype(np.float64)
+
+
+def box_aggregates_2d(n: int, width: int = 3):
+    """box_aggregates for an n^2 node lattice."""
+    maps, sides = [], [n]
+    nl = n
+    while True:
+        a = -(-nl // width)
+        if a < 2:
+            break
+        f = (np.arange(nl, dtype=np.int64) * a) // nl
+        maps.append((f[None, :] + a * f[:, None]).ravel().astype(np.int32))
+        sides.append(a)
+        nl = a
+    return maps, sides
+
+
+def problem_2d(kind: str, N: int, sigma: float = 1.0, f_seed: int = 0) -> dict:
+    """The 2D constant-sigma model problem on N^2 squares ("tri" or "quad")."""
+    mesh = tri_mesh(N) if kind == "tri" else quad_mesh(N)
+    ncell = mesh["tris"].shape[0] if kind == "tri" else N * N
+    sig = np.full(ncell, float(sigma))
+    A = (assemble_tri if kind == "tri" else assemble_quad)(mesh, sig, "A")
+    out = dict(mesh=mesh, sigma=sig, A=A, tail=mesh["tail"], head=mesh["head"], coords=mesh["coords"])
+    maps, sides = box_aggregates_2d(mesh["n"])
+    out["aggregates"] = maps
+    out["sides"] = sides
+    out["f"] = rhs(mesh["tail"].shape[0], f_seed)
+    return out

@@ -157,3 +157,86 @@ def test_hex_elements_null_space_and_gradient_mass(N):
     A = _mat(p["A"])
     assert abs(A - A.T).max() == 0.0
     assert np.linalg.eigvalsh(A.toarray()).min() > 0
+
+
+# ---------------------------------------------------------------------------
+# 2D elements (Tables 1 and 2)
+# ---------------------------------------------------------------------------
+def _table12():
+    rows = {}
+    for line in open(os.path.join(GOLDEN, "table12_2d_iterations.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        kind, n, _, _, _, edges, _ = line.split()
+        rows[(kind, int(n))] = int(edges)
+    return sorted(rows.items())
+
+
+@pytest.mark.parametrize("key,edges", _table12())
+def test_2d_edge_counts_tables_1_2(key, edges):
+    """#edges of Tables 1 and 2 (generated meshes up to 244^2, closed forms
+    above)."""
+    kind, n = key
+    N = n - 1
+    closed = 2 * n * N + (N * N if kind == "tri" else 0)
+    assert closed == edges
+    if n <= 244:
+        mesh = synth.tri_mesh(N) if kind == "tri" else synth.quad_mesh(N)
+        assert len(mesh["tail"]) == edges
+
+
+def _p1_stiffness_2d(mesh):
+    """P1 stiffness by the per-triangle gradient formula."""
+    X = mesh["coords"][mesh["tris"]]
+    rows, cols, vals = [], [], []
+    for t in range(X.shape[0]):
+        B = np.array([X[t, 1] - X[t, 0], X[t, 2] - X[t, 0]]).T
+        Gr = np.linalg.inv(B).T @ np.array([[-1.0, 1.0, 0.0], [-1.0, 0.0, 1.0]])
+        area = 0.5 * abs(np.linalg.det(B))
+        K = area * Gr.T @ Gr
+        for a in range(3):
+            for b in range(3):
+                rows.append(mesh["tris"][t, a]); cols.append(mesh["tris"][t, b]); vals.append(K[a, b])
+    m = mesh["coords"].shape[0]
+    return sp.csr_matrix((vals, (rows, cols)), shape=(m, m))
+
+
+def _q1_stiffness_2d(N):
+    g = np.array([-np.sqrt(0.6), 0.0, np.sqrt(0.6)]) * 0.5 + 0.5
+    w = np.array([5.0, 8.0, 5.0]) / 18.0
+    corners = [(a, b) for b in (0, 1) for a in (0, 1)]
+    f = lambda s, t: t if s else 1.0 - t
+    df = lambda s: 1.0 if s else -1.0
+    K = np.zeros((4, 4))
+    for x, wx in zip(g, w):
+        for y, wy in zip(g, w):
+            G = np.array([[df(a) * f(b, y), f(a, x) * df(b)] for a, b in corners])
+            K += wx * wy * G @ G.T
+    n = N + 1
+    rows, cols, vals = [], [], []
+    for j in range(N):
+        for i in range(N):
+            ids = [(i + a) + n * (j + b) for a, b in corners]
+            for p_, u in enumerate(ids):
+                for q_, v in enumerate(ids):
+                    rows.append(u); cols.append(v); vals.append(K[p_, q_])
+    return sp.csr_matrix((vals, (rows, cols)), shape=(n * n, n * n))
+
+
+@pytest.mark.parametrize("kind", ["tri", "quad"])
+def test_2d_elements_null_space_and_gradient_mass(kind):
+    """S_h D_h = 0 and D^T M D = sigma times the P1 (triangles) or Q1
+    (squares) stiffness, each formed independently here."""
+    N = 4
+    p = synth.problem_2d(kind, N, sigma=0.7)
+    n = N + 1
+    D = _grad(p["tail"], p["head"], n * n)
+    asm = synth.assemble_tri if kind == "tri" else synth.assemble_quad
+    S = _mat(asm(p["mesh"], p["sigma"], "S"))
+    M = _mat(asm(p["mesh"], p["sigma"], "M"))
+    assert abs(S @ D).max() <= 1e-13 * abs(S).max()
+    K = _p1_stiffness_2d(p["mesh"]) if kind == "tri" else _q1_stiffness_2d(N)
+    assert abs(D.T @ M @ D - 0.7 * K).max() <= 1e-13 * abs(K).max()
+    A = _mat(p["A"])
+    assert abs(A - A.T).max() == 0.0
+    assert np.linalg.eigvalsh(A.toarray()).min() > 0
