@@ -558,3 +558,68 @@ def problem_2d(kind: str, N: int, sigma: float = 1.0, f_seed: int = 0) -> dict:
     out["sides"] = sides
     out["f"] = rhs(mesh["tail"].shape[0], f_seed)
     return out
+
+
+def refined_triangles(M: int) -> dict:
+    """A coarse triangle mesh of M^2 squares and its uniform refinement by two
+    (N = 2M, the same diagonals), for the ideal-interpolation case of Sec. 5:
+      Pn     linear (P1) interpolation from coarse to fine nodes;
+      Pe     the ideal edge prolongator: the tangential moment of every coarse
+             Whitney basis function along every fine edge (exact at the
+             fine edge's midpoint, the basis being affine in each triangle);
+      agg    fine node (x, y) -> coarse node (x // 2, y // 2), whose RS coarse
+             gradient is the coarse mesh's own."""
+    import scipy.sparse as sp
+    fine, coarse = tri_mesh(2 * M), tri_mesh(M)
+    nf, nc = 2 * M + 1, M + 1
+    v = np.arange(nf * nf)
+    x, y = v % nf, v // nf
+    # P1 interpolation: a fine node at a coarse vertex copies it, a midpoint
+    # (odd coordinates) averages the two ends of the coarse edge it lies on
+    rows, cols, vals = [], [], []
+    xl, yl = x // 2, y // 2
+    ox, oy = x % 2, y % 2
+    rows.append(v); cols.append(xl + nc * yl); vals.append(np.where((ox == 0) & (oy == 0), 1.0, 0.5))
+    mid = (ox == 1) | (oy == 1)
+    rows.append(v[mid]); cols.append((xl + ox + nc * (yl + oy))[mid]); vals.append(np.full(int(mid.sum()), 0.5))
+    Pn = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(nf * nf, nc * nc))
+    Pn.sort_indices()
+    # ideal edge prolongator
+    X = fine["coords"]
+    pm = 0.5 * (X[fine["tail"]] + X[fine["head"]])
+    tvec = X[fine["head"]] - X[fine["tail"]]
+    # coarse triangle containing each fine midpoint: square (floor) and the
+    # side of its diagonal (y - y0 > x - x0: the upper triangle)
+    h = 1.0 / M
+    sx = np.minimum((pm[:, 0] / h).astype(np.int64), M - 1)
+    sy = np.minimum((pm[:, 1] / h).astype(np.int64), M - 1)
+    upper = (pm[:, 1] - sy * h) > (pm[:, 0] - sx * h)
+    t = (sx + M * sy) + np.where(upper, M * M, 0)  # tri_mesh order: lower triangles, then upper
+    T = coarse["tris"][t]
+    Xc = coarse["coords"]
+    P0 = Xc[T[:, 0]]
+    e1, e2 = Xc[T[:, 1]] - P0, Xc[T[:, 2]] - P0
+    det = e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0]
+    g1 = np.stack([e2[:, 1], -e2[:, 0]], 1) / det[:, None]
+    g2 = np.stack([-e1[:, 1], e1[:, 0]], 1) / det[:, None]
+    G = np.stack([-(g1 + g2), g1, g2], 1)
+    d = pm - P0
+    l1 = (d * g1).sum(1)
+    l2 = (d * g2).sum(1)
+    lam = np.stack([1.0 - l1 - l2, l1, l2], 1)
+    r, c, w = [], [], []
+    for aa, bb in ((0, 1), (0, 2), (1, 2)):
+        ga, gb = T[:, aa], T[:, bb]
+        lo_is_a = ga < gb
+        la = np.where(lo_is_a, aa, bb)
+        lb = np.where(lo_is_a, bb, aa)
+        idx = np.arange(len(t))
+        Nv = lam[idx, la][:, None] * G[idx, lb] - lam[idx, lb][:, None] * G[idx, la]
+        r.append(idx); c.append(_edge_id(coarse, ga, gb)); w.append((Nv * tvec).sum(1))
+    Pe = sp.csr_matrix((np.concatenate(w), (np.concatenate(r), np.concatenate(c))),
+                       shape=(len(fine["tail"]), len(coarse["tail"])))
+    Pe.data[np.abs(Pe.data) < 1e-12] = 0.0  # zeros that the evaluation left at rounding level
+    Pe.eliminate_zeros()
+    Pe.sort_indices()
+    agg = (xl + nc * yl).astype(np.int32)
+    return dict(fine=fine, coarse=coarse, Pn=Pn, Pe=Pe, agg=agg)

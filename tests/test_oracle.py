@@ -690,3 +690,35 @@ def test_mis2_hierarchy_converges():
         assert ncomp == a.max() + 1
     _, it, rel, _ = O.pcg(lv, p["f"])
     assert rel <= 1e-8 and it < 60
+
+
+# ---------------------------------------------------------------------------
+# Sec. 5: ideal interpolation on refined triangles
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("M", [4, 6])
+def test_ideal_interpolation_is_a_fixed_point_on_refined_triangles(M):
+    """Sec. 5: with P^(n) the linear interpolation of a uniform refinement, the
+    coarse Whitney basis sampled on the fine edges is feasible (it lies in the
+    pattern of Alg. 2 and meets P^(e) D_H = D_h P^(n)), and the curl-curl
+    energy has no projected gradient there (delta P = 0 solves the KKT
+    system), so projected CG from it does not move."""
+    r = synth.refined_triangles(M)
+    f, c = r["fine"], r["coarse"]
+    nf, nc = 2 * M + 1, M + 1
+    D = O.gradient_matrix(f["tail"], f["head"], nf * nf)
+    th, hd = O.coarse_gradient(D, r["agg"], nc * nc)
+    assert np.array_equal(th, c["tail"]) and np.array_equal(hd, c["head"])
+    DH = O.gradient_matrix(th, hd, nc * nc)
+    assert abs(r["Pe"] @ DH - D @ r["Pn"]).max() <= 1e-14
+    N, T, R = O.emin_pattern(D, r["Pn"], DH)
+    assert abs(O.on_pattern(N, r["Pe"]) - r["Pe"]).max() == 0.0
+    lt, lh = O.local_graphs(N, T, th, hd)
+    loc = O.LocalSystems(N, T, R, lt, lh)
+    p = O.on_pattern(N, r["Pe"]).data
+    assert abs(loc.make_feasible(p) - p).max() <= 1e-14
+    S = O.csr(synth.assemble_tri(f, np.ones(f["tris"].shape[0]), "S"))
+    g = O.masked_product(S, O.with_values(N, p), N)
+    assert abs(g).max() > 1.0
+    assert abs(loc.project(g)).max() <= 1e-12 * abs(g).max()
+    q, E, _ = O.projected_cg(S, N, loc, p, 5)
+    assert abs(q - p).max() <= 1e-12 and abs(E[-1] - E[0]) <= 1e-12 * E[0]
