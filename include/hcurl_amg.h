@@ -156,9 +156,14 @@ void hcurl_amg_default_opts(hcurl_amg_opts* opts);
  * hcurl_amg_setup -- build the hierarchy (Alg. 3 on every level).
  *   A       n_h x n_h edge operator A^(e) = S + M, symmetric positive definite,
  *           positive diagonal (Sec. 1, eq. "discrete eddy").
- *   Dh      n_h x m_h discrete gradient: every row exactly two entries, -1 at the
- *           tail node and +1 at the head node (Sec. 1).  Rows with one entry
- *           (Dirichlet edges) are rejected with HCURL_EINVAL in this version.
+ *   Dh      n_h x m_h discrete gradient: every row two entries, -1 at the tail
+ *           node and +1 at the head node (Sec. 1), or a single +-1: a Dirichlet
+ *           edge whose other node was eliminated (Sec. 2).  Every coarse node
+ *           that a Dirichlet edge's remaining node is aggregated to gets one
+ *           single-node coarse edge (+1 at that node), placed after the two-node
+ *           coarse edges in node order; Alg. 2 weighs it by W = 2 and the local
+ *           systems that hold one keep every column.  The learned initial guess
+ *           does not take Dirichlet edges (HCURL_EUNSUPPORTED).
  *   coords  m_h x 3 node coordinates (row-major) or NULL; kept for the learned
  *           initial guess features, not needed otherwise.
  *   aggregates[l]  for l < n_agg_levels: int32 map from the nodes of level l to

@@ -30,6 +30,10 @@ Readings where the paper is silent or garbled (each is listed in the design doc):
   R6  Reduce_Dimension drops the column of the largest coarse node id of T_i.
   R25 setup reuse (suggested in Sec. 3 and after Table 4): see ``update``.
   R26 aggregates when the caller gives none: see ``mis2_aggregates``.
+  R27 Dirichlet edges (one entry in D_h): one single-node coarse edge, +1 at
+      the node, for every coarse node their remaining node is aggregated to,
+      after the two-node edges in node order; W = 2 in Alg. 2; a row holding
+      one keeps every column of its local system; 255 marks the absent end.
   R8  sparsity patterns are symbolic: products of absolute values, structural
       zeros kept (Alg. 2 uses |.|).
   R9  the energy is measured in A^(e) (footnote to eq. min2_hcurl allows it).
@@ -59,6 +63,7 @@ import scipy.sparse as sp
 from scipy.sparse.csgraph import connected_components
 
 MASK64 = (1 << 64) - 1
+MISSING = 255  # local index of the absent end of a Dirichlet coarse edge
 
 
 # ---------------------------------------------------------------------------
@@ -84,12 +89,15 @@ def csr(A, shape=None) -> sp.csr_matrix:
 
 def gradient_matrix(tail, head, m: int) -> sp.csr_matrix:
     """Discrete gradient D (n x m): row e has -1 at its tail node and +1 at its
-    head node (Sec. 1, the discrete gradient has at most two +-1 per row)."""
+    head node (Sec. 1, the discrete gradient has at most two +-1 per row).  An
+    endpoint -1 marks a Dirichlet edge whose other node was eliminated: its row
+    keeps one entry (Sec. 2)."""
     n = len(tail)
     rows = np.repeat(np.arange(n), 2)
-    cols = np.stack([tail, head], axis=1).ravel()
+    cols = np.stack([np.asarray(tail, np.int64), np.asarray(head, np.int64)], axis=1).ravel()
     vals = np.tile([-1.0, 1.0], n)
-    return csr(sp.csr_matrix((vals, (rows, cols)), shape=(n, m)))
+    keep = cols >= 0
+    return csr(sp.csr_matrix((vals[keep], (rows[keep], cols[keep])), shape=(n, m)))
 
 
 def symbolic_product(*mats) -> sp.csr_matrix:
@@ -325,6 +333,15 @@ def coarse_gradient(D: sp.csr_matrix, agg: np.ndarray, m_coarse: int):
     rows = np.repeat(np.arange(m_coarse), np.diff(U.indptr))
     tail = rows.astype(np.int32)
     head = U.indices.astype(np.int32)
+    # Dirichlet edges (one entry in D): every coarse node that the interior
+    # node of one interpolates to gets one single-node coarse edge (Sec. 2),
+    # +1 at that node (reading R27), after the two-node edges in node order
+    D = csr(D)
+    single = np.nonzero(np.diff(D.indptr) == 1)[0]
+    if len(single):
+        nodes = np.unique(np.asarray(agg)[D.indices[D.indptr[single]]]).astype(np.int32)
+        tail = np.r_[tail, np.full(len(nodes), -1, np.int32)]
+        head = np.r_[head, nodes]
     return tail, head
 
 
@@ -373,14 +390,16 @@ def local_graphs(N: sp.csr_matrix, T: sp.csr_matrix, tail, head):
     trow_of = np.repeat(np.arange(nrow, dtype=np.int64), np.diff(T.indptr))
     tkey = trow_of * mH + T.indices.astype(np.int64)
     j = N.indices
-    kt = nrow_of * mH + np.asarray(tail, np.int64)[j]
-    kh = nrow_of * mH + np.asarray(head, np.int64)[j]
-    pt = np.searchsorted(tkey, kt)
-    ph = np.searchsorted(tkey, kh)
-    assert np.all(tkey[pt] == kt) and np.all(tkey[ph] == kh)
-    lt = pt - T.indptr[nrow_of]
-    lh = ph - T.indptr[nrow_of]
-    return lt.astype(np.int64), lh.astype(np.int64)
+    out = []
+    for ends in (tail, head):
+        e = np.asarray(ends, np.int64)[j]
+        k = nrow_of * mH + np.maximum(e, 0)
+        pos = np.searchsorted(tkey, k)
+        ok = e >= 0
+        assert np.all(tkey[pos[ok]] == k[ok])
+        # a Dirichlet coarse edge has no node at this end: local index 255
+        out.append(np.where(ok, pos - T.indptr[nrow_of], MISSING).astype(np.int64))
+    return out[0], out[1]
 
 
 def disconnected_rows(N, T, lt, lh):
@@ -394,7 +413,8 @@ def disconnected_rows(N, T, lt, lh):
         if b == a:
             bad.append(i)
             continue
-        G = sp.csr_matrix((np.ones(b - a), (lt[a:b], lh[a:b])), shape=(nJ, nJ))
+        two = (lt[a:b] != MISSING) & (lh[a:b] != MISSING)
+        G = sp.csr_matrix((np.ones(int(two.sum())), (lt[a:b][two], lh[a:b][two])), shape=(nJ, nJ))
         nc, _ = connected_components(G, directed=False)
         if nc > 1:
             bad.append(i)
@@ -413,28 +433,38 @@ class LocalSystems:
         npv = np.diff(N.indptr)
         Jv = np.diff(T.indptr)
         self.groups = []
-        shapes = np.stack([npv, Jv], axis=1)
+        # rows holding a Dirichlet coarse edge have a full-rank G (Alg. 2:
+        # no Reduce_Dimension)
+        nrow_of = np.repeat(np.arange(self.nrow), npv)
+        dirich = np.zeros(self.nrow, np.int64)
+        np.add.at(dirich, nrow_of, ((lt == MISSING) | (lh == MISSING)).astype(np.int64))
+        hasd = (dirich > 0).astype(np.int64)
+        shapes = np.stack([npv, Jv, hasd], axis=1)
         keys, inv = np.unique(shapes, axis=0, return_inverse=True)
         inv = inv.ravel()
-        for g, (n_p, nJ) in enumerate(keys):
+        for g, (n_p, nJ, hd) in enumerate(keys):
             rows = np.nonzero(inv == g)[0]
-            if nJ <= 1:
-                # |T_i| = 1: empty row of P^(e); the constraint needs r_i = 0
+            if n_p == 0:
+                # no pattern entry (|T_i| = 1 without a Dirichlet edge): an empty
+                # row of P^(e); the constraint needs r_i = 0
                 r = R.data[T.indptr[rows]] if nJ == 1 else np.zeros(0)
-                self.groups.append(dict(rows=rows, n_p=0, k=0, r_empty=r))
+                self.groups.append(dict(rows=rows, n_p=0, k=0, nJ=int(nJ), r_empty=r))
                 continue
-            k = nJ - 1  # reading R6: drop the last (largest) coarse node
+            k = nJ if hd else nJ - 1  # reading R6: else drop the last (largest) coarse node
             pos = N.indptr[rows][:, None] + np.arange(n_p)[None, :]
-            G = np.zeros((len(rows), n_p, nJ))
+            G = np.zeros((len(rows), n_p, nJ + 1))  # column nJ collects the missing ends
             bidx = np.repeat(np.arange(len(rows)), n_p)
             eidx = np.tile(np.arange(n_p), len(rows))
-            G[bidx, eidx, lt[pos].ravel()] = -1.0
-            G[bidx, eidx, lh[pos].ravel()] = 1.0
+            ltp = np.minimum(lt[pos].ravel(), nJ)
+            lhp = np.minimum(lh[pos].ravel(), nJ)
+            G[bidx, eidx, ltp] = -1.0
+            G[bidx, eidx, lhp] = 1.0
+            G = G[:, :, :nJ]
             Gt = G[:, :, :k]
             Q, Rr = np.linalg.qr(Gt, mode="reduced")
             rpos = T.indptr[rows][:, None] + np.arange(nJ)[None, :]
             rfull = R.data[rpos]
-            self.groups.append(dict(rows=rows, n_p=n_p, k=k, pos=pos, G=G, Gt=Gt, Q=Q, R=Rr,
+            self.groups.append(dict(rows=rows, n_p=n_p, k=k, nJ=int(nJ), pos=pos, G=G, Gt=Gt, Q=Q, R=Rr,
                                     rt=rfull[:, :k], rfull=rfull))
 
     def project(self, x: np.ndarray) -> np.ndarray:
@@ -467,8 +497,7 @@ class LocalSystems:
         Tables 2 and 4)."""
         h = {}
         for g in self.groups:
-            nJ = g["k"] + 1 if g["n_p"] else (1 if len(g.get("r_empty", [])) else 0)
-            key = (int(nJ), int(g["n_p"]))
+            key = (g["nJ"], int(g["n_p"]))
             h[key] = h.get(key, 0) + len(g["rows"])
         return h
 
@@ -496,7 +525,8 @@ def make_irreducible(D, Pn, DH_tail, DH_head, mH):
             nodes = T.indices[T.indptr[i]:T.indptr[i + 1]]
             a, b = N.indptr[i], N.indptr[i + 1]
             nJ = len(nodes)
-            G = sp.csr_matrix((np.ones(b - a), (lt[a:b], lh[a:b])), shape=(nJ, nJ))
+            two = (lt[a:b] != MISSING) & (lh[a:b] != MISSING)
+            G = sp.csr_matrix((np.ones(int(two.sum())), (lt[a:b][two], lh[a:b][two])), shape=(nJ, nJ))
             _, lab = connected_components(G, directed=False)
             c0 = lab[0]
             best = None
@@ -509,9 +539,11 @@ def make_irreducible(D, Pn, DH_tail, DH_head, mH):
                     if best is None or cand < best:
                         best = cand
             new.add((best[1], best[2]))
-        edges = sorted(set(zip(tail.tolist(), head.tolist())) | new)
-        tail = np.array([e[0] for e in edges], np.int32)
-        head = np.array([e[1] for e in edges], np.int32)
+        two = tail >= 0
+        edges = sorted(set(zip(tail[two].tolist(), head[two].tolist())) | new)
+        # Dirichlet (single-node) coarse edges stay after the two-node ones
+        tail = np.r_[np.array([e[0] for e in edges], np.int32), tail[~two]]
+        head = np.r_[np.array([e[1] for e in edges], np.int32), head[~two]]
         added_total += len(new)
     raise RuntimeError("make_irreducible did not converge")
 

@@ -265,7 +265,10 @@ def hcurl_amg_export_csr(h, level: int, which: str):
         elif which == "R":
             nr, nc, nnz = n, nxt["n_nodes"], info["nnz_T"]
         elif which == "DH":
-            nr, nc, nnz = nxt["n_edges"], nxt["n_nodes"], 2 * nxt["n_edges"]
+            nr, nc = nxt["n_edges"], nxt["n_nodes"]
+            rp = np.empty(nr + 1, np.int64)  # Dirichlet coarse edges hold one entry: count first
+            _check(lib.hcurl_amg_export_csr(h, level, EXPORT[which], _ptr(rp), None, None))
+            nnz = int(rp[-1])
         else:
             raise ValueError(which)
     rowptr = np.empty(nr + 1, np.int64)

@@ -44,6 +44,8 @@ struct Level {
   DBuf<double> p0;        // initial guess, kept for export
   int maxJ = 0, maxNp = 0;
   int n_coarse = 0;
+  int nsingle = 0;         // Dirichlet edges of this level (one entry in D)
+  int nsingle_coarse = 0;  // single-node coarse edges made for the next level
   int64_t irreducible_added = 0;  // coarse edges make_irreducible added
   double rho = 0.0, omega = 0.0;
   double cancel = 0.0;  // max over nodes of (|D|^T |A| |D| 1)_u / (D^T A D)_uu

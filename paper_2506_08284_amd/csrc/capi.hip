@@ -209,13 +209,24 @@ int hcurl_amg_export_csr(hcurl_amg h, int level, int which, int64_t* rowptr, int
         std::vector<int> t(N->n), hd(N->n);
         hc::d2h(t.data(), N->tail.p, N->n, c);
         hc::d2h(hd.data(), N->head.p, N->n, c);
+        // a single-node (Dirichlet) coarse edge has one entry; call with col
+        // and val NULL to read the entry count from rowptr first
+        int64_t o = 0;
         for (int e = 0; e < N->n; ++e) {
-          if (rowptr) rowptr[e] = 2LL * e;
+          if (rowptr) rowptr[e] = o;
+          if (t[e] < 0 || hd[e] < 0) {
+            const bool at_head = t[e] < 0;
+            if (col) col[o] = at_head ? hd[e] : t[e];
+            if (val) val[o] = at_head ? 1.0 : -1.0;
+            o += 1;
+            continue;
+          }
           const bool up = t[e] < hd[e];
-          if (col) { col[2 * e] = up ? t[e] : hd[e]; col[2 * e + 1] = up ? hd[e] : t[e]; }
-          if (val) { val[2 * e] = up ? -1.0 : 1.0; val[2 * e + 1] = up ? 1.0 : -1.0; }
+          if (col) { col[o] = up ? t[e] : hd[e]; col[o + 1] = up ? hd[e] : t[e]; }
+          if (val) { val[o] = up ? -1.0 : 1.0; val[o + 1] = up ? 1.0 : -1.0; }
+          o += 2;
         }
-        if (rowptr) rowptr[N->n] = 2LL * N->n;
+        if (rowptr) rowptr[N->n] = o;
         break;
       }
       default: hc::fail(HCURL_EINVAL, "unknown export");

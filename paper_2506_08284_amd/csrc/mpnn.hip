@@ -111,6 +111,7 @@ __global__ void k_features(int64_t E, const int* __restrict__ row_of, const int*
 }
 
 void mpnn_build_sample(Hierarchy& H, Level& L0, const Level& L1, const double* p0plain, const double* pmin, Sample& S) {
+  if (L0.nsingle > 0) fail(HCURL_EUNSUPPORTED, "the learned initial guess does not take Dirichlet edges");
   Ctx& c = H.ctx;
   if (!H.coords.p) fail(HCURL_EINVAL, "the learned initial guess needs node coordinates at setup");
   S.s = c.s;

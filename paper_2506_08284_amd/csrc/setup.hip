@@ -16,13 +16,26 @@ enum { F_BAD = 2, F_DISCONNECTED, F_MAXJ, F_MAXNP, F_TOOBIG, F_NOTSPD };
 // ---------------------------------------------------------------------------
 // discrete gradient
 // ---------------------------------------------------------------------------
-// Reads a caller CSR gradient: every row exactly one -1 and one +1.
+// Reads a caller CSR gradient: every row one -1 and one +1, or a single +-1
+// (a Dirichlet edge whose other node was eliminated, Sec. 2); the absent end
+// is stored as -1.
 __global__ void k_grad_from_csr(const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ val,
-                                int n, int m, int* __restrict__ tail, int* __restrict__ head, long long* __restrict__ bad) {
+                                int n, int m, int* __restrict__ tail, int* __restrict__ head, long long* __restrict__ bad,
+                                long long* __restrict__ single) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int a = rp[i];
-  if (rp[i + 1] - a != 2) { atomicAdd((unsigned long long*)bad, 1ULL); return; }
+  const int len = rp[i + 1] - a;
+  if (len == 1) {
+    const int c0 = col[a];
+    const double v0 = val[a];
+    if (c0 < 0 || c0 >= m || (v0 != 1.0 && v0 != -1.0)) { atomicAdd((unsigned long long*)bad, 1ULL); return; }
+    tail[i] = v0 < 0.0 ? c0 : -1;
+    head[i] = v0 < 0.0 ? -1 : c0;
+    atomicAdd((unsigned long long*)single, 1ULL);
+    return;
+  }
+  if (len != 2) { atomicAdd((unsigned long long*)bad, 1ULL); return; }
   const int c0 = col[a], c1 = col[a + 1];
   const double v0 = val[a], v1 = val[a + 1];
   if (c0 < 0 || c1 < 0 || c0 >= m || c1 >= m || c0 == c1) { atomicAdd((unsigned long long*)bad, 1ULL); return; }
@@ -31,25 +44,34 @@ __global__ void k_grad_from_csr(const int* __restrict__ rp, const int* __restric
   else atomicAdd((unsigned long long*)bad, 1ULL);
 }
 
-// D as CSR with sorted columns from the endpoint arrays.
-__global__ void k_grad_csr(const int* __restrict__ tail, const int* __restrict__ head, int n, int* __restrict__ rp,
+// D as CSR with sorted columns from the endpoint arrays (an absent end, -1,
+// gives no entry).
+__global__ void k_grad_count(const int* __restrict__ tail, const int* __restrict__ head, int n, int* __restrict__ cnt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) cnt[i] = (tail[i] >= 0) + (head[i] >= 0);
+}
+__global__ void k_grad_csr(const int* __restrict__ tail, const int* __restrict__ head, int n, const int* __restrict__ rp,
                            int* __restrict__ col, double* __restrict__ val) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i > n) return;
-  rp[i] = 2 * i;
-  if (i == n) return;
-  const int t = tail[i], h = head[i];
-  if (t < h) { col[2 * i] = t; col[2 * i + 1] = h; val[2 * i] = -1.0; val[2 * i + 1] = 1.0; }
-  else { col[2 * i] = h; col[2 * i + 1] = t; val[2 * i] = 1.0; val[2 * i + 1] = -1.0; }
+  if (i >= n) return;
+  const int t = tail[i], h = head[i], o = rp[i];
+  if (t < 0) { col[o] = h; val[o] = 1.0; return; }
+  if (h < 0) { col[o] = t; val[o] = -1.0; return; }
+  if (t < h) { col[o] = t; col[o + 1] = h; val[o] = -1.0; val[o + 1] = 1.0; }
+  else { col[o] = h; col[o + 1] = t; val[o] = 1.0; val[o + 1] = -1.0; }
 }
 
 static void gradient_csr(Level& L, Ctx& c) {
-  L.D.nrows = L.n; L.D.ncols = L.m; L.D.nnz = 2LL * L.n;
+  L.D.nrows = L.n; L.D.ncols = L.m;
   L.D.rowptr.alloc(L.n + 1, c.s);
-  L.D.col.alloc(2 * (size_t)L.n, c.s);
-  L.D.val.alloc(2 * (size_t)L.n, c.s);
+  DBuf<int> cnt(L.n + 1, c.s);
+  k_grad_count<<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, L.n, cnt.p);
+  HC_LAUNCH_CHECK();
+  L.D.nnz = exclusive_scan(cnt.p, L.D.rowptr.p, L.n, c);
+  L.D.col.alloc(std::max<int64_t>(L.D.nnz, 1), c.s);
+  L.D.val.alloc(std::max<int64_t>(L.D.nnz, 1), c.s);
   c.run("grad_csr", 24.0 * L.n, [&] {
-    k_grad_csr<<<ceil_div(L.n + 1, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, L.n, L.D.rowptr.p, L.D.col.p, L.D.val.p);
+    k_grad_csr<<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, L.n, L.D.rowptr.p, L.D.col.p, L.D.val.p);
   });
   transpose(L.D, L.DT, true, c);
 }
@@ -252,16 +274,41 @@ __global__ void k_alg1_leftover(const int* __restrict__ rp, const int* __restric
 __global__ void k_cross_count(const int* __restrict__ tail, const int* __restrict__ head, const int* __restrict__ agg,
                               int n, int* __restrict__ cnt) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) cnt[i] = agg[tail[i]] != agg[head[i]] ? 2 : 0;
+  if (i >= n) return;
+  const int t = tail[i], h = head[i];
+  cnt[i] = (t >= 0 && h >= 0 && agg[t] != agg[h]) ? 2 : 0;
 }
 __global__ void k_cross_fill(const int* __restrict__ tail, const int* __restrict__ head, const int* __restrict__ agg,
                              int n, const int* __restrict__ rp, int* __restrict__ col) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int I = agg[tail[i]], K = agg[head[i]];
+  const int t = tail[i], h = head[i];
+  if (t < 0 || h < 0) return;
+  const int I = agg[t], K = agg[h];
   if (I == K) return;
   col[rp[i]] = min(I, K);
   col[rp[i] + 1] = max(I, K);
+}
+// Dirichlet edges: the coarse node their remaining node belongs to gets one
+// single-node coarse edge (Sec. 2)
+__global__ void k_single_mark(const int* __restrict__ tail, const int* __restrict__ head, const int* __restrict__ agg,
+                              int n, int* __restrict__ mark) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int t = tail[i], h = head[i];
+  if (t < 0 && h >= 0) mark[agg[h]] = 1;
+  else if (h < 0 && t >= 0) mark[agg[t]] = 1;
+}
+// sne[I] = id of node I's single-node coarse edge (after the nTwo two-node
+// edges, in node order) or -1; also writes the edges' ends
+__global__ void k_single_ids(int mH, const int* __restrict__ mark, const int* __restrict__ pos, int nTwo,
+                             int* __restrict__ sne, int* __restrict__ ctail, int* __restrict__ chead) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= mH) return;
+  if (!mark[I]) { sne[I] = -1; return; }
+  const int e = nTwo + pos[I];
+  sne[I] = e;
+  if (ctail) { ctail[e] = -1; chead[e] = I; }
 }
 __global__ void k_upper_count(const int* __restrict__ rp, const int* __restrict__ col, int n, int* __restrict__ cnt) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -289,8 +336,9 @@ static constexpr int kMaxJ = 32;
 
 template <bool FILL>
 __global__ void k_pattern(int n, const int* __restrict__ Trp, const int* __restrict__ Tcol, const int* __restrict__ tptr,
-                          const int* __restrict__ chead, int* __restrict__ cnt, const int* __restrict__ Nrp,
-                          int* __restrict__ Ncol, uint16_t* __restrict__ lpair, long long* __restrict__ flags) {
+                          const int* __restrict__ chead, const int* __restrict__ sne, int* __restrict__ cnt,
+                          const int* __restrict__ Nrp, int* __restrict__ Ncol, uint16_t* __restrict__ lpair,
+                          long long* __restrict__ flags) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int t0 = Trp[i];
@@ -322,6 +370,18 @@ __global__ void k_pattern(int n, const int* __restrict__ Trp, const int* __restr
       }
     }
   }
+  // single-node coarse edges of T_i's nodes (W = 2 in Alg. 2); their ids
+  // follow every two-node id and increase with the node
+  if (sne)
+    for (int a = 0; a < nJ; ++a) {
+      const int e = sne[Tcol[t0 + a]];
+      if (e < 0) continue;
+      if (FILL) {
+        Ncol[o + c] = e;
+        lpair[o + c] = (uint16_t)(255 | (a << 8));
+      }
+      ++c;
+    }
   if (!FILL) {
     cnt[i] = c;
     atomicMax((unsigned long long*)&flags[F_MAXJ], (unsigned long long)nJ);
@@ -457,7 +517,11 @@ __device__ __forceinline__ bool local_solve(double* x, const uint16_t* __restric
                                             const double* __restrict__ rrow) {
   constexpr int MK = MAXJ - 1;
   constexpr int NL = MK * (MK + 1) / 2;
-  const int k = nJ - 1;
+  // a Dirichlet (single-node) coarse edge, marked by the local index 255 at
+  // its absent end, makes G~ full rank: no column is dropped (Alg. 2)
+  int miss = 0;
+  for (int e = 0; e < np; ++e) miss |= ((lp[e] & 255) == 255) | ((lp[e] >> 8) == 255);
+  const int k = nJ - 1 + miss;
   if (k <= 0 || np == 0) return true;
   double L[NL];
   double y[MK];
@@ -851,7 +915,7 @@ static int emin_apply(Level& L, const double* dscale, const double* X, double* O
     constexpr int kProjCap = 1536;
     const int RP = std::max(1, std::min(kRowsCap, kProjCap / std::max(1, L.maxNp)));
     const int pgrid = emin_grid(L.n, RP);
-    with_maxj(L.maxJ, [&](auto mj) {
+    with_maxj(L.maxJ + (L.nsingle_coarse ? 1 : 0), [&](auto mj) {
       c.run("emin_projection", 26.0 * L.Pe.nnz, [&] {
         k_emin_project<decltype(mj)::value, kProjCap><<<pgrid, 64, 0, c.s>>>(L.n, RP, L.Pe.rowptr.p, Y, L.lpair.p,
                                                                              L.R.rowptr.p, X, Out, flags, part, c.iscal.p);
@@ -863,7 +927,7 @@ static int emin_apply(Level& L, const double* dscale, const double* X, double* O
 }
 
 static void make_feasible(Level& L, double* x, bool ones, Ctx& c) {
-  with_maxj(L.maxJ, [&](auto mj) {
+  with_maxj(L.maxJ + (L.nsingle_coarse ? 1 : 0), [&](auto mj) {
     c.run("emin_affine", 26.0 * L.Pe.nnz, [&] {
       k_make_feasible<decltype(mj)::value><<<ceil_div(L.n, 128), 128, 0, c.s>>>(
           L.n, L.Pe.rowptr.p, x, L.lpair.p, L.R.rowptr.p, L.R.val.p, ones ? 1 : 0, c.iscal.p);
@@ -1269,6 +1333,20 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
     k_upper_fill<<<ceil_div(mH, 256), 256, 0, c.s>>>(Z.rowptr.p, Z.col.p, mH, tptr.p, next->tail.p, next->head.p);
     HC_LAUNCH_CHECK();
   }
+  // Dirichlet edges (Sec. 2): one single-node coarse edge for every coarse
+  // node that a fine Dirichlet edge's remaining node belongs to, placed after
+  // the two-node edges in node order, +1 at the node
+  DBuf<int> smark, spos, sne;
+  int nsingle = 0;
+  if (L.nsingle > 0) {
+    smark.alloc(mH + 1, c.s);
+    spos.alloc(mH + 1, c.s);
+    sne.alloc(mH, c.s);
+    HC_HIP(hipMemsetAsync(smark.p, 0, sizeof(int) * (mH + 1), c.s));
+    k_single_mark<<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, pbar, L.n, smark.p);
+    HC_LAUNCH_CHECK();
+    nsingle = (int)exclusive_scan(smark.p, spos.p, mH, c);
+  }
   L.n_coarse = next->n;
   // T and R = D P^(n) on T
   spgemm(L.D, L.Pn, L.R, true, c, "spgemm_DPn");
@@ -1280,9 +1358,14 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
     L.irreducible_added = 0;
     for (int round = 0;; ++round) {
       for (int f = F_DISCONNECTED; f <= F_TOOBIG; ++f) clear_flag(f, c);
+      if (nsingle) {
+        k_single_ids<<<ceil_div(mH, 256), 256, 0, c.s>>>(mH, smark.p, spos.p, next->n, sne.p, nullptr, nullptr);
+        HC_LAUNCH_CHECK();
+      }
       c.run("pattern", 8.0 * L.R.nnz, [&] {
         k_pattern<false><<<ceil_div(L.n, 128), 128, 0, c.s>>>(L.n, L.R.rowptr.p, L.R.col.p, tptr.p, next->head.p,
-                                                              cnt.p, nullptr, nullptr, nullptr, c.iscal.p);
+                                                              nsingle ? sne.p : nullptr, cnt.p, nullptr, nullptr,
+                                                              nullptr, c.iscal.p);
       });
       d2h(fl, c.iscal.p, 6, c);
       if (fl[F_TOOBIG]) fail(HCURL_EUNSUPPORTED, "a fine edge touches more than 32 coarse nodes");
@@ -1323,8 +1406,23 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
       next->head = std::move(nhead);
       tptr = std::move(nptr);
     }
+    if (nsingle) {
+      const int nTwo = next->n;
+      DBuf<int> nt(nTwo + nsingle, c.s), nh(nTwo + nsingle, c.s);
+      d2d(nt.p, next->tail.p, nTwo, c);
+      d2d(nh.p, next->head.p, nTwo, c);
+      k_single_ids<<<ceil_div(mH, 256), 256, 0, c.s>>>(mH, smark.p, spos.p, nTwo, sne.p, nt.p, nh.p);
+      HC_LAUNCH_CHECK();
+      next->tail = std::move(nt);
+      next->head = std::move(nh);
+      next->n = nTwo + nsingle;
+    }
+    next->nsingle = nsingle;
+    L.nsingle_coarse = nsingle;
     L.n_coarse = next->n;
     L.maxJ = (int)fl[F_MAXJ];
+    if (nsingle && L.maxJ + 1 > kMaxJ)
+      fail(HCURL_EUNSUPPORTED, "a fine edge with a Dirichlet coarse edge touches 32 coarse nodes");
     L.maxNp = (int)fl[F_MAXNP];
     if (L.maxNp > kPatCap) fail(HCURL_EUNSUPPORTED, "a row of P^(e) has more than 512 pattern entries");
     L.Pe.nrows = L.n;
@@ -1334,7 +1432,8 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
     L.Pe.col.alloc(L.Pe.nnz, c.s);
     L.lpair.alloc(L.Pe.nnz, c.s);
     c.run("pattern", 14.0 * L.R.nnz, [&] {
-      k_pattern<true><<<ceil_div(L.n, 128), 128, 0, c.s>>>(L.n, L.R.rowptr.p, L.R.col.p, tptr.p, next->head.p, nullptr,
+      k_pattern<true><<<ceil_div(L.n, 128), 128, 0, c.s>>>(L.n, L.R.rowptr.p, L.R.col.p, tptr.p, next->head.p,
+                                                           nsingle ? sne.p : nullptr, nullptr,
                                                            L.Pe.rowptr.p, L.Pe.col.p, L.lpair.p, c.iscal.p);
     });
   }
@@ -1371,12 +1470,16 @@ void build_hierarchy(Hierarchy& H, const hcurl_csr& A, const hcurl_csr& Dh, cons
     L0->tail.alloc(L0->n, c.s);
     L0->head.alloc(L0->n, c.s);
     clear_flag(F_BAD, c);
+    clear_flag(F_TOOBIG, c);
     if (L0->n)
       k_grad_from_csr<<<ceil_div(L0->n, 256), 256, 0, c.s>>>(Du.rowptr.p, Du.col.p, Du.val.p, L0->n, L0->m, L0->tail.p,
-                                                             L0->head.p, c.iscal.p + F_BAD);
+                                                             L0->head.p, c.iscal.p + F_BAD, c.iscal.p + F_TOOBIG);
     HC_LAUNCH_CHECK();
     if (read_flag(F_BAD, c))
-      fail(HCURL_EINVAL, "every row of D_h must hold exactly one -1 and one +1 (Dirichlet rows are not supported)");
+      fail(HCURL_EINVAL, "every row of D_h must hold one -1 and one +1, or a single +-1 (a Dirichlet edge)");
+    L0->nsingle = (int)read_flag(F_TOOBIG, c);
+    if (L0->nsingle && H.opts.init_guess == HCURL_INIT_MPNN)
+      fail(HCURL_EUNSUPPORTED, "the learned initial guess does not take Dirichlet edges");
   }
   if (H.opts.init_guess == HCURL_INIT_GIVEN && !H.opts.init_values)
     fail(HCURL_EINVAL, "init_guess = HCURL_INIT_GIVEN needs init_values");

@@ -297,7 +297,9 @@ template <class T>
 __global__ void k_grad_add(const int* __restrict__ tail, const int* __restrict__ head, int n, const T* __restrict__ cn,
                            T* __restrict__ x) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) x[e] += cn[head[e]] - cn[tail[e]];
+  if (e >= n) return;
+  const int h = head[e], t = tail[e];  // -1: the eliminated end of a Dirichlet edge
+  x[e] += (h >= 0 ? cn[h] : T(0)) - (t >= 0 ? cn[t] : T(0));
 }
 
 // dense coarsest solve x = A^-1 b (one wave per row)
@@ -508,15 +510,20 @@ static void make32(Csr& A, Ctx& c) {
 }
 
 // Cancellation ratio of D^T A D at node u: (|D|^T |A| |D| 1)_u / (D^T A D)_uu
-// = 2 sum over the edges e at u of sum_j |a_ej|, over A^(n)_uu.  For a
+// = sum over the edges e at u of s_e, over A^(n)_uu.  For a
 // gradient field x, A x = sigma M x while the terms summed are of size
 // |S||x|: an operator rounded with relative error u leaves an error of about
 // u times this ratio relative to the result.
-__global__ void k_abs_rowsum(const int* __restrict__ rp, const double* __restrict__ val, int n, double* __restrict__ s) {
+// s_e = sum_f |a_ef| (|D| 1)_f: two per edge, one per Dirichlet edge
+__global__ void k_abs_rowsum(const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ val,
+                             const int* __restrict__ drp, int n, double* __restrict__ s) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double t = 0.0;
-  for (int q = rp[i]; q < rp[i + 1]; ++q) t += fabs(val[q]);
+  for (int q = rp[i]; q < rp[i + 1]; ++q) {
+    const int f = col[q];
+    t += fabs(val[q]) * (double)(drp[f + 1] - drp[f]);
+  }
   s[i] = t;
 }
 __global__ void __launch_bounds__(256) k_cancel_max(const int* __restrict__ rp, const int* __restrict__ col, int m,
@@ -529,7 +536,7 @@ __global__ void __launch_bounds__(256) k_cancel_max(const int* __restrict__ rp, 
     double t = 0.0;
     for (int q = rp[u]; q < rp[u + 1]; ++q) t += s[col[q]];
     const double d = dinv[u];
-    if (d > 0.0) r = 2.0 * t * d;
+    if (d > 0.0) r = t * d;
   }
   for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o, 64));
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = r;
@@ -548,7 +555,9 @@ static double cancellation_ratio(Level& L, Ctx& c) {
   DBuf<double> s;
   s.alloc(L.n, c.s);
   HC_HIP(hipMemsetAsync(out, 0, sizeof(unsigned long long), c.s));
-  c.run("cancel_rowsum", 12.0 * L.A.nnz, [&] { k_abs_rowsum<<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.A.rowptr.p, L.A.val.p, L.n, s.p); });
+  c.run("cancel_rowsum", 16.0 * L.A.nnz, [&] {
+    k_abs_rowsum<<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.A.rowptr.p, L.A.col.p, L.A.val.p, L.D.rowptr.p, L.n, s.p);
+  });
   c.run("cancel_max", 12.0 * L.DT.nnz, [&] {
     k_cancel_max<<<ceil_div(L.m, 256), 256, 0, c.s>>>(L.DT.rowptr.p, L.DT.col.p, L.m, s.p, L.dinvAn.p, out);
   });

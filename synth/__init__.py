@@ -623,3 +623,37 @@ def refined_triangles(M: int) -> dict:
     Pe.sort_indices()
     agg = (xl + nc * yl).astype(np.int32)
     return dict(fine=fine, coarse=coarse, Pn=Pn, Pe=Pe, agg=agg)
+
+
+def dirichlet_problem(N: int, sigma=("const", 1.0), f_seed: int = 0, jitter: float = 0.0,
+                      jitter_seed: int | None = None) -> dict:
+    """The Kuhn-tet problem with Dirichlet conditions on the whole boundary:
+    boundary nodes are eliminated and so is every edge with both ends on the
+    boundary; an edge with one boundary end keeps one entry in D_h (a
+    Dirichlet edge, Sec. 2).  A is the kept principal submatrix; tail/head
+    hold -1 for an eliminated end.  Interior nodes keep their lattice order;
+    the level-0 aggregates are the box aggregates restricted to them and
+    renumbered in order."""
+    pr = problem(N, jitter=jitter, jitter_seed=jitter_seed, sigma=sigma, f_seed=f_seed)
+    n = N + 1
+    v = np.arange(n ** 3)
+    i, j, k = v % n, (v // n) % n, v // (n * n)
+    interior = (i > 0) & (i < N) & (j > 0) & (j < N) & (k > 0) & (k < N)
+    new_id = np.full(n ** 3, -1, np.int64)
+    new_id[interior] = np.arange(int(interior.sum()))
+    t, h = pr["tail"].astype(np.int64), pr["head"].astype(np.int64)
+    keep = interior[t] | interior[h]
+    kept = np.nonzero(keep)[0]
+    import scipy.sparse as sp
+    A = sp.csr_matrix((pr["A"][2], pr["A"][1], pr["A"][0]), shape=(len(t), len(t)))
+    Ak = A[kept][:, kept].tocsr()
+    Ak.sort_indices()
+    agg0 = pr["aggregates"][0][interior]
+    _, agg0 = np.unique(agg0, return_inverse=True)
+    out = dict(mesh=pr["mesh"], sigma=pr["sigma"], A=(Ak.indptr.astype(np.int64), Ak.indices.astype(np.int32),
+                                                      Ak.data.astype(np.float64)),
+               tail=new_id[t[kept]].astype(np.int32), head=new_id[h[kept]].astype(np.int32),
+               coords=pr["coords"][interior], m=int(interior.sum()), kept_edges=kept,
+               aggregates=[agg0.astype(np.int32)])
+    out["f"] = rhs(len(kept), f_seed)
+    return out

@@ -722,3 +722,80 @@ def test_ideal_interpolation_is_a_fixed_point_on_refined_triangles(M):
     assert abs(loc.project(g)).max() <= 1e-12 * abs(g).max()
     q, E, _ = O.projected_cg(S, N, loc, p, 5)
     assert abs(q - p).max() <= 1e-12 and abs(E[-1] - E[0]) <= 1e-12 * E[0]
+
+
+# ---------------------------------------------------------------------------
+# Dirichlet (single-node) edges: Sec. 2 and Alg. 2 (reading R27)
+# ---------------------------------------------------------------------------
+def _dirichlet(N, **kw):
+    p = synth.dirichlet_problem(N, **kw)
+    return p, O.gradient_matrix(p["tail"], p["head"], p["m"])
+
+
+def test_dirichlet_problem_keeps_the_null_space():
+    """With boundary nodes and boundary edges eliminated, S D = 0 still holds
+    on the kept edges (Sec. 2), and rows of D have one or two entries."""
+    p, D = _dirichlet(6, sigma=("lognormal", 3, 1.0))
+    full = synth.problem(6, sigma=("lognormal", 3, 1.0), with_S=True)
+    S = sp.csr_matrix((full["S"][2], full["S"][1], full["S"][0]))[p["kept_edges"]][:, p["kept_edges"]]
+    assert abs(S @ D).max() <= 1e-13 * abs(S).max()
+    cnt = np.diff(D.indptr)
+    assert set(np.unique(cnt)) == {1, 2}
+
+
+def test_dirichlet_rs_special_case():
+    """P^(n) = P-bar: the RS prolongator (a Dirichlet fine edge to the
+    single-node coarse edge of its interior node's aggregate, with the sign
+    of its D row; two-node edges as before) meets the commuting relation with
+    the single-node coarse edges; the single-node edges of Alg. 2's pattern
+    (W = 2) give rows near the boundary free entries, so the energy minimiser
+    may differ from it but has no more energy."""
+    p, D = _dirichlet(8)
+    agg = p["aggregates"][0]
+    mH = int(agg.max()) + 1
+    Pbar = O.tentative_prolongator(agg, mH)
+    lvl, _ = O.build_level(O.csr(p["A"]), p["tail"], p["head"], p["m"], agg, dict(Pn=Pbar))
+    th, hd = lvl["DH_tail"], lvl["DH_head"]
+    two = {(a, b): e for e, (a, b) in enumerate(zip(th, hd)) if a >= 0}
+    one = {b: e for e, (a, b) in enumerate(zip(th, hd)) if a < 0}
+    Pe = lvl["Pe"].toarray()
+    ref = np.zeros_like(Pe)
+    t, h = p["tail"], p["head"]
+    for e in range(len(t)):
+        if t[e] < 0 or h[e] < 0:
+            node, sgn = (h[e], 1.0) if t[e] < 0 else (t[e], -1.0)
+            ref[e, one[agg[node]]] = sgn
+        elif agg[t[e]] < agg[h[e]]:
+            ref[e, two[(agg[t[e]], agg[h[e]])]] = 1.0
+        elif agg[t[e]] > agg[h[e]]:
+            ref[e, two[(agg[h[e]], agg[t[e]])]] = -1.0
+    DH = O.gradient_matrix(th, hd, mH)
+    assert abs(ref @ DH - (D @ Pbar).toarray()).max() == 0.0
+    A = O.csr(p["A"])
+    assert O.energy(A, lvl["N"], lvl["Pe"].data) <= O.energy(A, lvl["N"], O.on_pattern(lvl["N"], sp.csr_matrix(ref)).data)
+    assert abs(O.on_pattern(lvl["N"], sp.csr_matrix(ref)) - sp.csr_matrix(ref)).max() == 0.0
+
+
+@pytest.mark.parametrize("N", [4, 5])
+def test_dirichlet_projected_cg_reaches_dense_kkt_solution(N):
+    """With Dirichlet edges in the pattern the local systems keep every
+    column (full rank); many projected-CG iterations reach the dense KKT
+    minimiser, and the commuting relation holds."""
+    p, D = _dirichlet(N, jitter=0.1, jitter_seed=4, sigma=("lognormal", 9, 1.0))
+    agg = p["aggregates"][0]
+    lvl, _ = O.build_level(O.csr(p["A"]), p["tail"], p["head"], p["m"], agg, dict(emin_iters=400))
+    assert np.any(lvl["lt"] == O.MISSING)
+    ref = _kkt_dense(lvl)
+    assert np.max(abs(lvl["Pe"].data - ref)) <= 1e-8 * np.max(abs(ref))
+    assert O.commuting_residual(lvl) <= 1e-12 * abs(lvl["D"] @ lvl["Pn"]).max()
+
+
+def test_dirichlet_hierarchy_converges():
+    p, D = _dirichlet(10, sigma=("inclusions", 8, 1.0, 1e-3), f_seed=9)
+    lv = O.setup(p["A"], p["tail"], p["head"], p["m"], p["aggregates"], dict(aggregation="mis2", coarse_max_rows=150))
+    assert len(lv) >= 3
+    for l in lv[:-1]:
+        assert O.commuting_residual(l) <= 1e-12 * max(1.0, abs(l["D"] @ l["Pn"]).max())
+        assert np.all(np.diff(l["energies"]) <= 1e-12 * l["energies"][0])
+    _, it, rel, _ = O.pcg(lv, p["f"])
+    assert rel <= 1e-8 and it < 80
