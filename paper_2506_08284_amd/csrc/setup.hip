@@ -1291,6 +1291,8 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
         fail(HCURL_EINVAL, agg_in || agg_ready ? "aggregate ids are not contiguous (an id is unused)"
                                                : "Alg. 1 left a coarse node of the given P^(n) without fine nodes");
   }
+  if (mH < 2 && L.nsingle == 0)
+    fail(HCURL_EINVAL, "the aggregates leave no coarse edge (every fine edge inside one aggregate)");
   // smoothed aggregation P^(n)
   if (!Pgiven) smoothed_aggregation(H, L, agg.p, mH);
   // P-bar from Alg. 1 on the smoothed P^(n) instead of the aggregates
@@ -1347,6 +1349,8 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
     HC_LAUNCH_CHECK();
     nsingle = (int)exclusive_scan(smark.p, spos.p, mH, c);
   }
+  if (next->n == 0 && nsingle == 0)
+    fail(HCURL_EINVAL, "the aggregates leave no coarse edge (every fine edge inside one aggregate)");
   L.n_coarse = next->n;
   // T and R = D P^(n) on T
   spgemm(L.D, L.Pn, L.R, true, c, "spgemm_DPn");
@@ -1458,6 +1462,7 @@ void build_hierarchy(Hierarchy& H, const hcurl_csr& A, const hcurl_csr& Dh, cons
   Ctx& c = H.ctx;
   const bool dev = H.opts.mem_space == HCURL_MEM_DEVICE;
   if (A.nrows != A.ncols) fail(HCURL_EINVAL, "A must be square");
+  if (A.nrows == 0 || Dh.ncols == 0) fail(HCURL_EINVAL, "empty problem: A and D_h need at least one edge and one node");
   if (Dh.nrows != A.nrows) fail(HCURL_EINVAL, "D_h must have one row per edge");
   if (nagg < 0 || (nagg > 0 && !aggs)) fail(HCURL_EINVAL, "aggregates missing");
   auto L0 = std::make_unique<Level>();

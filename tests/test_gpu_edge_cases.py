@@ -1,0 +1,68 @@
+"""Degenerate inputs on the GPU: a zero right-hand side, an empty problem, a
+single aggregate (no coarse edge), every node its own aggregate (a coarse
+level as large as the fine one), and a problem small enough to be the
+coarsest level at once."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import hcurl_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    import paper_2506_08284_amd as P
+    return P
+
+
+def test_zero_right_hand_side_gives_zero_solution():
+    P = _lib()
+    pr = synth.problem(6, sigma=("const", 1.0))
+    H = P.Hierarchy(pr["A"], synth.gradient_csr(pr["tail"], pr["head"]), pr["aggregates"], n_nodes=343)
+    u = np.full(pr["A"][0].shape[0] - 1, 7.0)
+    it, rel, rc = H.solve(np.zeros_like(u), u)
+    assert rc == 0 and it == 0 and rel == 0.0 and np.all(u == 0.0)
+    H.close()
+
+
+def test_empty_problem_is_rejected():
+    P = _lib()
+    A = (np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0))
+    with pytest.raises(P.HcurlError) as e:
+        P.Hierarchy(A, (np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0)), [], n_nodes=0)
+    assert e.value.code == P.HCURL_EINVAL
+
+
+def test_single_aggregate_is_rejected():
+    """All nodes in one aggregate: no coarse edge exists, so there is no
+    transfer to build."""
+    P = _lib()
+    pr = synth.problem(4)
+    Dh = synth.gradient_csr(pr["tail"], pr["head"])
+    with pytest.raises(P.HcurlError) as e:
+        P.Hierarchy(pr["A"], Dh, [np.zeros(125, np.int32)], n_nodes=125)
+    assert e.value.code == P.HCURL_EINVAL
+
+
+def test_identity_aggregates_against_oracle():
+    """Every node its own aggregate: the coarse level has the fine level's
+    size, D_H = D_h, P^(n) is the smoothed identity; structures bit for bit,
+    the solve against the oracle's."""
+    P = _lib()
+    pr = synth.problem(4, jitter=0.1, jitter_seed=3, sigma=("lognormal", 4, 1.0), f_seed=2)
+    m = 125
+    ident = np.arange(m, dtype=np.int32)
+    levels = O.setup(pr["A"], pr["tail"], pr["head"], m, [ident])
+    H = P.Hierarchy(pr["A"], synth.gradient_csr(pr["tail"], pr["head"]), [ident], n_nodes=m)
+    arrs, shape = H.export_csr(0, "DH")
+    assert np.array_equal(arrs[1], O.gradient_matrix(pr["tail"], pr["head"], m).indices)
+    assert H.level_info(1)["n_edges"] == pr["A"][0].shape[0] - 1
+    arrs, shape = H.export_csr(0, "Pe")
+    assert np.array_equal(arrs[0], levels[0]["N"].indptr) and np.array_equal(arrs[1], levels[0]["N"].indices)
+    n = pr["A"][0].shape[0] - 1
+    u = np.empty(n)
+    it, rel, rc = H.solve(pr["f"], u)
+    uo, ito, _, _ = O.pcg(levels, pr["f"])
+    assert rc == 0 and rel <= 1e-8 and abs(it - ito) <= 1
+    H.close()
