@@ -108,18 +108,19 @@ typedef struct {
                               P^(n) keeps constants; an empty row, a zero or
                               non-finite row sum is HCURL_EINVAL.  If aggregates[0]
                               is NULL the level-0 aggregates (the piecewise-constant
-                              P-bar behind D_H) come from Alg. 1 in the parallel
-                              form below; otherwise aggregates[0] must map onto
+                              P-bar behind D_H) come from Alg. 1 as described
+                              below; otherwise aggregates[0] must map onto
                               exactly the m_1 columns.  level_info reports rho and
                               omega as 0 for that level. */
-  int alg1_passes;         /* passes of the parallel Alg. 1 (default 2, >= 1).  Column j
-                              gets the target t_j = ceil(nnz(P_:j) m_h / nnz(P)); in
-                              each pass every column proposes its ceil(t_j / passes)
-                              unassigned rows of largest |p_ij| (ties: smaller row) and
-                              a row proposed by several columns takes the largest
-                              |p_ij| (ties: smaller column); rows left over take the
-                              column of their largest |p_ij| (ties: smaller column).
-                              A column left without rows is HCURL_EINVAL. */
+  int alg1_passes;         /* passes of Alg. 1 (default 2, >= 1).  Column j gets the
+                              target t_j = ceil(nnz(P_:j) m_h / nnz(P)).  In each pass
+                              the columns, in order, take their ceil(t_j / passes)
+                              still unassigned rows of largest |p_ij| (ties: smaller
+                              row).  Rows left over take the column of their largest
+                              |p_ij| (ties: smaller column).  Then, columns in order,
+                              a column left without rows takes its row of largest
+                              |p_ij| (ties: smaller row) among rows whose column keeps
+                              another row; if it has none, HCURL_EINVAL. */
   int pbar_alg1;           /* 0 (default): P-bar behind D_H is the piecewise-constant
                               prolongator of the aggregates.  1: P-bar comes from
                               Alg. 1 applied to the smoothed P^(n) of every level, as
