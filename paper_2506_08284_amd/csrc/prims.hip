@@ -203,16 +203,18 @@ __global__ void k_transpose_scatter(const int* __restrict__ rowptr, const int* _
 
 // Sorts the column indices (unique within a row) of every row, carrying
 // values, by rank counting in LDS: one wave per row, rows up to kSortCap.
+// Longer rows are listed in long_rows (count in *n_long) for k_sort_rows_wg.
 static constexpr int kSortCap = 1024;
 __global__ void __launch_bounds__(64) k_sort_rows(const int* __restrict__ rowptr, int nrows, int* __restrict__ col,
-                                                  double* __restrict__ val, int* __restrict__ too_long) {
+                                                  double* __restrict__ val, int* __restrict__ n_long,
+                                                  int* __restrict__ long_rows) {
   __shared__ int kk[kSortCap];
   __shared__ double vv[kSortCap];
   for (int i = blockIdx.x; i < nrows; i += gridDim.x) {
     const int a = rowptr[i], len = rowptr[i + 1] - a;
     if (len <= 1) continue;
     if (len > kSortCap) {
-      if (threadIdx.x == 0) atomicAdd(too_long, 1);
+      if (threadIdx.x == 0) long_rows[atomicAdd(n_long, 1)] = i;
       continue;
     }
     for (int t = threadIdx.x; t < len; t += 64) {
@@ -231,23 +233,53 @@ __global__ void __launch_bounds__(64) k_sort_rows(const int* __restrict__ rowptr
   }
 }
 
-// Fallback for rows longer than kSortCap: insertion sort by one thread.
-__global__ void k_sort_rows_long(const int* __restrict__ rowptr, int nrows, int* __restrict__ col, double* __restrict__ val) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nrows) return;
-  const int a = rowptr[i], b = rowptr[i + 1];
-  if (b - a <= kSortCap) return;
-  for (int q = a + 1; q < b; ++q) {
-    int key = col[q];
-    double v = val ? val[q] : 0.0;
-    int r = q - 1;
-    while (r >= a && col[r] > key) {
-      col[r + 1] = col[r];
-      if (val) val[r + 1] = val[r];
-      --r;
+// Rows longer than kSortCap, one workgroup per listed row.  Every thread
+// takes kLongPer of the row's entries at a time and ranks them against the
+// whole row, staged through LDS in chunks of kLongChunk keys; entries go to
+// their ranks in tcol/tval (same offsets as col), and after a barrier the
+// row is copied back.  The row is only read before the barrier and only
+// written after it.
+static constexpr int kLongPer = 8;
+static constexpr int kLongChunk = 8192;
+__global__ void __launch_bounds__(1024) k_sort_rows_wg(const int* __restrict__ rowptr, const int* __restrict__ long_rows,
+                                                       int* __restrict__ col, double* __restrict__ val,
+                                                       int* __restrict__ tcol, double* __restrict__ tval) {
+  __shared__ int sk[kLongChunk];
+  const int i = long_rows[blockIdx.x];
+  const int a = rowptr[i], len = rowptr[i + 1] - a;
+  const int tid = threadIdx.x;
+  for (int base = 0; base < len; base += 1024 * kLongPer) {
+    int key[kLongPer], rk[kLongPer];
+#pragma unroll
+    for (int u = 0; u < kLongPer; ++u) {
+      const int t = base + u * 1024 + tid;
+      key[u] = t < len ? col[a + t] : 0x7fffffff;
+      rk[u] = 0;
     }
-    col[r + 1] = key;
-    if (val) val[r + 1] = v;
+    for (int c0 = 0; c0 < len; c0 += kLongChunk) {
+      const int nc = min(kLongChunk, len - c0);
+      __syncthreads();  // the previous chunk has been consumed
+      for (int t = tid; t < nc; t += 1024) sk[t] = col[a + c0 + t];
+      __syncthreads();
+      for (int v = 0; v < nc; ++v) {
+        const int kv = sk[v];
+#pragma unroll
+        for (int u = 0; u < kLongPer; ++u) rk[u] += kv < key[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kLongPer; ++u) {
+      const int t = base + u * 1024 + tid;
+      if (t < len) {
+        tcol[a + rk[u]] = key[u];
+        if (val) tval[a + rk[u]] = val[a + t];
+      }
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < len; t += 1024) {
+    col[a + t] = tcol[a + t];
+    if (val) val[a + t] = tval[a + t];
   }
 }
 
@@ -255,13 +287,21 @@ static void sort_rows(Csr& C, Ctx& c) {
   if (C.nrows == 0 || C.nnz == 0) return;
   long long* flag = c.iscal.p + 0;
   HC_HIP(hipMemsetAsync(flag, 0, sizeof(long long), c.s));
+  // at most nnz / (kSortCap + 1) rows are longer than kSortCap
+  DBuf<int> long_rows(C.nnz / (kSortCap + 1) + 1, c.s);
   int nb = std::min(C.nrows, 65536);
-  c.run("sort_rows", 16.0 * C.nnz, [&] { k_sort_rows<<<nb, 64, 0, c.s>>>(C.rowptr.p, C.nrows, C.col.p, C.val.p, (int*)flag); });
+  c.run("sort_rows", 16.0 * C.nnz,
+        [&] { k_sort_rows<<<nb, 64, 0, c.s>>>(C.rowptr.p, C.nrows, C.col.p, C.val.p, (int*)flag, long_rows.p); });
   long long h = 0;
   d2h(&h, flag, 1, c);
-  if ((int)h > 0)
-    c.run("sort_rows_long", 16.0 * C.nnz,
-          [&] { k_sort_rows_long<<<ceil_div(C.nrows, 64), 64, 0, c.s>>>(C.rowptr.p, C.nrows, C.col.p, C.val.p); });
+  const int nlong = (int)h;
+  if (nlong > 0) {
+    DBuf<int> tcol(C.nnz, c.s);
+    DBuf<double> tval(C.val.p ? C.nnz : 0, c.s);
+    c.run("sort_rows_long", 32.0 * C.nnz, [&] {
+      k_sort_rows_wg<<<nlong, 1024, 0, c.s>>>(C.rowptr.p, long_rows.p, C.col.p, C.val.p, tcol.p, tval.p);
+    });
+  }
 }
 
 void transpose(const Csr& A, Csr& AT, bool values, Ctx& c) {

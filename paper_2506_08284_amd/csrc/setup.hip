@@ -603,6 +603,25 @@ __device__ __forceinline__ bool local_solve(double* x, const uint16_t* __restric
   return ok;
 }
 
+// Runs each row in the smallest register layout that holds it: the unknowns
+// a >= k never enter the arithmetic, so a row with k unknowns gives the same
+// bits in every layout with MAXJ - 1 >= k, and a level whose largest rows need
+// a wide layout does not make every row pay for it.
+template <int MAXJ>
+__device__ __forceinline__ bool local_solve_fit(double* x, const uint16_t* __restrict__ lp, int np, int nJ,
+                                                const double* __restrict__ rrow) {
+  if constexpr (MAXJ > 8) {
+    int miss = 0;
+    for (int e = 0; e < np; ++e) miss |= ((lp[e] & 255) == 255) | ((lp[e] >> 8) == 255);
+    const int k = nJ - 1 + miss;
+    if (k <= 7) return local_solve<8>(x, lp, np, nJ, rrow);
+    if constexpr (MAXJ > 16) {
+      if (k <= 15) return local_solve<16>(x, lp, np, nJ, rrow);
+    }
+  }
+  return local_solve<MAXJ>(x, lp, np, nJ, rrow);
+}
+
 // Affine step on every row: x <- x + G~ L~^-1 (r~ - G~^T x).  With `ones` the
 // row is first set to ones (the plain initial guess of Sec. 6.1).
 template <int MAXJ>
@@ -615,7 +634,7 @@ __global__ void k_make_feasible(int n, const int* __restrict__ Prp, double* __re
   if (ones)
     for (int e = 0; e < np; ++e) x[p0 + e] = 1.0;
   const int t0 = Trp[i];
-  if (!local_solve<MAXJ>(x + p0, lp + p0, np, Trp[i + 1] - t0, Rval + t0)) atomicAdd((unsigned long long*)&flags[F_NOTSPD], 1ULL);
+  if (!local_solve_fit<MAXJ>(x + p0, lp + p0, np, Trp[i + 1] - t0, Rval + t0)) atomicAdd((unsigned long long*)&flags[F_NOTSPD], 1ULL);
 }
 
 // ---------------------------------------------------------------------------
@@ -759,7 +778,7 @@ __global__ void __launch_bounds__(64) k_emin_project(int nrows, int R, const int
     if (l < nr) {
       const int i = r0 + l;
       const int t0 = Trp[i];
-      if (!local_solve<MAXJ>(acc + pofs[l], lpair + p0 + pofs[l], pofs[l + 1] - pofs[l], Trp[i + 1] - t0, nullptr))
+      if (!local_solve_fit<MAXJ>(acc + pofs[l], lpair + p0 + pofs[l], pofs[l + 1] - pofs[l], Trp[i + 1] - t0, nullptr))
         atomicAdd((unsigned long long*)&iflags[F_NOTSPD], 1ULL);
     }
     __syncthreads();

@@ -66,3 +66,39 @@ def test_identity_aggregates_against_oracle():
     uo, ito, _, _ = O.pcg(levels, pr["f"])
     assert rc == 0 and rel <= 1e-8 and abs(it - ito) <= 1
     H.close()
+
+
+def test_slab_aggregates_long_transposed_rows():
+    """Three slabs of 5 x 15 x 15 nodes as the aggregates: the transposes of
+    P^(n) and P^(e) get rows of more than 1024 entries (the interface's coarse
+    edge lies in the pattern of thousands of fine edges), which the library
+    sorts in its long-row path.  Structures bit for bit, the coarse operator
+    and the solve against the oracle."""
+    P = _lib()
+    N = 14
+    m = (N + 1) ** 3
+    pr = synth.problem(N, sigma=("const", 1.0), f_seed=5)
+    agg = ((np.arange(m) % (N + 1)) // 5).astype(np.int32)
+    levels = O.setup(pr["A"], pr["tail"], pr["head"], m, [agg])
+    H = P.Hierarchy(pr["A"], synth.gradient_csr(pr["tail"], pr["head"]), [agg], n_nodes=m)
+    assert H.num_levels() == len(levels) == 2
+    Pe = O.csr(levels[0]["N"])
+    assert np.bincount(Pe.indices).max() > 1024
+    arrs, shape = H.export_csr(0, "Pe")
+    assert np.array_equal(arrs[0], Pe.indptr) and np.array_equal(arrs[1], Pe.indices)
+    ref = O.csr(levels[0]["Pe"])
+    assert np.max(abs(arrs[2] - ref.data)) <= 1e-10 * abs(ref.data).max()
+    arrs, shape = H.export_csr(0, "DH")
+    DH = O.gradient_matrix(levels[0]["DH_tail"], levels[0]["DH_head"], 3)
+    assert np.array_equal(arrs[1], DH.indices) and np.array_equal(arrs[2], DH.data)
+    arrs, shape = H.export_csr(1, "A")
+    A1 = O.csr(levels[1]["A"])
+    assert np.array_equal(arrs[0], A1.indptr) and np.array_equal(arrs[1], A1.indices)
+    assert np.max(abs(arrs[2] - A1.data)) <= 1e-10 * abs(A1.data).max()
+    n = pr["A"][0].shape[0] - 1
+    u = np.empty(n)
+    it, rel, rc = H.solve(pr["f"], u)
+    uo, ito, _, _ = O.pcg(levels, pr["f"])
+    assert rc == 0 and rel <= 1e-8 and abs(it - ito) <= 1
+    assert np.linalg.norm(u - uo) <= 1e-6 * np.linalg.norm(uo)
+    H.close()
