@@ -218,6 +218,15 @@ typedef struct {
 
 int hcurl_amg_level_info(hcurl_amg h, int level, hcurl_level_info* info);
 
+/* Structure check of level l < levels-1 (the commuting relation of Sec. 4.2,
+ * P^(e)_l D_{l+1} = D_l P^(n)_l), computed on the device over every row:
+ * abs_max = max |(P^(e) D_{l+1} - D_l P^(n))_iK| and ref_max = max |(D_l P^(n))_iK|
+ * over the pattern T_l (which holds both products' patterns).  The library
+ * keeps the relation to rounding, so abs_max / ref_max is a small multiple of
+ * the FP64 epsilon; a NaN anywhere makes abs_max NaN.  Host outputs.
+ * Errors: HCURL_EINVAL (level, NULL outputs, unusable handle). */
+int hcurl_amg_commute_residual(hcurl_amg h, int level, double* abs_max, double* ref_max);
+
 /* Export of level data to caller-allocated HOST arrays sized from level_info.
  * which: */
 enum {

@@ -25,7 +25,8 @@ VEC = {"colors_A": 0, "colors_An": 1, "energy": 2, "local_pairs": 3, "pcg_histor
 # every function declared in include/hcurl_amg.h
 EXPORTED_SYMBOLS = [
     "hcurl_amg_default_opts", "hcurl_amg_setup", "hcurl_amg_solve", "hcurl_amg_vcycle", "hcurl_amg_update",
-    "hcurl_amg_destroy", "hcurl_amg_num_levels", "hcurl_amg_level_info", "hcurl_amg_export_csr", "hcurl_amg_export_vec",
+    "hcurl_amg_destroy", "hcurl_amg_num_levels", "hcurl_amg_level_info", "hcurl_amg_commute_residual",
+    "hcurl_amg_export_csr", "hcurl_amg_export_vec",
     "hcurl_amg_stats", "hcurl_amg_kernel_stats", "hcurl_amg_reset_kernel_stats", "hcurl_last_error",
     "hcurl_error_string", "hcurl_mpnn_num_params", "hcurl_mpnn_create", "hcurl_mpnn_get_params", "hcurl_mpnn_destroy",
     "hcurl_amg_mpnn_sample", "hcurl_mpnn_sample_entries", "hcurl_mpnn_sample_export", "hcurl_mpnn_sample_destroy",
@@ -99,6 +100,9 @@ def _load():
     L.hcurl_amg_num_levels.restype = ctypes.c_int
     L.hcurl_amg_level_info.argtypes = [P, ctypes.c_int, ctypes.POINTER(hcurl_level_info)]
     L.hcurl_amg_level_info.restype = ctypes.c_int
+    L.hcurl_amg_commute_residual.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_double)]
+    L.hcurl_amg_commute_residual.restype = ctypes.c_int
     L.hcurl_amg_export_csr.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, P]
     L.hcurl_amg_export_csr.restype = ctypes.c_int
     L.hcurl_amg_export_vec.argtypes = [P, ctypes.c_int, ctypes.c_int, P, ctypes.c_int64]
@@ -246,6 +250,13 @@ def hcurl_amg_level_info(h, level: int) -> dict:
     info = hcurl_level_info()
     _check(lib.hcurl_amg_level_info(h, level, ctypes.byref(info)))
     return {k: getattr(info, k) for k, _ in info._fields_}
+
+
+def hcurl_amg_commute_residual(h, level: int):
+    """(max |P^(e) D_H - D_h P^(n)|, max |D_h P^(n)|) over every row of the level."""
+    a, r = ctypes.c_double(), ctypes.c_double()
+    _check(lib.hcurl_amg_commute_residual(h, level, ctypes.byref(a), ctypes.byref(r)))
+    return a.value, r.value
 
 
 def hcurl_amg_export_csr(h, level: int, which: str):
@@ -434,6 +445,9 @@ class Hierarchy:
 
     def level_info(self, level):
         return hcurl_amg_level_info(self.h, level)
+
+    def commute_residual(self, level):
+        return hcurl_amg_commute_residual(self.h, level)
 
     def export_csr(self, level, which):
         return hcurl_amg_export_csr(self.h, level, which)

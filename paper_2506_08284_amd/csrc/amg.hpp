@@ -96,6 +96,8 @@ void update_hierarchy(Hierarchy& H, const hcurl_csr& A, int mode, int iters);
 // the local min-norm correction x <- x + G~ L~^-1 (r~ - G~^T x) on every row
 // (with `ones`, x is first set to ones)
 void emin_make_feasible(Level& L, double* x, bool ones, Ctx& c);
+// max |P^(e) D_H - D_h P^(n)| over the level's rows and max |D_h P^(n)| on T
+void commute_residual(Level& L, double* abs_max, double* ref_max, Ctx& c);
 
 // solve.hip
 void color_rows(const Csr& A, DBuf<int>& color, DBuf<int>& rows, std::vector<int>& cptr, int& ncol, Ctx& c);

@@ -187,6 +187,16 @@ int hcurl_amg_level_info(hcurl_amg h, int level, hcurl_level_info* info) {
   });
 }
 
+int hcurl_amg_commute_residual(hcurl_amg h, int level, double* abs_max, double* ref_max) {
+  if (!abs_max || !ref_max) return HCURL_EINVAL;
+  return guarded([&]() -> int {
+    hc::Level* L = level_of(h, level);
+    if (!h->H.valid) hc::fail(HCURL_EINVAL, "the handle is unusable after a failed hcurl_amg_update");
+    hc::commute_residual(*L, abs_max, ref_max, h->H.ctx);
+    return HCURL_OK;
+  });
+}
+
 int hcurl_amg_export_csr(hcurl_amg h, int level, int which, int64_t* rowptr, int32_t* col, double* val) {
   return guarded([&]() -> int {
     hc::Level* L = level_of(h, level);

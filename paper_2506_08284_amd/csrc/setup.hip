@@ -3,6 +3,8 @@
 // constrained energy minimisation of P^(e) (Sec. 3, Sec. 4), Galerkin RAP.
 #include <chrono>
 #include <cmath>
+#include <cstring>
+#include <limits>
 
 #include "mpnn.hpp"
 
@@ -955,6 +957,77 @@ static void make_feasible(Level& L, double* x, bool ones, Ctx& c) {
 }
 
 void emin_make_feasible(Level& L, double* x, bool ones, Ctx& c) { make_feasible(L, x, ones, c); }
+
+// Commuting residual of a level (Sec. 4.2: P^(e) D_H = D_h P^(n)).  Row i of
+// P^(e) D_H lies on the coarse nodes T_i: pattern entry (i, e) adds -p at the
+// local tail and +p at the local head of coarse edge e (an end with local
+// index 255 is absent: a single-node coarse edge).  One single-wave
+// workgroup per row accumulates the row in LDS, subtracts R_i = (D_h P^(n))_i
+// on T_i and keeps the largest |difference| and |R|; out holds their bit
+// patterns (non-negative doubles order like their bits) and a NaN count.
+__global__ void __launch_bounds__(64) k_commute_residual(int n, const int* __restrict__ Prp, const double* __restrict__ pv,
+                                                         const uint16_t* __restrict__ lp, const int* __restrict__ Trp,
+                                                         const double* __restrict__ Rv,
+                                                         unsigned long long* __restrict__ out) {
+  __shared__ double b[256];
+  const int l = threadIdx.x;
+  double cmax = 0.0, rmax = 0.0;
+  unsigned long long nan = 0;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const int t0 = Trp[i], nt = Trp[i + 1] - t0;
+    const int p0 = Prp[i], np = Prp[i + 1] - p0;
+    if (nt > 255) {  // local indices are 8-bit: cannot occur
+      nan += l == 0;
+      continue;
+    }
+    for (int k = l; k < nt; k += 64) b[k] = 0.0;
+    __syncthreads();
+    for (int e = l; e < np; e += 64) {
+      const int q = lp[p0 + e], t = q & 255, h = q >> 8;
+      const double p = pv[p0 + e];
+      if (t < nt) atomicAdd(&b[t], -p);
+      if (h < nt) atomicAdd(&b[h], p);
+    }
+    __syncthreads();
+    for (int k = l; k < nt; k += 64) {
+      const double r = Rv[t0 + k], d = fabs(b[k] - r);
+      nan += (d != d) || (r != r);
+      cmax = d > cmax ? d : cmax;
+      rmax = fabs(r) > rmax ? fabs(r) : rmax;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    cmax = fmax(cmax, __shfl_xor(cmax, o, 64));
+    rmax = fmax(rmax, __shfl_xor(rmax, o, 64));
+  }
+  nan = wave_sum(nan);
+  if (l == 0) {
+    atomicMax(out + 0, (unsigned long long)__double_as_longlong(cmax));
+    atomicMax(out + 1, (unsigned long long)__double_as_longlong(rmax));
+    if (nan) atomicAdd(out + 2, nan);
+  }
+}
+
+void commute_residual(Level& L, double* abs_max, double* ref_max, Ctx& c) {
+  if (!L.has_transfer) fail(HCURL_EINVAL, "level has no transfer");
+  DBuf<unsigned long long> r(3, c.s);
+  HC_HIP(hipMemsetAsync(r.p, 0, 3 * sizeof(unsigned long long), c.s));
+  if (L.n > 0) {
+    const int grid = std::min(L.n, 65536);
+    c.run("commute_residual", 14.0 * L.Pe.nnz + 8.0 * L.R.nnz, [&] {
+      k_commute_residual<<<grid, 64, 0, c.s>>>(L.n, L.Pe.rowptr.p, L.Pe.val.p, L.lpair.p, L.R.rowptr.p, L.R.val.p, r.p);
+    });
+  }
+  unsigned long long h[3];
+  d2h(h, r.p, 3, c);
+  double a, b;
+  std::memcpy(&a, &h[0], sizeof a);
+  std::memcpy(&b, &h[1], sizeof b);
+  *abs_max = h[2] ? std::numeric_limits<double>::quiet_NaN() : a;
+  *ref_max = b;
+}
 
 __global__ void k_add2(int64_t n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ y) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -80,6 +80,10 @@ def test_dirichlet_hierarchy_matches_oracle(name):
     D0 = O.gradient_matrix(p["tail"], p["head"], m)
     C = _export(H, 0, "Pe") @ _export(H, 0, "DH") - D0 @ _export(H, 0, "Pn")
     assert abs(C).max() <= 1e-12 * abs(D0 @ _export(H, 0, "Pn")).max()
+    # the library's own check, with single-node coarse edges on every level
+    for l in range(H.num_levels() - 1):
+        a, r = H.commute_residual(l)
+        assert a <= 1e-12 * r, (l, a, r)
     n = p["A"][0].shape[0] - 1
     u = np.empty(n)
     it, rel, rc = H.solve(p["f"], u, 1e-8, 500)

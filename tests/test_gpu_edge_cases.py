@@ -91,6 +91,8 @@ def test_slab_aggregates_long_transposed_rows():
     arrs, shape = H.export_csr(0, "DH")
     DH = O.gradient_matrix(levels[0]["DH_tail"], levels[0]["DH_head"], 3)
     assert np.array_equal(arrs[1], DH.indices) and np.array_equal(arrs[2], DH.data)
+    a, r = H.commute_residual(0)
+    assert a <= 1e-12 * r
     arrs, shape = H.export_csr(1, "A")
     A1 = O.csr(levels[1]["A"])
     assert np.array_equal(arrs[0], A1.indptr) and np.array_equal(arrs[1], A1.indices)

@@ -185,6 +185,10 @@ def test_cube128_contrast_bench_configuration():
     # commuting relation P^(e) D_H = D_h P^(n) on the sampled rows
     C = O.csr(Pe[I] @ DH_o - D[I] @ Pn)
     assert abs(C.data).max(initial=0.0) <= 1e-11 * abs(O.csr(D[I] @ Pn).data).max()
+    # the commuting relation over every row of every level, on the device
+    for l in range(H.num_levels() - 1):
+        a, r = H.commute_residual(l)
+        assert a <= 1e-11 * r, (l, a, r)
     # energy decreases over the projected-CG iterations on every level
     for l in range(H.num_levels() - 1):
         E = H.export_vec(l, "energy")

@@ -100,6 +100,8 @@ def test_learned_guess_keeps_commuting_relation(case):
     DH = sp.csr_matrix((a3[2], a3[1], a3[0]), shape=s3)
     D = O.gradient_matrix(pr["tail"], pr["head"], 343)
     assert abs(Pe @ DH - D @ Pn).max() <= 1e-12 * abs(D @ Pn).max()
+    a, r = HL.commute_residual(0)
+    assert a <= 1e-12 * r
 
 
 def _energy(P, pr, m, **opts):

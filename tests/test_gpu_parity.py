@@ -145,6 +145,19 @@ def test_structure_preservation_on_gpu_output(name):
     S = O.csr(synth.assemble(pr["mesh"], pr["sigma"], "S"))
     SH = Pe.T @ S @ Pe
     assert abs(SH @ DH).max() <= 1e-11 * abs(SH).max()
+    # the library's own check over every row of every level: its reference
+    # maximum is the exported R's exactly, its residual at rounding level like
+    # the one formed here from the exports
+    for l in range(H.num_levels() - 1):
+        a, r = H.commute_residual(l)
+        R = O.csr(_export(H, l, "R"))
+        assert r == abs(R.data).max()
+        Dl = O.gradient_matrix(levels[l]["DH_tail"], levels[l]["DH_head"], levels[l]["Pn"].shape[1])
+        Eh = O.csr(_export(H, l, "Pe") @ Dl - R)
+        assert a <= 1e-12 * r and abs(Eh.data).max(initial=0.0) <= 1e-12 * r
+    P = _lib()
+    with pytest.raises(P.HcurlError):
+        H.commute_residual(H.num_levels() - 1)
 
 
 @pytest.mark.parametrize("name", list(CASES))

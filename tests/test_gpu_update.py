@@ -106,6 +106,9 @@ def test_update_warm_matches_oracle():
     D = O.gradient_matrix(p2["tail"], p2["head"], m)
     C = _export(H, 0, "Pe") @ _export(H, 0, "DH") - D @ _export(H, 0, "Pn")
     assert abs(C).max() <= 1e-12 * abs(D @ _export(H, 0, "Pn")).max()
+    for l in range(H.num_levels() - 1):
+        a, r = H.commute_residual(l)
+        assert a <= 1e-12 * r
     n = p2["A"][0].shape[0] - 1
     u = np.empty(n)
     it, rel, rc = H.solve(p2["f"], u, 1e-8, 500)
