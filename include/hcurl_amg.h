@@ -148,6 +148,22 @@ typedef struct {
                               the solve time carries little event overhead. */
   int mem_space;           /* HCURL_MEM_HOST or HCURL_MEM_DEVICE */
   void* stream;            /* hipStream_t */
+  /* Device memory of the handle.  NULL (default, both): hipMallocAsync and
+     hipFreeAsync on `stream`.  Otherwise dev_alloc(bytes, stream, alloc_ctx)
+     returns device memory for use in stream order on `stream` (NULL makes the
+     call fail with HCURL_ENOMEM) and dev_free(ptr, bytes, stream, alloc_ctx)
+     gives it back; both are called on the thread that calls the library,
+     from hcurl_amg_setup, _solve, _vcycle, _update, _commute_residual, the
+     exports and hcurl_amg_destroy, never while a graph is being captured.
+     Work enqueued on `stream` may still use a buffer when it is freed: the
+     allocator must not hand it to other streams before that work completes
+     (a stream-ordered pool on the same stream, such as PyTorch's caching
+     allocator, does this).  Both functions must stay valid until
+     hcurl_amg_destroy returns.  Set both or neither (HCURL_EINVAL).  Training
+     samples (hcurl_amg_mpnn_sample) and networks use the default. */
+  void* (*dev_alloc)(size_t bytes, void* stream, void* alloc_ctx);
+  void (*dev_free)(void* ptr, size_t bytes, void* stream, void* alloc_ctx);
+  void* alloc_ctx;
 } hcurl_amg_opts;
 
 /* Fills the defaults listed above. */

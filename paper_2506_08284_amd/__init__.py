@@ -16,5 +16,5 @@ from .binding import (  # noqa: F401
     hcurl_amg_kernel_stats, hcurl_amg_reset_kernel_stats, hcurl_last_error, hcurl_error_string, Hierarchy,
     hcurl_mpnn_num_params, hcurl_mpnn_create, hcurl_mpnn_get_params, hcurl_mpnn_destroy, hcurl_amg_mpnn_sample,
     hcurl_mpnn_sample_entries, hcurl_mpnn_sample_export, hcurl_mpnn_sample_destroy, hcurl_mpnn_forward,
-    hcurl_mpnn_loss_grad, hcurl_mpnn_train_step, Network,
+    hcurl_mpnn_loss_grad, hcurl_mpnn_train_step, Network, DEV_ALLOC_FN, DEV_FREE_FN,
 )

@@ -46,7 +46,40 @@ class hcurl_amg_opts(ctypes.Structure):
                 ("vcycle_fp32", ctypes.c_int), ("nodal_prolongator", ctypes.c_void_p), ("alg1_passes", ctypes.c_int),
                 ("pbar_alg1", ctypes.c_int), ("aggregation", ctypes.c_int),
                 ("power_iters", ctypes.c_int), ("record_energy", ctypes.c_int), ("profile", ctypes.c_int),
-                ("mem_space", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("mem_space", ctypes.c_int), ("stream", ctypes.c_void_p), ("dev_alloc", ctypes.c_void_p),
+                ("dev_free", ctypes.c_void_p), ("alloc_ctx", ctypes.c_void_p)]
+
+# device-memory callbacks of hcurl_amg_opts (dev_alloc, dev_free)
+DEV_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+DEV_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+
+
+def _allocator_callbacks(allocator):
+    """(dev_alloc, dev_free) ctypes callbacks for `allocator`: "torch" (the
+    PyTorch caching allocator, stream-ordered on the handle's stream) or a
+    pair of Python callables alloc(nbytes, stream) -> int pointer (0 on
+    failure) and free(ptr, nbytes, stream)."""
+    if allocator == "torch":
+        import torch
+
+        def alloc(nbytes, stream):
+            return torch.cuda.caching_allocator_alloc(nbytes, stream=stream or 0)
+
+        def free(ptr, nbytes, stream):
+            torch.cuda.caching_allocator_delete(ptr)
+    else:
+        alloc, free = allocator
+
+    def c_alloc(nbytes, stream, ctx):
+        try:
+            return alloc(int(nbytes), stream or 0) or None
+        except Exception:
+            return None
+
+    def c_free(ptr, nbytes, stream, ctx):
+        free(ptr, int(nbytes), stream or 0)
+
+    return DEV_ALLOC_FN(c_alloc), DEV_FREE_FN(c_free)
 
 
 class hcurl_level_info(ctypes.Structure):
@@ -426,8 +459,16 @@ class Network:
 class Hierarchy:
     """Owns a handle; methods map one to one onto the C calls."""
 
-    def __init__(self, A, Dh, aggregates, n_nodes, coords=None, **opts):
+    def __init__(self, A, Dh, aggregates, n_nodes, coords=None, allocator=None, **opts):
+        """allocator: None (the library's stream-ordered hipMallocAsync), "torch"
+        (PyTorch's caching allocator) or (alloc(nbytes, stream) -> ptr,
+        free(ptr, nbytes, stream)); the callbacks live as long as the handle."""
+        self.h = None
+        self._cbs = _allocator_callbacks(allocator) if allocator is not None else None
         self.opts = hcurl_amg_default_opts(**opts)
+        if self._cbs:
+            self.opts.dev_alloc = ctypes.cast(self._cbs[0], ctypes.c_void_p).value
+            self.opts.dev_free = ctypes.cast(self._cbs[1], ctypes.c_void_p).value
         self._keep = (A, Dh, aggregates, opts.get("init_values"), opts.get("mpnn"), opts.get("nodal_prolongator"), coords)
         self.h = hcurl_amg_setup(A, Dh, aggregates, coords, self.opts, n_nodes=n_nodes)
 

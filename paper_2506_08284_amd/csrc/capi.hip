@@ -6,6 +6,7 @@
 #include "mpnn.hpp"
 
 struct hcurl_amg_s {
+  hc::Allocator alloc;  // declared first: outlives every buffer of H
   hc::Hierarchy H;
 };
 
@@ -35,6 +36,9 @@ int guarded(F&& f) {
     return HCURL_EHIP;
   }
 }
+
+// the handle's allocator for the scope of an entry point (null: the default)
+const hc::Allocator* alloc_of(hcurl_amg h) { return h && h->alloc.alloc ? &h->alloc : nullptr; }
 
 hc::Level* level_of(hcurl_amg h, int level) {
   if (!h || level < 0 || level >= (int)h->H.lv.size()) hc::fail(HCURL_EINVAL, "level out of range");
@@ -94,6 +98,11 @@ int hcurl_amg_setup(const hcurl_csr* A, const hcurl_csr* Dh, const double* coord
       hc::fail(HCURL_EINVAL, "unknown aggregation");
     if ((h->H.opts.nodal_prolongator || h->H.opts.pbar_alg1) && h->H.opts.alg1_passes < 1)
       hc::fail(HCURL_EINVAL, "alg1_passes must be >= 1");
+    if (!h->H.opts.dev_alloc != !h->H.opts.dev_free) hc::fail(HCURL_EINVAL, "dev_alloc and dev_free go together");
+    h->alloc.alloc = h->H.opts.dev_alloc;
+    h->alloc.free = h->H.opts.dev_free;
+    h->alloc.ctx = h->H.opts.alloc_ctx;
+    hc::AllocatorScope scope(alloc_of(h));
     h->H.ctx.init((hipStream_t)h->H.opts.stream, h->H.opts.profile != 0);
     auto t0 = std::chrono::steady_clock::now();
     hc::build_hierarchy(h->H, *A, *Dh, coords, aggregates, n_agg_levels);
@@ -114,6 +123,7 @@ int hcurl_amg_setup(const hcurl_csr* A, const hcurl_csr* Dh, const double* coord
 int hcurl_amg_solve(hcurl_amg h, const double* f, double* u, double rtol, int maxit, int* iters, double* relres) {
   if (!h || !f || !u || maxit < 0) return HCURL_EINVAL;
   return guarded([&]() -> int {
+    hc::AllocatorScope scope(alloc_of(h));
     auto& H = h->H;
     auto& c = H.ctx;
     if (!H.valid) hc::fail(HCURL_EINVAL, "the handle is unusable after a failed hcurl_amg_update");
@@ -136,6 +146,7 @@ int hcurl_amg_solve(hcurl_amg h, const double* f, double* u, double rtol, int ma
 int hcurl_amg_vcycle(hcurl_amg h, const double* r, double* z) {
   if (!h || !r || !z) return HCURL_EINVAL;
   return guarded([&]() -> int {
+    hc::AllocatorScope scope(alloc_of(h));
     auto& H = h->H;
     auto& c = H.ctx;
     if (!H.valid) hc::fail(HCURL_EINVAL, "the handle is unusable after a failed hcurl_amg_update");
@@ -190,6 +201,7 @@ int hcurl_amg_level_info(hcurl_amg h, int level, hcurl_level_info* info) {
 int hcurl_amg_commute_residual(hcurl_amg h, int level, double* abs_max, double* ref_max) {
   if (!abs_max || !ref_max) return HCURL_EINVAL;
   return guarded([&]() -> int {
+    hc::AllocatorScope scope(alloc_of(h));
     hc::Level* L = level_of(h, level);
     if (!h->H.valid) hc::fail(HCURL_EINVAL, "the handle is unusable after a failed hcurl_amg_update");
     hc::commute_residual(*L, abs_max, ref_max, h->H.ctx);
@@ -199,6 +211,7 @@ int hcurl_amg_commute_residual(hcurl_amg h, int level, double* abs_max, double* 
 
 int hcurl_amg_export_csr(hcurl_amg h, int level, int which, int64_t* rowptr, int32_t* col, double* val) {
   return guarded([&]() -> int {
+    hc::AllocatorScope scope(alloc_of(h));
     hc::Level* L = level_of(h, level);
     auto& c = h->H.ctx;
     switch (which) {
@@ -247,6 +260,7 @@ int hcurl_amg_export_csr(hcurl_amg h, int level, int which, int64_t* rowptr, int
 
 int hcurl_amg_export_vec(hcurl_amg h, int level, int which, void* out, int64_t capacity) {
   return guarded([&]() -> int {
+    hc::AllocatorScope scope(alloc_of(h));
     hc::Level* L = level_of(h, level);
     auto& c = h->H.ctx;
     auto need = [&](int64_t b) {
@@ -283,6 +297,7 @@ int hcurl_amg_update(hcurl_amg h, const hcurl_csr* A, int mode, int iters) {
   if (!h || !A) return HCURL_EINVAL;
   if (mode != HCURL_REUSE_TRANSFERS && mode != HCURL_REUSE_WARM) return HCURL_EINVAL;
   return guarded([&]() -> int {
+    hc::AllocatorScope scope(alloc_of(h));
     auto& H = h->H;
     if (!H.valid) hc::fail(HCURL_EINVAL, "the handle is unusable after a failed hcurl_amg_update");
     if (H.lv.size() < 2) hc::fail(HCURL_EINVAL, "a single-level hierarchy has no transfers to reuse");

@@ -31,21 +31,42 @@ struct Error {
 
 #define HC_LAUNCH_CHECK() HC_HIP(hipGetLastError())
 
-// Device buffer allocated in stream order on the owning handle's stream.
+// Device memory source of a handle: the caller's allocator, or (no
+// functions) hipMallocAsync / hipFreeAsync on the buffer's stream.
+struct Allocator {
+  void* (*alloc)(size_t, void*, void*) = nullptr;
+  void (*free)(void*, size_t, void*, void*) = nullptr;
+  void* ctx = nullptr;
+};
+
+// The allocator of the handle the calling thread works for (null: the
+// default), set for the duration of each entry point that takes a handle.
+inline thread_local const Allocator* tl_allocator = nullptr;
+struct AllocatorScope {
+  const Allocator* prev;
+  explicit AllocatorScope(const Allocator* a) : prev(tl_allocator) { tl_allocator = a; }
+  ~AllocatorScope() { tl_allocator = prev; }
+  AllocatorScope(const AllocatorScope&) = delete;
+  AllocatorScope& operator=(const AllocatorScope&) = delete;
+};
+
+// Device buffer allocated in stream order on the owning handle's stream,
+// from the allocator current when it was allocated (kept for its release).
 template <class T>
 struct DBuf {
   T* p = nullptr;
   size_t n = 0;
   hipStream_t s = nullptr;
+  const Allocator* a = nullptr;
   DBuf() = default;
   DBuf(size_t count, hipStream_t st) { alloc(count, st); }
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
-  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), s(o.s) { o.p = nullptr; o.n = 0; }
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), s(o.s), a(o.a) { o.p = nullptr; o.n = 0; }
   DBuf& operator=(DBuf&& o) noexcept {
     if (this != &o) {
       release();
-      p = o.p; n = o.n; s = o.s;
+      p = o.p; n = o.n; s = o.s; a = o.a;
       o.p = nullptr; o.n = 0;
     }
     return *this;
@@ -55,10 +76,23 @@ struct DBuf {
     release();
     s = st;
     n = count;
-    if (count) HC_HIP(hipMallocAsync((void**)&p, count * sizeof(T), st));
+    a = tl_allocator;
+    if (!count) return;
+    if (a) {
+      p = (T*)a->alloc(count * sizeof(T), (void*)st, a->ctx);
+      if (!p) {
+        n = 0;
+        fail(HCURL_ENOMEM, "the caller's allocator returned NULL for " + std::to_string(count * sizeof(T)) + " bytes");
+      }
+    } else {
+      HC_HIP(hipMallocAsync((void**)&p, count * sizeof(T), st));
+    }
   }
   void release() noexcept {
-    if (p) (void)hipFreeAsync(p, s);
+    if (p) {
+      if (a) a->free((void*)p, n * sizeof(T), (void*)s, a->ctx);
+      else (void)hipFreeAsync(p, s);
+    }
     p = nullptr;
     n = 0;
   }
