@@ -213,6 +213,48 @@ def vertex_centred_aggregates(n: int):
     return agg, a
 
 
+def random_aggregates(tail: np.ndarray, head: np.ndarray, m: int, size: int, seed: int) -> np.ndarray:
+    """Irregular connected aggregates of the graph with edges (tail, head):
+    seeds are taken in a seeded random node order; each unassigned seed
+    grows breadth-first over unassigned nodes until it holds `size` nodes or
+    cannot grow; a node left in an aggregate smaller than 2 joins the
+    aggregate of its first assigned neighbour.  Ids follow the seeds' order
+    (every id used).  Input data only: no step of the method."""
+    rng = np.random.default_rng(seed)
+    nbr = [[] for _ in range(m)]
+    for a, b in zip(tail.tolist(), head.tolist()):
+        if a >= 0 and b >= 0:
+            nbr[a].append(b)
+            nbr[b].append(a)
+    agg = np.full(m, -1, np.int64)
+    members = []
+    for s in rng.permutation(m).tolist():
+        if agg[s] >= 0:
+            continue
+        k = len(members)
+        agg[s] = k
+        grp, q = [s], [s]
+        while q and len(grp) < size:
+            u = q.pop(0)
+            for v in nbr[u]:
+                if agg[v] < 0 and len(grp) < size:
+                    agg[v] = k
+                    grp.append(v)
+                    q.append(v)
+        members.append(grp)
+    # singletons join a neighbour's aggregate (their ids are then unused)
+    for k, grp in enumerate(members):
+        if len(grp) == 1:
+            u = grp[0]
+            for v in nbr[u]:
+                if agg[v] != k:
+                    agg[u] = agg[v]
+                    break
+    # drop the ids of the absorbed singletons; the rest keep the seed order
+    _, ids = np.unique(agg, return_inverse=True)
+    return ids.astype(np.int32)
+
+
 def rhs(n_edges: int, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).uniform(-1.0, 1.0, size=n_edges)
 

@@ -240,3 +240,22 @@ def test_2d_elements_null_space_and_gradient_mass(kind):
     A = _mat(p["A"])
     assert abs(A - A.T).max() == 0.0
     assert np.linalg.eigvalsh(A.toarray()).min() > 0
+
+
+def test_random_aggregates_are_connected_and_numbered():
+    """synth.random_aggregates: every id used, every aggregate connected in
+    the mesh graph with at least two nodes, and the same map for the same seed."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+    pr = synth.problem(6)
+    m = 343
+    agg = synth.random_aggregates(pr["tail"], pr["head"], m, 9, 4)
+    assert np.array_equal(agg, synth.random_aggregates(pr["tail"], pr["head"], m, 9, 4))
+    K = int(agg.max()) + 1
+    assert np.array_equal(np.unique(agg), np.arange(K))
+    assert np.bincount(agg).min() >= 2
+    G = sp.coo_matrix((np.ones(len(pr["tail"])), (pr["tail"], pr["head"])), shape=(m, m)).tocsr()
+    for k in range(K):
+        idx = np.nonzero(agg == k)[0]
+        ncomp, _ = connected_components(G[idx][:, idx], directed=False)
+        assert ncomp == 1, k
