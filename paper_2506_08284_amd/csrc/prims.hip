@@ -720,18 +720,16 @@ static void spmv_t(const int* rp, const int* col, const V* val, int n, int64_t n
   const double bytes = (double)nnz * (4 + sizeof(V)) + 4.0 * (n + 1) + (double)n * (sizeof(X) + sizeof(Y)) +
                        (mode ? (double)n * sizeof(Y) : 0.0);
   const int64_t nb = n;
-  // lanes per row: about two or more entries per lane, so each lane has
-  // independent gathers in flight
-  if (avg <= 3)
+  // lanes per row: measured at 128^3 (A^(e) ~16, P^(e) ~8, D^T A ~69,
+  // A_1 ~40, P^(e)T ~230 entries per row), wider rows run fastest with
+  // four or more entries per lane, so each lane has independent gathers in
+  // flight; rows of 13-20 entries (A^(e), D^T) keep two per lane
+  if (avg <= 12)
     c.run(tag, bytes, [&] { k_spmv<V, X, Y, 2><<<ceil_div(nb * 2, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
-  else if (avg <= 12)
-    c.run(tag, bytes, [&] { k_spmv<V, X, Y, 4><<<ceil_div(nb * 4, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
-  else if (avg <= 20)
-    c.run(tag, bytes, [&] { k_spmv<V, X, Y, 8><<<ceil_div(nb * 8, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
   else if (avg <= 48)
-    c.run(tag, bytes, [&] { k_spmv<V, X, Y, 16><<<ceil_div(nb * 16, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
+    c.run(tag, bytes, [&] { k_spmv<V, X, Y, 8><<<ceil_div(nb * 8, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
   else if (avg <= 96)
-    c.run(tag, bytes, [&] { k_spmv<V, X, Y, 32><<<ceil_div(nb * 32, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
+    c.run(tag, bytes, [&] { k_spmv<V, X, Y, 16><<<ceil_div(nb * 16, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
   else
     c.run(tag, bytes, [&] { k_spmv<V, X, Y, 64><<<ceil_div(nb * 64, 256), 256, 0, c.s>>>(rp, col, val, x, y, b, n, mode); });
 }
