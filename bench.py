@@ -44,7 +44,7 @@ def run_step(P, A_t, D_t, aggs_t, f_t, u_t, m, stream, maxit=1000, coords=None, 
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     return H, dict(setup_s=t1 - t0, solve_s=t2 - t1, total_s=t2 - t0, iters=it, relres=rel, rc=rc,
-                   vcycle_fp32=bool(H.stats()["vcycle_fp32"]))
+                   ms_per_pcg_iteration=1e3 * (t2 - t1) / max(it, 1), vcycle_fp32=bool(H.stats()["vcycle_fp32"]))
 
 
 # The HBM traffic of the dominant kernel comes from rocprofv3 counter runs
@@ -317,6 +317,9 @@ def main():
         "setup_s": mean("setup_s", results),
         "solve_s": mean("solve_s", results),
         "iters": results[-1]["iters"],
+        # at contrast 1e6 the iteration count moves by several per cent with the
+        # rounding order of any kernel; the time per iteration does not
+        "ms_per_pcg_iteration": mean("ms_per_pcg_iteration", results),
         "relres": results[-1]["relres"],
         "untimed_forms": extra,
         "setup_reuse": sequence,

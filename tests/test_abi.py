@@ -27,3 +27,24 @@ def test_error_strings_without_gpu():
     import paper_2506_08284_amd as P
     assert P.hcurl_error_string(P.HCURL_EREDUCIBLE).startswith("disconnected")
     assert P.hcurl_error_string(0) == "ok"
+
+
+def build_c_demo(out_dir):
+    """Compiles tests/c/abi_demo.c as C99 against include/hcurl_amg.h and
+    links it to the library: the header is plain C and every symbol the
+    program uses resolves."""
+    import shutil
+    import subprocess
+    import paper_2506_08284_amd as P
+    cc = shutil.which("gcc") or shutil.which("cc")
+    exe = os.path.join(out_dir, "abi_demo")
+    libdir = os.path.dirname(P.library_path)
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", os.path.join(ROOT, "include"),
+                        os.path.join(ROOT, "tests", "c", "abi_demo.c"), "-L", libdir, "-l:libhcurl_amg.so",
+                        "-Wl,-rpath," + libdir, "-o", exe], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    return exe
+
+
+def test_c_caller_compiles_and_links(tmp_path):
+    assert os.path.exists(build_c_demo(str(tmp_path)))
