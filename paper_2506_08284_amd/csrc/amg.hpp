@@ -10,6 +10,7 @@ namespace hc {
 // gradient, its nodal operator and (unless it is the coarsest) the transfer to
 // level l+1 with everything the energy minimisation built for it.
 struct Level {
+  bool fine = false;  // level 0: its setup kernels are booked under "_l0" tags
   int n = 0;  // edges (rows of A)
   int m = 0;  // nodes (columns of D)
   Csr A;

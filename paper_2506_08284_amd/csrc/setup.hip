@@ -923,7 +923,7 @@ static int emin_apply(Level& L, const double* dscale, const double* X, double* O
   const double bytes = 12.0 * L.A.nnz + 4.0 * (L.n + 1) * 2 + 12.0 * L.Pe.nnz + 8.0 * L.Pe.nnz;
   const bool proj = flags & EM_PROJECT;
   double* tgt = proj ? Y : Out;
-  c.run("emin_masked_spgemm", bytes, [&] {
+  c.run(L.fine ? "emin_masked_spgemm_l0" : "emin_masked_spgemm", bytes, [&] {
     if (small)
       k_emin_masked<kPatSmall><<<grid, 64, 0, c.s>>>(L.n, R, L.A.rowptr.p, L.A.col.p, L.A.val.p, dscale, L.Pe.rowptr.p,
                                                      L.Pe.col.p, X, tgt, proj ? 0 : flags, part);
@@ -937,7 +937,7 @@ static int emin_apply(Level& L, const double* dscale, const double* X, double* O
     const int RP = std::max(1, std::min(kRowsCap, kProjCap / std::max(1, L.maxNp)));
     const int pgrid = emin_grid(L.n, RP);
     with_maxj(L.maxJ + (L.nsingle_coarse ? 1 : 0), [&](auto mj) {
-      c.run("emin_projection", 26.0 * L.Pe.nnz, [&] {
+      c.run(L.fine ? "emin_projection_l0" : "emin_projection", 26.0 * L.Pe.nnz, [&] {
         k_emin_project<decltype(mj)::value, kProjCap><<<pgrid, 64, 0, c.s>>>(L.n, RP, L.Pe.rowptr.p, Y, L.lpair.p,
                                                                              L.R.rowptr.p, X, Out, flags, part, c.iscal.p);
       });
@@ -949,7 +949,7 @@ static int emin_apply(Level& L, const double* dscale, const double* X, double* O
 
 static void make_feasible(Level& L, double* x, bool ones, Ctx& c) {
   with_maxj(L.maxJ + (L.nsingle_coarse ? 1 : 0), [&](auto mj) {
-    c.run("emin_affine", 26.0 * L.Pe.nnz, [&] {
+    c.run(L.fine ? "emin_affine_l0" : "emin_affine", 26.0 * L.Pe.nnz, [&] {
       k_make_feasible<decltype(mj)::value><<<ceil_div(L.n, 128), 128, 0, c.s>>>(
           L.n, L.Pe.rowptr.p, x, L.lpair.p, L.R.rowptr.p, L.R.val.p, ones ? 1 : 0, c.iscal.p);
     });
@@ -1153,8 +1153,8 @@ static void coarsest_factor(Hierarchy& H, Level& L) {
 static void nodal_operators(Hierarchy& H, Level& L) {
   Ctx& c = H.ctx;
   Csr AD;
-  spgemm(L.A, L.D, AD, true, c, "spgemm_AD");
-  spgemm(L.DT, AD, L.An, true, c, "spgemm_DtAD");
+  spgemm(L.A, L.D, AD, true, c, L.fine ? "spgemm_AD_l0" : "spgemm_AD");
+  spgemm(L.DT, AD, L.An, true, c, L.fine ? "spgemm_DtAD_l0" : "spgemm_DtAD");
   transpose(AD, L.DTA, true, c);
   L.dinvA.alloc(L.n, c.s);
   L.dinvAn.alloc(L.m, c.s);
@@ -1445,7 +1445,7 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
     fail(HCURL_EINVAL, "the aggregates leave no coarse edge (every fine edge inside one aggregate)");
   L.n_coarse = next->n;
   // T and R = D P^(n) on T
-  spgemm(L.D, L.Pn, L.R, true, c, "spgemm_DPn");
+  spgemm(L.D, L.Pn, L.R, true, c, L.fine ? "spgemm_DPn_l0" : "spgemm_DPn");
   // pattern N, with make_irreducible while a local graph is disconnected
   {
     DBuf<int> cnt(L.n + 1, c.s);
@@ -1542,8 +1542,8 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
   // Galerkin A_H = P^T A P
   {
     Csr AP;
-    spgemm(L.A, L.Pe, AP, true, c, "spgemm_AP");
-    spgemm(L.PeT, AP, next->A, true, c, "spgemm_PtAP");
+    spgemm(L.A, L.Pe, AP, true, c, L.fine ? "spgemm_AP_l0" : "spgemm_AP");
+    spgemm(L.PeT, AP, next->A, true, c, L.fine ? "spgemm_PtAP_l0" : "spgemm_PtAP");
   }
   L.has_transfer = true;
   return next;
@@ -1558,6 +1558,7 @@ void build_hierarchy(Hierarchy& H, const hcurl_csr& A, const hcurl_csr& Dh, cons
   if (Dh.nrows != A.nrows) fail(HCURL_EINVAL, "D_h must have one row per edge");
   if (nagg < 0 || (nagg > 0 && !aggs)) fail(HCURL_EINVAL, "aggregates missing");
   auto L0 = std::make_unique<Level>();
+  L0->fine = true;
   L0->n = (int)A.nrows;
   L0->m = (int)Dh.ncols;
   upload_csr(A, dev, L0->A, true, c);
@@ -1650,15 +1651,15 @@ void update_hierarchy(Hierarchy& H, const hcurl_csr& A, int mode, int iters) {
     nodal_operators(H, L);
     if (mode == HCURL_REUSE_WARM) {
       if (!(l == 0 && H.pn_given)) smoothed_aggregation(H, L, L.agg.p, L.Pn.ncols);
-      spgemm(L.D, L.Pn, L.R, true, c, "spgemm_DPn");
+      spgemm(L.D, L.Pn, L.R, true, c, L.fine ? "spgemm_DPn_l0" : "spgemm_DPn");
       energy_minimisation(H, L, &N, K, true, L.Pe.val.p, true, false);
       transpose(L.Pe, L.PeT, true, c);
     } else {
       L.energy.clear();
     }
     Csr AP;
-    spgemm(L.A, L.Pe, AP, true, c, "spgemm_AP");
-    spgemm(L.PeT, AP, N.A, true, c, "spgemm_PtAP");
+    spgemm(L.A, L.Pe, AP, true, c, L.fine ? "spgemm_AP_l0" : "spgemm_AP");
+    spgemm(L.PeT, AP, N.A, true, c, L.fine ? "spgemm_PtAP_l0" : "spgemm_PtAP");
   }
   coarsest_factor(H, *H.lv.back());
   prepare_solve(H);
