@@ -281,9 +281,10 @@ def main():
         log("untimed plain_fp64 with MIS-2 aggregates: %s" % json.dumps(r))
 
     top = sorted(kstats.items(), key=lambda kv: -kv[1]["ms"])
-    for name, d in top[:14]:
+    for name, d in top[:30]:
         gbs = d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0
-        log("kernel %-22s launches %7d  %9.2f ms/step  %8.1f GB/s" % (name, d["launches"], d["ms"] / args.steps, gbs))
+        log("kernel %-24s launches %7d  %9.2f ms/step  %8.1f us/launch  %8.1f GB/s" % (
+            name, d["launches"], d["ms"] / args.steps, 1e3 * d["ms"] / max(d["launches"], 1), gbs))
     # the dominant kernel of the step (rocprofv3 kernel statistics of this
     # command: 47 % of GPU time) is the level-0 edge Gauss-Seidel; its events
     # are sampled, so ranking by booked time would favour setup kernels
