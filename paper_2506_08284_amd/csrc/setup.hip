@@ -1449,7 +1449,7 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
   // pattern N, with make_irreducible while a local graph is disconnected
   {
     DBuf<int> cnt(L.n + 1, c.s);
-    long long fl[6];
+    long long fl[F_NOTSPD + 1];
     Csr Zw;  // P^(n)T D^T D P^(n) = R^T R, formed on the first repair
     L.irreducible_added = 0;
     for (int round = 0;; ++round) {
@@ -1463,7 +1463,7 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
                                                               nsingle ? sne.p : nullptr, cnt.p, nullptr, nullptr,
                                                               nullptr, c.iscal.p);
       });
-      d2h(fl, c.iscal.p, 6, c);
+      d2h(fl, c.iscal.p, F_NOTSPD + 1, c);
       if (fl[F_TOOBIG]) fail(HCURL_EUNSUPPORTED, "a fine edge touches more than 32 coarse nodes");
       if (!fl[F_DISCONNECTED]) break;
       if (round == 64)

@@ -429,7 +429,6 @@ static void vcycle32(Hierarchy& H, int l, const T* b, T* x) {
 }
 
 static void vcycle_direct(Hierarchy& H, const double* r, double* z) {
-  Ctx& c = H.ctx;
   if (H.fp32 && H.lv.size() > 1) {
     vcycle32<double>(H, 0, r, z);
   } else {

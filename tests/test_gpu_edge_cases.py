@@ -104,3 +104,26 @@ def test_slab_aggregates_long_transposed_rows():
     assert rc == 0 and rel <= 1e-8 and abs(it - ito) <= 1
     assert np.linalg.norm(u - uo) <= 1e-6 * np.linalg.norm(uo)
     H.close()
+
+
+def test_fine_edge_touching_too_many_coarse_nodes_is_refused():
+    """A caller P^(n) whose row reaches 40 coarse nodes gives fine edges with
+    |T_i| > 32, beyond the library's local-system layouts: HCURL_EUNSUPPORTED,
+    not a wrong answer."""
+    P = _lib()
+    pr = synth.problem(6)
+    m = 343
+    maps, _ = synth.box_aggregates(7, width=2)
+    agg = maps[0]
+    mH = int(agg.max()) + 1
+    assert mH == 64
+    Pn = O.tentative_prolongator(agg, mH).tolil()
+    Pn[0, :] = 0.0
+    for j in range(40):
+        Pn[0, j] = 1.0 / 40
+    Pn = O.csr(Pn.tocsr())
+    given = (Pn.indptr.astype(np.int64), Pn.indices.astype(np.int32), Pn.data.copy(), mH)
+    with pytest.raises(P.HcurlError) as e:
+        P.Hierarchy(pr["A"], synth.gradient_csr(pr["tail"], pr["head"]), [agg], n_nodes=m, nodal_prolongator=given)
+    assert e.value.code == P.HCURL_EUNSUPPORTED
+    assert "32 coarse nodes" in str(e.value)
