@@ -54,7 +54,8 @@ def run_step(P, A_t, D_t, aggs_t, f_t, u_t, m, stream, maxit=1000, coords=None, 
 # that code is unchanged.
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "sgs_edge_l0_cube128_contrast_pmc.txt")
 DOMINANT = "sgs_edge_l0"
-TRAFFIC_CODE = [("paper_2506_08284_amd/csrc/solve.hip", "__global__ void __launch_bounds__(256) k_gs_color("),
+TRAFFIC_CODE = [("paper_2506_08284_amd/csrc/solve.hip", "__device__ __forceinline__ void gs_row("),
+                ("paper_2506_08284_amd/csrc/solve.hip", "__global__ void __launch_bounds__(256) k_gs_color("),
                 ("paper_2506_08284_amd/csrc/solve.hip", "static void sgs_t("),
                 ("paper_2506_08284_amd/csrc/solve.hip", "void color_rows(")]
 

@@ -178,15 +178,12 @@ void gather_vec(const double* x, const int* rows, double* y, int n, Ctx& c) {
 // matrix is the colour-major copy: the colour's rows are contiguous (g) and
 // rows[g] is the original row index, used for b and x.
 // ---------------------------------------------------------------------------
-template <class V, class T, int LPR, int TAG>
-__global__ void __launch_bounds__(256) k_gs_color(int g0, int nr, const int* __restrict__ rows, const int* __restrict__ rp,
-                                                  const int* __restrict__ col, const V* __restrict__ val,
-                                                  const T* __restrict__ dinv, const T* __restrict__ b, T* __restrict__ x) {
-  // neighbouring row blocks share gathered x entries: give every XCD a
-  // contiguous range of blocks so they meet in the same L2
-  const int g = g0 + (xcd_block(gridDim.x) * blockDim.x + threadIdx.x) / LPR;
-  const int l = threadIdx.x & (LPR - 1);
-  if (g >= g0 + nr) return;
+// One row by a group of LPR lanes; every kernel below sums a row this way, so
+// a row gives the same bits whichever kernel updates it.
+template <class V, class T, int LPR>
+__device__ __forceinline__ void gs_row(int g, int l, const int* __restrict__ rows, const int* __restrict__ rp,
+                                       const int* __restrict__ col, const V* __restrict__ val,
+                                       const T* __restrict__ dinv, const T* __restrict__ b, T* __restrict__ x) {
   T s = 0;
   const int a = rp[g], e = rp[g + 1];
   const int i = rows[g];
@@ -215,6 +212,39 @@ __global__ void __launch_bounds__(256) k_gs_color(int g0, int nr, const int* __r
   if (l == 0) x[i] += (bi - s) * di;
 }
 
+template <class V, class T, int LPR, int TAG>
+__global__ void __launch_bounds__(256) k_gs_color(int g0, int nr, const int* __restrict__ rows, const int* __restrict__ rp,
+                                                  const int* __restrict__ col, const V* __restrict__ val,
+                                                  const T* __restrict__ dinv, const T* __restrict__ b, T* __restrict__ x) {
+  // neighbouring row blocks share gathered x entries: give every XCD a
+  // contiguous range of blocks so they meet in the same L2
+  const int g = g0 + (xcd_block(gridDim.x) * blockDim.x + threadIdx.x) / LPR;
+  const int l = threadIdx.x & (LPR - 1);
+  if (g >= g0 + nr) return;
+  gs_row<V, T, LPR>(g, l, rows, rp, col, val, dinv, b, x);
+}
+
+// Colours k0, k0 + dir, ..., nk of them, in one workgroup with a barrier
+// between colours: for runs of small colour classes, whose launches would
+// cost more than their rows.  The coarse levels' colour classes have a long
+// tail: the densest rows of a Galerkin operator can form a clique, which takes
+// one colour per row.
+template <class V, class T, int LPR>
+__global__ void __launch_bounds__(1024) k_gs_chain(int k0, int nk, int dir, const int* __restrict__ cptr,
+                                                   const int* __restrict__ rows, const int* __restrict__ rp,
+                                                   const int* __restrict__ col, const V* __restrict__ val,
+                                                   const T* __restrict__ dinv, const T* __restrict__ b,
+                                                   T* __restrict__ x) {
+  const int l = threadIdx.x & (LPR - 1);
+  const int grp = threadIdx.x / LPR;
+  constexpr int NG = 1024 / LPR;
+  for (int t = 0; t < nk; ++t) {
+    const int k = k0 + dir * t;
+    for (int g = cptr[k] + grp; g < cptr[k + 1]; g += NG) gs_row<V, T, LPR>(g, l, rows, rp, col, val, dinv, b, x);
+    __syncthreads();
+  }
+}
+
 // The whole symmetric sweep (all colours forward, then backward) in one
 // workgroup, for levels small enough that launches would dominate.
 template <class V, class T, int LPR>
@@ -231,31 +261,7 @@ __global__ void __launch_bounds__(1024) k_gs_sweep_small(int ncol, const int* __
   // (rows of one colour do not couple), so repeating it changes nothing
   for (int step = 0; step < 2 * ncol - 1; ++step) {
     const int k = step < ncol ? step : 2 * ncol - 2 - step;
-    for (int g = cptr[k] + grp; g < cptr[k + 1]; g += NG) {
-      T s = 0;
-      const int e = rp[g + 1];
-      const int i = rows[g];
-      // up to four entries per lane loaded before they are summed
-      int q = rp[g] + l;
-      for (; q + 3 * LPR < e; q += 4 * LPR) {
-        const int c0 = col[q], c1 = col[q + LPR], c2 = col[q + 2 * LPR], c3 = col[q + 3 * LPR];
-        const V v0 = val[q], v1 = val[q + LPR], v2 = val[q + 2 * LPR], v3 = val[q + 3 * LPR];
-        s += (T)v0 * x[c0] + (T)v1 * x[c1] + (T)v2 * x[c2] + (T)v3 * x[c3];
-      }
-      int cc[3];
-      V vv[3];
-#pragma unroll
-      for (int u = 0; u < 3; ++u) {
-        const int qq = q + u * LPR;
-        cc[u] = qq < e ? col[qq] : i;
-        vv[u] = qq < e ? val[qq] : V(0);
-      }
-#pragma unroll
-      for (int u = 0; u < 3; ++u) s += (T)vv[u] * x[cc[u]];
-#pragma unroll
-      for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LPR);
-      if (l == 0) x[i] += (b[i] - s) * dinv[g];
-    }
+    for (int g = cptr[k] + grp; g < cptr[k + 1]; g += NG) gs_row<V, T, LPR>(g, l, rows, rp, col, val, dinv, b, x);
     __syncthreads();
   }
 }
@@ -275,21 +281,51 @@ static void sgs_t(const Csr& A, const V* val, const T* dinv, const DBuf<int>& ro
     c.run("sgs_small", bytes, [&] { k_gs_sweep_small<V, T, 8><<<1, 1024, 0, c.s>>>(ncol, cptr_d.p, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
     return;
   }
+  const int lpr = avg <= 20 ? 8 : avg <= 48 ? 16 : 32;
   auto launch = [&](int k) {
     const int g0 = cptr[k], nr = cptr[k + 1] - cptr[k];
     if (!nr) return;
     const double bytes = (double)nr * avg * (4 + sizeof(V)) + (double)nr * (8 + 4 * sizeof(T));
-    if (avg <= 20)
+    if (lpr == 8)
       c.run(tag, bytes, [&] { k_gs_color<V, T, 8, TAG><<<ceil_div((int64_t)nr * 8, 256), 256, 0, c.s>>>(g0, nr, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
-    else if (avg <= 48)
+    else if (lpr == 16)
       c.run(tag, bytes, [&] { k_gs_color<V, T, 16, TAG><<<ceil_div((int64_t)nr * 16, 256), 256, 0, c.s>>>(g0, nr, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
     else
       c.run(tag, bytes, [&] { k_gs_color<V, T, 32, TAG><<<ceil_div((int64_t)nr * 32, 256), 256, 0, c.s>>>(g0, nr, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
   };
-  for (int k = 0; k < ncol; ++k) launch(k);
-  // backward from the second-to-last colour: the last colour's rows already
-  // solve their equations after the forward pass, so repeating it is a no-op
-  for (int k = ncol - 2; k >= 0; --k) launch(k);
+  // a run of colours k0, k0 + dir, ... that one 1024-thread workgroup covers
+  // in one pass each
+  const int tiny = 1024 / lpr;
+  auto chain = [&](int k0, int nk, int dir) {
+    double nr = 0.0;
+    for (int t = 0; t < nk; ++t) nr += cptr[k0 + dir * t + 1] - cptr[k0 + dir * t];
+    const double bytes = nr * avg * (4 + sizeof(V)) + nr * (8 + 4 * sizeof(T));
+    if (lpr == 8)
+      c.run(tag, bytes, [&] { k_gs_chain<V, T, 8><<<1, 1024, 0, c.s>>>(k0, nk, dir, cptr_d.p, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
+    else if (lpr == 16)
+      c.run(tag, bytes, [&] { k_gs_chain<V, T, 16><<<1, 1024, 0, c.s>>>(k0, nk, dir, cptr_d.p, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
+    else
+      c.run(tag, bytes, [&] { k_gs_chain<V, T, 32><<<1, 1024, 0, c.s>>>(k0, nk, dir, cptr_d.p, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
+  };
+  // colours in sweep order, forward then backward from the second-to-last
+  // (the last colour's rows already solve their equations after the forward
+  // pass, so repeating it is a no-op); runs of two or more small colours in
+  // one direction go to one chain launch
+  auto pass = [&](int first, int last, int dir) {
+    for (int k = first; k != last + dir;) {
+      int n = 0;
+      while (k + dir * n != last + dir && cptr[k + dir * n + 1] - cptr[k + dir * n] <= tiny) ++n;
+      if (n >= 2) {
+        chain(k, n, dir);
+        k += dir * n;
+      } else {
+        launch(k);
+        k += dir;
+      }
+    }
+  };
+  pass(0, ncol - 1, 1);
+  if (ncol >= 2) pass(ncol - 2, 0, -1);
 }
 
 // x += D c  with D given by its endpoints: x_e += c[head] - c[tail]
