@@ -103,3 +103,39 @@ def test_dirichlet_learned_guess_is_refused():
                     p["aggregates"], n_nodes=p["m"], coords=p["coords"], init_guess=2, mpnn=net,
                     aggregation="mis2", coarse_max_rows=100)
     assert e.value.code == P.HCURL_EUNSUPPORTED
+
+
+def test_dirichlet_update_warm_matches_oracle():
+    """Setup reuse on a boundary-eliminated problem: a second sigma field on
+    the same mesh (same pattern), warm mode with MIS-2 levels below a box
+    map; the rebuilt P^(n), the re-minimised P^(e) with its single-node
+    coarse edges, the Galerkin operators and the solve against the oracle."""
+    import paper_2506_08284_amd as P
+    p1 = synth.dirichlet_problem(10, sigma=("lognormal", 6, 1.5), f_seed=3)
+    p2 = synth.dirichlet_problem(10, sigma=("lognormal", 12, 1.5), f_seed=3)
+    assert np.array_equal(p1["A"][0], p2["A"][0]) and np.array_equal(p1["A"][1], p2["A"][1])
+    m = p1["m"]
+    opts = dict(aggregation="mis2", coarse_max_rows=150)
+    lv = O.setup(p1["A"], p1["tail"], p1["head"], m, p1["aggregates"], dict(opts, record_energy=True))
+    ref = O.update(lv, p2["A"], "warm", iters=4)
+    Dh = O.gradient_matrix(p1["tail"], p1["head"], m)
+    H = P.Hierarchy(p1["A"], (Dh.indptr.astype(np.int64), Dh.indices.astype(np.int32), Dh.data.copy()),
+                    p1["aggregates"], n_nodes=m, record_energy=1, **opts)
+    H.update(p2["A"], "warm", 4)
+    assert H.num_levels() == len(ref) >= 3
+    for l, r in enumerate(ref[:-1]):
+        kappa = H.level_info(l)["cancellation_ratio"]
+        t_n, t_e = max(1e-11, 100 * EPS * kappa), max(1e-10, 1000 * EPS * kappa)
+        _close(_export(H, l, "Pn"), r["Pn"], t_n)
+        _close(_export(H, l, "R"), r["R"], t_n)
+        _close(_export(H, l, "Pe"), r["Pe"], t_e)
+        _close(_export(H, l + 1, "A"), ref[l + 1]["A"], t_e)
+        a, rr = H.commute_residual(l)
+        assert a <= 1e-12 * rr
+    n = p2["A"][0].shape[0] - 1
+    u = np.empty(n)
+    it, rel, rc = H.solve(p2["f"], u, 1e-8, 500)
+    uo, ito, _, _ = O.pcg(ref, p2["f"])
+    assert rc == 0 and rel <= 1e-8 and abs(it - ito) <= 1
+    assert np.linalg.norm(u - uo) <= 1e-6 * np.linalg.norm(uo)
+    H.close()
