@@ -140,7 +140,7 @@ def main():
                     help="first copy a 1 GiB buffer three times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md on sharding)",
+        print("bench.py runs on one GPU only: the library has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
 

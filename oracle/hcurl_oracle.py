@@ -10,7 +10,7 @@ method for the eddy current equations").
 
 Paper references in docstrings name the section, equation, algorithm or table.
 
-Readings where the paper is silent or garbled (each is listed in the design doc):
+Readings where the paper is silent or garbled (the library follows the same ones):
   R1  coarse edges of D_H are ordered lexicographically by (I, K), I < K, with
       -1 at I and +1 at K (Sec. 2, eq. "RS coarse gradient" only says "strictly
       upper triangular").
