@@ -246,27 +246,34 @@ __global__ void __launch_bounds__(1024) k_gs_chain(int k0, int nk, int dir, cons
 }
 
 // The whole symmetric sweep (all colours forward, then backward) in one
-// workgroup, for levels small enough that launches would dominate.
+// workgroup, for levels small enough that launches would dominate.  The
+// level's x (at most kSmallRows entries) lives in LDS for the sweep: one CU
+// would otherwise fetch a cache line per gathered entry.
+static constexpr int kSmallRows = 8192;
 template <class V, class T, int LPR>
-__global__ void __launch_bounds__(1024) k_gs_sweep_small(int ncol, const int* __restrict__ cptr,
+__global__ void __launch_bounds__(1024) k_gs_sweep_small(int n, int ncol, const int* __restrict__ cptr,
                                                          const int* __restrict__ rows, const int* __restrict__ rp,
                                                          const int* __restrict__ col, const V* __restrict__ val,
                                                          const T* __restrict__ dinv, const T* __restrict__ b,
                                                          T* __restrict__ x) {
+  __shared__ T xs[kSmallRows];
   const int l = threadIdx.x & (LPR - 1);
   const int grp = threadIdx.x / LPR;
   constexpr int NG = 1024 / LPR;
+  for (int i = threadIdx.x; i < n; i += 1024) xs[i] = x[i];
+  __syncthreads();
   // forward over the colours, then backward from the second-to-last: the
   // last colour's rows already solve their equations after the forward pass
   // (rows of one colour do not couple), so repeating it changes nothing
   for (int step = 0; step < 2 * ncol - 1; ++step) {
     const int k = step < ncol ? step : 2 * ncol - 2 - step;
-    for (int g = cptr[k] + grp; g < cptr[k + 1]; g += NG) gs_row<V, T, LPR>(g, l, rows, rp, col, val, dinv, b, x);
+    for (int g = cptr[k] + grp; g < cptr[k + 1]; g += NG) gs_row<V, T, LPR>(g, l, rows, rp, col, val, dinv, b, xs);
     __syncthreads();
   }
+  for (int i = threadIdx.x; i < n; i += 1024) x[i] = xs[i];
 }
 
-static constexpr int kSmallLevel = 8192;
+static constexpr int kSmallLevel = kSmallRows;
 
 // Algorithmic bytes of one colour launch: the rows' CSR data (column and
 // value per entry, row pointer and original row index per row), their b,
@@ -278,7 +285,7 @@ static void sgs_t(const Csr& A, const V* val, const T* dinv, const DBuf<int>& ro
   const double avg = A.nrows ? (double)A.nnz / A.nrows : 0.0;
   if (A.nrows <= kSmallLevel) {
     const double bytes = 2.0 * ((double)A.nnz * (4 + sizeof(V)) + (double)A.nrows * (8 + 4 * sizeof(T)));
-    c.run("sgs_small", bytes, [&] { k_gs_sweep_small<V, T, 8><<<1, 1024, 0, c.s>>>(ncol, cptr_d.p, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
+    c.run("sgs_small", bytes, [&] { k_gs_sweep_small<V, T, 8><<<1, 1024, 0, c.s>>>(A.nrows, ncol, cptr_d.p, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
     return;
   }
   const int lpr = avg <= 20 ? 8 : avg <= 48 ? 16 : 32;
