@@ -127,3 +127,47 @@ def test_fine_edge_touching_too_many_coarse_nodes_is_refused():
         P.Hierarchy(pr["A"], synth.gradient_csr(pr["tail"], pr["head"]), [agg], n_nodes=m, nodal_prolongator=given)
     assert e.value.code == P.HCURL_EUNSUPPORTED
     assert "32 coarse nodes" in str(e.value)
+
+
+def test_largest_local_systems_against_oracle():
+    """A caller P^(n) whose row 0 spreads over 30 coarse nodes (a 3 x 3 x 3 +
+    3 block of aggregates) gives fine edges with |T_i| = 30: the widest
+    local-system layout the library has (32).  Pattern, local pairs and D_H
+    bit for bit, P^(e) within the usual tolerance, the solve."""
+    import scipy.sparse as sp
+    P = _lib()
+    pr = synth.problem(6, sigma=("const", 1.0), f_seed=2)
+    m = 343
+    maps, _ = synth.box_aggregates(7, width=2)
+    agg = maps[0]
+    mH = int(agg.max()) + 1
+    Pn = O.tentative_prolongator(agg, mH).tolil()
+    cols = [0, 1, 2, 4, 5, 6, 8, 9, 10, 16, 17, 18, 20, 21, 22, 24, 25, 26, 32, 33, 34, 36, 37, 38, 40, 41, 42,
+            48, 49, 50]
+    Pn[0, :] = 0.0
+    for j in cols:
+        Pn[0, j] = 1.0 / len(cols)
+    Pn = O.csr(Pn.tocsr())
+    levels = O.setup(pr["A"], pr["tail"], pr["head"], m, [agg], dict(Pn=Pn))
+    lv = levels[0]
+    assert np.diff(O.csr(lv["R"]).indptr).max() == 30
+    given = (Pn.indptr.astype(np.int64), Pn.indices.astype(np.int32), Pn.data.copy(), mH)
+    H = P.Hierarchy(pr["A"], synth.gradient_csr(pr["tail"], pr["head"]), [agg], n_nodes=m, nodal_prolongator=given)
+    ex = lambda w: (lambda a: sp.csr_matrix((a[0][2], a[0][1], a[0][0]), shape=a[1]))(H.export_csr(0, w))
+    DH = O.csr(ex("DH"))
+    ref = O.gradient_matrix(lv["DH_tail"], lv["DH_head"], mH)
+    assert np.array_equal(DH.indptr, ref.indptr) and np.array_equal(DH.indices, ref.indices)
+    Pe = O.csr(ex("Pe"))
+    N = O.csr(lv["N"])
+    assert np.array_equal(Pe.indptr, N.indptr) and np.array_equal(Pe.indices, N.indices)
+    lp = H.export_vec(0, "local_pairs")
+    assert np.array_equal(lp & 255, lv["lt"]) and np.array_equal(lp >> 8, lv["lh"])
+    assert np.max(abs(Pe.data - O.csr(lv["Pe"]).data)) <= 1e-10 * abs(lv["Pe"].data).max()
+    a, r = H.commute_residual(0)
+    assert a <= 1e-12 * r
+    n = pr["A"][0].shape[0] - 1
+    u = np.empty(n)
+    it, rel, rc = H.solve(pr["f"], u)
+    uo, ito, _, _ = O.pcg(levels, pr["f"])
+    assert rc == 0 and rel <= 1e-8 and abs(it - ito) <= 1
+    H.close()
