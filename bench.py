@@ -137,7 +137,8 @@ def main():
     ap.add_argument("--no-sequence", action="store_true",
                     help="skip the untimed setup-reuse runs on a second system of the same mesh")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="first copy a 1 GiB buffer three times (reference for HBM byte counters)")
+                    help="accepted for the counter commands; every run makes the 1 GiB device copies that "
+                         "calibrate FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path",
@@ -153,14 +154,22 @@ def main():
     torch.cuda.set_device(0)
     side = torch.cuda.Stream()  # default priority; a non-null stream lets the V-cycle run as a HIP graph
     torch.cuda.set_stream(side)
-    if args.calibrate_copy:
-        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log("copy calibration: 3 copies of %d bytes" % (src.numel() * 4))
-        del src, dst
+    # a plain 1 GiB device copy: the bandwidth this machine reaches with a copy
+    # (read + write), quoted beside the nominal peak; with --calibrate-copy
+    # these copies also calibrate the HBM counters
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(3):
+        dst.copy_(src)
+    ev1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 3 * 2 * src.numel() * 4 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    log("device copy: 3 copies of %d bytes, %.0f GB/s (read + write)" % (src.numel() * 4, copy_gbs))
+    del src, dst
     t0 = time.perf_counter()
     pr = synth.workload(args.workload)
     N = synth.WORKLOADS[args.workload]["N"]
@@ -333,7 +342,8 @@ def main():
                      "sampled_launches_per_step": dom["launches"] / args.steps,
                      "sampling": "HIP events on every launch of PCG iterations 0, 16, 32, ...",
                      "bytes_per_launch": dom["bytes"] / dom["launches"],
-                     "avg_launch_us": dom["ms"] * 1e3 / dom["launches"]},
+                     "avg_launch_us": dom["ms"] * 1e3 / dom["launches"],
+                     "device_copy_GBs": copy_gbs},
     }
     if args.cpu_sample > 0:
         log("timing the oracle on the %d^3 sample ..." % args.cpu_sample)
