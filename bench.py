@@ -298,7 +298,9 @@ def main():
     # the dominant kernel of the step (rocprofv3 kernel statistics of this
     # command: 47 % of GPU time) is the level-0 edge Gauss-Seidel; its events
     # are sampled, so ranking by booked time would favour setup kernels
-    dom_name = DOMINANT
+    # (in the FP32 form of the V-cycle the same sweep reads FP32 values and is
+    # booked as sgs_edge32_l0)
+    dom_name = DOMINANT if DOMINANT in kstats else "sgs_edge32_l0"
     dom = kstats[dom_name]
     achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
     mean = lambda key, rs: float(np.mean([x[key] for x in rs])) if rs else None
