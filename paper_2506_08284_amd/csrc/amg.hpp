@@ -9,6 +9,15 @@ namespace hc {
 // One level of the hierarchy.  Level l owns its edge operator, its discrete
 // gradient, its nodal operator and (unless it is the coarsest) the transfer to
 // level l+1 with everything the energy minimisation built for it.
+// A run of consecutive small colour classes that one workgroup sweeps with
+// the x entries it touches held in LDS: U lists those entries (sorted), lcol
+// gives each matrix entry of the run its slot in U, lrow each row's own slot.
+struct ChainRun {
+  int k0 = 0, nk = 0, dir = 1;
+  int g_lo = 0, g_hi = 0, e_lo = 0, nU = 0;
+  DBuf<int> U, lcol, lrow;
+};
+
 struct Level {
   bool fine = false;  // level 0: its setup kernels are booked under "_l0" tags
   int n = 0;  // edges (rows of A)
@@ -31,6 +40,7 @@ struct Level {
   // colour-major copies: row g is original row rows[g], columns unchanged,
   // so every colour is one contiguous block of rows
   Csr Acm, Ancm;
+  std::vector<ChainRun> chainsA, chainsAn;  // LDS plans of the sweeps' small-colour runs
   DBuf<double> dinvAcm, dinvAncm;
   DBuf<float> dinvAcm32, dinvAncm32;
 

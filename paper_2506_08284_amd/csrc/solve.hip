@@ -2,6 +2,7 @@
 // smoothing, V-cycle with a direct coarsest solve, preconditioned CG.
 #include <chrono>
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 
 #include "amg.hpp"
@@ -245,6 +246,68 @@ __global__ void __launch_bounds__(1024) k_gs_chain(int k0, int nk, int dir, cons
   }
 }
 
+// gs_row on a run's LDS copy of x: lcol[q - e_lo] is the slot of entry q's
+// column, lrow[g - g_lo] the slot of row g's own entry; b and 1/a_ii are read
+// as in gs_row.  Same arithmetic in the same order as gs_row.
+template <class V, class T, int LPR>
+__device__ __forceinline__ void gs_row_lds(int g, int l, int g_lo, int e_lo, const int* __restrict__ lcol,
+                                           const int* __restrict__ lrow, const int* __restrict__ rows,
+                                           const int* __restrict__ rp, const V* __restrict__ val,
+                                           const T* __restrict__ dinv, const T* __restrict__ b, T* xs) {
+  T s = 0;
+  const int a = rp[g], e = rp[g + 1];
+  const int i = rows[g];
+  const int il = lrow[g - g_lo];
+  const T bi = b[i], di = dinv[g];
+  int q = a + l;
+  for (; q + 3 * LPR < e; q += 4 * LPR) {
+    const int c0 = lcol[q - e_lo], c1 = lcol[q + LPR - e_lo], c2 = lcol[q + 2 * LPR - e_lo],
+              c3 = lcol[q + 3 * LPR - e_lo];
+    const V v0 = val[q], v1 = val[q + LPR], v2 = val[q + 2 * LPR], v3 = val[q + 3 * LPR];
+    s += (T)v0 * xs[c0] + (T)v1 * xs[c1] + (T)v2 * xs[c2] + (T)v3 * xs[c3];
+  }
+  int cc[3];
+  V vv[3];
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    const int qq = q + u * LPR;
+    cc[u] = qq < e ? lcol[qq - e_lo] : il;
+    vv[u] = qq < e ? val[qq] : V(0);
+  }
+#pragma unroll
+  for (int u = 0; u < 3; ++u) s += (T)vv[u] * xs[cc[u]];
+#pragma unroll
+  for (int o = LPR / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, LPR);
+  if (l == 0) xs[il] += (bi - s) * di;
+}
+
+// k_gs_chain with the x entries the run touches (nU <= kChainSlots of them,
+// listed in U) copied to LDS first: each chained colour then gathers from LDS
+// instead of L2.  The run's own rows are written back at the end; the other
+// entries of U do not change during the run.
+static constexpr int kChainSlots = 16384;
+template <class V, class T, int LPR>
+__global__ void __launch_bounds__(1024) k_gs_chain_lds(int k0, int nk, int dir, const int* __restrict__ cptr, int g_lo,
+                                                       int g_hi, int e_lo, int nU, const int* __restrict__ U,
+                                                       const int* __restrict__ lcol, const int* __restrict__ lrow,
+                                                       const int* __restrict__ rows, const int* __restrict__ rp,
+                                                       const V* __restrict__ val, const T* __restrict__ dinv,
+                                                       const T* __restrict__ b, T* __restrict__ x) {
+  __shared__ T xs[kChainSlots];
+  const int l = threadIdx.x & (LPR - 1);
+  const int grp = threadIdx.x / LPR;
+  constexpr int NG = 1024 / LPR;
+  for (int j = threadIdx.x; j < nU; j += 1024) xs[j] = x[U[j]];
+  __syncthreads();
+  for (int t = 0; t < nk; ++t) {
+    const int k = k0 + dir * t;
+    for (int g = cptr[k] + grp; g < cptr[k + 1]; g += NG)
+      gs_row_lds<V, T, LPR>(g, l, g_lo, e_lo, lcol, lrow, rows, rp, val, dinv, b, xs);
+    __syncthreads();
+  }
+  for (int g = g_lo + (int)threadIdx.x; g < g_hi; g += 1024) x[rows[g]] = xs[lrow[g - g_lo]];
+}
+
 // The whole symmetric sweep (all colours forward, then backward) in one
 // workgroup, for levels small enough that launches would dominate.  The
 // level's x (at most kSmallRows entries) lives in LDS for the sweep: one CU
@@ -279,16 +342,92 @@ static constexpr int kSmallLevel = kSmallRows;
 // value per entry, row pointer and original row index per row), their b,
 // 1/a_ii and x written, and every x entry gathered once per sweep (ideal reuse
 // of the gathered neighbours): nnz_c (4 + sizeof V) + rows_c (8 + 4 sizeof T).
+static int gs_lpr(double avg) { return avg <= 20 ? 8 : avg <= 48 ? 16 : 32; }
+
+// Launch plan of one symmetric sweep: colours in sweep order, forward, then
+// backward from the second-to-last (the last colour's rows already solve
+// their equations after the forward pass, so repeating it is a no-op); a run
+// of two or more consecutive colours in one direction whose classes have at
+// most `tiny` rows goes to one chain launch.
+template <class F, class G>
+static void sweep_plan(const std::vector<int>& cptr, int ncol, int tiny, F&& single, G&& chain) {
+  auto pass = [&](int first, int last, int dir) {
+    for (int k = first; k != last + dir;) {
+      int n = 0;
+      while (k + dir * n != last + dir && cptr[k + dir * n + 1] - cptr[k + dir * n] <= tiny) ++n;
+      if (n >= 2) {
+        chain(k, n, dir);
+        k += dir * n;
+      } else {
+        single(k);
+        k += dir;
+      }
+    }
+  };
+  pass(0, ncol - 1, 1);
+  if (ncol >= 2) pass(ncol - 2, 0, -1);
+}
+
+// LDS plans of the chain runs of a colour-major matrix (levels swept by
+// launches only): the x entries each run touches, and every entry's and row's
+// slot among them.
+void plan_chains(const Csr& Acm, const DBuf<int>& rows, const std::vector<int>& cptr, int ncol,
+                 std::vector<ChainRun>& out, Ctx& c) {
+  out.clear();
+  if (Acm.nrows <= kSmallRows || Acm.nrows == 0) return;
+  const int tiny = 1024 / gs_lpr((double)Acm.nnz / Acm.nrows);
+  sweep_plan(cptr, ncol, tiny, [](int) {}, [&](int k0, int nk, int dir) {
+    ChainRun R;
+    R.k0 = k0;
+    R.nk = nk;
+    R.dir = dir;
+    const int klo = dir > 0 ? k0 : k0 - (nk - 1), khi = dir > 0 ? k0 + nk - 1 : k0;
+    R.g_lo = cptr[klo];
+    R.g_hi = cptr[khi + 1];
+    const int nr = R.g_hi - R.g_lo;
+    std::vector<int> rp(nr + 1), rw(std::max(nr, 1));
+    d2h(rp.data(), Acm.rowptr.p + R.g_lo, nr + 1, c);
+    if (nr) d2h(rw.data(), rows.p + R.g_lo, nr, c);
+    R.e_lo = rp[0];
+    const int ne = rp[nr] - rp[0];
+    std::vector<int> cl(std::max(ne, 1));
+    if (ne) d2h(cl.data(), Acm.col.p + R.e_lo, ne, c);
+    std::vector<int> U(cl.begin(), cl.begin() + ne);
+    U.insert(U.end(), rw.begin(), rw.begin() + nr);
+    std::sort(U.begin(), U.end());
+    U.erase(std::unique(U.begin(), U.end()), U.end());
+    R.nU = (int)U.size();
+    if (R.nU <= kChainSlots && nr > 0) {
+      auto slot = [&](int v) { return (int)(std::lower_bound(U.begin(), U.end(), v) - U.begin()); };
+      std::vector<int> lc(std::max(ne, 1)), lr(nr);
+      for (int q = 0; q < ne; ++q) lc[q] = slot(cl[q]);
+      for (int g = 0; g < nr; ++g) lr[g] = slot(rw[g]);
+      R.U.alloc(R.nU, c.s);
+      R.lcol.alloc(std::max(ne, 1), c.s);
+      R.lrow.alloc(nr, c.s);
+      h2d(R.U.p, U.data(), R.nU, c);
+      h2d(R.lcol.p, lc.data(), std::max(ne, 1), c);
+      h2d(R.lrow.p, lr.data(), nr, c);
+    }
+    out.push_back(std::move(R));
+  });
+}
+
+// Algorithmic bytes of one colour launch: the rows' CSR data (column and
+// value per entry, row pointer and original row index per row), their b,
+// 1/a_ii and x written, and every x entry gathered once per sweep (ideal reuse
+// of the gathered neighbours): nnz_c (4 + sizeof V) + rows_c (8 + 4 sizeof T).
 template <class V, class T, int TAG>
 static void sgs_t(const Csr& A, const V* val, const T* dinv, const DBuf<int>& rows, const std::vector<int>& cptr,
-                  const DBuf<int>& cptr_d, int ncol, const T* b, T* x, Ctx& c, const char* tag) {
+                  const DBuf<int>& cptr_d, int ncol, const std::vector<ChainRun>& runs, const T* b, T* x, Ctx& c,
+                  const char* tag) {
   const double avg = A.nrows ? (double)A.nnz / A.nrows : 0.0;
   if (A.nrows <= kSmallLevel) {
     const double bytes = 2.0 * ((double)A.nnz * (4 + sizeof(V)) + (double)A.nrows * (8 + 4 * sizeof(T)));
     c.run("sgs_small", bytes, [&] { k_gs_sweep_small<V, T, 8><<<1, 1024, 0, c.s>>>(A.nrows, ncol, cptr_d.p, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
     return;
   }
-  const int lpr = avg <= 20 ? 8 : avg <= 48 ? 16 : 32;
+  const int lpr = gs_lpr(avg);
   auto launch = [&](int k) {
     const int g0 = cptr[k], nr = cptr[k + 1] - cptr[k];
     if (!nr) return;
@@ -300,13 +439,22 @@ static void sgs_t(const Csr& A, const V* val, const T* dinv, const DBuf<int>& ro
     else
       c.run(tag, bytes, [&] { k_gs_color<V, T, 32, TAG><<<ceil_div((int64_t)nr * 32, 256), 256, 0, c.s>>>(g0, nr, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
   };
-  // a run of colours k0, k0 + dir, ... that one 1024-thread workgroup covers
-  // in one pass each
-  const int tiny = 1024 / lpr;
   auto chain = [&](int k0, int nk, int dir) {
     double nr = 0.0;
     for (int t = 0; t < nk; ++t) nr += cptr[k0 + dir * t + 1] - cptr[k0 + dir * t];
     const double bytes = nr * avg * (4 + sizeof(V)) + nr * (8 + 4 * sizeof(T));
+    const ChainRun* R = nullptr;
+    for (const ChainRun& r : runs)
+      if (r.k0 == k0 && r.nk == nk && r.dir == dir && r.U.p) R = &r;
+    if (R) {
+      if (lpr == 8)
+        c.run(tag, bytes, [&] { k_gs_chain_lds<V, T, 8><<<1, 1024, 0, c.s>>>(k0, nk, dir, cptr_d.p, R->g_lo, R->g_hi, R->e_lo, R->nU, R->U.p, R->lcol.p, R->lrow.p, rows.p, A.rowptr.p, val, dinv, b, x); });
+      else if (lpr == 16)
+        c.run(tag, bytes, [&] { k_gs_chain_lds<V, T, 16><<<1, 1024, 0, c.s>>>(k0, nk, dir, cptr_d.p, R->g_lo, R->g_hi, R->e_lo, R->nU, R->U.p, R->lcol.p, R->lrow.p, rows.p, A.rowptr.p, val, dinv, b, x); });
+      else
+        c.run(tag, bytes, [&] { k_gs_chain_lds<V, T, 32><<<1, 1024, 0, c.s>>>(k0, nk, dir, cptr_d.p, R->g_lo, R->g_hi, R->e_lo, R->nU, R->U.p, R->lcol.p, R->lrow.p, rows.p, A.rowptr.p, val, dinv, b, x); });
+      return;
+    }
     if (lpr == 8)
       c.run(tag, bytes, [&] { k_gs_chain<V, T, 8><<<1, 1024, 0, c.s>>>(k0, nk, dir, cptr_d.p, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
     else if (lpr == 16)
@@ -314,25 +462,7 @@ static void sgs_t(const Csr& A, const V* val, const T* dinv, const DBuf<int>& ro
     else
       c.run(tag, bytes, [&] { k_gs_chain<V, T, 32><<<1, 1024, 0, c.s>>>(k0, nk, dir, cptr_d.p, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
   };
-  // colours in sweep order, forward then backward from the second-to-last
-  // (the last colour's rows already solve their equations after the forward
-  // pass, so repeating it is a no-op); runs of two or more small colours in
-  // one direction go to one chain launch
-  auto pass = [&](int first, int last, int dir) {
-    for (int k = first; k != last + dir;) {
-      int n = 0;
-      while (k + dir * n != last + dir && cptr[k + dir * n + 1] - cptr[k + dir * n] <= tiny) ++n;
-      if (n >= 2) {
-        chain(k, n, dir);
-        k += dir * n;
-      } else {
-        launch(k);
-        k += dir;
-      }
-    }
-  };
-  pass(0, ncol - 1, 1);
-  if (ncol >= 2) pass(ncol - 2, 0, -1);
+  sweep_plan(cptr, ncol, 1024 / lpr, launch, chain);
 }
 
 // x += D c  with D given by its endpoints: x_e += c[head] - c[tail]
@@ -365,15 +495,15 @@ __global__ void __launch_bounds__(256) k_dense_apply(const double* __restrict__ 
 // the fine-level sweeps from the launch-bound coarse ones.
 static void hiptmair64(Level& L, bool fine, double* x, const double* b, const double* dtb, Ctx& c) {
   auto edge = [&] {
-    if (fine) sgs_t<double, double, 1>(L.Acm, L.Acm.val.p, L.dinvAcm.p, L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, b, x, c, "sgs_edge_l0");
-    else sgs_t<double, double, 0>(L.Acm, L.Acm.val.p, L.dinvAcm.p, L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, b, x, c, "sgs_edge");
+    if (fine) sgs_t<double, double, 1>(L.Acm, L.Acm.val.p, L.dinvAcm.p, L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, L.chainsA, b, x, c, "sgs_edge_l0");
+    else sgs_t<double, double, 0>(L.Acm, L.Acm.val.p, L.dinvAcm.p, L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, L.chainsA, b, x, c, "sgs_edge");
   };
   edge();
   // nodal right-hand side D^T (b - A x) = D^T b - (D^T A) x
   spmv(L.DTA, x, L.rn.p, dtb, 1, c, fine ? "nodal_residual_l0" : "nodal_residual");
   fill(L.cn.p, 0.0, L.m, c);
-  if (fine) sgs_t<double, double, 2>(L.Ancm, L.Ancm.val.p, L.dinvAncm.p, L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.rn.p, L.cn.p, c, "sgs_node_l0");
-  else sgs_t<double, double, 0>(L.Ancm, L.Ancm.val.p, L.dinvAncm.p, L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.rn.p, L.cn.p, c, "sgs_node");
+  if (fine) sgs_t<double, double, 2>(L.Ancm, L.Ancm.val.p, L.dinvAncm.p, L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.chainsAn, L.rn.p, L.cn.p, c, "sgs_node_l0");
+  else sgs_t<double, double, 0>(L.Ancm, L.Ancm.val.p, L.dinvAncm.p, L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.chainsAn, L.rn.p, L.cn.p, c, "sgs_node");
   c.run("grad_add", 24.0 * L.n, [&] { k_grad_add<double><<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, L.n, L.cn.p, x); });
   edge();
 }
@@ -411,15 +541,15 @@ template <class T>
 static void hiptmair32(Level& L, bool fine, T* x, const T* b, const T* dtb, Ctx& c) {
   using F = Vec32Form<T>;
   auto edge = [&] {
-    if (fine) sgs_t<float, T, 1>(L.Acm, L.Acm.val32.p, F::dA(L), L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, b, x, c, "sgs_edge32_l0");
-    else sgs_t<float, T, 0>(L.Acm, L.Acm.val32.p, F::dA(L), L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, b, x, c, "sgs_edge32");
+    if (fine) sgs_t<float, T, 1>(L.Acm, L.Acm.val32.p, F::dA(L), L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, L.chainsA, b, x, c, "sgs_edge32_l0");
+    else sgs_t<float, T, 0>(L.Acm, L.Acm.val32.p, F::dA(L), L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, L.chainsA, b, x, c, "sgs_edge32");
   };
   edge();
   // nodal right-hand side D^T b - (D^T A) x with the FP64 operator
   spmv_v64<T, T>(L.DTA, x, F::rn(L), dtb, 1, c, fine ? "nodal_residual32_l0" : "nodal_residual32");
   fill_t(F::cn(L), T(0), L.m, c);
-  if (fine) sgs_t<float, T, 2>(L.Ancm, L.Ancm.val32.p, F::dAn(L), L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, F::rn(L), F::cn(L), c, "sgs_node32_l0");
-  else sgs_t<float, T, 0>(L.Ancm, L.Ancm.val32.p, F::dAn(L), L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, F::rn(L), F::cn(L), c, "sgs_node32");
+  if (fine) sgs_t<float, T, 2>(L.Ancm, L.Ancm.val32.p, F::dAn(L), L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.chainsAn, F::rn(L), F::cn(L), c, "sgs_node32_l0");
+  else sgs_t<float, T, 0>(L.Ancm, L.Ancm.val32.p, F::dAn(L), L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.chainsAn, F::rn(L), F::cn(L), c, "sgs_node32");
   c.run("grad_add32", (8.0 + 3.0 * sizeof(T)) * L.n, [&] { k_grad_add<T><<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, L.n, F::cn(L), x); });
   edge();
 }
@@ -638,6 +768,8 @@ void prepare_solve(Hierarchy& H) {
     L.cptrAn_d.alloc(L.ncolAn + 1, c.s);
     h2d(L.cptrA_d.p, L.cptrA.data(), L.ncolA + 1, c);
     h2d(L.cptrAn_d.p, L.cptrAn.data(), L.ncolAn + 1, c);
+    plan_chains(L.Acm, L.rowsA, L.cptrA, L.ncolA, L.chainsA, c);
+    plan_chains(L.Ancm, L.rowsAn, L.cptrAn, L.ncolAn, L.chainsAn, c);
     L.dinvAcm.alloc(L.n, c.s);
     L.dinvAncm.alloc(L.m, c.s);
     gather_vec(L.dinvA.p, L.rowsA.p, L.dinvAcm.p, L.n, c);
