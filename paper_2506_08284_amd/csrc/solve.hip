@@ -350,7 +350,7 @@ static int gs_lpr(double avg) { return avg <= 20 ? 8 : avg <= 48 ? 16 : 32; }
 // of two or more consecutive colours in one direction whose classes have at
 // most `tiny` rows goes to one chain launch.
 template <class F, class G>
-static void sweep_plan(const std::vector<int>& cptr, int ncol, int tiny, F&& single, G&& chain) {
+static void sweep_plan(const std::vector<int>& cptr, int ncol, int tiny, F&& single, G&& chain, int first = 0) {
   auto pass = [&](int first, int last, int dir) {
     for (int k = first; k != last + dir;) {
       int n = 0;
@@ -364,7 +364,7 @@ static void sweep_plan(const std::vector<int>& cptr, int ncol, int tiny, F&& sin
       }
     }
   };
-  pass(0, ncol - 1, 1);
+  pass(first, ncol - 1, 1);
   if (ncol >= 2) pass(ncol - 2, 0, -1);
 }
 
@@ -420,7 +420,7 @@ void plan_chains(const Csr& Acm, const DBuf<int>& rows, const std::vector<int>& 
 template <class V, class T, int TAG>
 static void sgs_t(const Csr& A, const V* val, const T* dinv, const DBuf<int>& rows, const std::vector<int>& cptr,
                   const DBuf<int>& cptr_d, int ncol, const std::vector<ChainRun>& runs, const T* b, T* x, Ctx& c,
-                  const char* tag) {
+                  const char* tag, int first = 0) {
   const double avg = A.nrows ? (double)A.nnz / A.nrows : 0.0;
   if (A.nrows <= kSmallLevel) {
     const double bytes = 2.0 * ((double)A.nnz * (4 + sizeof(V)) + (double)A.nrows * (8 + 4 * sizeof(T)));
@@ -462,7 +462,8 @@ static void sgs_t(const Csr& A, const V* val, const T* dinv, const DBuf<int>& ro
     else
       c.run(tag, bytes, [&] { k_gs_chain<V, T, 32><<<1, 1024, 0, c.s>>>(k0, nk, dir, cptr_d.p, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
   };
-  sweep_plan(cptr, ncol, 1024 / lpr, launch, chain);
+  // first = 1: the caller has swept colour 0 already (k_gs_first_colour)
+  sweep_plan(cptr, ncol, 1024 / lpr, launch, chain, first);
 }
 
 // x += D c  with D given by its endpoints: x_e += c[head] - c[tail]
@@ -493,19 +494,46 @@ __global__ void __launch_bounds__(256) k_dense_apply(const double* __restrict__ 
 // ---------------------------------------------------------------------------
 // Level 0 gets its own kernel instances (TAG 1, 2) so that profiles separate
 // the fine-level sweeps from the launch-bound coarse ones.
-static void hiptmair64(Level& L, bool fine, double* x, const double* b, const double* dtb, Ctx& c) {
-  auto edge = [&] {
-    if (fine) sgs_t<double, double, 1>(L.Acm, L.Acm.val.p, L.dinvAcm.p, L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, L.chainsA, b, x, c, "sgs_edge_l0");
-    else sgs_t<double, double, 0>(L.Acm, L.Acm.val.p, L.dinvAcm.p, L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, L.chainsA, b, x, c, "sgs_edge");
+// The first colour of a sweep that starts from x = 0 gathers only zeros, so
+// its rows become 0 + (b_i - 0) / a_ii (gs_row's value, bit for bit) and
+// every other row stays zero: one pass over the level in place of the fill
+// and that colour's launch.  color and dinv are in original row order.
+template <class T>
+__global__ void k_gs_first_colour(int n, const int* __restrict__ color, const T* __restrict__ dinv,
+                                  const T* __restrict__ b, T* __restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T v = 0;
+  if (color[i] == 0) v += (b[i] - T(0)) * dinv[i];
+  x[i] = v;
+}
+
+// Levels that sweep by launches; the others sweep in one workgroup
+static bool swept_by_launches(const Level& L) { return L.Acm.nrows > kSmallLevel; }
+
+// x_zero: x is to start from zero (the pre-smoother of a V-cycle visit); on
+// levels swept by launches the first sweep then writes x itself.
+static void hiptmair64(Level& L, bool fine, double* x, const double* b, const double* dtb, Ctx& c, bool x_zero) {
+  auto edge = [&](int first) {
+    if (fine) sgs_t<double, double, 1>(L.Acm, L.Acm.val.p, L.dinvAcm.p, L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, L.chainsA, b, x, c, "sgs_edge_l0", first);
+    else sgs_t<double, double, 0>(L.Acm, L.Acm.val.p, L.dinvAcm.p, L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, L.chainsA, b, x, c, "sgs_edge", first);
   };
-  edge();
+  if (x_zero && swept_by_launches(L)) {
+    c.run(fine ? "sgs_first_l0" : "sgs_first", 28.0 * L.n, [&] {
+      k_gs_first_colour<double><<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.n, L.colorA.p, L.dinvA.p, b, x);
+    });
+    edge(1);
+  } else {
+    if (x_zero) fill(x, 0.0, L.n, c);
+    edge(0);
+  }
   // nodal right-hand side D^T (b - A x) = D^T b - (D^T A) x
   spmv(L.DTA, x, L.rn.p, dtb, 1, c, fine ? "nodal_residual_l0" : "nodal_residual");
   fill(L.cn.p, 0.0, L.m, c);
   if (fine) sgs_t<double, double, 2>(L.Ancm, L.Ancm.val.p, L.dinvAncm.p, L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.chainsAn, L.rn.p, L.cn.p, c, "sgs_node_l0");
   else sgs_t<double, double, 0>(L.Ancm, L.Ancm.val.p, L.dinvAncm.p, L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.chainsAn, L.rn.p, L.cn.p, c, "sgs_node");
   c.run("grad_add", 24.0 * L.n, [&] { k_grad_add<double><<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, L.n, L.cn.p, x); });
-  edge();
+  edge(0);
 }
 
 // FP32 form of the V-cycle: smoothers and transfers read the FP32 copies of
@@ -566,15 +594,14 @@ static void vcycle64(Hierarchy& H, int l, const double* b, double* x) {
   }
   Level& L = *H.lv[l];
   Level& N = *H.lv[l + 1];
-  fill(x, 0.0, L.n, c);
   spmv(L.DT, b, L.dtb.p, nullptr, 0, c, "grad_transpose");
-  hiptmair64(L, l == 0, x, b, L.dtb.p, c);
+  hiptmair64(L, l == 0, x, b, L.dtb.p, c, true);
   spmv(L.A, x, L.r.p, b, 1, c, l == 0 ? "residual_l0" : "residual");
   spmv(L.PeT, L.r.p, N.b.p, nullptr, 0, c, "restrict");
   if (l == 0) coarse_cycle(H);
   else vcycle64(H, l + 1, N.b.p, N.x.p);
   spmv(L.Pe, N.x.p, x, nullptr, 2, c, "prolong");
-  hiptmair64(L, l == 0, x, b, L.dtb.p, c);
+  hiptmair64(L, l == 0, x, b, L.dtb.p, c, false);
 }
 
 // Level l of the FP32 form (T = double on level 0, float below).
