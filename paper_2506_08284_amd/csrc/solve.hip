@@ -497,14 +497,15 @@ __global__ void __launch_bounds__(256) k_dense_apply(const double* __restrict__ 
 // The first colour of a sweep that starts from x = 0 gathers only zeros, so
 // its rows become 0 + (b_i - 0) / a_ii (gs_row's value, bit for bit) and
 // every other row stays zero: one pass over the level in place of the fill
-// and that colour's launch.  color and dinv are in original row order.
+// and that colour's launch.  color and dinv are in original row order; dinv
+// is rounded to T as the sweeps' copies of it are.
 template <class T>
-__global__ void k_gs_first_colour(int n, const int* __restrict__ color, const T* __restrict__ dinv,
+__global__ void k_gs_first_colour(int n, const int* __restrict__ color, const double* __restrict__ dinv,
                                   const T* __restrict__ b, T* __restrict__ x) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   T v = 0;
-  if (color[i] == 0) v += (b[i] - T(0)) * dinv[i];
+  if (color[i] == 0) v += (b[i] - T(0)) * (T)dinv[i];
   x[i] = v;
 }
 
@@ -566,20 +567,28 @@ struct Vec32Form<float> {
 };
 
 template <class T>
-static void hiptmair32(Level& L, bool fine, T* x, const T* b, const T* dtb, Ctx& c) {
+static void hiptmair32(Level& L, bool fine, T* x, const T* b, const T* dtb, Ctx& c, bool x_zero) {
   using F = Vec32Form<T>;
-  auto edge = [&] {
-    if (fine) sgs_t<float, T, 1>(L.Acm, L.Acm.val32.p, F::dA(L), L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, L.chainsA, b, x, c, "sgs_edge32_l0");
-    else sgs_t<float, T, 0>(L.Acm, L.Acm.val32.p, F::dA(L), L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, L.chainsA, b, x, c, "sgs_edge32");
+  auto edge = [&](int first) {
+    if (fine) sgs_t<float, T, 1>(L.Acm, L.Acm.val32.p, F::dA(L), L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, L.chainsA, b, x, c, "sgs_edge32_l0", first);
+    else sgs_t<float, T, 0>(L.Acm, L.Acm.val32.p, F::dA(L), L.rowsA, L.cptrA, L.cptrA_d, L.ncolA, L.chainsA, b, x, c, "sgs_edge32", first);
   };
-  edge();
+  if (x_zero && swept_by_launches(L)) {
+    c.run(fine ? "sgs_first32_l0" : "sgs_first32", (12.0 + 2.0 * sizeof(T)) * L.n, [&] {
+      k_gs_first_colour<T><<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.n, L.colorA.p, L.dinvA.p, b, x);
+    });
+    edge(1);
+  } else {
+    if (x_zero) fill_t(x, T(0), L.n, c);
+    edge(0);
+  }
   // nodal right-hand side D^T b - (D^T A) x with the FP64 operator
   spmv_v64<T, T>(L.DTA, x, F::rn(L), dtb, 1, c, fine ? "nodal_residual32_l0" : "nodal_residual32");
   fill_t(F::cn(L), T(0), L.m, c);
   if (fine) sgs_t<float, T, 2>(L.Ancm, L.Ancm.val32.p, F::dAn(L), L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.chainsAn, F::rn(L), F::cn(L), c, "sgs_node32_l0");
   else sgs_t<float, T, 0>(L.Ancm, L.Ancm.val32.p, F::dAn(L), L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.chainsAn, F::rn(L), F::cn(L), c, "sgs_node32");
   c.run("grad_add32", (8.0 + 3.0 * sizeof(T)) * L.n, [&] { k_grad_add<T><<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, L.n, F::cn(L), x); });
-  edge();
+  edge(0);
 }
 
 static void coarse_cycle(Hierarchy& H);
@@ -617,15 +626,14 @@ static void vcycle32(Hierarchy& H, int l, const T* b, T* x) {
   Level& L = *H.lv[l];
   Level& N = *H.lv[l + 1];
   using F = Vec32Form<T>;
-  fill_t(x, T(0), L.n, c);
   spmv_v32<T, T>(L.DT, b, F::dtb(L), nullptr, 0, c, "grad_transpose32");
-  hiptmair32<T>(L, l == 0, x, b, F::dtb(L), c);
+  hiptmair32<T>(L, l == 0, x, b, F::dtb(L), c, true);
   spmv_v64<T, T>(L.A, x, F::r(L), b, 1, c, l == 0 ? "residual32_l0" : "residual32");
   spmv_v32<T, float>(L.PeT, F::r(L), N.b32.p, nullptr, 0, c, "restrict32");
   if (l == 0) coarse_cycle(H);
   else vcycle32<float>(H, l + 1, N.b32.p, N.x32.p);
   spmv_v32<float, T>(L.Pe, N.x32.p, x, nullptr, 2, c, "prolong32");
-  hiptmair32<T>(L, l == 0, x, b, F::dtb(L), c);
+  hiptmair32<T>(L, l == 0, x, b, F::dtb(L), c, false);
 }
 
 static void vcycle_direct(Hierarchy& H, const double* r, double* z) {
