@@ -799,3 +799,90 @@ def test_dirichlet_hierarchy_converges():
         assert np.all(np.diff(l["energies"]) <= 1e-12 * l["energies"][0])
     _, it, rel, _ = O.pcg(lv, p["f"])
     assert rel <= 1e-8 and it < 80
+
+
+# --------------------------------------------------------------------------
+# hand-worked pins of smoothed aggregation and of the colouring rule
+# --------------------------------------------------------------------------
+
+def _complete_graph_operator(n, c):
+    """(n + c) I - J: the Laplacian of the complete graph K_n plus c I.  Its
+    Jacobi-scaled form D^-1 A has the eigenvalue c / (n - 1 + c) on constants
+    and (n + c) / (n - 1 + c) on every vector of mean zero."""
+    return O.csr(sp.csr_matrix((n + c) * np.eye(n) - np.ones((n, n))))
+
+
+@pytest.mark.parametrize("c,expect", [
+    # K_6, aggregates {0,1} and {2,3,4,5}; rho = 6/5, omega = 4/(3 rho) = 10/9,
+    # omega / d = 2/9; (A Pbar) rows (4, -4) and (-2, 2):
+    # P = Pbar - 2/9 A Pbar, rows already sum to one
+    (0.0, [[1 / 9, 8 / 9], [4 / 9, 5 / 9]]),
+    # K_6 + I: rho = 7/6, omega = 8/7, omega / d = 4/21; (A Pbar) rows (5, -4)
+    # and (-2, 3): rows (1/21, 16/21) and (8/21, 9/21) sum to 17/21 and are
+    # scaled to one (Sec. 4.2)
+    (1.0, [[1 / 17, 16 / 17], [8 / 17, 9 / 17]]),
+])
+def test_sa_prolongator_hand_worked(c, expect):
+    """Smoothed aggregation with omega = 4 / (3 rho(D^-1 A^(n))) (Sec. 3,
+    reading R12), worked by hand on K_6: the power iteration reaches the
+    closed-form rho and every entry of P^(n) matches.  A damping of 1/rho, a
+    dropped D^-1 or a missing row scaling each change these values."""
+    An = _complete_graph_operator(6, c)
+    agg = np.array([0, 0, 1, 1, 1, 1], np.int32)
+    Pn, info = O.sa_prolongator(An, agg, 2)
+    rho = (6 + c) / (5 + c)
+    assert abs(info["rho"] - rho) <= 1e-14 * rho
+    assert abs(info["omega"] - 4 / (3 * rho)) <= 1e-14
+    P = Pn.toarray()
+    want = np.array([expect[0]] * 2 + [expect[1]] * 4)
+    assert np.max(np.abs(P - want)) <= 1e-14
+    assert Pn.nnz == 12  # pattern of Pbar union A^(n) Pbar: every entry
+
+
+def _greedy_by_priority(A):
+    """Sequential restatement of the colouring rule: visit the vertices in
+    decreasing priority (splitmix64(i), i) and give each the smallest colour
+    none of its already coloured neighbours has.  Jones-Plassmann rounds
+    colour a vertex exactly when all its neighbours of higher priority are
+    coloured and none of lower priority is, so the two agree vertex by
+    vertex."""
+    A = O.csr(A)
+    n = A.shape[0]
+    h = [int(v) for v in O.splitmix64(np.arange(n))]
+    order = sorted(range(n), key=lambda i: (h[i], i), reverse=True)
+    color = [-1] * n
+    for v in order:
+        used = {color[w] for w in A.indices[A.indptr[v]:A.indptr[v + 1]] if w != v and color[w] >= 0}
+        k = 0
+        while k in used:
+            k += 1
+        color[v] = k
+    return np.array(color)
+
+
+def test_coloring_is_greedy_in_priority_order(c1):
+    """Jones-Plassmann colouring (reading R18) equals the sequential greedy
+    colouring in decreasing priority on the level-0 edge and nodal graphs of
+    the 8^3 cube, its coarse level and a random graph.  The greedy colouring
+    in increasing priority, a different rule, differs on each."""
+    p, levels = c1
+    rng = np.random.default_rng(8)
+    R = sp.random(400, 400, density=0.02, random_state=rng)
+    graphs = [levels[0]["A"], levels[0]["An"], levels[1]["A"], O.csr(R + R.T + sp.eye(400))]
+    for G in graphs:
+        want = _greedy_by_priority(G)
+        assert np.array_equal(O.color_graph(G), want)
+        # discriminating: the reversed priority order gives another colouring
+        Gr = O.csr(G)
+        n = Gr.shape[0]
+        rev = np.empty(n, np.int64)
+        h = [int(v) for v in O.splitmix64(np.arange(n))]
+        col = [-1] * n
+        for v in sorted(range(n), key=lambda i: (h[i], i)):
+            used = {col[w] for w in Gr.indices[Gr.indptr[v]:Gr.indptr[v + 1]] if w != v and col[w] >= 0}
+            k = 0
+            while k in used:
+                k += 1
+            col[v] = k
+        rev[:] = col
+        assert not np.array_equal(rev, want)

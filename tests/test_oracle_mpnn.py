@@ -57,3 +57,43 @@ def test_features_of_the_lattice(small):
     assert np.array_equal(X[:, 13:], np.zeros((X.shape[0], 3)))
     DH = O.gradient_matrix(lvl["DH_tail"], lvl["DH_head"], lvl["Pn"].shape[1])
     assert abs(O.with_values(lvl["N"], X[:, 1]) @ DH - lvl["D"] @ lvl["Pn"]).max() < 1e-12
+
+
+def test_forward_worked_by_hand_on_three_entries():
+    """The reference forward pass on a 2 x 2 pattern with three entries
+    e0 = (row 0, col 0), e1 = (row 0, col 1), e2 = (row 1, col 0), hidden
+    width 2, one layer, against the network's definition written out entry by
+    entry in scalars: h0 = silu(x W_in + b_in); the row and column means
+    (row 0 averages two entries, row 1 one; column 0 two, column 1 one);
+    z = [h, mean_row, mean_col]; h1 = h0 + silu(z W_0 + b_0); delta =
+    h1 . w_out + b_out.  Sums in place of means, swapped row and column
+    messages or a dropped residual term each change delta."""
+    import math
+    import scipy.sparse as sp
+
+    def s(u):
+        return u / (1.0 + math.exp(-u))
+
+    N = sp.csr_matrix((np.ones(3), np.array([0, 1, 0]), np.array([0, 2, 3])), shape=(2, 2))
+    g = M.graph(N)
+    X = np.array([[1.0, 0.0], [0.0, 1.0], [1.0, 1.0]])
+    W0 = np.zeros((6, 2))
+    W0[2, 0] = 1.0  # u[0] = first component of the row mean
+    W0[5, 1] = 1.0  # u[1] = second component of the column mean
+    p = {"W_in": np.eye(2), "b_in": np.array([0.0, -1.0]), "W0": W0, "b0": np.zeros(2),
+         "w_out": np.array([1.0, 2.0]), "b_out": np.array([0.5])}
+    delta, _ = M.forward(p, X, g, layers=1)
+    # by hand: u0 = x + (0, -1)
+    h = {0: (s(1.0), s(-1.0)), 1: (s(0.0), s(0.0)), 2: (s(1.0), s(0.0))}
+    row_mean = {0: ((h[0][0] + h[1][0]) / 2, (h[0][1] + h[1][1]) / 2), 1: h[2]}
+    col_mean = {0: ((h[0][0] + h[2][0]) / 2, (h[0][1] + h[2][1]) / 2), 1: h[1]}
+    where = {0: (0, 0), 1: (0, 1), 2: (1, 0)}
+    want = []
+    for e in range(3):
+        r, c = where[e]
+        u = (row_mean[r][0], col_mean[c][1])
+        h1 = (h[e][0] + s(u[0]), h[e][1] + s(u[1]))
+        want.append(h1[0] * 1.0 + h1[1] * 2.0 + 0.5)
+    assert np.max(np.abs(delta - np.array(want))) <= 1e-15
+    # the same numbers to twelve digits from 40-digit decimal arithmetic
+    assert np.allclose(delta, [0.783533156687, 0.715800544717, 1.599107429996], atol=1e-11, rtol=0)
