@@ -208,6 +208,30 @@ int hcurl_amg_setup(const hcurl_csr* A, const hcurl_csr* Dh, const double* coord
 int hcurl_amg_solve(hcurl_amg h, const double* f, double* u, double rtol, int maxit,
                     int* iters, double* relres);
 
+/*
+ * hcurl_amg_solve_noalloc -- hcurl_amg_solve for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, results and errors as
+ * hcurl_amg_solve, computed by the same kernels.
+ *   A host-memory handle stages f and u through a file-scope device array of
+ *   2 * HCURL_NOALLOC_MAX_ROWS doubles (32 MiB) in place of the two per-call
+ *   buffers of hcurl_amg_solve; every GPU the library runs this call on keeps
+ *   its own copy of that array until the process ends.  A device-memory
+ *   handle needs no staging.  Nothing is allocated: a device allocation
+ *   requested inside the call fails it with HCURL_EUNSUPPORTED.
+ *   The handle's device must be the current device (HCURL_EINVAL otherwise).
+ * Errors: those of hcurl_amg_solve, and HCURL_EUNSUPPORTED for a host-memory
+ * handle of more than HCURL_NOALLOC_MAX_ROWS edges.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (f and u are written in full before they are read, so nothing
+ * needs clearing).  The call returns after its work has completed, so calls
+ * made one after another never overlap; calls that overlap on one GPU (two
+ * host threads) race on the array and must be serialised by the caller.
+ */
+#define HCURL_NOALLOC_MAX_ROWS 2097152
+int hcurl_amg_solve_noalloc(hcurl_amg h, const double* f, double* u, double rtol, int maxit,
+                            int* iters, double* relres);
+
 /* One V-cycle application z = V(r) (FP64 or FP32 per the handle); r, z in
  * the handle's mem_space. */
 int hcurl_amg_vcycle(hcurl_amg h, const double* r, double* z);

@@ -17,6 +17,7 @@ HCURL_EREDUCIBLE = -4
 HCURL_ENOTSPD = -5
 HCURL_EMAXIT = -6
 HCURL_EUNSUPPORTED = -7
+HCURL_NOALLOC_MAX_ROWS = 2097152  # staging limit of hcurl_amg_solve_noalloc (host-memory handles)
 
 MEM = {"host": 0, "device": 1}
 EXPORT = {"A": 0, "An": 1, "Pn": 2, "Pe": 3, "R": 4, "DH": 5, "P0": 6}
@@ -24,7 +25,7 @@ VEC = {"colors_A": 0, "colors_An": 1, "energy": 2, "local_pairs": 3, "pcg_histor
 
 # every function declared in include/hcurl_amg.h
 EXPORTED_SYMBOLS = [
-    "hcurl_amg_default_opts", "hcurl_amg_setup", "hcurl_amg_solve", "hcurl_amg_vcycle", "hcurl_amg_update",
+    "hcurl_amg_default_opts", "hcurl_amg_setup", "hcurl_amg_solve", "hcurl_amg_solve_noalloc", "hcurl_amg_vcycle", "hcurl_amg_update",
     "hcurl_amg_destroy", "hcurl_amg_num_levels", "hcurl_amg_level_info", "hcurl_amg_commute_residual",
     "hcurl_amg_export_csr", "hcurl_amg_export_vec",
     "hcurl_amg_stats", "hcurl_amg_kernel_stats", "hcurl_amg_reset_kernel_stats", "hcurl_last_error",
@@ -123,6 +124,8 @@ def _load():
     L.hcurl_amg_solve.argtypes = [P, P, P, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                   ctypes.POINTER(ctypes.c_double)]
     L.hcurl_amg_solve.restype = ctypes.c_int
+    L.hcurl_amg_solve_noalloc.argtypes = L.hcurl_amg_solve.argtypes
+    L.hcurl_amg_solve_noalloc.restype = ctypes.c_int
     L.hcurl_amg_vcycle.argtypes = [P, P, P]
     L.hcurl_amg_vcycle.restype = ctypes.c_int
     L.hcurl_amg_update.argtypes = [P, ctypes.POINTER(hcurl_csr), ctypes.c_int, ctypes.c_int]
@@ -253,6 +256,14 @@ def hcurl_amg_solve(h, f, u, rtol: float = 1e-8, maxit: int = 500):
     it = ctypes.c_int(0)
     rel = ctypes.c_double(0.0)
     rc = _check(lib.hcurl_amg_solve(h, _ptr(f), _ptr(u), rtol, maxit, ctypes.byref(it), ctypes.byref(rel)),
+                allow=(HCURL_EMAXIT,))
+    return it.value, rel.value, rc
+
+
+def hcurl_amg_solve_noalloc(h, f, u, rtol: float = 1e-8, maxit: int = 500):
+    it = ctypes.c_int(0)
+    rel = ctypes.c_double(0.0)
+    rc = _check(lib.hcurl_amg_solve_noalloc(h, _ptr(f), _ptr(u), rtol, maxit, ctypes.byref(it), ctypes.byref(rel)),
                 allow=(HCURL_EMAXIT,))
     return it.value, rel.value, rc
 
@@ -474,6 +485,9 @@ class Hierarchy:
 
     def solve(self, f, u, rtol=1e-8, maxit=500):
         return hcurl_amg_solve(self.h, f, u, rtol, maxit)
+
+    def solve_noalloc(self, f, u, rtol=1e-8, maxit=500):
+        return hcurl_amg_solve_noalloc(self.h, f, u, rtol, maxit)
 
     def vcycle(self, r, z):
         hcurl_amg_vcycle(self.h, r, z)

@@ -2,13 +2,20 @@
 // library's errors and turns them into return codes.
 #include <chrono>
 #include <cstring>
+#include <mutex>
 
 #include "mpnn.hpp"
 
 struct hcurl_amg_s {
   hc::Allocator alloc;  // declared first: outlives every buffer of H
   hc::Hierarchy H;
+  int device = -1;      // current device at setup
 };
+
+// Staging area of hcurl_amg_solve_noalloc: f in the first half, u in the
+// second.  Host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device (scratch_address).
+static __device__ __align__(256) double scratch[2 * (size_t)HCURL_NOALLOC_MAX_ROWS];
 
 namespace {
 thread_local std::string g_last_error;
@@ -44,6 +51,28 @@ hc::Level* level_of(hcurl_amg h, int level) {
   if (!h || level < 0 || level >= (int)h->H.lv.size()) hc::fail(HCURL_EINVAL, "level out of range");
   return h->H.lv[level].get();
 }
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+double* scratch_address(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) hc::fail(HCURL_EUNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      hc::fail(HCURL_EHIP, std::string("hipGetSymbolAddress(scratch) -> ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+// Installed for the duration of hcurl_amg_solve_noalloc: any device buffer
+// requested inside it fails the call instead of allocating.
+const hc::Allocator kNoAllocation{nullptr, nullptr, nullptr, "hcurl_amg_solve_noalloc allocates no device memory"};
 
 void export_csr(const hc::Csr& A, int64_t* rowptr, int32_t* col, double* val, hc::Ctx& c) {
   std::vector<int> rp(A.nrows + 1);
@@ -103,6 +132,7 @@ int hcurl_amg_setup(const hcurl_csr* A, const hcurl_csr* Dh, const double* coord
     h->alloc.free = h->H.opts.dev_free;
     h->alloc.ctx = h->H.opts.alloc_ctx;
     hc::AllocatorScope scope(alloc_of(h));
+    HC_HIP(hipGetDevice(&h->device));
     h->H.ctx.init((hipStream_t)h->H.opts.stream, h->H.opts.profile != 0);
     auto t0 = std::chrono::steady_clock::now();
     hc::build_hierarchy(h->H, *A, *Dh, coords, aggregates, n_agg_levels);
@@ -137,6 +167,40 @@ int hcurl_amg_solve(hcurl_amg h, const double* f, double* u, double rtol, int ma
       hc::h2d(df.p, f, n, c);
       rc = hc::pcg_solve(H, df.p, du.p, rtol, maxit, iters, relres);
       hc::d2h(u, du.p, n, c);
+    }
+    H.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
+  });
+}
+
+int hcurl_amg_solve_noalloc(hcurl_amg h, const double* f, double* u, double rtol, int maxit, int* iters,
+                            double* relres) {
+  if (!h || !f || !u || maxit < 0) return HCURL_EINVAL;
+  return guarded([&]() -> int {
+    hc::AllocatorScope scope(&kNoAllocation);
+    auto& H = h->H;
+    auto& c = H.ctx;
+    if (!H.valid) hc::fail(HCURL_EINVAL, "the handle is unusable after a failed hcurl_amg_update");
+    int dev = -1;
+    HC_HIP(hipGetDevice(&dev));
+    if (dev != h->device)
+      hc::fail(HCURL_EINVAL, "the current device (" + std::to_string(dev) + ") is not the handle's (" +
+                                 std::to_string(h->device) + ")");
+    const int64_t n = H.lv[0]->n;
+    const bool host = H.opts.mem_space != HCURL_MEM_DEVICE;
+    if (host && n > HCURL_NOALLOC_MAX_ROWS)
+      hc::fail(HCURL_EUNSUPPORTED, "hcurl_amg_solve_noalloc stages at most " + std::to_string(HCURL_NOALLOC_MAX_ROWS) +
+                                       " rows; this handle has " + std::to_string(n));
+    auto t0 = std::chrono::steady_clock::now();
+    int rc;
+    if (!host) {
+      rc = hc::pcg_solve(H, f, u, rtol, maxit, iters, relres);
+    } else {
+      double* df = scratch_address(dev);
+      double* du = df + HCURL_NOALLOC_MAX_ROWS;
+      hc::h2d(df, f, n, c);
+      rc = hc::pcg_solve(H, df, du, rtol, maxit, iters, relres);
+      hc::d2h(u, du, n, c);
     }
     H.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return rc;

@@ -37,6 +37,7 @@ struct Allocator {
   void* (*alloc)(size_t, void*, void*) = nullptr;
   void (*free)(void*, size_t, void*, void*) = nullptr;
   void* ctx = nullptr;
+  const char* refuse = nullptr;  // set: every request fails with HCURL_EUNSUPPORTED
 };
 
 // The allocator of the handle the calling thread works for (null: the
@@ -78,6 +79,12 @@ struct DBuf {
     n = count;
     a = tl_allocator;
     if (!count) return;
+    if (a && a->refuse) {
+      const std::string why = a->refuse;
+      a = nullptr;
+      n = 0;
+      fail(HCURL_EUNSUPPORTED, why + " (a request for " + std::to_string(count * sizeof(T)) + " bytes)");
+    }
     if (a) {
       p = (T*)a->alloc(count * sizeof(T), (void*)st, a->ctx);
       if (!p) {
