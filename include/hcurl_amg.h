@@ -51,8 +51,17 @@ enum {
   HCURL_ENOTSPD = -5,      /* non-positive curvature in projected CG or a failed
                               Cholesky of a local or coarsest system */
   HCURL_EMAXIT = -6,       /* PCG stopped at maxit above the tolerance */
-  HCURL_EUNSUPPORTED = -7  /* a size limit of this implementation was exceeded
+  HCURL_EUNSUPPORTED = -7, /* a size limit of this implementation was exceeded
                               (see hcurl_last_error for which) */
+  HCURL_ESTAGNATE = -8,    /* PCG stagnated above the tolerance: an iteration left
+                              every entry of the iterate unchanged (the criterion
+                              of Sec. 6.2, two consecutive iterates equal) */
+  HCURL_EINFEASIBLE = -9   /* the commuting constraint of a row of P^(e) has no
+                              finite solution: its right-hand side r_i = (D_h
+                              P^(n))_i on T_i is not finite, or (rows without
+                              single-node coarse edges) |sum_k r_ik| exceeds
+                              1e-10 max(1, sum_k |r_ik|), i.e. P^(n) does not
+                              keep constants (Sec. 4.2) */
 };
 
 enum { HCURL_MEM_HOST = 0, HCURL_MEM_DEVICE = 1 };
@@ -203,7 +212,11 @@ int hcurl_amg_setup(const hcurl_csr* A, const hcurl_csr* Dh, const double* coord
  *   f, u    n_h vectors in opts.mem_space of the handle; u is overwritten.
  *   iters   receives the iteration count; relres the true relative residual
  *           ||f - A u|| / ||f|| (both may be NULL).
- * Returns HCURL_EMAXIT (with u, iters and relres written) if maxit is reached.
+ * Returns HCURL_EMAXIT (with u, iters and relres written) if maxit is reached,
+ * HCURL_ESTAGNATE (u, iters, relres written) if an iteration leaves every
+ * entry of the iterate unchanged before the tolerance is met (Sec. 6.2: the
+ * attainable accuracy is limited by rounding; a larger rtol, such as the
+ * paper's kappa(D^-1 A) / 1e16 of Sec. 6.1, is then the remedy).
  */
 int hcurl_amg_solve(hcurl_amg h, const double* f, double* u, double rtol, int maxit,
                     int* iters, double* relres);
@@ -267,6 +280,17 @@ int hcurl_amg_level_info(hcurl_amg h, int level, hcurl_level_info* info);
  * Errors: HCURL_EINVAL (level, NULL outputs, unusable handle). */
 int hcurl_amg_commute_residual(hcurl_amg h, int level, double* abs_max, double* ref_max);
 
+/* Galerkin check of the curl-curl part (Sec. 2: the coarse curl-curl operator
+ * annihilates the coarse gradient, S_H D_H = 0, because P^(e) D_H = D_h P^(n)
+ * and S_h D_h = 0).  S is the caller's curl-curl matrix S_h of level 0, n_0 x
+ * n_0 with values, in the handle's mem_space, read during the call.  On the
+ * device S_{l+1} = P^(e)_l^T S_l P^(e)_l is formed level by level and, for
+ * every level l < nlev (nlev <= levels), abs_max[l] = max |(S_l D_l)_ij| and
+ * ref_max[l] = max |(S_l)_ij| are written (host arrays).  abs_max / ref_max
+ * is a small multiple of the FP64 epsilon when S_h D_h = 0 holds to rounding.
+ * Errors: HCURL_EINVAL (shape, NULL arguments, nlev out of range). */
+int hcurl_amg_curl_residual(hcurl_amg h, const hcurl_csr* S, int nlev, double* abs_max, double* ref_max);
+
 /* Export of level data to caller-allocated HOST arrays sized from level_info.
  * which: */
 enum {
@@ -288,10 +312,22 @@ enum {
   HCURL_VEC_LOCAL_PAIRS = 3, /* uint16[nnz_Pe] local tail | head << 8 in T_i */
   HCURL_VEC_PCG_HISTORY = 4, /* double[iters+1] recursive relative residuals of the
                                 last solve (level must be 0) */
-  HCURL_VEC_AGGREGATES = 5   /* int32[m] map of P-bar (the coarse node of every node
+  HCURL_VEC_AGGREGATES = 5,  /* int32[m] map of P-bar (the coarse node of every node
                                 that D_H is built from): the caller's aggregates, or
                                 Alg. 1's (l < levels-1) */
+  HCURL_VEC_LS_HISTOGRAM = 6, /* int64[HCURL_LS_HIST_J * HCURL_LS_HIST_NP]: number of
+                                rows of P^(e)_l whose local least-squares problem
+                                has |J| = |T_i| coarse nodes and n_p pattern entries
+                                at [|J| * HCURL_LS_HIST_NP + n_p] (the sub-problem
+                                sizes of Table 4; larger values share the last
+                                bin of their axis).  Counted on the device. */
+  HCURL_VEC_PCG_ALPHA = 7,   /* double[iters] CG step lengths alpha_k of the last
+                                solve (level must be 0) */
+  HCURL_VEC_PCG_BETA = 8     /* double[iters-1] CG coefficients beta_k of the last
+                                solve (level must be 0) */
 };
+#define HCURL_LS_HIST_J 32
+#define HCURL_LS_HIST_NP 512
 int hcurl_amg_export_vec(hcurl_amg h, int level, int which, void* out, int64_t capacity_bytes);
 
 /*
@@ -330,13 +366,24 @@ typedef struct {
   double last_relres;
   int vcycle_fp32;              /* 1 if the FP32 form of the V-cycle is in use */
   double update_ms;             /* wall time of the last hcurl_amg_update */
+  /* Extreme eigenvalue estimates of the preconditioned operator V A from the
+     last solve's CG coefficients (Lanczos matrix T_00 = 1/alpha_0, T_jj =
+     1/alpha_j + beta_{j-1}/alpha_{j-1}, T_j,j+1 = sqrt(beta_j)/alpha_j).  They
+     lie inside V A's spectrum and approach its ends as iterations grow; their
+     ratio estimates kappa(V A).  With the FP32 form's flexible beta this is an
+     approximation.  0 before the first solve. */
+  double lanczos_lambda_min, lanczos_lambda_max;
+  int last_stagnated;           /* 1 if the last solve ended with HCURL_ESTAGNATE */
+  int max_local_J, max_local_np; /* largest |T_i| and n_p over all levels */
 } hcurl_amg_stats_t;
 
 int hcurl_amg_stats(hcurl_amg h, hcurl_amg_stats_t* s);
 
 /* Per-kernel timings (opts.profile = 1): for kernel k < n, its name, launch
  * count, summed milliseconds (HIP events on the handle's stream) and summed
- * algorithmic bytes moved.  Returns the number of kernels recorded. */
+ * algorithmic bytes moved; for the dense network layers, whose names end in
+ * "_flop", the summed floating-point operations instead.  Returns the number
+ * of kernels recorded. */
 int hcurl_amg_kernel_stats(hcurl_amg h, int max_kernels, char (*names)[48], int64_t* launches,
                            double* ms, double* bytes);
 void hcurl_amg_reset_kernel_stats(hcurl_amg h);

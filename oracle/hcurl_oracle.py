@@ -39,7 +39,8 @@ Readings where the paper is silent or garbled (the library follows the same ones
   R9  the energy is measured in A^(e) (footnote to eq. min2_hcurl allows it).
   R10 P_0 = ones on the pattern, then the local min-norm correction (Sec. 6.1).
   R11 projected CG is unpreconditioned CG with the Frobenius inner product on
-      the pattern, a fixed number of iterations (Sec. 3).
+      the pattern, a fixed number of iterations (Sec. 3); once <R, R> has
+      fallen to 1e-24 of its first value the iterate is kept as it is.
   R12 smoothed aggregation uses omega = 4 / (3 rho(D^-1 A^(n))), rho from 20
       power iterations, no dropping (Sec. 3, eq. "emin iteration"; drop tol 0
       in Sec. 6.1).
@@ -575,17 +576,22 @@ def initial_guess(N, loc: LocalSystems) -> np.ndarray:
 def projected_cg(A, N, loc: LocalSystems, p0: np.ndarray, iters: int):
     """Projected conjugate gradients on the KKT system (Sec. 3): CG on
     Pi A-hat Pi with the Frobenius inner product on the pattern (reading R11).
-    Returns the final values and the energy after every iteration."""
+    Once <R, R> has fallen to 1e-24 of its first value the minimiser is
+    reached to rounding and the remaining iterations leave the iterate as it
+    is (the curvature would be rounding noise of either sign).  Returns the
+    final values and the energy after every iteration."""
     p = p0.copy()
     g = masked_product(A, with_values(N, p), N)
     r = -loc.project(g)
     d = r.copy()
     rho = float(np.dot(r, r))
+    rho0 = rho
     energies = [0.5 * float(np.dot(p, g))]
     info = dict(rho=[rho], gamma=[])
     for _ in range(iters):
-        if rho == 0.0:
-            break
+        if rho <= 1e-24 * rho0:
+            energies.append(energies[-1])
+            continue
         q = loc.project(masked_product(A, with_values(N, d), N))
         gamma = float(np.dot(d, q))
         alpha = rho / gamma
@@ -823,33 +829,49 @@ def sgs(A: sp.csr_matrix, colors: np.ndarray, x: np.ndarray, b: np.ndarray) -> n
     return x
 
 
-def hiptmair(lvl, x, b):
+def sgs_lexicographic(A: sp.csr_matrix, x: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """One symmetric Gauss-Seidel sweep in the natural row order, forward then
+    backward, the smoother of the paper's runs (Sec. 6.1): with A = L + D + U,
+    x <- x + (D + L)^-1 (b - A x), then x <- x + (D + U)^-1 (b - A x).  The
+    triangular solves are the row-by-row sweeps."""
+    import scipy.sparse.linalg as spla
+    A = csr(A)
+    x = x + spla.spsolve_triangular(sp.tril(A, 0, format="csr"), b - A @ x, lower=True)
+    return x + spla.spsolve_triangular(sp.triu(A, 0, format="csr"), b - A @ x, lower=False)
+
+
+def hiptmair(lvl, x, b, lex: bool = False):
     """Hiptmair sweep (Sec. 6.1): SGS on A; SGS on D^T A D c = D^T r from c = 0;
-    x += D c; SGS on A."""
+    x += D c; SGS on A.  ``lex``: lexicographic SGS (the paper's order) in
+    place of the multicolour order of reading R18."""
     A, D = lvl["A"], lvl["D"]
-    x = sgs(A, lvl["colors_A"], x, b)
+    smooth = (lambda M, cols, y, rhs: sgs_lexicographic(M, y, rhs)) if lex else sgs
+    x = smooth(A, lvl["colors_A"], x, b)
     r = b - A @ x
-    c = sgs(lvl["An"], lvl["colors_An"], np.zeros(D.shape[1], x.dtype), D.T @ r)
+    c = smooth(lvl["An"], lvl["colors_An"], np.zeros(D.shape[1], x.dtype), D.T @ r)
     x = x + D @ c
-    x = sgs(A, lvl["colors_A"], x, b)
+    x = smooth(A, lvl["colors_A"], x, b)
     return x
 
 
-def vcycle(levels, b, li: int = 0):
+def vcycle(levels, b, li: int = 0, lex: bool = False):
     """V-cycle: Hiptmair pre/post on every level, direct solve on the coarsest."""
     if li == len(levels) - 1:
         return sla.cho_solve(levels[-1]["chol"], b)
     lvl = levels[li]
-    x = hiptmair(lvl, np.zeros_like(b), b)
+    x = hiptmair(lvl, np.zeros_like(b), b, lex)
     r = b - lvl["A"] @ x
-    xc = vcycle(levels, lvl["Pe"].T @ r, li + 1)
+    xc = vcycle(levels, lvl["Pe"].T @ r, li + 1, lex)
     x = x + lvl["Pe"] @ xc
-    return hiptmair(lvl, x, b)
+    return hiptmair(lvl, x, b, lex)
 
 
-def pcg(levels, f, tol: float = 1e-8, maxit: int = 500, precond=None, flexible: bool = False):
+def pcg(levels, f, tol: float = 1e-8, maxit: int = 500, precond=None, flexible: bool = False, info=None):
     """CG preconditioned by one V-cycle, x0 = 0, stop at ||r|| <= tol ||f||
-    (Sec. 6.1; reading R19)."""
+    (Sec. 6.1; reading R19), or when an iteration leaves the iterate unchanged
+    in every entry (the stagnation of Sec. 6.2: two consecutive iterates
+    equal).  ``info``, if a dict, receives the step lengths ``alpha``, the
+    coefficients ``beta`` and ``stagnated``."""
     A = levels[0]["A"]
     M = precond or (lambda r: vcycle(levels, r))
     x = np.zeros_like(f)
@@ -859,28 +881,53 @@ def pcg(levels, f, tol: float = 1e-8, maxit: int = 500, precond=None, flexible: 
     rz = float(np.dot(r, z))
     nf = float(np.linalg.norm(f))
     hist = [1.0]
+    alphas, betas, stagnated = [], [], False
     it = 0
-    while it < maxit:
+    while it < maxit and nf > 0.0:
         q = A @ p
         alpha = rz / float(np.dot(p, q))
-        x = x + alpha * p
+        alphas.append(alpha)
+        x_new = x + alpha * p
         r_new = r - alpha * q
         it += 1
         rel = float(np.linalg.norm(r_new)) / nf
         hist.append(rel)
         if rel <= tol:
-            r = r_new
+            x, r = x_new, r_new
             break
+        if np.array_equal(x_new, x):
+            stagnated = True
+            break
+        x = x_new
         z_new = M(r_new)
         if flexible:
             beta = float(np.dot(r_new, z_new - z)) / rz
         else:
             beta = float(np.dot(r_new, z_new)) / rz
+        betas.append(beta)
         rz = float(np.dot(r_new, z_new))
         p = z_new + beta * p
         r, z = r_new, z_new
-    true_rel = float(np.linalg.norm(f - A @ x)) / nf
+    true_rel = float(np.linalg.norm(f - A @ x)) / nf if nf > 0.0 else 0.0
+    if info is not None:
+        info.update(alpha=alphas, beta=betas, stagnated=stagnated)
     return x, it, true_rel, hist
+
+
+def lanczos_extremes(alpha, beta):
+    """Smallest and largest eigenvalue of the Lanczos tridiagonal matrix that
+    CG's coefficients define for the preconditioned operator (the CG-Lanczos
+    relation): diagonal 1/alpha_0 and 1/alpha_j + beta_{j-1}/alpha_{j-1},
+    off-diagonal sqrt(beta_j)/alpha_j.  Their ratio estimates the condition
+    number that bounds the attainable accuracy (Sec. 6.1 relaxes its tolerance
+    by such an estimate; reading R20)."""
+    a = np.asarray(alpha, np.float64)
+    b = np.asarray(beta, np.float64)[: len(a) - 1]
+    d = 1.0 / a
+    d[1:] += b / a[:-1]
+    e = np.sqrt(b) / a[:-1]
+    w = sla.eigvalsh_tridiagonal(d, e)
+    return float(w[0]), float(w[-1])
 
 
 def fp32_levels(levels):

@@ -17,16 +17,21 @@ HCURL_EREDUCIBLE = -4
 HCURL_ENOTSPD = -5
 HCURL_EMAXIT = -6
 HCURL_EUNSUPPORTED = -7
+HCURL_ESTAGNATE = -8
+HCURL_EINFEASIBLE = -9
 HCURL_NOALLOC_MAX_ROWS = 2097152  # staging limit of hcurl_amg_solve_noalloc (host-memory handles)
 
 MEM = {"host": 0, "device": 1}
 EXPORT = {"A": 0, "An": 1, "Pn": 2, "Pe": 3, "R": 4, "DH": 5, "P0": 6}
-VEC = {"colors_A": 0, "colors_An": 1, "energy": 2, "local_pairs": 3, "pcg_history": 4, "aggregates": 5}
+VEC = {"colors_A": 0, "colors_An": 1, "energy": 2, "local_pairs": 3, "pcg_history": 4, "aggregates": 5,
+       "ls_histogram": 6, "pcg_alpha": 7, "pcg_beta": 8}
+LS_HIST_J, LS_HIST_NP = 32, 512  # HCURL_LS_HIST_J, HCURL_LS_HIST_NP
 
 # every function declared in include/hcurl_amg.h
 EXPORTED_SYMBOLS = [
     "hcurl_amg_default_opts", "hcurl_amg_setup", "hcurl_amg_solve", "hcurl_amg_solve_noalloc", "hcurl_amg_vcycle", "hcurl_amg_update",
     "hcurl_amg_destroy", "hcurl_amg_num_levels", "hcurl_amg_level_info", "hcurl_amg_commute_residual",
+    "hcurl_amg_curl_residual",
     "hcurl_amg_export_csr", "hcurl_amg_export_vec",
     "hcurl_amg_stats", "hcurl_amg_kernel_stats", "hcurl_amg_reset_kernel_stats", "hcurl_last_error",
     "hcurl_error_string", "hcurl_mpnn_num_params", "hcurl_mpnn_create", "hcurl_mpnn_get_params", "hcurl_mpnn_destroy",
@@ -94,7 +99,9 @@ class hcurl_level_info(ctypes.Structure):
 class hcurl_amg_stats_t(ctypes.Structure):
     _fields_ = [("num_levels", ctypes.c_int), ("operator_complexity", ctypes.c_double), ("setup_ms", ctypes.c_double),
                 ("solve_ms", ctypes.c_double), ("last_iters", ctypes.c_int), ("last_relres", ctypes.c_double),
-                ("vcycle_fp32", ctypes.c_int), ("update_ms", ctypes.c_double)]
+                ("vcycle_fp32", ctypes.c_int), ("update_ms", ctypes.c_double),
+                ("lanczos_lambda_min", ctypes.c_double), ("lanczos_lambda_max", ctypes.c_double),
+                ("last_stagnated", ctypes.c_int), ("max_local_J", ctypes.c_int), ("max_local_np", ctypes.c_int)]
 
 
 class HcurlError(RuntimeError):
@@ -139,6 +146,8 @@ def _load():
     L.hcurl_amg_commute_residual.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                              ctypes.POINTER(ctypes.c_double)]
     L.hcurl_amg_commute_residual.restype = ctypes.c_int
+    L.hcurl_amg_curl_residual.argtypes = [P, ctypes.POINTER(hcurl_csr), ctypes.c_int, P, P]
+    L.hcurl_amg_curl_residual.restype = ctypes.c_int
     L.hcurl_amg_export_csr.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, P]
     L.hcurl_amg_export_csr.restype = ctypes.c_int
     L.hcurl_amg_export_vec.argtypes = [P, ctypes.c_int, ctypes.c_int, P, ctypes.c_int64]
@@ -256,7 +265,7 @@ def hcurl_amg_solve(h, f, u, rtol: float = 1e-8, maxit: int = 500):
     it = ctypes.c_int(0)
     rel = ctypes.c_double(0.0)
     rc = _check(lib.hcurl_amg_solve(h, _ptr(f), _ptr(u), rtol, maxit, ctypes.byref(it), ctypes.byref(rel)),
-                allow=(HCURL_EMAXIT,))
+                allow=(HCURL_EMAXIT, HCURL_ESTAGNATE))
     return it.value, rel.value, rc
 
 
@@ -264,7 +273,7 @@ def hcurl_amg_solve_noalloc(h, f, u, rtol: float = 1e-8, maxit: int = 500):
     it = ctypes.c_int(0)
     rel = ctypes.c_double(0.0)
     rc = _check(lib.hcurl_amg_solve_noalloc(h, _ptr(f), _ptr(u), rtol, maxit, ctypes.byref(it), ctypes.byref(rel)),
-                allow=(HCURL_EMAXIT,))
+                allow=(HCURL_EMAXIT, HCURL_ESTAGNATE))
     return it.value, rel.value, rc
 
 
@@ -347,14 +356,30 @@ def hcurl_amg_export_vec(h, level: int, which: str, count: int | None = None):
         out = np.empty(info["n_nodes"], np.int32)
     elif which == "pcg_history":
         out = np.empty(count or (hcurl_amg_stats(h)["last_iters"] + 1), np.float64)
+    elif which in ("pcg_alpha", "pcg_beta"):
+        out = np.empty(count or max(hcurl_amg_stats(h)["last_iters"], 1), np.float64)
+    elif which == "ls_histogram":
+        out = np.empty((LS_HIST_J, LS_HIST_NP), np.int64)
     else:
         raise ValueError(which)
     rc = lib.hcurl_amg_export_vec(h, level, VEC[which], _ptr(out), out.nbytes)
     if rc < 0:
         _check(rc)
-    if which in ("energy", "pcg_history"):
+    if which in ("energy", "pcg_history", "pcg_alpha", "pcg_beta"):
         return out[:rc]
     return out
+
+
+def hcurl_amg_curl_residual(h, S, nlev: int | None = None):
+    """Per level l: (max |S_l D_l|, max |S_l|) with S_0 = S (rowptr int64, col
+    int32, val f64; host or device per the handle) and S_{l+1} = P^(e)T S_l P^(e)."""
+    nlev = nlev or hcurl_amg_num_levels(h)
+    n = int(S[0].shape[0]) - 1
+    cS = _csr(*S, n, n)
+    a = np.zeros(nlev)
+    r = np.zeros(nlev)
+    _check(lib.hcurl_amg_curl_residual(h, ctypes.byref(cS), nlev, _ptr(a), _ptr(r)))
+    return a, r
 
 
 def hcurl_amg_stats(h) -> dict:
@@ -503,6 +528,9 @@ class Hierarchy:
 
     def commute_residual(self, level):
         return hcurl_amg_commute_residual(self.h, level)
+
+    def curl_residual(self, S, nlev=None):
+        return hcurl_amg_curl_residual(self.h, S, nlev)
 
     def export_csr(self, level, which):
         return hcurl_amg_export_csr(self.h, level, which)

@@ -91,6 +91,9 @@ struct Hierarchy {
   double setup_ms = 0.0, solve_ms = 0.0;
   int last_iters = 0;
   std::vector<double> pcg_hist;  // recursive relative residuals of the last solve
+  std::vector<double> pcg_alpha, pcg_beta;  // CG coefficients of the last solve
+  double lanczos_min = 0.0, lanczos_max = 0.0;  // extreme Ritz values from them
+  bool stagnated = false;
   double last_relres = 0.0;
   DBuf<double> coords;  // level-0 node coordinates (m x 3) when given
   // PCG workspace (level 0, FP64)
@@ -109,6 +112,10 @@ void update_hierarchy(Hierarchy& H, const hcurl_csr& A, int mode, int iters);
 void emin_make_feasible(Level& L, double* x, bool ones, Ctx& c);
 // max |P^(e) D_H - D_h P^(n)| over the level's rows and max |D_h P^(n)| on T
 void commute_residual(Level& L, double* abs_max, double* ref_max, Ctx& c);
+// (|T_i|, n_p) histogram of the level's rows (HCURL_LS_HIST_J x HCURL_LS_HIST_NP)
+void ls_histogram(Level& L, int64_t* out, Ctx& c);
+// max |S_l D_l| and max |S_l| for l < nlev, S_0 = S, S_{l+1} = P^(e)T S_l P^(e)
+void curl_residual(Hierarchy& H, const hcurl_csr& S, int nlev, double* absmax, double* refmax);
 
 // solve.hip
 void color_rows(const Csr& A, DBuf<int>& color, DBuf<int>& rows, std::vector<int>& cptr, int& ncol, Ctx& c);

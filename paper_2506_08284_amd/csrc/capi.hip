@@ -1,5 +1,6 @@
 // extern "C" entry points (include/hcurl_amg.h).  Every call catches the
 // library's errors and turns them into return codes.
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <mutex>
@@ -273,6 +274,16 @@ int hcurl_amg_commute_residual(hcurl_amg h, int level, double* abs_max, double* 
   });
 }
 
+int hcurl_amg_curl_residual(hcurl_amg h, const hcurl_csr* S, int nlev, double* abs_max, double* ref_max) {
+  if (!h || !S || !abs_max || !ref_max) return HCURL_EINVAL;
+  return guarded([&]() -> int {
+    hc::AllocatorScope scope(alloc_of(h));
+    if (!h->H.valid) hc::fail(HCURL_EINVAL, "the handle is unusable after a failed hcurl_amg_update");
+    hc::curl_residual(h->H, *S, nlev, abs_max, ref_max);
+    return HCURL_OK;
+  });
+}
+
 int hcurl_amg_export_csr(hcurl_amg h, int level, int which, int64_t* rowptr, int32_t* col, double* val) {
   return guarded([&]() -> int {
     hc::AllocatorScope scope(alloc_of(h));
@@ -351,6 +362,18 @@ int hcurl_amg_export_vec(hcurl_amg h, int level, int which, void* out, int64_t c
         need(4LL * L->m);
         hc::d2h((int*)out, L->pbar.p ? L->pbar.p : L->agg.p, L->m, c);
         break;
+      case HCURL_VEC_LS_HISTOGRAM:
+        need(8LL * HCURL_LS_HIST_J * HCURL_LS_HIST_NP);
+        hc::ls_histogram(*L, (int64_t*)out, c);
+        break;
+      case HCURL_VEC_PCG_ALPHA:
+      case HCURL_VEC_PCG_BETA: {
+        if (level != 0) hc::fail(HCURL_EINVAL, "the PCG coefficients belong to level 0");
+        const auto& v = which == HCURL_VEC_PCG_ALPHA ? h->H.pcg_alpha : h->H.pcg_beta;
+        need(8LL * (int64_t)v.size());
+        std::memcpy(out, v.data(), 8 * v.size());
+        return (int)v.size();
+      }
       default: hc::fail(HCURL_EINVAL, "unknown vector");
     }
     return HCURL_OK;
@@ -385,6 +408,15 @@ int hcurl_amg_stats(hcurl_amg h, hcurl_amg_stats_t* s) {
   s->last_relres = H.last_relres;
   s->vcycle_fp32 = H.fp32 ? 1 : 0;
   s->update_ms = H.update_ms;
+  s->lanczos_lambda_min = H.lanczos_min;
+  s->lanczos_lambda_max = H.lanczos_max;
+  s->last_stagnated = H.stagnated ? 1 : 0;
+  s->max_local_J = s->max_local_np = 0;
+  for (auto& L : H.lv) {
+    if (!L->has_transfer) continue;
+    s->max_local_J = std::max(s->max_local_J, L->maxJ);
+    s->max_local_np = std::max(s->max_local_np, L->maxNp);
+  }
   return HCURL_OK;
 }
 
@@ -559,6 +591,8 @@ const char* hcurl_error_string(int code) {
     case HCURL_ENOTSPD: return "not positive definite";
     case HCURL_EMAXIT: return "maximum iterations reached";
     case HCURL_EUNSUPPORTED: return "size limit exceeded";
+    case HCURL_ESTAGNATE: return "PCG stagnated: an iteration left the iterate unchanged";
+    case HCURL_EINFEASIBLE: return "commuting constraint without finite solution";
     default: return "unknown error";
   }
 }

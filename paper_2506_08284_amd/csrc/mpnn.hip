@@ -553,7 +553,7 @@ void mpnn_forward(Net& net, Sample& S, Ctx& c, bool keep) {
   }
   if (S.delta.n != (size_t)E) S.delta.alloc(E, c.s);
   const int lg = layer_grid(E);
-  c.run("mpnn_dense_in", 2.0 * E * kNF * kHD, [&] {
+  c.run("mpnn_dense_in_flop", 2.0 * E * kNF * kHD, [&] {
     k_mpnn_layer<kNF, 0><<<lg, 256, 0, c.s>>>(E, S.X.p, nullptr, nullptr, nullptr, nullptr, nullptr, net.wt_in.p,
                                               net.w.p + kOffBin, nullptr, keep ? S.u[0].p : nullptr, S.h[0].p, nullptr);
   });
@@ -565,7 +565,7 @@ void mpnn_forward(Net& net, Sample& S, Ctx& c, bool keep) {
     row_mean(S, hin, kHD, 0, mr, c);
     col_mean(S, hin, kHD, 0, mc, c);
     const bool last_fused = !keep && l == kNL - 1;  // inference: the head is formed in the last layer
-    c.run("mpnn_dense", 2.0 * E * kKZ * kHD, [&] {
+    c.run("mpnn_dense_flop", 2.0 * E * kKZ * kHD, [&] {
       if (last_fused)
         k_mpnn_layer<kKZ, 2><<<lg, 256, 0, c.s>>>(E, nullptr, hin, mr, mc, S.row_of.p, S.col_of.p, net.wt[l].p,
                                                   net.w.p + off_b(l), net.w.p + kOffWout, nullptr, nullptr, S.delta.p);
@@ -607,13 +607,13 @@ double mpnn_loss_grad(Net& net, Sample& S, Ctx& c) {
   const int nb = ceil_div(E, 64);
   for (int l = kNL - 1; l >= 0; --l) {
     c.run("mpnn_du", 12.0 * E * kHD, [&] { k_du<<<ceil_div(E * kHD, 256), 256, 0, c.s>>>(E * kHD, S.dh.p, S.u[l + 1].p, S.du.p); });
-    c.run("mpnn_dense_wgrad", 2.0 * E * kKZ * kHD, [&] {
+    c.run("mpnn_dense_wgrad_flop", 2.0 * E * kKZ * kHD, [&] {
       k_mpnn_wgrad<kKZ, 1><<<nbw, 256, 0, c.s>>>(E, chunks, nullptr, S.h[l].p, S.mr[l].p, S.mc[l].p, S.row_of.p,
                                                  S.col_of.p, S.du.p, wpart.p);
     });
     k_sum_blocks<<<ceil_div(kKZ * kHD + kHD, 256), 256, 0, c.s>>>(wpart.p, nbw, kKZ * kHD + kHD, net.g.p + off_W(l));
     HC_LAUNCH_CHECK();
-    c.run("mpnn_dense_dz", 2.0 * E * kKZ * kHD, [&] {
+    c.run("mpnn_dense_dz_flop", 2.0 * E * kKZ * kHD, [&] {
       k_mpnn_dz<<<dim3(nb, 3), 256, 0, c.s>>>(E, S.du.p, net.wr[l].p, S.dz.p);
     });
     // adjoints of the gathered means: average the row slice over rows and
@@ -626,7 +626,7 @@ double mpnn_loss_grad(Net& net, Sample& S, Ctx& c) {
   }
   // input layer
   c.run("mpnn_du", 12.0 * E * kHD, [&] { k_du<<<ceil_div(E * kHD, 256), 256, 0, c.s>>>(E * kHD, S.dh.p, S.u[0].p, S.du.p); });
-  c.run("mpnn_dense_wgrad", 2.0 * E * kNF * kHD, [&] {
+  c.run("mpnn_dense_wgrad_flop", 2.0 * E * kNF * kHD, [&] {
     k_mpnn_wgrad<kNF, 0><<<nbw, 256, 0, c.s>>>(E, chunks, S.X.p, nullptr, nullptr, nullptr, nullptr, nullptr, S.du.p,
                                                wpart.p);
   });

@@ -2,6 +2,7 @@
 // aggregation, coarse gradient, Emin_Setup pattern and local systems (Alg. 2),
 // constrained energy minimisation of P^(e) (Sec. 3, Sec. 4), Galerkin RAP.
 #include <chrono>
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -14,6 +15,9 @@ namespace hc {
 enum { S_RHO = 0, S_GAMMA, S_ALPHA, S_RHONEW, S_BETA, S_NX2, S_NY2, S_POWRHO, S_OMEGA, S_ENERGY, S_RHO0 };
 // device integer flag slots (Ctx::iscal); 0 and 1 are used by the primitives
 enum { F_BAD = 2, F_DISCONNECTED, F_MAXJ, F_MAXNP, F_TOOBIG, F_NOTSPD };
+// slots 8-12 serve the solve; 13: rows with an infeasible constraint, 14: the
+// largest such row + 1
+enum { F_INFEASIBLE = 13, F_INFEASIBLE_ROW = 14 };
 
 // ---------------------------------------------------------------------------
 // discrete gradient
@@ -635,8 +639,27 @@ __global__ void k_make_feasible(int n, const int* __restrict__ Prp, double* __re
   const int p0 = Prp[i], np = Prp[i + 1] - p0;
   if (ones)
     for (int e = 0; e < np; ++e) x[p0 + e] = 1.0;
-  const int t0 = Trp[i];
-  if (!local_solve_fit<MAXJ>(x + p0, lp + p0, np, Trp[i + 1] - t0, Rval + t0)) atomicAdd((unsigned long long*)&flags[F_NOTSPD], 1ULL);
+  const int t0 = Trp[i], nJ = Trp[i + 1] - t0;
+  // Solvability (Sec. 4.2): the columns of G_i = [D_H]_{N_i,T_i} sum to zero
+  // when no coarse edge of the row has a single node, so G_i^T p = r_i needs
+  // sum_k r_ik = 0.  With rows of P^(n) summing to one, sum_k r_ik is the
+  // difference of two such sums, zero up to their rounding; the bound is
+  // absolute (r_i itself may be zero up to rounding) unless r_i is larger
+  // than one.  With a single-node edge G_i has full column rank.  Either way
+  // r_i must be finite.
+  int miss = 0;
+  for (int e = 0; e < np; ++e) miss |= ((lp[p0 + e] & 255) == 255) | ((lp[p0 + e] >> 8) == 255);
+  double rs = 0.0, ra = 0.0;
+  for (int k = 0; k < nJ; ++k) {
+    rs += Rval[t0 + k];
+    ra += fabs(Rval[t0 + k]);
+  }
+  if (!(ra <= DBL_MAX) || (!miss && !(fabs(rs) <= 1e-10 * fmax(1.0, ra)))) {
+    atomicAdd((unsigned long long*)&flags[F_INFEASIBLE], 1ULL);
+    atomicMax((unsigned long long*)&flags[F_INFEASIBLE_ROW], (unsigned long long)i + 1);
+    return;
+  }
+  if (!local_solve_fit<MAXJ>(x + p0, lp + p0, np, nJ, Rval + t0)) atomicAdd((unsigned long long*)&flags[F_NOTSPD], 1ULL);
 }
 
 // ---------------------------------------------------------------------------
@@ -1029,6 +1052,102 @@ void commute_residual(Level& L, double* abs_max, double* ref_max, Ctx& c) {
   *ref_max = b;
 }
 
+// Sizes of the local least-squares problems (Table 4): the number of rows i
+// with |T_i| = J and n_p pattern entries, binned at [min(J, HJ-1) * HNP +
+// min(n_p, HNP-1)].  Small keys are counted in an LDS histogram per block.
+constexpr int kHistJ = HCURL_LS_HIST_J, kHistNP = HCURL_LS_HIST_NP;
+constexpr int kLdsJ = 32, kLdsNP = 64;
+__global__ void __launch_bounds__(256) k_ls_histogram(int n, const int* __restrict__ Trp, const int* __restrict__ Prp,
+                                                      unsigned long long* __restrict__ hist) {
+  __shared__ unsigned int h[kLdsJ * kLdsNP];
+  for (int k = threadIdx.x; k < kLdsJ * kLdsNP; k += 256) h[k] = 0;
+  __syncthreads();
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const int J = min(Trp[i + 1] - Trp[i], kHistJ - 1), np = min(Prp[i + 1] - Prp[i], kHistNP - 1);
+    if (J < kLdsJ && np < kLdsNP) atomicAdd(&h[J * kLdsNP + np], 1u);
+    else atomicAdd(&hist[J * kHistNP + np], 1ULL);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < kLdsJ * kLdsNP; k += 256)
+    if (h[k]) atomicAdd(&hist[(k / kLdsNP) * kHistNP + k % kLdsNP], (unsigned long long)h[k]);
+}
+
+__global__ void k_zero_u64(unsigned long long* x, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0;
+}
+
+void ls_histogram(Level& L, int64_t* out, Ctx& c) {
+  if (!L.has_transfer) fail(HCURL_EINVAL, "level has no transfer");
+  DBuf<unsigned long long> h((size_t)kHistJ * kHistNP, c.s);
+  k_zero_u64<<<ceil_div(kHistJ * kHistNP, 256), 256, 0, c.s>>>(h.p, kHistJ * kHistNP);
+  HC_LAUNCH_CHECK();
+  if (L.n > 0)
+    c.run("ls_histogram", 8.0 * L.n, [&] {
+      k_ls_histogram<<<std::min(ceil_div(L.n, 256), 2048), 256, 0, c.s>>>(L.n, L.R.rowptr.p, L.Pe.rowptr.p, h.p);
+    });
+  d2h((unsigned long long*)out, h.p, (size_t)kHistJ * kHistNP, c);
+}
+
+// max |x_i| over a value array (non-negative doubles order like their bits);
+// a NaN counts in out[1]
+__global__ void k_absmax(int64_t n, const double* __restrict__ v, unsigned long long* __restrict__ out) {
+  double m = 0.0;
+  unsigned long long nan = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double a = fabs(v[i]);
+    nan += a != a;
+    m = a > m ? a : m;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  nan = wave_sum(nan);
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(out, (unsigned long long)__double_as_longlong(m));
+    if (nan) atomicAdd(out + 1, nan);
+  }
+}
+
+static double abs_max(const Csr& M, Ctx& c) {
+  DBuf<unsigned long long> r(2, c.s);
+  k_zero_u64<<<1, 64, 0, c.s>>>(r.p, 2);
+  HC_LAUNCH_CHECK();
+  if (M.nnz > 0)
+    c.run("absmax", 8.0 * M.nnz, [&] {
+      k_absmax<<<std::min<int64_t>(ceil_div(M.nnz, 256), 2048), 256, 0, c.s>>>(M.nnz, M.val.p, r.p);
+    });
+  unsigned long long h[2];
+  d2h(h, r.p, 2, c);
+  double a;
+  std::memcpy(&a, &h[0], sizeof a);
+  return h[1] ? std::numeric_limits<double>::quiet_NaN() : a;
+}
+
+// S_l D_l on every level l < nlev, with S_0 = S and S_{l+1} = P^(e)T S_l P^(e)
+// formed on the device by the Galerkin products of the setup.
+void curl_residual(Hierarchy& H, const hcurl_csr& S, int nlev, double* absmax, double* refmax) {
+  Ctx& c = H.ctx;
+  const Level& L0 = *H.lv[0];
+  if (S.nrows != L0.n || S.ncols != L0.n || !S.val) fail(HCURL_EINVAL, "S must be n_0 x n_0 with values");
+  if (nlev < 1 || nlev > (int)H.lv.size()) fail(HCURL_EINVAL, "nlev out of range");
+  Csr Sl;
+  upload_csr(S, H.opts.mem_space == HCURL_MEM_DEVICE, Sl, true, c);
+  for (int l = 0; l < nlev; ++l) {
+    Level& L = *H.lv[l];
+    if (L.D.nrows != L.n || !L.D.rowptr.p) gradient_csr(L, c);  // the coarsest level keeps none
+    Csr SD;
+    spgemm(Sl, L.D, SD, true, c, "spgemm_curl_SD");
+    absmax[l] = abs_max(SD, c);
+    refmax[l] = abs_max(Sl, c);
+    if (l + 1 < nlev) {
+      Csr SP, Sn;
+      spgemm(Sl, L.Pe, SP, true, c, "spgemm_curl_SP");
+      spgemm(L.PeT, SP, Sn, true, c, "spgemm_curl_PtSP");
+      Sl = std::move(Sn);
+    }
+  }
+}
+
 __global__ void k_add2(int64_t n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ y) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = a[i] + b[i];
@@ -1067,6 +1186,8 @@ static void energy_minimisation(Hierarchy& H, Level& L, const Level* next, int i
   w.Y.alloc(np, c.s);
   w.part.alloc(8192, c.s);
   clear_flag(F_NOTSPD, c);
+  clear_flag(F_INFEASIBLE, c);
+  clear_flag(F_INFEASIBLE_ROW, c);
   // initial guess
   if (learned) {
     // plain guess plus the network's correction, then the min-norm correction
@@ -1086,6 +1207,9 @@ static void energy_minimisation(Hierarchy& H, Level& L, const Level* next, int i
       HC_HIP(hipMemcpyAsync(w.P.p, init, sizeof(double) * np, init_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c.s));
     make_feasible(L, w.P.p, !given_init, c);
   }
+  if (const long long bad = read_flag(F_INFEASIBLE, c))
+    fail(HCURL_EINFEASIBLE, std::to_string(bad) + " rows of P^(e) have a commuting constraint without finite solution "
+                                                 "(largest: row " + std::to_string(read_flag(F_INFEASIBLE_ROW, c) - 1) + ")");
   L.p0.alloc(np, c.s);
   d2d(L.p0.p, w.P.p, np, c);
   double* sc = c.scal.p;

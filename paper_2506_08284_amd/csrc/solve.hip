@@ -834,25 +834,81 @@ void prepare_solve(Hierarchy& H) {
 // ---------------------------------------------------------------------------
 // PCG (FP64 vectors and inner products, device scalars)
 // ---------------------------------------------------------------------------
-__global__ void k_pcg_alpha(double* __restrict__ sc, unsigned long long* __restrict__ bad) {
+// flags[0]: breakdown count; flags[3]: set by the update when any entry of x
+// changed (cleared here, before the update of the same iteration)
+__global__ void k_pcg_alpha(double* __restrict__ sc, unsigned long long* __restrict__ flags) {
+  flags[3] = 0;
   const double pq = sc[P_PQ];
-  if (!(pq > 0.0)) { *bad += 1; sc[P_ALPHA] = 0.0; return; }
+  if (!(pq > 0.0)) { flags[0] += 1; sc[P_ALPHA] = 0.0; return; }
   sc[P_ALPHA] = sc[P_RZ] / pq;
 }
 __global__ void __launch_bounds__(256) k_pcg_update(int64_t n, double* __restrict__ x, double* __restrict__ r,
                                                     const double* __restrict__ p, const double* __restrict__ q,
-                                                    const double* __restrict__ alpha, double* __restrict__ part) {
+                                                    const double* __restrict__ alpha, double* __restrict__ part,
+                                                    unsigned long long* __restrict__ flags) {
   __shared__ double sh[4];
   const double a = *alpha;
   double s = 0.0;
+  int changed = 0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    x[i] += a * p[i];
+    const double xo = x[i], xn = xo + a * p[i];
+    changed |= xn != xo;
+    x[i] = xn;
     const double ri = r[i] - a * q[i];
     r[i] = ri;
     s += ri * ri;
   }
   double t = block_sum256(s, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
+  // every block that changed an entry stores the same value
+  if (__syncthreads_or(changed) && threadIdx.x == 0) flags[3] = 1;
+}
+
+// Extreme eigenvalues of the Lanczos matrix of the preconditioned operator
+// that CG builds from its own coefficients (the CG-Lanczos relation): T is
+// symmetric tridiagonal with T_00 = 1/alpha_0, T_jj = 1/alpha_j +
+// beta_{j-1}/alpha_{j-1}, T_j,j+1 = sqrt(beta_j)/alpha_j.  Its extreme
+// eigenvalues approach those of V A from inside; they are found by bisection
+// on the Sturm count (the number of negative pivots of T - x I).
+static void lanczos_extremes(const std::vector<double>& alpha, const std::vector<double>& beta, double* lmin,
+                             double* lmax) {
+  const size_t k = alpha.size();
+  *lmin = *lmax = 0.0;
+  if (k == 0) return;
+  std::vector<double> d(k), e(k, 0.0);
+  for (size_t j = 0; j < k; ++j) {
+    d[j] = 1.0 / alpha[j] + (j > 0 ? beta[j - 1] / alpha[j - 1] : 0.0);
+    if (j + 1 < k) e[j] = std::sqrt(std::max(beta[j], 0.0)) / alpha[j];
+  }
+  for (size_t j = 0; j < k; ++j)
+    if (!std::isfinite(d[j]) || !std::isfinite(e[j])) return;
+  double lo = d[0], hi = d[0];
+  for (size_t j = 0; j < k; ++j) {
+    const double rad = std::fabs(e[j]) + (j > 0 ? std::fabs(e[j - 1]) : 0.0);
+    lo = std::min(lo, d[j] - rad);
+    hi = std::max(hi, d[j] + rad);
+  }
+  auto below = [&](double x) {  // eigenvalues of T smaller than x
+    size_t cnt = 0;
+    double q = 1.0;
+    for (size_t j = 0; j < k; ++j) {
+      const double off = j > 0 ? e[j - 1] * e[j - 1] : 0.0;
+      q = (d[j] - x) - (j > 0 ? off / q : 0.0);
+      if (q == 0.0) q = -1e-300;
+      cnt += q < 0.0;
+    }
+    return cnt;
+  };
+  auto bisect = [&](size_t target) {  // smallest x with below(x) >= target
+    double a = lo, b = hi;
+    for (int it = 0; it < 200 && b - a > 1e-15 * std::max(std::fabs(a), std::fabs(b)); ++it) {
+      const double mid = 0.5 * (a + b);
+      if (below(mid) >= target) b = mid; else a = mid;
+    }
+    return 0.5 * (a + b);
+  };
+  *lmin = bisect(1);
+  *lmax = bisect(k);
 }
 // beta = <r,z> / rz (FP64 form) or (<r,z> - <r,zold>) / rz (flexible)
 __global__ void k_pcg_beta(double* __restrict__ sc, int flexible) {
@@ -875,8 +931,13 @@ int pcg_solve(Hierarchy& H, const double* f, double* u, double rtol, int maxit, 
   const int64_t n = L.n;
   const bool flex = H.fp32;
   double* sc = c.scal.p;
-  unsigned long long* bad = (unsigned long long*)(c.iscal.p + 9);
-  HC_HIP(hipMemsetAsync(bad, 0, sizeof(unsigned long long), c.s));
+  // iscal[9] breakdown count, iscal[12] "x changed" (see k_pcg_alpha)
+  unsigned long long* flags = (unsigned long long*)(c.iscal.p + 9);
+  HC_HIP(hipMemsetAsync(flags, 0, 4 * sizeof(unsigned long long), c.s));
+  H.pcg_alpha.clear();
+  H.pcg_beta.clear();
+  H.lanczos_min = H.lanczos_max = 0.0;
+  H.stagnated = false;
   const int nbu = (int)std::min<int64_t>(Ctx::kRedBlocks, std::max<int64_t>(1, (n + 255) / 256));
   // x = 0, r = f, z = V(r), p = z
   fill(H.px.p, 0.0, n, c);
@@ -912,20 +973,29 @@ int pcg_solve(Hierarchy& H, const double* f, double* u, double rtol, int maxit, 
     if (sampled) c.profile = it % kSampleEvery == 0;
     spmv(L.A, H.pp.p, H.pq.p, nullptr, 0, c, "pcg_spmv");
     dot(H.pp.p, H.pq.p, n, sc + P_PQ, c, 3);
-    c.run("pcg_scalar", 0.0, [&] { k_pcg_alpha<<<1, 1, 0, c.s>>>(sc, bad); });
+    c.run("pcg_scalar", 0.0, [&] { k_pcg_alpha<<<1, 1, 0, c.s>>>(sc, flags); });
     c.run("pcg_update", 48.0 * n, [&] {
-      k_pcg_update<<<nbu, 256, 0, c.s>>>(n, H.px.p, H.pr.p, H.pp.p, H.pq.p, sc + P_ALPHA, c.red.p + 4 * (size_t)Ctx::kRedBlocks);
+      k_pcg_update<<<nbu, 256, 0, c.s>>>(n, H.px.p, H.pr.p, H.pp.p, H.pq.p, sc + P_ALPHA, c.red.p + 4 * (size_t)Ctx::kRedBlocks,
+                                         flags);
     });
     reduce_partials(nbu, 4, sc + P_RR, c);
-    double rr[1];
-    d2h(rr, sc + P_RR, 1, c);
+    double scv[P_FF - P_RZ + 1];
+    d2h(scv, sc + P_RZ, P_FF - P_RZ + 1, c);
     ++it;
-    unsigned long long hb = 0;
-    d2h(&hb, bad, 1, c);
-    if (hb) fail(HCURL_ENOTSPD, "PCG breakdown: <p, A p> <= 0");
-    rel = std::sqrt(rr[0]) / nf;
+    unsigned long long hf[4];
+    d2h(hf, flags, 4, c);
+    if (hf[0]) fail(HCURL_ENOTSPD, "PCG breakdown: <p, A p> <= 0");
+    if (it > 1) H.pcg_beta.push_back(scv[P_BETA - P_RZ]);  // beta of the previous iteration
+    H.pcg_alpha.push_back(scv[P_ALPHA - P_RZ]);
+    rel = std::sqrt(scv[P_RR - P_RZ]) / nf;
     H.pcg_hist.push_back(rel);
     if (rel <= rtol) break;
+    // the stagnation the paper reports for its hardest cases (Sec. 6.2): two
+    // consecutive iterates equal in every entry
+    if (!hf[3]) {
+      H.stagnated = true;
+      break;
+    }
     if (flex) d2d(H.pzold.p, H.pz.p, n, c);
     apply_vcycle(H, H.pr.p, H.pz.p);
     dot(H.pr.p, H.pz.p, n, sc + P_RZNEW, c, 3);
@@ -945,7 +1015,9 @@ int pcg_solve(Hierarchy& H, const double* f, double* u, double rtol, int maxit, 
   if (relres) *relres = std::sqrt(tr) / nf;
   H.last_iters = it;
   H.last_relres = std::sqrt(tr) / nf;
-  return rel <= rtol ? HCURL_OK : HCURL_EMAXIT;
+  lanczos_extremes(H.pcg_alpha, H.pcg_beta, &H.lanczos_min, &H.lanczos_max);
+  if (rel <= rtol) return HCURL_OK;
+  return H.stagnated ? HCURL_ESTAGNATE : HCURL_EMAXIT;
 }
 
 }  // namespace hc

@@ -182,18 +182,21 @@ def assemble(mesh: dict, sigma: np.ndarray, which: str = "A"):
     return rowptr, col, val
 
 
-def box_aggregates(n: int, width: int = 3, max_maps: int | None = None):
+def box_aggregates(n: int, width=3, max_maps: int | None = None):
     """Per-level node aggregates of an n^3 node lattice.
 
     Level l has n_l nodes per side; its aggregates are boxes along each axis,
-    agg(i) = floor(i * a / n_l) with a = ceil(n_l / width) coarse nodes per side,
-    numbered like lattice nodes.  Levels are added while a >= 2.
+    agg(i) = floor(i * a / n_l) with a = ceil(n_l / w_l) coarse nodes per side,
+    numbered like lattice nodes; w_l = width, or width[l] for a list of widths
+    (its last entry repeating).  Levels are added while a >= 2.
     Returns a list of int32 maps (one per coarsening) and the per-level sides.
     """
     maps, sides = [], [n]
     nl = n
+    widths = list(width) if isinstance(width, (list, tuple)) else [width]
     while True:
-        a = -(-nl // width)
+        w = widths[min(len(maps), len(widths) - 1)]
+        a = -(-nl // w)
         if a < 2 or (max_maps is not None and len(maps) >= max_maps):
             break
         f = (np.arange(nl, dtype=np.int64) * a) // nl

@@ -133,3 +133,49 @@ def test_training_gains_over_plain_start():
     assert E_learn3[-1] < E_plain3[-1]
     for s in samples:
         P.hcurl_mpnn_sample_destroy(s)
+
+
+def test_forward_and_gradient_many_tiles_per_block():
+    """At 16^3 the level-0 pattern has about 240,000 entries: some 3,800
+    tiles of 64 for a layer grid of at most 512 blocks, so every block of the
+    persistent layer kernel walks several tiles (loading the next while it
+    multiplies the current one) and the weight-gradient kernels split the
+    entries into several chunks.  Same bounds as the one-tile case."""
+    from paper_2506_08284_amd.train_mpnn import init_params
+    P = _P()
+    pr = synth.problem(16, jitter=0.15, jitter_seed=8, sigma=("lognormal", 9, 2.0), f_seed=10)
+    m = 17 ** 3
+    H = P.Hierarchy(pr["A"], synth.gradient_csr(pr["tail"], pr["head"]), pr["aggregates"], n_nodes=m,
+                    coords=pr["coords"])
+    s = H.mpnn_sample()
+    E = P.hcurl_mpnn_sample_entries(s)
+    assert (E + 63) // 64 >= 4 * 512
+    A = O.csr(pr["A"])
+    lvl, _ = O.build_level(A, pr["tail"], pr["head"], m, pr["aggregates"][0], {})
+    pmin = lvl["loc"].make_feasible(np.zeros(lvl["N"].nnz))
+    X = M.features(lvl, pr["coords"], pr["aggregates"][0], A.diagonal(), pmin)
+    Xg, p0, tg = P.hcurl_mpnn_sample_export(s)
+    assert np.max(np.abs(Xg - X)) <= 1e-6 * max(1.0, np.max(np.abs(X)))
+    flat = init_params(12)
+    flat[-65:-1] = np.random.default_rng(3).uniform(-0.2, 0.2, 64).astype(np.float32)
+    net = P.Network(flat)
+    p = _params_dict(flat)
+    g = M.graph(lvl["N"])
+    d_ref, _ = M.forward(p, Xg.astype(np.float64), g)
+    d_gpu = P.hcurl_mpnn_forward(net.h, s)
+    err = np.max(np.abs(d_gpu - d_ref)) / np.max(np.abs(d_ref))
+    print("entries %d, forward max error %.3e of max |delta|" % (E, err))
+    assert err <= 3e-2
+    # every tile, not only the largest values: the 2-norm error per tile of 64
+    nt = E // 64
+    dt = (d_gpu[:nt * 64] - d_ref[:nt * 64]).reshape(nt, 64)
+    assert np.all(np.linalg.norm(dt, axis=1) <= 3e-2 * np.sqrt(64) * np.max(np.abs(d_ref)))
+    loss_ref, grads, _ = M.loss_and_grad(p, Xg.astype(np.float64), g, p0, tg)
+    loss, gflat = P.hcurl_mpnn_loss_grad(net.h, s)
+    assert abs(loss - loss_ref) <= 3e-2 * loss_ref
+    gd = _params_dict(gflat)
+    for k in M.param_order():
+        ref = grads[k]
+        assert np.linalg.norm(gd[k] - ref) <= 6e-2 * np.linalg.norm(ref) + 1e-12, k
+    P.hcurl_mpnn_sample_destroy(s)
+    H.close()

@@ -9,6 +9,7 @@ import scipy.sparse as sp
 
 import synth
 from oracle import hcurl_oracle as O
+from tests.stage_parity import library_levels, stage_isolated_check
 
 pytestmark = pytest.mark.gpu
 
@@ -104,28 +105,47 @@ def _cancellation_ratio(lv):
 
 
 @pytest.mark.parametrize("name", list(CASES))
+def test_stage_isolated_parity(name):
+    """Each stage of every level against the oracle fed the library's inputs to
+    that stage (see stage_isolated_check): P_0, P^(e), P^(n) and the energies
+    within 1e-12 relative, R bit for bit, A^(n) and A_H within a few eps of
+    their absolute terms."""
+    pr, m, levels, H = _case(name)
+    for l in range(len(levels) - 1):
+        stage_isolated_check(H, levels, l)
+
+
+@pytest.mark.parametrize("name", list(CASES))
 def test_hierarchy_values_within_tolerance(name):
-    """Tolerances: 1e-12 (A^(n)), 1e-11 (P^(n), R) and 1e-10 (P_0, P^(e),
-    A_H) relative to the largest entry, widened by 100 eps and 1000 eps times
-    the cancellation ratio of the level where that is larger."""
+    """End to end (the oracle's own hierarchy): rounding differences of the
+    first stages reach P^(n) through rho and the Jacobi step, and every later
+    quantity carries them.  Their size is eps times the level's cancellation
+    ratio kappa (the curl-curl part of A cancels in D^T A D only in exact
+    arithmetic).  Tolerances relative to the largest entry: A^(n) max(1e-12,
+    5 eps kappa), P^(n), R max(1e-11, 4 eps kappa), P_0, P^(e) max(1e-10, 4 eps
+    kappa), A_H and energies max(1e-10, eps kappa): ten times the largest
+    error measured on these cases and the 32^3 workload, in units of eps
+    kappa (A^(n) 0.5, P^(n) 0.41, P^(e) 0.42, A_H 0.045, energies 0.076).
+    The stage-isolated test holds every stage to 1e-12 instead."""
     pr, m, levels, H = _case(name)
     for l, lv in enumerate(levels[:-1]):
         info = H.level_info(l)
-        kappa = _cancellation_ratio(lv)
-        t_n = max(1e-11, 100 * EPS * kappa)
-        t_e = max(1e-10, 1000 * EPS * kappa)
+        ek = EPS * _cancellation_ratio(lv)
+        t_n = max(1e-11, 4 * ek)
+        t_e = max(1e-10, 4 * ek)
+        t_h = max(1e-10, ek)
         if "rho" in lv["sa"]:
-            assert abs(info["rho"] - lv["sa"]["rho"]) <= max(1e-10, 100 * EPS * kappa) * lv["sa"]["rho"]
-        _close(_export(H, l, "An"), lv["An"], max(1e-12, 10 * EPS * kappa))
+            assert abs(info["rho"] - lv["sa"]["rho"]) <= t_n * lv["sa"]["rho"]
+        _close(_export(H, l, "An"), lv["An"], max(1e-12, 5 * ek))
         _close(_export(H, l, "Pn"), lv["Pn"], t_n)
         _close(_export(H, l, "R"), lv["R"], t_n)
         _close(_export(H, l, "P0"), O.with_values(lv["N"], lv["p0"]), t_e)
         _close(_export(H, l, "Pe"), lv["Pe"], t_e)
-        _close(_export(H, l + 1, "A"), levels[l + 1]["A"], t_e)
+        _close(_export(H, l + 1, "A"), levels[l + 1]["A"], t_h)
         E = H.export_vec(l, "energy")
         Eo = np.array(lv["energies"])
         assert len(E) == len(Eo)
-        assert np.all(abs(E - Eo) <= t_e * abs(Eo))
+        assert np.all(abs(E - Eo) <= t_h * abs(Eo))
         assert np.all(np.diff(E) <= 0)
 
 
@@ -162,20 +182,36 @@ def test_structure_preservation_on_gpu_output(name):
 
 @pytest.mark.parametrize("name", list(CASES))
 def test_vcycle_and_pcg_parity(name):
+    """V-cycle: on the library's own operators the oracle's V-cycle agrees
+    entry by entry within max(1e-11, eps kappa_0 / 2) of the largest entry
+    (kappa_0: level 0's cancellation ratio; the two sides form the Hiptmair
+    nodal right-hand side D^T (b - A x) in different orders, whose rounding
+    is of that size; largest measured 0.044 eps kappa_0); end to end within
+    1e-8.  PCG: iterations within one, the true residual at 1e-8 and the
+    solution within 1e-9 in the 2-norm and entry by entry (largest measured
+    difference 1e-10)."""
     pr, m, levels, H = _case(name)
     n = pr["A"][0].shape[0] - 1
     r = np.random.default_rng(11).standard_normal(n)
     z = np.empty(n)
     H.vcycle(r, z)
+    zl = O.vcycle(library_levels(H, levels), r)
+    err_iso = np.max(abs(z - zl)) / np.max(abs(zl))
     zo = O.vcycle(levels, r)
-    assert np.linalg.norm(z - zo) <= 1e-8 * np.linalg.norm(zo)
+    err = np.max(abs(z - zo)) / np.max(abs(zo))
+    print("%s: V-cycle max error %.2e on the library's operators, %.2e end to end" % (name, err_iso, err))
+    assert err_iso <= max(1e-11, 0.5 * EPS * _cancellation_ratio(levels[0]))
+    assert err <= 1e-8 and np.linalg.norm(z - zo) <= 1e-8 * np.linalg.norm(zo)
     f = pr["f"]
     u = np.empty(n)
     it, rel, rc = H.solve(f, u, 1e-8, 500)
     uo, ito, relo, _ = O.pcg(levels, f)
+    du = np.linalg.norm(u - uo) / np.linalg.norm(uo)
+    print("%s: PCG %d / %d iterations, solution difference %.2e" % (name, it, ito, du))
     assert rc == 0 and rel <= 1e-8
     assert abs(it - ito) <= 1
-    assert np.linalg.norm(u - uo) <= 1e-6 * np.linalg.norm(uo)
+    assert du <= 1e-9
+    assert np.max(abs(u - uo)) <= 1e-9 * np.max(abs(uo))
 
 
 def test_fp32_vcycle_in_fp64_pcg():
@@ -199,6 +235,41 @@ def test_fp32_vcycle_in_fp64_pcg():
     # FP32 sums of the coarse-level smoothers run in different orders on the
     # two sides; level-0 vectors and all residuals are FP64
     assert err <= 1e-5, err
+
+
+def test_fp32_vcycle_on_launch_swept_levels():
+    """33^3 jittered lognormal cube: level 1 has 10,439 edges, more than the
+    8,192 rows one workgroup sweeps, so the FP32 sweeps below level 0 run one
+    launch per colour (or per run of small colours), and the pre-smoother's
+    first colour from x = 0 is written in one pass on FP32 vectors.  The
+    V-cycle agrees with the oracle's FP32 V-cycle within 1e-5 and PCG with it
+    reaches 1e-8 in at most one iteration more than the FP64 form."""
+    pr = synth.problem(33, jitter=0.2, jitter_seed=21, sigma=("lognormal", 22, 2.0), f_seed=23)
+    m = 34 ** 3
+    P = _lib()
+    Dh = synth.gradient_csr(pr["tail"], pr["head"])
+    H = P.Hierarchy(pr["A"], Dh, pr["aggregates"], n_nodes=m, vcycle_fp32=1)
+    H64 = P.Hierarchy(pr["A"], Dh, pr["aggregates"], n_nodes=m)
+    assert H.stats()["vcycle_fp32"] == 1
+    assert H.level_info(1)["n_edges"] > 8192
+    n = pr["A"][0].shape[0] - 1
+    u = np.empty(n)
+    it, rel, rc = H.solve(pr["f"], u, 1e-8, 500)
+    it64, rel64, _ = H64.solve(pr["f"], np.empty(n), 1e-8, 500)
+    print("FP32 form %d iterations (relres %.2e), FP64 form %d (%.2e)" % (it, rel, it64, rel64))
+    assert rc == 0 and rel <= 1e-8
+    assert it <= it64 + 1
+    levels = O.setup(pr["A"], pr["tail"], pr["head"], m, pr["aggregates"])
+    l32 = O.fp32_levels(levels)
+    r = np.random.default_rng(2).standard_normal(n)
+    z = np.empty(n)
+    H.vcycle(r, z)
+    zo = O.vcycle_fp32(l32, r)
+    err = np.linalg.norm(z - zo) / np.linalg.norm(zo)
+    print("FP32 V-cycle relative error %.3e" % err)
+    assert err <= 1e-5, err
+    H.close()
+    H64.close()
 
 
 @pytest.mark.parametrize("name", list(CASES))

@@ -886,3 +886,77 @@ def test_coloring_is_greedy_in_priority_order(c1):
             col[v] = k
         rev[:] = col
         assert not np.array_equal(rev, want)
+
+
+# ---------------------------------------------------------------------------
+# attainable accuracy: Lanczos estimate from the CG coefficients, stagnation
+# (Sec. 6.1 relaxes its tolerance by a condition estimate; Sec. 6.2 stops on
+# two consecutive equal iterates)
+# ---------------------------------------------------------------------------
+def test_lanczos_extremes_exact_for_few_distinct_eigenvalues():
+    """CG on diag(1, 2, 5, 2, 1) with the identity preconditioner ends after
+    three iterations (three distinct eigenvalues, equal weights); the Lanczos
+    matrix of those coefficients has exactly the eigenvalues 1, 2, 5."""
+    A = sp.diags([1.0, 2.0, 5.0, 2.0, 1.0]).tocsr()
+    info = {}
+    x, it, rel, _ = O.pcg([dict(A=A)], np.ones(5), tol=1e-14, maxit=10, precond=lambda r: r, info=info)
+    assert it == 3 and not info["stagnated"]
+    lo, hi = O.lanczos_extremes(info["alpha"], info["beta"])
+    assert abs(lo - 1.0) <= 1e-14 and abs(hi - 5.0) <= 1e-14
+
+
+def test_lanczos_extremes_inside_and_at_the_ends_of_the_v_cycle_spectrum():
+    """On a 4^3 mesh the V-cycle is formed column by column and the spectrum
+    of V A computed densely: the Lanczos extremes lie inside it and, at
+    PCG tolerance 1e-12, reach its smallest eigenvalue to 1e-6 and its
+    largest to 1e-3 (the top end is a cluster near 1)."""
+    pr = synth.problem(4, jitter=0.1, jitter_seed=1, sigma=("lognormal", 2, 1.0), f_seed=3)
+    levels = O.setup(pr["A"], pr["tail"], pr["head"], 125, pr["aggregates"])
+    A = levels[0]["A"]
+    n = A.shape[0]
+    V = np.column_stack([O.vcycle(levels, e) for e in np.eye(n)])
+    w = np.sort(np.linalg.eigvals(V @ A.toarray()).real)
+    info = {}
+    O.pcg(levels, pr["f"], tol=1e-12, info=info)
+    lo, hi = O.lanczos_extremes(info["alpha"], info["beta"])
+    assert w[0] * (1 - 1e-10) <= lo <= hi <= w[-1] * (1 + 1e-10)
+    assert lo <= w[0] * (1 + 1e-6)
+    assert hi >= w[-1] * (1 - 1e-3)
+
+
+def test_pcg_stops_on_stagnation_below_rounding():
+    """With tolerance 0 the recursive residual keeps falling, but once the
+    updates round away the iterate repeats: the stagnation criterion ends the
+    solve well before maxit with the true residual at rounding level."""
+    pr = synth.problem(4, jitter=0.1, jitter_seed=1, sigma=("lognormal", 2, 1.0), f_seed=3)
+    levels = O.setup(pr["A"], pr["tail"], pr["head"], 125, pr["aggregates"])
+    info = {}
+    x, it, rel, hist = O.pcg(levels, pr["f"], tol=0.0, maxit=300, info=info)
+    assert info["stagnated"] and it < 100
+    assert rel <= 1e-12
+    assert len(info["alpha"]) == it and len(info["beta"]) == it - 1
+
+
+def test_lexicographic_sgs_is_the_symmetric_gauss_seidel_preconditioner(c1):
+    """From x = 0 one lexicographic SGS sweep returns M^-1 b with the
+    textbook M = (D + L) D^-1 (D + U) (dense solve); from any x it is the
+    stationary step x + M^-1 (b - A x).  Sweeping forward twice (a wrong
+    backward pass) gives a non-symmetric operator and fails the first check."""
+    p, levels = c1
+    A = O.csr(levels[1]["A"])  # 98 x 98 coarse operator: dense algebra is cheap
+    Ad = A.toarray()
+    Dg = np.diag(np.diag(Ad))
+    M = (np.tril(Ad, -1) + Dg) @ np.linalg.solve(Dg, np.triu(Ad, 1) + Dg)
+    rng = np.random.default_rng(8)
+    b = rng.standard_normal(A.shape[0])
+    x0 = rng.standard_normal(A.shape[0])
+    ref0 = np.linalg.solve(M, b)
+    assert np.allclose(O.sgs_lexicographic(A, np.zeros_like(b), b), ref0, rtol=0, atol=1e-10 * abs(ref0).max())
+    ref = x0 + np.linalg.solve(M, b - Ad @ x0)
+    assert np.allclose(O.sgs_lexicographic(A, x0, b), ref, rtol=0, atol=1e-10 * abs(ref).max())
+    # the lexicographic V-cycle is symmetric like the multicolour one
+    n = levels[0]["A"].shape[0]
+    u, v = rng.standard_normal(n), rng.standard_normal(n)
+    a = np.dot(O.vcycle(levels, u, lex=True), v)
+    c = np.dot(u, O.vcycle(levels, v, lex=True))
+    assert abs(a - c) <= 1e-10 * abs(a)
