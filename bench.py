@@ -310,9 +310,11 @@ def main():
         extra["plain_fp64_mis2_aggregates"] = r
         log("untimed plain_fp64 with MIS-2 aggregates: %s" % json.dumps(r))
         # the literal six-level hierarchy of this workload (reading R21): box
-        # widths 3, 2, 2, 2, 3 per level (129 -> 43 -> 22 -> 11 -> 6 -> 2 nodes
-        # per side) down to a coarsest level of 19 edges
-        widths = [3, 2, 2, 2, 3]
+        # widths 3, 3, 3, 2, 2 per level (129 -> 43 -> 15 -> 5 -> 3 -> 2 nodes
+        # per side) down to a coarsest level of 19 edges.  (Two-wide boxes
+        # from level 1 on, 3, 2, 2, 2, 3, give level-1 rows whose T_i spans
+        # more than the 32 coarse nodes of the widest local-system layout.)
+        widths = [3, 3, 3, 2, 2]
         maps6, sides6 = synth.box_aggregates(N + 1, widths)
         aggs6 = [torch.from_numpy(a).to(dev) for a in maps6]
         try:

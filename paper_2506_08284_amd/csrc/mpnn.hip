@@ -1,16 +1,26 @@
 // Message-passing network for the learned P^(e) initial guess: per-entry
-// features, BF16 matrix-core (MFMA 32x32x8) dense layers with FP32
+// features, BF16 matrix-core (MFMA 32x32x16) dense layers with FP32
 // accumulation, segment means over pattern rows and columns, MSE loss,
 // backward pass and Adam.
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "mpnn.hpp"
 
 namespace hc {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// one 32x32x16 matrix-core product (gfx950): lane l supplies A[l % 32][k]
+// and B[k][l % 32] for the eight k = k0 + 8 (l / 32) + v, v < 8, read as 16
+// bytes from LDS rows of bf16; any fixed assignment of the k values works as
+// long as A and B use the same one
+__device__ __forceinline__ f32x16 mfma16(const uint16_t* a, const uint16_t* b, f32x16 acc) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)a, *(const bf16x8*)b, acc, 0, 0, 0);
+}
+__device__ __forceinline__ float bf2f(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
   uint32_t u = __float_as_uint(f);
@@ -160,9 +170,8 @@ void mpnn_build_sample(Hierarchy& H, Level& L0, const Level& L1, const double* p
 
 // ---------------------------------------------------------------------------
 // dense layers on the matrix cores.  Tiles of 64 entries x 64 outputs, four
-// waves each computing a 32x32 block with v_mfma_f32_32x32x8_bf16: lane l holds
-// A[l%32][4(l/32)+v], B[4(l/32)+v][l%32], and accumulator r is element
-// (8(r/4) + 4(l/32) + r%4, l%32).
+// waves each computing a 32x32 block with v_mfma_f32_32x32x16_bf16 (mfma16);
+// accumulator r of lane l is element (8(r/4) + 4(l/32) + r%4, l%32).
 // ---------------------------------------------------------------------------
 // Z row of entry e for layer input: MODE 0 the features, MODE 1 the
 // concatenation [h_e, mean_row(i(e)), mean_col(j(e))].
@@ -176,60 +185,66 @@ __device__ __forceinline__ float z_value(int64_t e, int k, const float* __restri
   return mc[(int64_t)col_of[e] * kHD + (k - 2 * kHD)];
 }
 
-// Persistent form of the dense layer: every block loads W^T once and then
-// takes 64-entry tiles in turn.  Each thread stages whole float4 pieces of
-// the Z rows (the h row, the row mean and the column mean are 16 float4 each),
-// all loaded before any is converted, so the tile costs one round of loads.
-// MODE 0: Z = features (K = 16).  MODE 1: Z = [h, mean_row, mean_col]
-// (K = 192), output h + silu(Z W + b).  MODE 2: as MODE 1, and the head
-// delta = h_out . w_out + b_out is formed in place of writing h_out.
-template <int K, int MODE>
-__device__ __forceinline__ void layer_load(int64_t E, int64_t e0, int t, const float* __restrict__ X,
-                                           const float* __restrict__ hin, const float* __restrict__ mr,
-                                           const float* __restrict__ mc, const int* __restrict__ row_of,
-                                           const int* __restrict__ col_of, float4* v) {
-  constexpr int F4 = K / 4;
-  constexpr int PER = 64 * F4 / 256;
+// Storage of the activations: FP32 (training keeps them for the backward
+// pass) or BF16 (inference: the products take BF16 operands anyway, and the
+// layer moves half the bytes).
+__device__ __forceinline__ uint16_t to_store(float v, uint16_t*) { return f2bf(v); }
+__device__ __forceinline__ float to_store(float v, float*) { return v; }
+
+// The Z row of an entry is staged in 16-byte pieces: 4 FP32 or 8 BF16 values
+// of the features (MODE 0) or of [h, mean_row, mean_col] (MODE 1, 2).
+template <int K, int MODE, class IT>
+__device__ __forceinline__ void layer_load(int64_t E, int64_t e0, int t, const IT* __restrict__ zin,
+                                           const IT* __restrict__ mr, const IT* __restrict__ mc,
+                                           const int* __restrict__ row_of, const int* __restrict__ col_of, uint4* v) {
+  constexpr int PW = 16 / sizeof(IT);
+  constexpr int NP = K / PW;
+  constexpr int PER = 64 * NP / 256;
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int j = t + 256 * u;
-    const int r = j / F4, c4 = j - r * F4;
+    const int r = j / NP, kz = (j - r * NP) * PW;
     const int64_t e = e0 + r;
-    v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+    v[u] = make_uint4(0u, 0u, 0u, 0u);
     if (e < E) {
-      const float* src;
+      const IT* src;
       if (MODE == 0) {
-        src = X + e * K + c4 * 4;
+        src = zin + e * K + kz;
       } else {
-        const int seg = c4 >> 4, f = (c4 & 15) * 4;
-        src = seg == 0 ? hin + e * kHD + f
+        const int seg = kz / kHD, f = kz % kHD;
+        src = seg == 0 ? zin + e * kHD + f
                        : seg == 1 ? mr + (int64_t)row_of[e] * kHD + f : mc + (int64_t)col_of[e] * kHD + f;
       }
-      v[u] = *(const float4*)src;
+      v[u] = *(const uint4*)src;
     }
   }
 }
 
-// Persistent form of the dense layer: every block loads W^T once and then
-// takes 64-entry tiles in turn.  Each thread stages whole float4 pieces of
-// the Z rows (the h row, the row mean and the column mean are 16 float4 each);
-// the pieces of the next tile are loaded while the current one is multiplied,
-// and the FP32 h rows of the tile stay in LDS for the residual term.
-// MODE 0: Z = features (K = 16).  MODE 1: Z = [h, mean_row, mean_col]
-// (K = 192), output h + silu(Z W + b).  MODE 2: as MODE 1, and the head
-// delta = h_out . w_out + b_out is formed in place of writing h_out.
-template <int K, int MODE>
-__global__ void __launch_bounds__(256) k_mpnn_layer(int64_t E, const float* __restrict__ X, const float* __restrict__ hin,
-                                                    const float* __restrict__ mr, const float* __restrict__ mc,
+// Persistent form of the dense layer: every block loads W^T into LDS once and
+// then takes 64-entry tiles in turn.  Each thread stages whole 16-byte pieces
+// of the Z rows in LDS; the pieces of the next tile are loaded while the
+// current one is multiplied; the residual term reads the tile's h rows (FP32
+// inputs keep an FP32 copy in LDS).  MODE 0: Z = features (K = 16, FP32).  MODE 1: Z = [h, mean_row,
+// mean_col] (K = 192), output h + silu(Z W + b).  MODE 2: as MODE 1, and the
+// head delta = h_out . w_out + b_out is formed in place of writing h_out.
+// HT: storage type of h and the means (float, or uint16_t holding BF16).
+template <int K, int MODE, class HT>
+__global__ void __launch_bounds__(256) k_mpnn_layer(int64_t E, const float* __restrict__ X, const HT* __restrict__ hin,
+                                                    const HT* __restrict__ mr, const HT* __restrict__ mc,
                                                     const int* __restrict__ row_of, const int* __restrict__ col_of,
                                                     const uint16_t* __restrict__ Wt, const float* __restrict__ bias,
                                                     const float* __restrict__ wout, float* __restrict__ U,
-                                                    float* __restrict__ hout, double* __restrict__ delta) {
+                                                    HT* __restrict__ hout, double* __restrict__ delta) {
+  using IT = typename std::conditional<MODE == 0, float, HT>::type;
+  constexpr bool IBF = sizeof(IT) == 2;
+  constexpr int PW = 16 / sizeof(IT);
+  constexpr int NP = K / PW;
+  constexpr int PER = 64 * NP / 256;
+  static_assert((64 * NP) % 256 == 0 && K % 16 == 0, "tile staging");
   constexpr int KP = K + 8;
-  constexpr int F4 = K / 4;
-  constexpr int PER = 64 * F4 / 256;
-  static_assert((64 * F4) % 256 == 0, "tile staging");
-  constexpr int HR = MODE ? 64 : 1;
+  // FP32 inputs keep their h rows in LDS for the residual; BF16 inputs read
+  // them back from the staged tile (the stored values themselves)
+  constexpr int HR = (MODE && !IBF) ? 64 : 1;
   __shared__ __attribute__((aligned(16))) uint16_t Zs[64][KP];
   __shared__ __attribute__((aligned(16))) uint16_t Ws[64][KP];
   __shared__ __attribute__((aligned(16))) float Hs[HR][kHD + 4];
@@ -242,44 +257,50 @@ __global__ void __launch_bounds__(256) k_mpnn_layer(int64_t E, const float* __re
   const float bcol = bias[col];
   const float wcol = MODE == 2 ? wout[col] : 0.0f;
   const float bout = MODE == 2 ? wout[kHD] : 0.0f;
+  const IT* zin;
+  if constexpr (MODE == 0) zin = X; else zin = hin;
   const int64_t ntiles = (E + 63) / 64;
-  float4 v[PER];
+  uint4 v[PER];
   int64_t tile = blockIdx.x;
-  if (tile < ntiles) layer_load<K, MODE>(E, tile * 64, t, X, hin, mr, mc, row_of, col_of, v);
+  const IT* mri = reinterpret_cast<const IT*>(mr);
+  const IT* mci = reinterpret_cast<const IT*>(mc);
+  if (tile < ntiles) layer_load<K, MODE, IT>(E, tile * 64, t, zin, mri, mci, row_of, col_of, v);
   for (; tile < ntiles; tile += gridDim.x) {
     const int64_t e0 = tile * 64;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int j = t + 256 * u;
-      const int r = j / F4, c4 = j - r * F4;
-      bf16x4 b;
-      b[0] = (short)f2bf(v[u].x);
-      b[1] = (short)f2bf(v[u].y);
-      b[2] = (short)f2bf(v[u].z);
-      b[3] = (short)f2bf(v[u].w);
-      *(bf16x4*)&Zs[r][c4 * 4] = b;
-      if (MODE && c4 < 16) *(float4*)&Hs[r][c4 * 4] = v[u];
+      const int r = j / NP, kz = (j - r * NP) * PW;
+      if constexpr (IBF) {
+        *(uint4*)&Zs[r][kz] = v[u];
+      } else {
+        const float* fv = (const float*)&v[u];
+        uint2 packed;
+        packed.x = (uint32_t)f2bf(fv[0]) | ((uint32_t)f2bf(fv[1]) << 16);
+        packed.y = (uint32_t)f2bf(fv[2]) | ((uint32_t)f2bf(fv[3]) << 16);
+        *(uint2*)&Zs[r][kz] = packed;
+        if (HR > 1 && kz < kHD) *(float4*)&Hs[r][kz] = *(const float4*)fv;
+      }
     }
     __syncthreads();
     // next tile's pieces are in flight during the products and the epilogue
     const int64_t next = tile + gridDim.x;
-    if (next < ntiles) layer_load<K, MODE>(E, next * 64, t, X, hin, mr, mc, row_of, col_of, v);
+    if (next < ntiles) layer_load<K, MODE, IT>(E, next * 64, t, zin, mri, mci, row_of, col_of, v);
     f32x16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
 #pragma unroll
-    for (int kk = 0; kk < K; kk += 8) {
-      const bf16x4 a = *(const bf16x4*)&Zs[mt * 32 + (l & 31)][kk + 4 * (l >> 5)];
-      const bf16x4 b = *(const bf16x4*)&Ws[nt * 32 + (l & 31)][kk + 4 * (l >> 5)];
-      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
-    }
+    for (int kk = 0; kk < K; kk += 16)
+      acc = mfma16(&Zs[mt * 32 + (l & 31)][kk + 8 * (l >> 5)], &Ws[col][kk + 8 * (l >> 5)], acc);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int row = mt * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
       const int64_t e = e0 + row;
       const bool ok = e < E;
       const float u = acc[r] + bcol;
-      const float hv = (MODE ? Hs[MODE ? row : 0][col] : 0.0f) + silu_f(u);
+      float hres = 0.0f;
+      if constexpr (MODE != 0) hres = HR > 1 ? Hs[HR > 1 ? row : 0][col] : bf2f(Zs[row][col]);
+      const float hv = hres + silu_f(u);
       if (MODE == 2) {
         float d = ok ? hv * wcol : 0.0f;
 #pragma unroll
@@ -287,7 +308,7 @@ __global__ void __launch_bounds__(256) k_mpnn_layer(int64_t E, const float* __re
         if ((l & 31) == 0) red[row][nt] = d;
       } else if (ok) {
         if (U) U[e * kHD + col] = u;
-        hout[e * kHD + col] = hv;
+        hout[e * kHD + col] = to_store(hv, hout);
       }
     }
     if (MODE == 2) {
@@ -298,9 +319,10 @@ __global__ void __launch_bounds__(256) k_mpnn_layer(int64_t E, const float* __re
   }
 }
 
+// up to three resident blocks per CU (LDS: two 64-row tiles of bf16)
 static int layer_grid(int64_t E) {
   const int64_t tiles = (E + 63) / 64;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, 256 * 2));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, 256 * 3));
 }
 
 // dZ = du W^T: du (E x 64), W (192 x 64) bf16 row-major, dz (E x 192); grid.y
@@ -325,11 +347,8 @@ __global__ void __launch_bounds__(256) k_mpnn_dz(int64_t E, const float* __restr
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
 #pragma unroll
-  for (int kk = 0; kk < kHD; kk += 8) {
-    const bf16x4 a = *(const bf16x4*)&As[mt * 32 + (l & 31)][kk + 4 * (l >> 5)];
-    const bf16x4 b = *(const bf16x4*)&Bs[nt * 32 + (l & 31)][kk + 4 * (l >> 5)];
-    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
-  }
+  for (int kk = 0; kk < kHD; kk += 16)
+    acc = mfma16(&As[mt * 32 + (l & 31)][kk + 8 * (l >> 5)], &Bs[nt * 32 + (l & 31)][kk + 8 * (l >> 5)], acc);
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int row = mt * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
@@ -382,11 +401,8 @@ __global__ void __launch_bounds__(256) k_mpnn_wgrad(int64_t E, int chunks, const
       if (ti < NT) {
         const int tm = ti >> 1, tn = ti & 1;
 #pragma unroll
-        for (int kk = 0; kk < 64; kk += 8) {
-          const bf16x4 a = *(const bf16x4*)&Zt[tm * 32 + (l & 31)][kk + 4 * (l >> 5)];
-          const bf16x4 b = *(const bf16x4*)&Dt[tn * 32 + (l & 31)][kk + 4 * (l >> 5)];
-          acc[s] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[s], 0, 0, 0);
-        }
+        for (int kk = 0; kk < 64; kk += 16)
+          acc[s] = mfma16(&Zt[tm * 32 + (l & 31)][kk + 8 * (l >> 5)], &Dt[tn * 32 + (l & 31)][kk + 8 * (l >> 5)], acc[s]);
       }
     }
     __syncthreads();
@@ -418,10 +434,14 @@ __global__ void k_sum_blocks(const float* __restrict__ part, int nb, int stride,
 }
 
 // mean over segments: dst[s][f] = mean of src[e][off + f] over the segment's
-// entries (idx maps positions to entries, NULL = identity); one wave per segment
+// entries (idx maps positions to entries, NULL = identity); one wave per
+// segment, sums in FP32 whatever the storage type T
+__device__ __forceinline__ float ld_f(const float* p) { return *p; }
+__device__ __forceinline__ float ld_f(const uint16_t* p) { return bf2f(*p); }
+template <class T>
 __global__ void __launch_bounds__(256) k_seg_mean(int nseg, const int* __restrict__ ptr, const int* __restrict__ idx,
-                                                  const float* __restrict__ src, int stride, int off,
-                                                  float* __restrict__ dst) {
+                                                  const T* __restrict__ src, int stride, int off,
+                                                  T* __restrict__ dst) {
   const int sgi = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int f = threadIdx.x & 63;
   if (sgi >= nseg) return;
@@ -432,14 +452,14 @@ __global__ void __launch_bounds__(256) k_seg_mean(int nseg, const int* __restric
   for (; q + 3 < b; q += 4) {
     const int64_t e0 = idx ? idx[q] : q, e1 = idx ? idx[q + 1] : q + 1;
     const int64_t e2 = idx ? idx[q + 2] : q + 2, e3 = idx ? idx[q + 3] : q + 3;
-    acc0 += src[e0 * stride + off + f];
-    acc1 += src[e1 * stride + off + f];
-    acc2 += src[e2 * stride + off + f];
-    acc3 += src[e3 * stride + off + f];
+    acc0 += ld_f(src + e0 * stride + off + f);
+    acc1 += ld_f(src + e1 * stride + off + f);
+    acc2 += ld_f(src + e2 * stride + off + f);
+    acc3 += ld_f(src + e3 * stride + off + f);
   }
-  for (; q < b; ++q) acc0 += src[(idx ? idx[q] : q) * (int64_t)stride + off + f];
+  for (; q < b; ++q) acc0 += ld_f(src + (idx ? idx[q] : q) * (int64_t)stride + off + f);
   const float acc = (acc0 + acc1) + (acc2 + acc3);
-  dst[(int64_t)sgi * kHD + f] = b > a ? acc / (float)(b - a) : 0.0f;
+  dst[(int64_t)sgi * kHD + f] = to_store(b > a ? acc / (float)(b - a) : 0.0f, dst);
 }
 
 // delta_e = h_e . w_out + b_out; with training: residual, loss, dh = dd w_out,
@@ -529,56 +549,85 @@ void Net::refresh_bf16(Ctx& c) {
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-static void row_mean(Sample& S, const float* src, int stride, int off, float* mr, Ctx& c) {
-  c.run("mpnn_segment_mean", 8.0 * S.E * kHD, [&] {
-    k_seg_mean<<<ceil_div((int64_t)S.nrow * 64, 256), 256, 0, c.s>>>(S.nrow, S.rowptr.p, nullptr, src, stride, off, mr);
+template <class T>
+static void row_mean(Sample& S, const T* src, int stride, int off, T* mr, Ctx& c) {
+  c.run("mpnn_segment_mean", (4.0 + sizeof(T)) * S.E * kHD, [&] {
+    k_seg_mean<T><<<ceil_div((int64_t)S.nrow * 64, 256), 256, 0, c.s>>>(S.nrow, S.rowptr.p, nullptr, src, stride, off, mr);
   });
 }
-static void col_mean(Sample& S, const float* src, int stride, int off, float* mc, Ctx& c) {
-  c.run("mpnn_segment_mean", 8.0 * S.E * kHD, [&] {
-    k_seg_mean<<<ceil_div((int64_t)S.ncol * 64, 256), 256, 0, c.s>>>(S.ncol, S.colptr.p, S.colidx.p, src, stride, off, mc);
+template <class T>
+static void col_mean(Sample& S, const T* src, int stride, int off, T* mc, Ctx& c) {
+  c.run("mpnn_segment_mean", (4.0 + sizeof(T)) * S.E * kHD, [&] {
+    k_seg_mean<T><<<ceil_div((int64_t)S.ncol * 64, 256), 256, 0, c.s>>>(S.ncol, S.colptr.p, S.colidx.p, src, stride, off, mc);
   });
+}
+
+// The layers on activation buffers of storage type HT: h[l] / h[l + 1] are
+// the input and output of layer l, mr[l] / mc[l] its row and column means.
+// With `keep` (training) every buffer is distinct and the pre-activations go
+// to S.u; otherwise buffers alternate and the head is fused into the last
+// layer.
+template <class HT>
+static void forward_layers(Net& net, Sample& S, Ctx& c, bool keep, HT* const* h, HT* const* mr, HT* const* mc) {
+  const int64_t E = S.E;
+  const int lg = layer_grid(E);
+  c.run("mpnn_dense_in_flop", 2.0 * E * kNF * kHD, [&] {
+    k_mpnn_layer<kNF, 0, HT><<<lg, 256, 0, c.s>>>(E, S.X.p, nullptr, nullptr, nullptr, nullptr, nullptr, net.wt_in.p,
+                                                  net.w.p + kOffBin, nullptr, keep ? S.u[0].p : nullptr, h[0], nullptr);
+  });
+  for (int l = 0; l < kNL; ++l) {
+    HT* hin = h[l];
+    HT* hout = h[l + 1];
+    row_mean(S, (const HT*)hin, kHD, 0, mr[l], c);
+    col_mean(S, (const HT*)hin, kHD, 0, mc[l], c);
+    const bool last_fused = !keep && l == kNL - 1;  // inference: the head is formed in the last layer
+    c.run("mpnn_dense_flop", 2.0 * E * kKZ * kHD, [&] {
+      if (last_fused)
+        k_mpnn_layer<kKZ, 2, HT><<<lg, 256, 0, c.s>>>(E, nullptr, hin, mr[l], mc[l], S.row_of.p, S.col_of.p, net.wt[l].p,
+                                                      net.w.p + off_b(l), net.w.p + kOffWout, nullptr, nullptr, S.delta.p);
+      else
+        k_mpnn_layer<kKZ, 1, HT><<<lg, 256, 0, c.s>>>(E, nullptr, hin, mr[l], mc[l], S.row_of.p, S.col_of.p, net.wt[l].p,
+                                                      net.w.p + off_b(l), nullptr, keep ? S.u[l + 1].p : nullptr, hout,
+                                                      nullptr);
+    });
+  }
 }
 
 void mpnn_forward(Net& net, Sample& S, Ctx& c, bool keep) {
   const int64_t E = S.E;
-  const int nbuf = keep ? kNL + 1 : 2;
-  for (int k = 0; k < nbuf; ++k) {
-    if (S.h[k].n != (size_t)(E * kHD)) S.h[k].alloc(E * kHD, c.s);
-    if (keep && S.u[k].n != (size_t)(E * kHD)) S.u[k].alloc(E * kHD, c.s);
-  }
-  for (int l = 0; l < (keep ? kNL : 1); ++l) {
-    if (S.mr[l].n != (size_t)S.nrow * kHD) S.mr[l].alloc((size_t)S.nrow * kHD, c.s);
-    if (S.mc[l].n != (size_t)S.ncol * kHD) S.mc[l].alloc((size_t)S.ncol * kHD, c.s);
-  }
   if (S.delta.n != (size_t)E) S.delta.alloc(E, c.s);
-  const int lg = layer_grid(E);
-  c.run("mpnn_dense_in_flop", 2.0 * E * kNF * kHD, [&] {
-    k_mpnn_layer<kNF, 0><<<lg, 256, 0, c.s>>>(E, S.X.p, nullptr, nullptr, nullptr, nullptr, nullptr, net.wt_in.p,
-                                              net.w.p + kOffBin, nullptr, keep ? S.u[0].p : nullptr, S.h[0].p, nullptr);
-  });
-  for (int l = 0; l < kNL; ++l) {
-    float* hin = keep ? S.h[l].p : S.h[l & 1].p;
-    float* hout = keep ? S.h[l + 1].p : S.h[(l + 1) & 1].p;
-    float* mr = keep ? S.mr[l].p : S.mr[0].p;
-    float* mc = keep ? S.mc[l].p : S.mc[0].p;
-    row_mean(S, hin, kHD, 0, mr, c);
-    col_mean(S, hin, kHD, 0, mc, c);
-    const bool last_fused = !keep && l == kNL - 1;  // inference: the head is formed in the last layer
-    c.run("mpnn_dense_flop", 2.0 * E * kKZ * kHD, [&] {
-      if (last_fused)
-        k_mpnn_layer<kKZ, 2><<<lg, 256, 0, c.s>>>(E, nullptr, hin, mr, mc, S.row_of.p, S.col_of.p, net.wt[l].p,
-                                                  net.w.p + off_b(l), net.w.p + kOffWout, nullptr, nullptr, S.delta.p);
-      else
-        k_mpnn_layer<kKZ, 1><<<lg, 256, 0, c.s>>>(E, nullptr, hin, mr, mc, S.row_of.p, S.col_of.p, net.wt[l].p,
-                                                  net.w.p + off_b(l), nullptr, keep ? S.u[l + 1].p : nullptr, hout, nullptr);
-    });
-  }
   if (keep) {
+    // training: FP32 activations, all kept for the backward pass
+    for (int k = 0; k <= kNL; ++k) {
+      if (S.h[k].n != (size_t)(E * kHD)) S.h[k].alloc(E * kHD, c.s);
+      if (S.u[k].n != (size_t)(E * kHD)) S.u[k].alloc(E * kHD, c.s);
+    }
+    for (int l = 0; l < kNL; ++l) {
+      if (S.mr[l].n != (size_t)S.nrow * kHD) S.mr[l].alloc((size_t)S.nrow * kHD, c.s);
+      if (S.mc[l].n != (size_t)S.ncol * kHD) S.mc[l].alloc((size_t)S.ncol * kHD, c.s);
+    }
+    float* h[kNL + 1];
+    float* mr[kNL];
+    float* mc[kNL];
+    for (int k = 0; k <= kNL; ++k) h[k] = S.h[k].p;
+    for (int l = 0; l < kNL; ++l) { mr[l] = S.mr[l].p; mc[l] = S.mc[l].p; }
+    forward_layers<float>(net, S, c, true, h, mr, mc);
     c.run("mpnn_head", 4.0 * E * kHD, [&] {
       k_head<<<1024, 256, 0, c.s>>>(E, S.h[kNL].p, net.w.p + kOffWout, nullptr, nullptr, S.delta.p, nullptr, nullptr);
     });
+    return;
   }
+  // inference: BF16 activations in two alternating buffers
+  for (int k = 0; k < 2; ++k)
+    if (S.hb[k].n != (size_t)(E * kHD)) S.hb[k].alloc(E * kHD, c.s);
+  if (S.mrb.n != (size_t)S.nrow * kHD) S.mrb.alloc((size_t)S.nrow * kHD, c.s);
+  if (S.mcb.n != (size_t)S.ncol * kHD) S.mcb.alloc((size_t)S.ncol * kHD, c.s);
+  uint16_t* h[kNL + 1];
+  uint16_t* mr[kNL];
+  uint16_t* mc[kNL];
+  for (int k = 0; k <= kNL; ++k) h[k] = S.hb[k & 1].p;
+  for (int l = 0; l < kNL; ++l) { mr[l] = S.mrb.p; mc[l] = S.mcb.p; }
+  forward_layers<uint16_t>(net, S, c, false, h, mr, mc);
 }
 
 double mpnn_loss_grad(Net& net, Sample& S, Ctx& c) {

@@ -40,6 +40,8 @@ struct Sample {
   // activations kept for the backward pass
   DBuf<float> h[kNL + 1], u[kNL + 1], mr[kNL], mc[kNL];
   DBuf<float> dh, du, dz, mdr, mdc;
+  // inference: BF16 activations (alternating) and means
+  DBuf<uint16_t> hb[2], mrb, mcb;
   DBuf<double> delta;
   // activations are transient: released after every forward / training step
   void release_workspace() {
@@ -48,6 +50,8 @@ struct Sample {
     for (auto& b : mr) b.release();
     for (auto& b : mc) b.release();
     dh.release(); du.release(); dz.release(); mdr.release(); mdc.release();
+    for (auto& b : hb) b.release();
+    mrb.release(); mcb.release();
   }
 };
 

@@ -88,7 +88,7 @@ def test_cube32_incl_whole_hierarchy():
         assert np.array_equal(H.export_vec(l, "colors_A"), lv["colors_A"])
         assert np.array_equal(H.export_vec(l, "colors_An"), lv["colors_An"])
         # every stage against the oracle fed the library's inputs of that stage
-        err = stage_isolated_check(H, levels, l)
+        err = stage_isolated_check(H, levels, l)["err"]
         # end to end: tolerances from the level's cancellation ratio (as in
         # the small-case parity tests; the largest measured errors there and
         # here are 0.42 eps kappa for P^(e))
