@@ -349,6 +349,13 @@ static int gs_lpr(double avg) { return avg <= 20 ? 8 : avg <= 48 ? 16 : 32; }
 // their equations after the forward pass, so repeating it is a no-op); a run
 // of two or more consecutive colours in one direction whose classes have at
 // most `tiny` rows goes to one chain launch.
+// Colour classes of at most this many rows go into single-workgroup chain
+// launches: one pass of the workgroup per class.  (Classes of up to four
+// passes measured no faster at 128^3: 4.01 against 3.95 ms for the coarse
+// levels of a V-cycle.)
+static constexpr int kChainPasses = 1;
+static int chain_rows(int lpr) { return kChainPasses * 1024 / lpr; }
+
 template <class F, class G>
 static void sweep_plan(const std::vector<int>& cptr, int ncol, int tiny, F&& single, G&& chain, int first = 0) {
   auto pass = [&](int first, int last, int dir) {
@@ -375,8 +382,12 @@ void plan_chains(const Csr& Acm, const DBuf<int>& rows, const std::vector<int>& 
                  std::vector<ChainRun>& out, Ctx& c) {
   out.clear();
   if (Acm.nrows <= kSmallRows || Acm.nrows == 0) return;
-  const int tiny = 1024 / gs_lpr((double)Acm.nnz / Acm.nrows);
-  sweep_plan(cptr, ncol, tiny, [](int) {}, [&](int k0, int nk, int dir) {
+  const int tiny = chain_rows(gs_lpr((double)Acm.nnz / Acm.nrows));
+  // the runs of a sweep from colour 0 and of one whose first colour was
+  // written by k_gs_first_colour (forward pass from colour 1)
+  auto add_run = [&](int k0, int nk, int dir) {
+    for (const ChainRun& r : out)
+      if (r.k0 == k0 && r.nk == nk && r.dir == dir) return;
     ChainRun R;
     R.k0 = k0;
     R.nk = nk;
@@ -410,7 +421,9 @@ void plan_chains(const Csr& Acm, const DBuf<int>& rows, const std::vector<int>& 
       h2d(R.lrow.p, lr.data(), nr, c);
     }
     out.push_back(std::move(R));
-  });
+  };
+  sweep_plan(cptr, ncol, tiny, [](int) {}, add_run, 0);
+  sweep_plan(cptr, ncol, tiny, [](int) {}, add_run, 1);
 }
 
 // Algorithmic bytes of one colour launch: the rows' CSR data (column and
@@ -463,7 +476,7 @@ static void sgs_t(const Csr& A, const V* val, const T* dinv, const DBuf<int>& ro
       c.run(tag, bytes, [&] { k_gs_chain<V, T, 32><<<1, 1024, 0, c.s>>>(k0, nk, dir, cptr_d.p, rows.p, A.rowptr.p, A.col.p, val, dinv, b, x); });
   };
   // first = 1: the caller has swept colour 0 already (k_gs_first_colour)
-  sweep_plan(cptr, ncol, 1024 / lpr, launch, chain, first);
+  sweep_plan(cptr, ncol, chain_rows(lpr), launch, chain, first);
 }
 
 // x += D c  with D given by its endpoints: x_e += c[head] - c[tail]
