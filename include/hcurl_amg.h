@@ -409,6 +409,13 @@ int64_t hcurl_mpnn_num_params(void);
 /* params: host array of hcurl_mpnn_num_params() floats, copied. */
 int hcurl_mpnn_create(const float* params, void* stream, hcurl_mpnn* out);
 int hcurl_mpnn_get_params(hcurl_mpnn net, float* params);
+/* Debug form of the dense products (on = 1): FP32 operands and master weights
+ * with plain FMAs in place of BF16 matrix-core products (weight gradients
+ * summed over the entries in FP64).  Forward, loss and gradients then agree
+ * with an FP64 evaluation of the same network to about 1e-5, which checks the
+ * structure of the forward and backward kernels apart from BF16 rounding.
+ * Slow: one thread per output.  on = 0 restores the BF16 products. */
+int hcurl_mpnn_set_fp32_products(hcurl_mpnn net, int on);
 void hcurl_mpnn_destroy(hcurl_mpnn net);
 
 /* Training sample from a hierarchy built with HCURL_INIT_ONES and coords:

@@ -35,6 +35,7 @@ EXPORTED_SYMBOLS = [
     "hcurl_amg_export_csr", "hcurl_amg_export_vec",
     "hcurl_amg_stats", "hcurl_amg_kernel_stats", "hcurl_amg_reset_kernel_stats", "hcurl_last_error",
     "hcurl_error_string", "hcurl_mpnn_num_params", "hcurl_mpnn_create", "hcurl_mpnn_get_params", "hcurl_mpnn_destroy",
+    "hcurl_mpnn_set_fp32_products",
     "hcurl_amg_mpnn_sample", "hcurl_mpnn_sample_entries", "hcurl_mpnn_sample_export", "hcurl_mpnn_sample_destroy",
     "hcurl_mpnn_forward", "hcurl_mpnn_loss_grad", "hcurl_mpnn_train_step",
 ]
@@ -168,6 +169,8 @@ def _load():
     L.hcurl_mpnn_create.restype = ctypes.c_int
     L.hcurl_mpnn_get_params.argtypes = [P, P]
     L.hcurl_mpnn_get_params.restype = ctypes.c_int
+    L.hcurl_mpnn_set_fp32_products.argtypes = [P, ctypes.c_int]
+    L.hcurl_mpnn_set_fp32_products.restype = ctypes.c_int
     L.hcurl_mpnn_destroy.argtypes = [P]
     L.hcurl_mpnn_destroy.restype = None
     L.hcurl_amg_mpnn_sample.argtypes = [P, ctypes.POINTER(P)]
@@ -479,6 +482,10 @@ class Network:
 
     def params(self):
         return hcurl_mpnn_get_params(self.h)
+
+    def set_fp32_products(self, on: bool = True):
+        """Debug: FP32-operand dense products (hcurl_mpnn_set_fp32_products)."""
+        _check(lib.hcurl_mpnn_set_fp32_products(self.h, 1 if on else 0))
 
     def close(self):
         if self.h:

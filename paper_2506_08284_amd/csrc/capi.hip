@@ -492,6 +492,12 @@ int hcurl_mpnn_get_params(hcurl_mpnn net, float* params) {
   });
 }
 
+int hcurl_mpnn_set_fp32_products(hcurl_mpnn net, int on) {
+  if (!net || (on != 0 && on != 1)) return HCURL_EINVAL;
+  net->net.fp32_products = on == 1;
+  return HCURL_OK;
+}
+
 void hcurl_mpnn_destroy(hcurl_mpnn net) {
   if (!net) return;
   try { (void)hipStreamSynchronize(net->net.ctx.s); } catch (...) {}

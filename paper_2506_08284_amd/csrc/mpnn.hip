@@ -562,6 +562,47 @@ static void col_mean(Sample& S, const T* src, int stride, int off, T* mc, Ctx& c
   });
 }
 
+// Debug form of the dense products (Net::fp32_products): FP32 operands and
+// master weights, no BF16 rounding, plain FMAs; the long reductions over the
+// entries (weight gradients) accumulate in FP64.  One thread per output.
+template <int K, int MODE>
+__global__ void k_dense_f32(int64_t E, const float* __restrict__ X, const float* __restrict__ hin,
+                            const float* __restrict__ mr, const float* __restrict__ mc, const int* __restrict__ row_of,
+                            const int* __restrict__ col_of, const float* __restrict__ W, const float* __restrict__ bias,
+                            float* __restrict__ U, float* __restrict__ hout) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= E * kHD) return;
+  const int64_t e = q / kHD;
+  const int col = (int)(q % kHD);
+  float u = bias[col];
+  for (int k = 0; k < K; ++k) u += z_value<K, MODE>(e, k, X, hin, mr, mc, row_of, col_of) * W[k * kHD + col];
+  U[q] = u;
+  hout[q] = (MODE ? hin[q] : 0.0f) + silu_f(u);
+}
+// dz[e][k] = sum_h du[e][h] W[k][h], k < 192
+__global__ void k_dz_f32(int64_t E, const float* __restrict__ du, const float* __restrict__ W, float* __restrict__ dz) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= E * kKZ) return;
+  const int64_t e = q / kKZ;
+  const int k = (int)(q % kKZ);
+  float s = 0.0f;
+  for (int h = 0; h < kHD; ++h) s += du[e * kHD + h] * W[k * kHD + h];
+  dz[q] = s;
+}
+// g[k][h] = sum_e Z[e][k] du[e][h] for k < K, and g[K][h] = sum_e du[e][h]
+template <int K, int MODE>
+__global__ void k_wgrad_f32(int64_t E, const float* __restrict__ X, const float* __restrict__ hin,
+                            const float* __restrict__ mr, const float* __restrict__ mc, const int* __restrict__ row_of,
+                            const int* __restrict__ col_of, const float* __restrict__ du, float* __restrict__ g) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (K + 1) * kHD) return;
+  const int k = q / kHD, h = q % kHD;
+  double s = 0.0;
+  for (int64_t e = 0; e < E; ++e)
+    s += (double)(k < K ? z_value<K, MODE>(e, k, X, hin, mr, mc, row_of, col_of) : 1.0f) * (double)du[e * kHD + h];
+  g[q] = (float)s;
+}
+
 // The layers on activation buffers of storage type HT: h[l] / h[l + 1] are
 // the input and output of layer l, mr[l] / mc[l] its row and column means.
 // With `keep` (training) every buffer is distinct and the pre-activations go
@@ -596,7 +637,7 @@ static void forward_layers(Net& net, Sample& S, Ctx& c, bool keep, HT* const* h,
 void mpnn_forward(Net& net, Sample& S, Ctx& c, bool keep) {
   const int64_t E = S.E;
   if (S.delta.n != (size_t)E) S.delta.alloc(E, c.s);
-  if (keep) {
+  if (keep || net.fp32_products) {
     // training: FP32 activations, all kept for the backward pass
     for (int k = 0; k <= kNL; ++k) {
       if (S.h[k].n != (size_t)(E * kHD)) S.h[k].alloc(E * kHD, c.s);
@@ -611,7 +652,21 @@ void mpnn_forward(Net& net, Sample& S, Ctx& c, bool keep) {
     float* mc[kNL];
     for (int k = 0; k <= kNL; ++k) h[k] = S.h[k].p;
     for (int l = 0; l < kNL; ++l) { mr[l] = S.mr[l].p; mc[l] = S.mc[l].p; }
-    forward_layers<float>(net, S, c, true, h, mr, mc);
+    if (net.fp32_products) {
+      const int g = ceil_div(E * kHD, 256);
+      k_dense_f32<kNF, 0><<<g, 256, 0, c.s>>>(E, S.X.p, nullptr, nullptr, nullptr, nullptr, nullptr, net.w.p + kOffWin,
+                                              net.w.p + kOffBin, S.u[0].p, h[0]);
+      HC_LAUNCH_CHECK();
+      for (int l = 0; l < kNL; ++l) {
+        row_mean(S, (const float*)h[l], kHD, 0, mr[l], c);
+        col_mean(S, (const float*)h[l], kHD, 0, mc[l], c);
+        k_dense_f32<kKZ, 1><<<g, 256, 0, c.s>>>(E, nullptr, h[l], mr[l], mc[l], S.row_of.p, S.col_of.p, net.w.p + off_W(l),
+                                                net.w.p + off_b(l), S.u[l + 1].p, h[l + 1]);
+        HC_LAUNCH_CHECK();
+      }
+    } else {
+      forward_layers<float>(net, S, c, true, h, mr, mc);
+    }
     c.run("mpnn_head", 4.0 * E * kHD, [&] {
       k_head<<<1024, 256, 0, c.s>>>(E, S.h[kNL].p, net.w.p + kOffWout, nullptr, nullptr, S.delta.p, nullptr, nullptr);
     });
@@ -656,15 +711,23 @@ double mpnn_loss_grad(Net& net, Sample& S, Ctx& c) {
   const int nb = ceil_div(E, 64);
   for (int l = kNL - 1; l >= 0; --l) {
     c.run("mpnn_du", 12.0 * E * kHD, [&] { k_du<<<ceil_div(E * kHD, 256), 256, 0, c.s>>>(E * kHD, S.dh.p, S.u[l + 1].p, S.du.p); });
-    c.run("mpnn_dense_wgrad_flop", 2.0 * E * kKZ * kHD, [&] {
-      k_mpnn_wgrad<kKZ, 1><<<nbw, 256, 0, c.s>>>(E, chunks, nullptr, S.h[l].p, S.mr[l].p, S.mc[l].p, S.row_of.p,
-                                                 S.col_of.p, S.du.p, wpart.p);
-    });
-    k_sum_blocks<<<ceil_div(kKZ * kHD + kHD, 256), 256, 0, c.s>>>(wpart.p, nbw, kKZ * kHD + kHD, net.g.p + off_W(l));
-    HC_LAUNCH_CHECK();
-    c.run("mpnn_dense_dz_flop", 2.0 * E * kKZ * kHD, [&] {
-      k_mpnn_dz<<<dim3(nb, 3), 256, 0, c.s>>>(E, S.du.p, net.wr[l].p, S.dz.p);
-    });
+    if (net.fp32_products) {
+      k_wgrad_f32<kKZ, 1><<<ceil_div((kKZ + 1) * kHD, 256), 256, 0, c.s>>>(E, nullptr, S.h[l].p, S.mr[l].p, S.mc[l].p,
+                                                                          S.row_of.p, S.col_of.p, S.du.p,
+                                                                          net.g.p + off_W(l));
+      k_dz_f32<<<ceil_div(E * kKZ, 256), 256, 0, c.s>>>(E, S.du.p, net.w.p + off_W(l), S.dz.p);
+      HC_LAUNCH_CHECK();
+    } else {
+      c.run("mpnn_dense_wgrad_flop", 2.0 * E * kKZ * kHD, [&] {
+        k_mpnn_wgrad<kKZ, 1><<<nbw, 256, 0, c.s>>>(E, chunks, nullptr, S.h[l].p, S.mr[l].p, S.mc[l].p, S.row_of.p,
+                                                   S.col_of.p, S.du.p, wpart.p);
+      });
+      k_sum_blocks<<<ceil_div(kKZ * kHD + kHD, 256), 256, 0, c.s>>>(wpart.p, nbw, kKZ * kHD + kHD, net.g.p + off_W(l));
+      HC_LAUNCH_CHECK();
+      c.run("mpnn_dense_dz_flop", 2.0 * E * kKZ * kHD, [&] {
+        k_mpnn_dz<<<dim3(nb, 3), 256, 0, c.s>>>(E, S.du.p, net.wr[l].p, S.dz.p);
+      });
+    }
     // adjoints of the gathered means: average the row slice over rows and
     // the column slice over columns
     row_mean(S, S.dz.p, kKZ, kHD, S.mdr.p, c);
@@ -675,11 +738,16 @@ double mpnn_loss_grad(Net& net, Sample& S, Ctx& c) {
   }
   // input layer
   c.run("mpnn_du", 12.0 * E * kHD, [&] { k_du<<<ceil_div(E * kHD, 256), 256, 0, c.s>>>(E * kHD, S.dh.p, S.u[0].p, S.du.p); });
-  c.run("mpnn_dense_wgrad_flop", 2.0 * E * kNF * kHD, [&] {
-    k_mpnn_wgrad<kNF, 0><<<nbw, 256, 0, c.s>>>(E, chunks, S.X.p, nullptr, nullptr, nullptr, nullptr, nullptr, S.du.p,
-                                               wpart.p);
-  });
-  k_sum_blocks<<<ceil_div(kNF * kHD + kHD, 256), 256, 0, c.s>>>(wpart.p, nbw, kNF * kHD + kHD, net.g.p + kOffWin);
+  if (net.fp32_products) {
+    k_wgrad_f32<kNF, 0><<<ceil_div((kNF + 1) * kHD, 256), 256, 0, c.s>>>(E, S.X.p, nullptr, nullptr, nullptr, nullptr,
+                                                                        nullptr, S.du.p, net.g.p + kOffWin);
+  } else {
+    c.run("mpnn_dense_wgrad_flop", 2.0 * E * kNF * kHD, [&] {
+      k_mpnn_wgrad<kNF, 0><<<nbw, 256, 0, c.s>>>(E, chunks, S.X.p, nullptr, nullptr, nullptr, nullptr, nullptr, S.du.p,
+                                                 wpart.p);
+    });
+    k_sum_blocks<<<ceil_div(kNF * kHD + kHD, 256), 256, 0, c.s>>>(wpart.p, nbw, kNF * kHD + kHD, net.g.p + kOffWin);
+  }
   HC_LAUNCH_CHECK();
   c.sync();
   return loss;

@@ -25,6 +25,7 @@ struct Net {
   DBuf<uint16_t> wt_in;    // W_in^T (64 x 16) bf16
   DBuf<uint16_t> wt[kNL];  // W_l^T (64 x 192) bf16, forward products
   DBuf<uint16_t> wr[kNL];  // W_l   (192 x 64) bf16, input-gradient products
+  bool fp32_products = false;  // debug: FP32-operand products (hcurl_mpnn_set_fp32_products)
   void refresh_bf16(Ctx& c);
 };
 

@@ -524,6 +524,7 @@ __global__ void k_gs_first_colour(int n, const int* __restrict__ color, const do
 
 // Levels that sweep by launches; the others sweep in one workgroup
 static bool swept_by_launches(const Level& L) { return L.Acm.nrows > kSmallLevel; }
+static bool nodes_swept_by_launches(const Level& L) { return L.Ancm.nrows > kSmallLevel; }
 
 // x_zero: x is to start from zero (the pre-smoother of a V-cycle visit); on
 // levels swept by launches the first sweep then writes x itself.
@@ -543,9 +544,19 @@ static void hiptmair64(Level& L, bool fine, double* x, const double* b, const do
   }
   // nodal right-hand side D^T (b - A x) = D^T b - (D^T A) x
   spmv(L.DTA, x, L.rn.p, dtb, 1, c, fine ? "nodal_residual_l0" : "nodal_residual");
-  fill(L.cn.p, 0.0, L.m, c);
-  if (fine) sgs_t<double, double, 2>(L.Ancm, L.Ancm.val.p, L.dinvAncm.p, L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.chainsAn, L.rn.p, L.cn.p, c, "sgs_node_l0");
-  else sgs_t<double, double, 0>(L.Ancm, L.Ancm.val.p, L.dinvAncm.p, L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.chainsAn, L.rn.p, L.cn.p, c, "sgs_node");
+  // the nodal sweep starts from c = 0: its first colour is written in one pass
+  // with the zero fill where the level is swept by launches
+  int nfirst = 0;
+  if (nodes_swept_by_launches(L)) {
+    c.run(fine ? "sgs_node_first_l0" : "sgs_node_first", 28.0 * L.m, [&] {
+      k_gs_first_colour<double><<<ceil_div(L.m, 256), 256, 0, c.s>>>(L.m, L.colorAn.p, L.dinvAn.p, L.rn.p, L.cn.p);
+    });
+    nfirst = 1;
+  } else {
+    fill(L.cn.p, 0.0, L.m, c);
+  }
+  if (fine) sgs_t<double, double, 2>(L.Ancm, L.Ancm.val.p, L.dinvAncm.p, L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.chainsAn, L.rn.p, L.cn.p, c, "sgs_node_l0", nfirst);
+  else sgs_t<double, double, 0>(L.Ancm, L.Ancm.val.p, L.dinvAncm.p, L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.chainsAn, L.rn.p, L.cn.p, c, "sgs_node", nfirst);
   c.run("grad_add", 24.0 * L.n, [&] { k_grad_add<double><<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, L.n, L.cn.p, x); });
   edge(0);
 }
@@ -597,9 +608,17 @@ static void hiptmair32(Level& L, bool fine, T* x, const T* b, const T* dtb, Ctx&
   }
   // nodal right-hand side D^T b - (D^T A) x with the FP64 operator
   spmv_v64<T, T>(L.DTA, x, F::rn(L), dtb, 1, c, fine ? "nodal_residual32_l0" : "nodal_residual32");
-  fill_t(F::cn(L), T(0), L.m, c);
-  if (fine) sgs_t<float, T, 2>(L.Ancm, L.Ancm.val32.p, F::dAn(L), L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.chainsAn, F::rn(L), F::cn(L), c, "sgs_node32_l0");
-  else sgs_t<float, T, 0>(L.Ancm, L.Ancm.val32.p, F::dAn(L), L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.chainsAn, F::rn(L), F::cn(L), c, "sgs_node32");
+  int nfirst = 0;
+  if (nodes_swept_by_launches(L)) {
+    c.run(fine ? "sgs_node_first32_l0" : "sgs_node_first32", (12.0 + 2.0 * sizeof(T)) * L.m, [&] {
+      k_gs_first_colour<T><<<ceil_div(L.m, 256), 256, 0, c.s>>>(L.m, L.colorAn.p, L.dinvAn.p, F::rn(L), F::cn(L));
+    });
+    nfirst = 1;
+  } else {
+    fill_t(F::cn(L), T(0), L.m, c);
+  }
+  if (fine) sgs_t<float, T, 2>(L.Ancm, L.Ancm.val32.p, F::dAn(L), L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.chainsAn, F::rn(L), F::cn(L), c, "sgs_node32_l0", nfirst);
+  else sgs_t<float, T, 0>(L.Ancm, L.Ancm.val32.p, F::dAn(L), L.rowsAn, L.cptrAn, L.cptrAn_d, L.ncolAn, L.chainsAn, F::rn(L), F::cn(L), c, "sgs_node32", nfirst);
   c.run("grad_add32", (8.0 + 3.0 * sizeof(T)) * L.n, [&] { k_grad_add<T><<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.tail.p, L.head.p, L.n, F::cn(L), x); });
   edge(0);
 }

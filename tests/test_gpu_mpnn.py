@@ -179,3 +179,31 @@ def test_forward_and_gradient_many_tiles_per_block():
         assert np.linalg.norm(gd[k] - ref) <= 6e-2 * np.linalg.norm(ref) + 1e-12, k
     P.hcurl_mpnn_sample_destroy(s)
     H.close()
+
+
+def test_fp32_products_match_reference_tightly(case):
+    """With the dense products in FP32 (the debug form: no BF16 rounding of
+    operands) the library's forward pass, loss and every gradient block agree
+    with the FP64 reference to 1e-5: what the BF16 bounds above leave open
+    (a wrong index, mean or adjoint of size below 6e-2) is pinned here."""
+    P, pr, H, s, lvl, X, flat = case
+    net = P.Network(flat)
+    net.set_fp32_products(True)
+    p = _params_dict(flat)
+    Xg, p0, tg = P.hcurl_mpnn_sample_export(s)
+    g = M.graph(lvl["N"])
+    d_ref, _ = M.forward(p, Xg.astype(np.float64), g)
+    d_gpu = P.hcurl_mpnn_forward(net.h, s)
+    err = np.max(np.abs(d_gpu - d_ref)) / np.max(np.abs(d_ref))
+    loss_ref, grads, _ = M.loss_and_grad(p, Xg.astype(np.float64), g, p0, tg)
+    loss, gflat = P.hcurl_mpnn_loss_grad(net.h, s)
+    gd = _params_dict(gflat)
+    gerr = {k: float(np.linalg.norm(gd[k] - grads[k]) / (np.linalg.norm(grads[k]) + 1e-300)) for k in M.param_order()}
+    print("FP32 products: forward %.2e, loss %.2e, gradients %s" % (
+        err, abs(loss - loss_ref) / loss_ref, {k: "%.1e" % v for k, v in gerr.items()}))
+    assert err <= 1e-5
+    assert abs(loss - loss_ref) <= 1e-5 * loss_ref
+    for k, e in gerr.items():
+        assert e <= 1e-5, k
+    net.set_fp32_products(False)
+    assert np.max(np.abs(P.hcurl_mpnn_forward(net.h, s) - d_ref)) <= 3e-2 * np.max(np.abs(d_ref))
