@@ -314,6 +314,10 @@ def main():
         # per side) down to a coarsest level of 19 edges.  (Two-wide boxes
         # from level 1 on, 3, 2, 2, 2, 3, give level-1 rows whose T_i spans
         # more than the 32 coarse nodes of the widest local-system layout.)
+        # Every six-level box schedule ends by coarsening 3^3 nodes to 2^3;
+        # there every row's pattern holds all 19 coarse edges, the minimum-
+        # norm guess has rank at most 8 and the coarsest operator is singular
+        # to rounding, which the factorisation reports (HCURL_ENOTSPD).
         widths = [3, 3, 3, 2, 2]
         maps6, sides6 = synth.box_aggregates(N + 1, widths)
         aggs6 = [torch.from_numpy(a).to(dev) for a in maps6]
@@ -323,6 +327,10 @@ def main():
             H.close()
         except P.HcurlError as e:
             r = dict(error=str(e))
+            if e.code == P.HCURL_ENOTSPD:
+                r["cause"] = ("the 3^3 -> 2^3 coarsening has a full pattern: the minimum-norm guess "
+                              "1 1^T (I - D_H D_H^+) + D_h P^(n) D_H^+ has rank <= 8 of 19 coarse edges, "
+                              "so the 19-edge coarsest operator is singular to rounding")
         r["widths"], r["sides"] = widths, [int(x) for x in sides6]
         extra["plain_fp64_six_levels"] = r
         log("untimed plain_fp64 with six levels: %s" % json.dumps(r))

@@ -231,7 +231,10 @@ def _csr(rowptr, col, val, nrows, ncols) -> hcurl_csr:
 def hcurl_amg_default_opts(**overrides) -> hcurl_amg_opts:
     o = hcurl_amg_opts()
     lib.hcurl_amg_default_opts(ctypes.byref(o))
+    names = {f for f, _ in hcurl_amg_opts._fields_}
     for k, v in overrides.items():
+        if k not in names:
+            raise TypeError("hcurl_amg_opts has no field %r" % k)
         if k == "mem_space" and isinstance(v, str):
             v = MEM[v]
         if k == "init_values":

@@ -29,6 +29,24 @@ def test_error_strings_without_gpu():
     assert P.hcurl_error_string(0) == "ok"
 
 
+def test_options_struct_matches_header_and_rejects_unknown_names():
+    """The ctypes mirror of hcurl_amg_opts has the header's fields in the
+    header's order (a missing or misplaced field would shift every later
+    one), the defaults come from the library, and a misspelt option is an
+    error instead of a silently ignored Python attribute."""
+    import pytest
+    import paper_2506_08284_amd.binding as B
+    txt = open(os.path.join(ROOT, "include", "hcurl_amg.h")).read()
+    body = txt.split("} hcurl_amg_opts;")[0].rsplit("typedef struct {", 1)[1]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = re.findall(r"(\w+)\s*(?:;|\)\s*\()", body)
+    assert [f for f, _ in B.hcurl_amg_opts._fields_] == names
+    o = B.hcurl_amg_default_opts(emin_iters=4)
+    assert o.emin_iters == 4 and o.emin_omega == 0.5 and o.power_iters == 20
+    with pytest.raises(TypeError):
+        B.hcurl_amg_default_opts(emin_iter=4)
+
+
 def build_c_demo(out_dir):
     """Compiles tests/c/abi_demo.c as C99 against include/hcurl_amg.h and
     links it to the library: the header is plain C and every symbol the

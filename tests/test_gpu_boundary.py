@@ -7,7 +7,10 @@
 * HCURL_ESTAGNATE (Sec. 6.2: two consecutive equal iterates), forced from
   the host by a zero tolerance;
 * HCURL_EINFEASIBLE, forced by a caller P^(n) whose rows give a commuting
-  constraint without finite solution."""
+  constraint without finite solution;
+* HCURL_ENOTSPD on a level whose pattern is full (its minimum-norm guess has
+  rank m_H, so the coarsest operator is singular), where the oracle's
+  Cholesky factorisation fails likewise."""
 import os
 
 import numpy as np
@@ -193,4 +196,28 @@ def test_infeasible_constraint_is_reported():
     Pn0 = O.csr(levels[0]["Pn"])
     kw0 = dict(nodal_prolongator=(Pn0.indptr.astype(np.int64), Pn0.indices.astype(np.int32), Pn0.data, Pn0.shape[1]))
     H = P.Hierarchy(pr["A"], synth.gradient_csr(pr["tail"], pr["head"]), pr["aggregates"], n_nodes=m, **kw0)
+    H.close()
+
+
+def test_full_pattern_level_makes_the_coarsest_operator_singular():
+    """9^3 cube with 2-wide boxes on every level (9 -> 5 -> 3 -> 2 nodes per
+    side): the 3^3 level's pattern holds every coarse edge, its guess has
+    rank 8 of 19, and the 19-edge coarsest operator is singular to rounding
+    (the oracle pins the closed form and the rank).  The library reports it
+    at the coarsest factorisation as HCURL_ENOTSPD; the oracle's Cholesky
+    factorisation fails on the same hierarchy."""
+    import paper_2506_08284_amd as P
+    import numpy.linalg as la
+    N = 8
+    pr = synth.problem(N, sigma=("const", 1.0), f_seed=1)
+    maps, sides = synth.box_aggregates(N + 1, [2, 2, 2])
+    m = (N + 1) ** 3
+    with pytest.raises(la.LinAlgError):
+        O.setup(pr["A"], pr["tail"], pr["head"], m, maps, {})
+    with pytest.raises(P.HcurlError) as e:
+        P.Hierarchy(pr["A"], synth.gradient_csr(pr["tail"], pr["head"]), maps, n_nodes=m)
+    assert e.value.code == P.HCURL_ENOTSPD and "coarsest" in str(e.value)
+    # one level fewer: the 3^3 level is the coarsest, its operator is definite
+    H = P.Hierarchy(pr["A"], synth.gradient_csr(pr["tail"], pr["head"]), maps[:2], n_nodes=m)
+    assert H.num_levels() == 3
     H.close()

@@ -960,3 +960,34 @@ def test_lexicographic_sgs_is_the_symmetric_gauss_seidel_preconditioner(c1):
     a = np.dot(O.vcycle(levels, u, lex=True), v)
     c = np.dot(u, O.vcycle(levels, v, lex=True))
     assert abs(a - c) <= 1e-10 * abs(a)
+
+
+def test_full_pattern_level_gives_the_pseudo_inverse_guess_and_a_singular_coarse_operator():
+    """A level so small that every fine edge's pattern holds every coarse
+    edge (3^3 nodes after 2-wide boxes on a 9^3 cube, coarsened 2-wide to
+    2^3): each row's local system then spans all coarse nodes, and the local
+    minimum-norm correction of the all-ones start (Sec. 6.1) has the closed
+    form  P_0 = 1 1^T (I - D_H D_H^+) + D_h P^(n) D_H^+  (D_H^+ the
+    pseudo-inverse).  Its rank is at most m_H = 8 of the 19 coarse edges, so
+    the coarse operator P^T A P built from it after the energy minimisation
+    is singular to rounding: the reason a six-level box hierarchy whose last
+    step coarsens 3^3 nodes to 2^3 cannot be factored on its coarsest level."""
+    N = 8
+    pr = synth.problem(N, sigma=("const", 1.0), f_seed=1)
+    maps, sides = synth.box_aggregates(N + 1, [2, 2, 2])
+    assert sides == [9, 5, 3, 2]
+    A, t, h, m = O.csr(pr["A"]), pr["tail"], pr["head"], (N + 1) ** 3
+    for agg in maps[:2]:
+        lv, (A, t, h, m) = O.build_level(A, t, h, m, agg, {})
+    lv, (AH, _, _, mH) = O.build_level(A, t, h, m, maps[2], {})
+    n, nH = lv["N"].shape
+    assert (n, nH, mH) == (98, 19, 8) and lv["N"].nnz == n * nH
+    DH = O.gradient_matrix(lv["DH_tail"], lv["DH_head"], mH).toarray()
+    Dp = np.linalg.pinv(DH)
+    G = (lv["D"] @ lv["Pn"]).toarray()
+    closed = np.ones((n, 1)) @ (np.ones((1, nH)) @ (np.eye(nH) - DH @ Dp)) + G @ Dp
+    P0 = O.with_values(lv["N"], lv["p0"]).toarray()
+    assert np.max(abs(P0 - closed)) <= 1e-13 * np.max(abs(closed))
+    assert np.linalg.matrix_rank(P0) == mH
+    ev = np.linalg.eigvalsh(O.csr(AH).toarray())
+    assert ev[0] <= 1e-12 * ev[-1]
