@@ -435,31 +435,58 @@ __global__ void k_sum_blocks(const float* __restrict__ part, int nb, int stride,
 
 // mean over segments: dst[s][f] = mean of src[e][off + f] over the segment's
 // entries (idx maps positions to entries, NULL = identity); one wave per
-// segment, sums in FP32 whatever the storage type T
-__device__ __forceinline__ float ld_f(const float* p) { return *p; }
-__device__ __forceinline__ float ld_f(const uint16_t* p) { return bf2f(*p); }
+// segment, sums in FP32 whatever the storage type T.  The wave reads four
+// entries at a time, a quarter-wave per entry and four features per lane (8
+// or 16 bytes), so quarter g holds the partial sum of the entries at
+// positions g mod 4 of every complete group of four (the remainder goes to
+// quarter 0); the quarters combine as (s0 + s1) + (s2 + s3).
+template <class T> struct Vec4;
+template <> struct Vec4<float> {
+  using V = float4;
+  static __device__ __forceinline__ void add(float* acc, V v) { acc[0] += v.x; acc[1] += v.y; acc[2] += v.z; acc[3] += v.w; }
+  static __device__ __forceinline__ V pack(const float* r) { return make_float4(r[0], r[1], r[2], r[3]); }
+};
+template <> struct Vec4<uint16_t> {
+  using V = uint2;
+  static __device__ __forceinline__ void add(float* acc, V v) {
+    acc[0] += bf2f((uint16_t)(v.x & 0xffffu)); acc[1] += bf2f((uint16_t)(v.x >> 16));
+    acc[2] += bf2f((uint16_t)(v.y & 0xffffu)); acc[3] += bf2f((uint16_t)(v.y >> 16));
+  }
+  static __device__ __forceinline__ V pack(const float* r) {
+    return make_uint2((uint32_t)f2bf(r[0]) | ((uint32_t)f2bf(r[1]) << 16), (uint32_t)f2bf(r[2]) | ((uint32_t)f2bf(r[3]) << 16));
+  }
+};
 template <class T>
 __global__ void __launch_bounds__(256) k_seg_mean(int nseg, const int* __restrict__ ptr, const int* __restrict__ idx,
                                                   const T* __restrict__ src, int stride, int off,
                                                   T* __restrict__ dst) {
+  using W = Vec4<T>;
   const int sgi = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int f = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4;
+  const int f0 = (lane & 15) * 4;
   if (sgi >= nseg) return;
   const int a = ptr[sgi], b = ptr[sgi + 1];
-  // four entries in flight per lane; partial sums combined in a fixed order
-  float acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f, acc3 = 0.0f;
+  float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
   int q = a;
+#pragma unroll 4
   for (; q + 3 < b; q += 4) {
-    const int64_t e0 = idx ? idx[q] : q, e1 = idx ? idx[q + 1] : q + 1;
-    const int64_t e2 = idx ? idx[q + 2] : q + 2, e3 = idx ? idx[q + 3] : q + 3;
-    acc0 += ld_f(src + e0 * stride + off + f);
-    acc1 += ld_f(src + e1 * stride + off + f);
-    acc2 += ld_f(src + e2 * stride + off + f);
-    acc3 += ld_f(src + e3 * stride + off + f);
+    const int64_t e = idx ? idx[q + g] : q + g;
+    W::add(acc, *(const typename W::V*)(src + e * stride + off + f0));
   }
-  for (; q < b; ++q) acc0 += ld_f(src + (idx ? idx[q] : q) * (int64_t)stride + off + f);
-  const float acc = (acc0 + acc1) + (acc2 + acc3);
-  dst[(int64_t)sgi * kHD + f] = to_store(b > a ? acc / (float)(b - a) : 0.0f, dst);
+  if (g == 0)
+    for (; q < b; ++q) {
+      const int64_t e = idx ? idx[q] : q;
+      W::add(acc, *(const typename W::V*)(src + e * stride + off + f0));
+    }
+  float r[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float s = acc[i] + __shfl_xor(acc[i], 16, 64);  // quarters 0+1 and 2+3
+    const float t = s + __shfl_xor(s, 32, 64);            // (0+1) + (2+3)
+    r[i] = b > a ? t / (float)(b - a) : 0.0f;
+  }
+  if (g == 0) *(typename W::V*)(dst + (int64_t)sgi * kHD + f0) = W::pack(r);
 }
 
 // delta_e = h_e . w_out + b_out; with training: residual, loss, dh = dd w_out,
