@@ -578,13 +578,17 @@ void Net::refresh_bf16(Ctx& c) {
 // ---------------------------------------------------------------------------
 template <class T>
 static void row_mean(Sample& S, const T* src, int stride, int off, T* mr, Ctx& c) {
-  c.run("mpnn_segment_mean", (4.0 + sizeof(T)) * S.E * kHD, [&] {
+  // the entries' features once, the means written, the row pointers
+  const double bytes = (double)sizeof(T) * kHD * ((double)S.E + S.nrow) + 4.0 * (S.nrow + 1);
+  c.run("mpnn_segment_mean", bytes, [&] {
     k_seg_mean<T><<<ceil_div((int64_t)S.nrow * 64, 256), 256, 0, c.s>>>(S.nrow, S.rowptr.p, nullptr, src, stride, off, mr);
   });
 }
 template <class T>
 static void col_mean(Sample& S, const T* src, int stride, int off, T* mc, Ctx& c) {
-  c.run("mpnn_segment_mean", (4.0 + sizeof(T)) * S.E * kHD, [&] {
+  // the entries' features once (gathered through colidx), the means written
+  const double bytes = (double)sizeof(T) * kHD * ((double)S.E + S.ncol) + 4.0 * (S.E + S.ncol + 1);
+  c.run("mpnn_segment_mean", bytes, [&] {
     k_seg_mean<T><<<ceil_div((int64_t)S.ncol * 64, 256), 256, 0, c.s>>>(S.ncol, S.colptr.p, S.colidx.p, src, stride, off, mc);
   });
 }

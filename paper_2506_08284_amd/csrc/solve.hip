@@ -96,9 +96,11 @@ void color_rows(const Csr& A, DBuf<int>& color, DBuf<int>& rows, std::vector<int
   unsigned long long* rem = (unsigned long long*)(c.iscal.p + 8);
   for (int round = 0;; ++round) {
     if (round > n + 1) fail(HCURL_EHIP, "colouring did not terminate");
-    c.run("jp_select", 12.0 * A.nnz, [&] { k_jp_select<<<ceil_div(n, 256), 256, 0, c.s>>>(A.rowptr.p, A.col.p, n, color.p); });
+    // booked bytes: every vertex's colour; the rows still uncoloured (read
+    // in full) shrink every round and are not counted, so this is a lower bound
+    c.run("jp_select", 4.0 * n, [&] { k_jp_select<<<ceil_div(n, 256), 256, 0, c.s>>>(A.rowptr.p, A.col.p, n, color.p); });
     HC_HIP(hipMemsetAsync(rem, 0, sizeof(unsigned long long), c.s));
-    c.run("jp_assign", 12.0 * A.nnz, [&] { k_jp_assign<<<ceil_div(n, 256), 256, 0, c.s>>>(A.rowptr.p, A.col.p, n, color.p, rem); });
+    c.run("jp_assign", 4.0 * n, [&] { k_jp_assign<<<ceil_div(n, 256), 256, 0, c.s>>>(A.rowptr.p, A.col.p, n, color.p, rem); });
     unsigned long long h = 0;
     d2h(&h, rem, 1, c);
     if (h == 0) break;
