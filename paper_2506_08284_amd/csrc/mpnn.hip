@@ -576,8 +576,13 @@ void Net::refresh_bf16(Ctx& c) {
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+static void check_mean_layout(int stride, int off) {
+  // k_seg_mean reads four features per lane with one 8- or 16-byte load
+  if (stride % 4 || off % 4) fail(HCURL_EINVAL, "segment mean: feature stride and offset must be multiples of 4");
+}
 template <class T>
 static void row_mean(Sample& S, const T* src, int stride, int off, T* mr, Ctx& c) {
+  check_mean_layout(stride, off);
   // the entries' features once, the means written, the row pointers
   const double bytes = (double)sizeof(T) * kHD * ((double)S.E + S.nrow) + 4.0 * (S.nrow + 1);
   c.run("mpnn_segment_mean", bytes, [&] {
@@ -586,6 +591,7 @@ static void row_mean(Sample& S, const T* src, int stride, int off, T* mr, Ctx& c
 }
 template <class T>
 static void col_mean(Sample& S, const T* src, int stride, int off, T* mc, Ctx& c) {
+  check_mean_layout(stride, off);
   // the entries' features once (gathered through colidx), the means written
   const double bytes = (double)sizeof(T) * kHD * ((double)S.E + S.ncol) + 4.0 * (S.E + S.ncol + 1);
   c.run("mpnn_segment_mean", bytes, [&] {
