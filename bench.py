@@ -309,6 +309,14 @@ def main():
         H.close()
         extra["plain_fp64_mis2_aggregates"] = r
         log("untimed plain_fp64 with MIS-2 aggregates: %s" % json.dumps(r))
+        # every box level of the default rule (reading R21: five levels at
+        # 128^3, down to the 19-edge level) in place of stopping at <= 1024
+        # edges (four levels)
+        H, r = run_step(P, A_t, D_t, aggs_t, f_t, u_t, m, stream, maxit=args.maxit, coarse_max_rows=0)
+        r["level_edges"] = [int(H.level_info(l)["n_edges"]) for l in range(H.num_levels())]
+        H.close()
+        extra["plain_fp64_all_box_levels"] = r
+        log("untimed plain_fp64 with every box level: %s" % json.dumps(r))
         # the literal six-level hierarchy of this workload (reading R21): box
         # widths 3, 3, 3, 2, 2 per level (129 -> 43 -> 15 -> 5 -> 3 -> 2 nodes
         # per side) down to a coarsest level of 19 edges.  (Two-wide boxes
