@@ -574,6 +574,86 @@ __global__ void __launch_bounds__(256) k_spgemm_wave(int nrows, const int* __res
 static constexpr int kHtSmall = 512;
 static constexpr int kHtLarge = 2048;
 
+// C = D B for a D whose rows hold at most two entries, each +-1 (a discrete
+// gradient): row i of C is the signed merge of at most two sorted rows of B,
+// a shared column summing the two products (one addition, whose order does not
+// matter), a lone column keeping its product.  The same pattern (structural
+// zeros kept) and values as spgemm; one thread per row.  A row of D outside
+// that form sets *bad, and the caller falls back to spgemm.
+template <bool FILL>
+__global__ void k_grad_rows(int n, const int* __restrict__ Drp, const int* __restrict__ Dcol,
+                            const double* __restrict__ Dval, const int* __restrict__ Brp, const int* __restrict__ Bcol,
+                            const double* __restrict__ Bval, int* __restrict__ cnt, const int* __restrict__ Crp,
+                            int* __restrict__ Ccol, double* __restrict__ Cval, int* __restrict__ bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int d0 = Drp[i], nd = Drp[i + 1] - d0;
+  int r0 = 0, r1 = 0;
+  double s0 = 0.0, s1 = 0.0;
+  if (nd >= 1) { r0 = Dcol[d0]; s0 = Dval[d0]; }
+  if (nd >= 2) { r1 = Dcol[d0 + 1]; s1 = Dval[d0 + 1]; }
+  if (!FILL && (nd > 2 || (nd >= 1 && fabs(s0) != 1.0) || (nd == 2 && (fabs(s1) != 1.0 || r1 <= r0)))) {
+    atomicOr(bad, 1);
+    cnt[i] = 0;
+    return;
+  }
+  int p = nd >= 1 ? Brp[r0] : 0, pe = nd >= 1 ? Brp[r0 + 1] : 0;
+  int q = nd >= 2 ? Brp[r1] : 0, qe = nd >= 2 ? Brp[r1 + 1] : 0;
+  int w = FILL ? Crp[i] : 0, m = 0;
+  while (p < pe || q < qe) {
+    const int cp = p < pe ? Bcol[p] : 0x7fffffff, cq = q < qe ? Bcol[q] : 0x7fffffff;
+    const int cmin = cp < cq ? cp : cq;
+    if (FILL) {
+      double v;
+      if (cp == cq) v = s0 * Bval[p] + s1 * Bval[q];
+      else if (cp < cq) v = s0 * Bval[p];
+      else v = s1 * Bval[q];
+      Ccol[w] = cmin;
+      Cval[w] = v;
+      ++w;
+    }
+    ++m;
+    if (cp == cmin) ++p;
+    if (cq == cmin) ++q;
+  }
+  if (!FILL) cnt[i] = m;
+}
+
+void gradient_product(const Csr& D, const Csr& B, Csr& C, Ctx& c, const char* tag) {
+  if (D.ncols != B.nrows) fail(HCURL_EINVAL, "gradient_product: inner dimensions differ");
+  if (!D.val.p || !B.val.p) {
+    spgemm(D, B, C, true, c, tag);
+    return;
+  }
+  C.nrows = D.nrows;
+  C.ncols = B.ncols;
+  C.rowptr.alloc(C.nrows + 1, c.s);
+  DBuf<int> cnt(C.nrows + 1, c.s);
+  int* bad = (int*)(c.iscal.p + 15);  // a slot no other primitive uses
+  HC_HIP(hipMemsetAsync(bad, 0, sizeof(int), c.s));
+  const std::string t = tag ? std::string(tag) : std::string("gradient_product");
+  const int nb = ceil_div(std::max(C.nrows, 1), 256);
+  if (C.nrows)
+    c.run((t + "_sym").c_str(), 20.0 * D.nrows + 4.0 * B.nnz, [&] {
+      k_grad_rows<false><<<nb, 256, 0, c.s>>>(C.nrows, D.rowptr.p, D.col.p, D.val.p, B.rowptr.p, B.col.p, B.val.p, cnt.p,
+                                             nullptr, nullptr, nullptr, bad);
+    });
+  int hbad = 0;
+  d2h(&hbad, bad, 1, c);
+  if (hbad) {
+    spgemm(D, B, C, true, c, tag);
+    return;
+  }
+  C.nnz = exclusive_scan(cnt.p, C.rowptr.p, C.nrows, c);
+  C.col.alloc(C.nnz, c.s);
+  C.val.alloc(C.nnz, c.s);
+  if (C.nrows)
+    c.run((t + "_num").c_str(), 20.0 * D.nrows + 12.0 * C.nnz, [&] {
+      k_grad_rows<true><<<nb, 256, 0, c.s>>>(C.nrows, D.rowptr.p, D.col.p, D.val.p, B.rowptr.p, B.col.p, B.val.p, nullptr,
+                                            C.rowptr.p, C.col.p, C.val.p, bad);
+    });
+}
+
 void spgemm(const Csr& A, const Csr& B, Csr& C, bool numeric, Ctx& c, const char* tag) {
   if (A.ncols != B.nrows) fail(HCURL_EINVAL, "spgemm: inner dimensions differ");
   numeric = numeric && A.val.p && B.val.p;

@@ -12,6 +12,11 @@ int64_t exclusive_scan(const int* in, int* out, int64_t n, Ctx& c);
 // sorted).  numeric: also the values (A and B must carry values).
 void spgemm(const Csr& A, const Csr& B, Csr& C, bool numeric, Ctx& c, const char* tag = nullptr);
 
+// C = D B for a discrete gradient D (rows of one or two entries +-1): the
+// same pattern and values as spgemm(D, B), by merging rows of B; any other D
+// goes to spgemm.
+void gradient_product(const Csr& D, const Csr& B, Csr& C, Ctx& c, const char* tag = nullptr);
+
 // AT = A^T with sorted columns; values copied when A has them and `values`.
 void transpose(const Csr& A, Csr& AT, bool values, Ctx& c);
 

@@ -1569,7 +1569,7 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
     fail(HCURL_EINVAL, "the aggregates leave no coarse edge (every fine edge inside one aggregate)");
   L.n_coarse = next->n;
   // T and R = D P^(n) on T
-  spgemm(L.D, L.Pn, L.R, true, c, L.fine ? "spgemm_DPn_l0" : "spgemm_DPn");
+  gradient_product(L.D, L.Pn, L.R, c, L.fine ? "grad_DPn_l0" : "grad_DPn");
   // pattern N, with make_irreducible while a local graph is disconnected
   {
     DBuf<int> cnt(L.n + 1, c.s);
@@ -1775,7 +1775,7 @@ void update_hierarchy(Hierarchy& H, const hcurl_csr& A, int mode, int iters) {
     nodal_operators(H, L);
     if (mode == HCURL_REUSE_WARM) {
       if (!(l == 0 && H.pn_given)) smoothed_aggregation(H, L, L.agg.p, L.Pn.ncols);
-      spgemm(L.D, L.Pn, L.R, true, c, L.fine ? "spgemm_DPn_l0" : "spgemm_DPn");
+      gradient_product(L.D, L.Pn, L.R, c, L.fine ? "grad_DPn_l0" : "grad_DPn");
       energy_minimisation(H, L, &N, K, true, L.Pe.val.p, true, false);
       transpose(L.Pe, L.PeT, true, c);
     } else {
