@@ -667,9 +667,18 @@ __global__ void k_make_feasible(int n, const int* __restrict__ Prp, double* __re
 // One 64-lane workgroup takes a block of R consecutive rows.  The products of
 // the block are flattened over the lanes (prefix sum of the pattern lengths
 // of the A-columns of each chunk of 64 A entries); each product finds its
-// slot in the row's pattern (binary search in LDS) and accumulates there with
-// an LDS atomic.  Two products per lane are in flight at a time.  With
-// EM_DOT the block also sums X * Y (the energy <P, A P>).
+// owner (the chunk's A entry) and its slot in the owner row's pattern (binary
+// searches in LDS) and accumulates there with an LDS atomic.  Two products
+// per lane are in flight at a time.  With EM_DOT the block also sums X * Y
+// (the energy <P, A P>).
+//
+// The pattern stays fixed over the iterations of an energy minimisation, so
+// the first launch can record both searches per product (MAP = 1) and the
+// later ones read them back (MAP = 2): a 16-bit code per product, in the
+// kernel's enumeration order, block after block (offsets from
+// k_emin_map_count and k_emin_map_offsets); bits 0-5 hold the owner lane and
+// bits 6-15 the slot within the owner row's pattern, kNoSlot marks a product
+// whose column is not in that pattern.
 // ---------------------------------------------------------------------------
 static constexpr int kPatCap = 512;
 static constexpr int kRowsCap = 64;
@@ -689,9 +698,12 @@ struct RowBlocks {
   __device__ int end() const { return min(nbr, (xcd + 1) * chunk); }
 };
 
+static constexpr unsigned kNoSlot = 0xFFFFu;
+
+template <bool BUILD>
 __device__ __forceinline__ void emin_product(int p, const int* pre, const int* kst, const int* arow, const double* av,
                                              const int* pofs, const int* pcol, double* acc, const int* __restrict__ Pcol,
-                                             const double* __restrict__ X) {
+                                             const double* __restrict__ X, uint16_t* __restrict__ mp) {
   int lo = 0, hi = 63;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -706,16 +718,71 @@ __device__ __forceinline__ void emin_product(int p, const int* pre, const int* k
     const int mid = (s + e) >> 1;
     if (pcol[mid] < key) s = mid + 1; else e = mid;
   }
-  if (s <= e && pcol[s] == key) atomicAdd(&acc[s], v);
+  const bool hit = s <= e && pcol[s] == key;
+  if (hit) atomicAdd(&acc[s], v);
+  if (BUILD) mp[p] = hit ? (uint16_t)(lo | ((s - pofs[rr]) << 6)) : (uint16_t)kNoSlot;
 }
 
-template <int CAP>
+// A product read back from its code: owner and slot come from the map.
+__device__ __forceinline__ void emin_mapped(int p, unsigned m, const int* pre, const int* kst, const int* sb,
+                                            const double* av, double* acc, const double* __restrict__ X) {
+  if (m == kNoSlot) return;
+  const int o = m & 63;
+  atomicAdd(&acc[sb[o] + (int)(m >> 6)], av[o] * X[kst[o] + (p - pre[o])]);
+}
+
+// Products per workgroup of k_emin_masked (same grid, same row blocks; rows
+// with an empty pattern contribute none).
+__global__ void __launch_bounds__(64) k_emin_map_count(int nrows, int R, const int* __restrict__ Arp,
+                                                       const int* __restrict__ Acol, const int* __restrict__ Prp,
+                                                       long long* __restrict__ cnt) {
+  const int l = threadIdx.x;
+  const RowBlocks B(nrows, R);
+  long long t = 0;
+  for (int rb = B.first(); rb < B.end(); rb += B.nw) {
+    const int i = rb * R + l;
+    if (l < R && i < nrows && Prp[i + 1] > Prp[i])
+      for (int q = Arp[i]; q < Arp[i + 1]; ++q) {
+        const int k = Acol[q];
+        t += Prp[k + 1] - Prp[k];
+      }
+  }
+  t = wave_sum(t);
+  if (l == 0) cnt[blockIdx.x] = t;
+}
+
+// Exclusive prefix sum of the per-workgroup counts (one 1024-thread
+// workgroup, n <= 8192); off[n] receives the total.
+__global__ void __launch_bounds__(1024) k_emin_map_offsets(const long long* __restrict__ cnt, int n,
+                                                           long long* __restrict__ off) {
+  __shared__ long long sh[1024];
+  const int t = threadIdx.x, per = (n + 1023) / 1024, b0 = t * per;
+  long long s = 0;
+  for (int i = b0; i < min(n, b0 + per); ++i) s += cnt[i];
+  sh[t] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const long long v = t >= o ? sh[t - o] : 0;
+    __syncthreads();
+    sh[t] += v;
+    __syncthreads();
+  }
+  long long run = sh[t] - s;
+  for (int i = b0; i < min(n, b0 + per); ++i) {
+    off[i] = run;
+    run += cnt[i];
+  }
+  if (t == 1023) off[n] = sh[t];
+}
+
+template <int CAP, int MAP>
 __global__ void __launch_bounds__(64) k_emin_masked(int nrows, int R, const int* __restrict__ Arp,
                                                     const int* __restrict__ Acol, const double* __restrict__ Aval,
                                                     const double* __restrict__ dscale, const int* __restrict__ Prp,
                                                     const int* __restrict__ Pcol, const double* __restrict__ X,
-                                                    double* __restrict__ Y, int flags, double* __restrict__ part) {
-  __shared__ int pcol[CAP];
+                                                    double* __restrict__ Y, int flags, double* __restrict__ part,
+                                                    uint16_t* __restrict__ pmap, const long long* __restrict__ moff) {
+  __shared__ int pcol[MAP == 2 ? 1 : CAP];
   __shared__ double acc[CAP];
   __shared__ int pofs[kRowsCap + 1];
   __shared__ int arp[kRowsCap + 1];
@@ -723,11 +790,15 @@ __global__ void __launch_bounds__(64) k_emin_masked(int nrows, int R, const int*
   __shared__ double av[64];
   const int l = threadIdx.x;
   const RowBlocks B(nrows, R);
+  long long mb = MAP ? moff[blockIdx.x] : 0;
   double dsum = 0.0;
   for (int rb = B.first(); rb < B.end(); rb += B.nw) {
     const int r0 = rb * R, r1 = min(r0 + R, nrows), nr = r1 - r0;
     const int p0 = Prp[r0], pn = Prp[r1] - p0;
-    for (int t = l; t < pn; t += 64) { pcol[t] = Pcol[p0 + t]; acc[t] = 0.0; }
+    for (int t = l; t < pn; t += 64) {
+      if (MAP != 2) pcol[t] = Pcol[p0 + t];
+      acc[t] = 0.0;
+    }
     for (int t = l; t <= nr; t += 64) { pofs[t] = Prp[r0 + t] - p0; arp[t] = Arp[r0 + t]; }
     __syncthreads();
     const int a0 = arp[0], a1 = arp[nr];
@@ -751,14 +822,27 @@ __global__ void __launch_bounds__(64) k_emin_masked(int nrows, int R, const int*
       }
       const int incl = wave_incl_scan(len);
       const int total = __shfl(incl, 63, 64);
-      kst[l] = st; pre[l] = incl - len; arow[l] = rl; av[l] = a;
+      // with MAP = 2, arow holds the owner row's first slot instead
+      kst[l] = st; pre[l] = incl - len; arow[l] = MAP == 2 ? pofs[rl] : rl; av[l] = a;
       __syncthreads();
       int p = l;
-      for (; p + 64 < total; p += 128) {
-        emin_product(p, pre, kst, arow, av, pofs, pcol, acc, Pcol, X);
-        emin_product(p + 64, pre, kst, arow, av, pofs, pcol, acc, Pcol, X);
+      if (MAP == 2) {
+        const uint16_t* mp = pmap + mb;
+        for (; p + 64 < total; p += 128) {
+          const unsigned m0 = mp[p], m1 = mp[p + 64];
+          emin_mapped(p, m0, pre, kst, arow, av, acc, X);
+          emin_mapped(p + 64, m1, pre, kst, arow, av, acc, X);
+        }
+        if (p < total) emin_mapped(p, mp[p], pre, kst, arow, av, acc, X);
+      } else {
+        uint16_t* mp = MAP ? pmap + mb : nullptr;
+        for (; p + 64 < total; p += 128) {
+          emin_product<MAP == 1>(p, pre, kst, arow, av, pofs, pcol, acc, Pcol, X, mp);
+          emin_product<MAP == 1>(p + 64, pre, kst, arow, av, pofs, pcol, acc, Pcol, X, mp);
+        }
+        if (p < total) emin_product<MAP == 1>(p, pre, kst, arow, av, pofs, pcol, acc, Pcol, X, mp);
       }
-      if (p < total) emin_product(p, pre, kst, arow, av, pofs, pcol, acc, Pcol, X);
+      mb += total;
       __syncthreads();
     }
     for (int t = l; t < pn; t += 64) {
@@ -938,22 +1022,67 @@ static int emin_rows_per_block(const Level& L) {
   return std::max(1, std::min(kRowsCap, cap / std::max(1, L.maxNp)));
 }
 
+// The product codes of one energy minimisation (see k_emin_masked).
+struct EminMap {
+  DBuf<uint16_t> codes;
+  DBuf<long long> off;
+  long long nprod = 0;
+  bool on = false, built = false;
+};
+
+// Codes take 2 bytes per product; above this size the searches are repeated.
+static constexpr double kEminMapMaxBytes = 16.0 * (1 << 30);
+
+static void emin_map_prepare(Level& L, EminMap& m, Ctx& c) {
+  const int R = emin_rows_per_block(L);
+  const int grid = emin_grid(L.n, R);
+  DBuf<long long> cnt(grid, c.s);
+  m.off.alloc(grid + 1, c.s);
+  c.run(L.fine ? "emin_map_count_l0" : "emin_map_count", 4.0 * (L.n + 1) + 4.0 * L.A.nnz + 8.0 * L.A.nnz, [&] {
+    k_emin_map_count<<<grid, 64, 0, c.s>>>(L.n, R, L.A.rowptr.p, L.A.col.p, L.Pe.rowptr.p, cnt.p);
+  });
+  c.run("emin_map_offsets", 16.0 * grid, [&] { k_emin_map_offsets<<<1, 1024, 0, c.s>>>(cnt.p, grid, m.off.p); });
+  d2h(&m.nprod, m.off.p + grid, 1, c);
+  m.built = false;
+  m.on = m.nprod > 0 && 2.0 * (double)m.nprod <= kEminMapMaxBytes;
+  if (m.on) m.codes.alloc((size_t)m.nprod, c.s);
+  else m.off.release();
+}
+
 static int emin_apply(Level& L, const double* dscale, const double* X, double* Out, int flags, double* part, double* Y,
-                      Ctx& c) {
+                      Ctx& c, EminMap* em = nullptr) {
   const int R = emin_rows_per_block(L);
   const bool small = L.maxNp * 4 <= kPatSmall;
   const int grid = emin_grid(L.n, R);
-  const double bytes = 12.0 * L.A.nnz + 4.0 * (L.n + 1) * 2 + 12.0 * L.Pe.nnz + 8.0 * L.Pe.nnz;
+  const int mode = em && em->on ? (em->built ? 2 : 1) : 0;
+  // the read-back launch does not read the pattern's columns
+  const double pbytes = mode == 2 ? 16.0 * L.Pe.nnz : 20.0 * L.Pe.nnz;
+  const double mbytes = mode ? 2.0 * (double)em->nprod : 0.0;
+  const double bytes = 12.0 * L.A.nnz + 4.0 * (L.n + 1) * 2 + pbytes + mbytes;
   const bool proj = flags & EM_PROJECT;
   double* tgt = proj ? Y : Out;
-  c.run(L.fine ? "emin_masked_spgemm_l0" : "emin_masked_spgemm", bytes, [&] {
-    if (small)
-      k_emin_masked<kPatSmall><<<grid, 64, 0, c.s>>>(L.n, R, L.A.rowptr.p, L.A.col.p, L.A.val.p, dscale, L.Pe.rowptr.p,
-                                                     L.Pe.col.p, X, tgt, proj ? 0 : flags, part);
-    else
-      k_emin_masked<kPatCap><<<grid, 64, 0, c.s>>>(L.n, R, L.A.rowptr.p, L.A.col.p, L.A.val.p, dscale, L.Pe.rowptr.p,
-                                                   L.Pe.col.p, X, tgt, proj ? 0 : flags, part);
+  uint16_t* codes = mode ? em->codes.p : nullptr;
+  const long long* moff = mode ? em->off.p : nullptr;
+  const char* tag = mode == 1 ? (L.fine ? "emin_masked_build_l0" : "emin_masked_build")
+                              : (L.fine ? "emin_masked_spgemm_l0" : "emin_masked_spgemm");
+  auto launch = [&](auto cap, auto md) {
+    k_emin_masked<decltype(cap)::value, decltype(md)::value><<<grid, 64, 0, c.s>>>(
+        L.n, R, L.A.rowptr.p, L.A.col.p, L.A.val.p, dscale, L.Pe.rowptr.p, L.Pe.col.p, X, tgt, proj ? 0 : flags, part,
+        codes, moff);
+  };
+  using SmallCap = std::integral_constant<int, kPatSmall>;
+  using BigCap = std::integral_constant<int, kPatCap>;
+  c.run(tag, bytes, [&] {
+    switch (mode * 2 + (small ? 0 : 1)) {
+      case 0: launch(SmallCap{}, std::integral_constant<int, 0>{}); break;
+      case 1: launch(BigCap{}, std::integral_constant<int, 0>{}); break;
+      case 2: launch(SmallCap{}, std::integral_constant<int, 1>{}); break;
+      case 3: launch(BigCap{}, std::integral_constant<int, 1>{}); break;
+      case 4: launch(SmallCap{}, std::integral_constant<int, 2>{}); break;
+      default: launch(BigCap{}, std::integral_constant<int, 2>{}); break;
+    }
   });
+  if (mode == 1) em->built = true;
   if (proj) {
     // one row per lane: blocks of up to 64 rows, LDS sized for them
     constexpr int kProjCap = 1536;
@@ -1153,8 +1282,8 @@ __global__ void k_add2(int64_t n, const double* __restrict__ a, const double* __
   if (i < n) y[i] = a[i] + b[i];
 }
 
-static double energy_of(Level& L, const double* P, EminWork& w, Ctx& c) {
-  int g = emin_apply(L, nullptr, P, w.Q.p, EM_DOT, w.part.p, nullptr, c);
+static double energy_of(Level& L, const double* P, EminWork& w, Ctx& c, EminMap* em) {
+  int g = emin_apply(L, nullptr, P, w.Q.p, EM_DOT, w.part.p, nullptr, c, em);
   // sum of partials (g may exceed kRedBlocks: reduce on host deterministically)
   std::vector<double> h(g);
   d2h(h.data(), w.part.p, g, c);
@@ -1215,25 +1344,29 @@ static void energy_minimisation(Hierarchy& H, Level& L, const Level* next, int i
   double* sc = c.scal.p;
   L.energy.clear();
   const bool rec = H.opts.record_energy != 0;
-  if (rec) L.energy.push_back(energy_of(L, w.P.p, w, c));
-  if (H.opts.emin_method == HCURL_EMIN_JACOBI) {
+  const bool jac = H.opts.emin_method == HCURL_EMIN_JACOBI;
+  // masked products of this minimisation: codes pay off from the second one
+  EminMap em;
+  if ((jac ? iters : iters + 1) + (rec ? iters + 1 : 0) >= 2) emin_map_prepare(L, em, c);
+  if (rec) L.energy.push_back(energy_of(L, w.P.p, w, c, &em));
+  if (jac) {
     DBuf<double> dinv(L.n, c.s);
     diagonal(L.A, dinv.p, true, c);
     for (int it = 0; it < iters; ++it) {
-      emin_apply(L, dinv.p, w.P.p, w.Q.p, EM_PROJECT, w.part.p, w.Y.p, c);
+      emin_apply(L, dinv.p, w.P.p, w.Q.p, EM_PROJECT, w.part.p, w.Y.p, c, &em);
       c.run("emin_axpy", 24.0 * np, [&] { k_axpy_scalar<<<ceil_div(np, 256), 256, 0, c.s>>>(np, w.P.p, w.Q.p, -H.opts.emin_omega); });
-      if (rec) L.energy.push_back(energy_of(L, w.P.p, w, c));
+      if (rec) L.energy.push_back(energy_of(L, w.P.p, w, c, &em));
     }
   } else {
     // R = -Pi(mask(A P)), Dir = R, rho = <R, R>
-    emin_apply(L, nullptr, w.P.p, w.Rv.p, EM_PROJECT | EM_NEGATE, w.part.p, w.Y.p, c);
+    emin_apply(L, nullptr, w.P.p, w.Rv.p, EM_PROJECT | EM_NEGATE, w.part.p, w.Y.p, c, &em);
     d2d(w.Dir.p, w.Rv.p, np, c);
     dot(w.Rv.p, w.Rv.p, np, sc + S_RHO, c, 0);
     c.run("cg_scalar", 0.0, [&] { k_copy_scalar<<<1, 1, 0, c.s>>>(sc + S_RHO, sc + S_RHO0); });
     const int ub = Ctx::kRedBlocks;
     const int nbu = (int)std::min<int64_t>(ub, std::max<int64_t>(1, (np + 255) / 256));
     for (int it = 0; it < iters; ++it) {
-      int g = emin_apply(L, nullptr, w.Dir.p, w.Q.p, EM_PROJECT | EM_DOT, w.part.p, w.Y.p, c);
+      int g = emin_apply(L, nullptr, w.Dir.p, w.Q.p, EM_PROJECT | EM_DOT, w.part.p, w.Y.p, c, &em);
       sum_partials(w.part.p, g, sc + S_GAMMA, c);
       c.run("cg_scalar", 0.0, [&] { k_cg_alpha<<<1, 1, 0, c.s>>>(sc, c.iscal.p); });
       c.run("emin_cg_update", 48.0 * np, [&] {
@@ -1242,7 +1375,7 @@ static void energy_minimisation(Hierarchy& H, Level& L, const Level* next, int i
       reduce_partials(nbu, 0, sc + S_RHONEW, c);
       c.run("cg_scalar", 0.0, [&] { k_cg_beta<<<1, 1, 0, c.s>>>(sc); });
       c.run("emin_cg_dir", 24.0 * np, [&] { k_cg_dir<<<ceil_div(np, 256), 256, 0, c.s>>>(np, w.Dir.p, w.Rv.p, sc + S_BETA); });
-      if (rec) L.energy.push_back(energy_of(L, w.P.p, w, c));
+      if (rec) L.energy.push_back(energy_of(L, w.P.p, w, c, &em));
     }
   }
   // rounding cleanup: re-apply the affine step
