@@ -677,8 +677,9 @@ __global__ void k_make_feasible(int n, const int* __restrict__ Prp, double* __re
 // later ones read them back (MAP = 2): a 16-bit code per product, in the
 // kernel's enumeration order, block after block (offsets from
 // k_emin_map_count and k_emin_map_offsets); bits 0-5 hold the owner lane and
-// bits 6-15 the slot within the owner row's pattern, kNoSlot marks a product
-// whose column is not in that pattern.
+// bits 6-15 the slot among the row block's pattern entries (fewer than
+// kPatCap), kNoSlot marks a product whose column is not in the owner row's
+// pattern.
 // ---------------------------------------------------------------------------
 static constexpr int kPatCap = 512;
 static constexpr int kRowsCap = 64;
@@ -720,19 +721,13 @@ __device__ __forceinline__ void emin_product(int p, const int* pre, const int* k
   }
   const bool hit = s <= e && pcol[s] == key;
   if (hit) atomicAdd(&acc[s], v);
-  if (BUILD) mp[p] = hit ? (uint16_t)(lo | ((s - pofs[rr]) << 6)) : (uint16_t)kNoSlot;
+  if (BUILD) mp[p] = hit ? (uint16_t)(lo | (s << 6)) : (uint16_t)kNoSlot;
 }
 
-// A product read back from its code: owner and slot come from the map.
-__device__ __forceinline__ void emin_mapped(int p, unsigned m, const int* pre, const int* kst, const int* sb,
-                                            const double* av, double* acc, const double* __restrict__ X) {
-  if (m == kNoSlot) return;
-  const int o = m & 63;
-  atomicAdd(&acc[sb[o] + (int)(m >> 6)], av[o] * X[kst[o] + (p - pre[o])]);
-}
+static constexpr int kMapBatch = 4;
 
-// Products per workgroup of k_emin_masked (same grid, same row blocks; rows
-// with an empty pattern contribute none).
+// Products per workgroup of k_emin_masked (same grid, same row blocks): the
+// pattern lengths of the A-columns of every A entry of its row blocks.
 __global__ void __launch_bounds__(64) k_emin_map_count(int nrows, int R, const int* __restrict__ Arp,
                                                        const int* __restrict__ Acol, const int* __restrict__ Prp,
                                                        long long* __restrict__ cnt) {
@@ -740,12 +735,11 @@ __global__ void __launch_bounds__(64) k_emin_map_count(int nrows, int R, const i
   const RowBlocks B(nrows, R);
   long long t = 0;
   for (int rb = B.first(); rb < B.end(); rb += B.nw) {
-    const int i = rb * R + l;
-    if (l < R && i < nrows && Prp[i + 1] > Prp[i])
-      for (int q = Arp[i]; q < Arp[i + 1]; ++q) {
-        const int k = Acol[q];
-        t += Prp[k + 1] - Prp[k];
-      }
+    const int r0 = rb * R, r1 = min(r0 + R, nrows);
+    for (int q = Arp[r0] + l; q < Arp[r1]; q += 64) {
+      const int k = Acol[q];
+      t += Prp[k + 1] - Prp[k];
+    }
   }
   t = wave_sum(t);
   if (l == 0) cnt[blockIdx.x] = t;
@@ -807,33 +801,46 @@ __global__ void __launch_bounds__(64) k_emin_masked(int nrows, int R, const int*
       int st = 0, len = 0, rl = 0;
       double a = 0.0;
       if (q < a1) {
-        int lo = 0, hi = nr - 1;
-        while (lo < hi) {  // largest rl with arp[rl] <= q
-          const int mid = (lo + hi + 1) >> 1;
-          if (arp[mid] <= q) lo = mid; else hi = mid - 1;
+        // the owner row of A entry q is only needed for the slot search (a
+        // row with an empty pattern gets no hits)
+        if (MAP != 2) {
+          int lo = 0, hi = nr - 1;
+          while (lo < hi) {  // largest rl with arp[rl] <= q
+            const int mid = (lo + hi + 1) >> 1;
+            if (arp[mid] <= q) lo = mid; else hi = mid - 1;
+          }
+          rl = lo;
         }
-        rl = lo;
-        if (pofs[rl + 1] > pofs[rl]) {
-          const int k = Acol[q];
-          a = Aval[q];
-          st = Prp[k];
-          len = Prp[k + 1] - st;
-        }
+        const int k = Acol[q];
+        a = Aval[q];
+        st = Prp[k];
+        len = Prp[k + 1] - st;
       }
       const int incl = wave_incl_scan(len);
       const int total = __shfl(incl, 63, 64);
-      // with MAP = 2, arow holds the owner row's first slot instead
-      kst[l] = st; pre[l] = incl - len; arow[l] = MAP == 2 ? pofs[rl] : rl; av[l] = a;
+      kst[l] = st; pre[l] = incl - len; arow[l] = rl; av[l] = a;
       __syncthreads();
       int p = l;
       if (MAP == 2) {
+        // kMapBatch products per lane: their codes, then their X gathers,
+        // then their LDS sums, so the loads of a batch are in flight together
         const uint16_t* mp = pmap + mb;
-        for (; p + 64 < total; p += 128) {
-          const unsigned m0 = mp[p], m1 = mp[p + 64];
-          emin_mapped(p, m0, pre, kst, arow, av, acc, X);
-          emin_mapped(p + 64, m1, pre, kst, arow, av, acc, X);
+        for (; p < total; p += 64 * kMapBatch) {
+          unsigned m[kMapBatch];
+#pragma unroll
+          for (int u = 0; u < kMapBatch; ++u) m[u] = p + 64 * u < total ? mp[p + 64 * u] : kNoSlot;
+          double xv[kMapBatch];
+          int sl[kMapBatch];
+#pragma unroll
+          for (int u = 0; u < kMapBatch; ++u) {
+            const int o = m[u] & 63;
+            sl[u] = (int)(m[u] >> 6);
+            xv[u] = m[u] != kNoSlot ? av[o] * X[kst[o] + (p + 64 * u - pre[o])] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < kMapBatch; ++u)
+            if (m[u] != kNoSlot) atomicAdd(&acc[sl[u]], xv[u]);
         }
-        if (p < total) emin_mapped(p, mp[p], pre, kst, arow, av, acc, X);
       } else {
         uint16_t* mp = MAP ? pmap + mb : nullptr;
         for (; p + 64 < total; p += 128) {
