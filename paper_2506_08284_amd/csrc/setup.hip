@@ -1045,7 +1045,7 @@ static void emin_map_prepare(Level& L, EminMap& m, Ctx& c) {
   const int grid = emin_grid(L.n, R);
   DBuf<long long> cnt(grid, c.s);
   m.off.alloc(grid + 1, c.s);
-  c.run(L.fine ? "emin_map_count_l0" : "emin_map_count", 4.0 * (L.n + 1) + 4.0 * L.A.nnz + 8.0 * L.A.nnz, [&] {
+  c.run(L.fine ? "emin_map_count_l0" : "emin_map_count", 8.0 * (L.n + 1) + 4.0 * L.A.nnz, [&] {
     k_emin_map_count<<<grid, 64, 0, c.s>>>(L.n, R, L.A.rowptr.p, L.A.col.p, L.Pe.rowptr.p, cnt.p);
   });
   c.run("emin_map_offsets", 16.0 * grid, [&] { k_emin_map_offsets<<<1, 1024, 0, c.s>>>(cnt.p, grid, m.off.p); });
