@@ -148,6 +148,15 @@ typedef struct {
                               does not reduce. */
   int power_iters;         /* power iterations for rho(D^-1 A^(n)), default 20 */
   int record_energy;       /* 1: measure 1/2 <P, A P> after every emin iteration */
+  int emin_codes;          /* 1 (default): the first masked product A X of an energy
+                              minimisation records, per product a_ik x_kj, a 2-byte
+                              code (the A entry it comes from and the slot of j in
+                              row i's pattern), and the later products of that
+                              minimisation read the codes back instead of searching.
+                              The codes live while the minimisation runs; a level
+                              whose codes would take more than 16 GiB searches.
+                              0: every product searches.  Both give the same
+                              P^(e) to rounding (the sums are LDS atomics). */
   int profile;             /* 0: off.  1: time every eagerly launched kernel with HIP
                               events (hcurl_amg_kernel_stats); on a non-null stream the
                               V-cycle levels below the finest replay as one HIP graph,

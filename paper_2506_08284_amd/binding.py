@@ -52,7 +52,8 @@ class hcurl_amg_opts(ctypes.Structure):
                 ("init_values", ctypes.c_void_p), ("emin_iters_given", ctypes.c_int), ("mpnn", ctypes.c_void_p),
                 ("vcycle_fp32", ctypes.c_int), ("nodal_prolongator", ctypes.c_void_p), ("alg1_passes", ctypes.c_int),
                 ("pbar_alg1", ctypes.c_int), ("aggregation", ctypes.c_int),
-                ("power_iters", ctypes.c_int), ("record_energy", ctypes.c_int), ("profile", ctypes.c_int),
+                ("power_iters", ctypes.c_int), ("record_energy", ctypes.c_int), ("emin_codes", ctypes.c_int),
+                ("profile", ctypes.c_int),
                 ("mem_space", ctypes.c_int), ("stream", ctypes.c_void_p), ("dev_alloc", ctypes.c_void_p),
                 ("dev_free", ctypes.c_void_p), ("alloc_ctx", ctypes.c_void_p)]
 

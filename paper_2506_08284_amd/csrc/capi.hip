@@ -108,6 +108,7 @@ void hcurl_amg_default_opts(hcurl_amg_opts* o) {
   o->aggregation = HCURL_AGG_GIVEN;
   o->power_iters = 20;
   o->record_energy = 0;
+  o->emin_codes = 1;
   o->profile = 0;
   o->mem_space = HCURL_MEM_HOST;
   o->stream = nullptr;
@@ -124,6 +125,7 @@ int hcurl_amg_setup(const hcurl_csr* A, const hcurl_csr* Dh, const double* coord
     if (opts) h->H.opts = *opts; else hcurl_amg_default_opts(&h->H.opts);
     if (h->H.opts.emin_iters < 0 || h->H.opts.power_iters < 1) hc::fail(HCURL_EINVAL, "bad iteration counts");
     if (h->H.opts.profile < 0 || h->H.opts.profile > 3) hc::fail(HCURL_EINVAL, "profile must be 0, 1, 2 or 3");
+    if (h->H.opts.emin_codes != 0 && h->H.opts.emin_codes != 1) hc::fail(HCURL_EINVAL, "emin_codes must be 0 or 1");
     if (h->H.opts.aggregation != HCURL_AGG_GIVEN && h->H.opts.aggregation != HCURL_AGG_MIS2)
       hc::fail(HCURL_EINVAL, "unknown aggregation");
     if ((h->H.opts.nodal_prolongator || h->H.opts.pbar_alg1) && h->H.opts.alg1_passes < 1)

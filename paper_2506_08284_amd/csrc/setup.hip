@@ -1354,7 +1354,7 @@ static void energy_minimisation(Hierarchy& H, Level& L, const Level* next, int i
   const bool jac = H.opts.emin_method == HCURL_EMIN_JACOBI;
   // masked products of this minimisation: codes pay off from the second one
   EminMap em;
-  if ((jac ? iters : iters + 1) + (rec ? iters + 1 : 0) >= 2) emin_map_prepare(L, em, c);
+  if (H.opts.emin_codes && (jac ? iters : iters + 1) + (rec ? iters + 1 : 0) >= 2) emin_map_prepare(L, em, c);
   if (rec) L.energy.push_back(energy_of(L, w.P.p, w, c, &em));
   if (jac) {
     DBuf<double> dinv(L.n, c.s);

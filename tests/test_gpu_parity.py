@@ -321,6 +321,37 @@ def test_projected_jacobi_variant():
     _close(_export(H, 0, "Pe"), lvl["Pe"], 1e-10)
 
 
+@pytest.mark.parametrize("method", [0, 1])
+def test_masked_product_codes_match_searching_form(method):
+    """The masked product A X of the energy minimisation with recorded codes
+    (emin_codes = 1, the default: the first product searches and records,
+    the later ones read back) and with a search in every product give the
+    same P^(e), energies and coarse operators to rounding, CG and Jacobi
+    alike, and both agree with the oracle at 1e-10."""
+    pr = synth.problem(12, jitter=0.2, jitter_seed=5, sigma=("lognormal", 6, 2.0), f_seed=7)
+    m = pr["mesh"]["n"] ** 3
+    P = _lib()
+    Dh = synth.gradient_csr(pr["tail"], pr["head"])
+    kw = dict(emin_method=method, emin_iters=10 if method == 0 else 3, emin_omega=0.5, record_energy=1)
+    Hc = P.Hierarchy(pr["A"], Dh, pr["aggregates"], n_nodes=m, emin_codes=1, **kw)
+    Hs = P.Hierarchy(pr["A"], Dh, pr["aggregates"], n_nodes=m, emin_codes=0, **kw)
+    levels = O.setup(pr["A"], pr["tail"], pr["head"], m, pr["aggregates"],
+                     dict(record_energy=True, emin_method="cg" if method == 0 else "jacobi",
+                          emin_iters=kw["emin_iters"], emin_omega=0.5))
+    assert Hc.num_levels() == Hs.num_levels() == len(levels)
+    for l in range(len(levels) - 1):
+        Pc, Ps = _export(Hc, l, "Pe"), _export(Hs, l, "Pe")
+        _same_pattern(Pc, Ps)
+        _close(Pc, Ps, 1e-13)
+        _close(Pc, levels[l]["Pe"], 1e-10)
+        Ec, Es = Hc.export_vec(l, "energy"), Hs.export_vec(l, "energy")
+        assert len(Ec) == len(Es) == kw["emin_iters"] + 1
+        assert np.allclose(Ec, Es, rtol=1e-13, atol=0.0)
+        _close(_export(Hc, l + 1, "A"), _export(Hs, l + 1, "A"), 1e-13)
+    with pytest.raises(P.HcurlError):
+        P.Hierarchy(pr["A"], Dh, pr["aggregates"], n_nodes=m, emin_codes=2)
+
+
 def test_given_initial_guess_is_projected_then_refined():
     """A caller-given level-0 guess is made feasible by the local min-norm
     correction and refined by 3 CG iterations, like the oracle with p_init."""
