@@ -881,6 +881,7 @@ __global__ void __launch_bounds__(64) k_emin_project(int nrows, int R, const int
                                                      double* __restrict__ Out, int flags, double* __restrict__ part,
                                                      long long* __restrict__ iflags) {
   __shared__ double acc[CAP];
+  __shared__ uint16_t lps[CAP];
   __shared__ int pofs[kRowsCap + 1];
   const int l = threadIdx.x;
   const RowBlocks B(nrows, R);
@@ -888,13 +889,15 @@ __global__ void __launch_bounds__(64) k_emin_project(int nrows, int R, const int
   for (int rb = B.first(); rb < B.end(); rb += B.nw) {
     const int r0 = rb * R, r1 = min(r0 + R, nrows), nr = r1 - r0;
     const int p0 = Prp[r0], pn = Prp[r1] - p0;
-    for (int t = l; t < pn; t += 64) acc[t] = Y[p0 + t];
+    // values and local endpoint pairs staged together: the row solves then
+    // read only LDS
+    for (int t = l; t < pn; t += 64) { acc[t] = Y[p0 + t]; lps[t] = lpair[p0 + t]; }
     for (int t = l; t <= nr; t += 64) pofs[t] = Prp[r0 + t] - p0;
     __syncthreads();
     if (l < nr) {
       const int i = r0 + l;
       const int t0 = Trp[i];
-      if (!local_solve_fit<MAXJ>(acc + pofs[l], lpair + p0 + pofs[l], pofs[l + 1] - pofs[l], Trp[i + 1] - t0, nullptr))
+      if (!local_solve_fit<MAXJ>(acc + pofs[l], lps + pofs[l], pofs[l + 1] - pofs[l], Trp[i + 1] - t0, nullptr))
         atomicAdd((unsigned long long*)&iflags[F_NOTSPD], 1ULL);
     }
     __syncthreads();
