@@ -133,7 +133,9 @@ def test_largest_local_systems_against_oracle():
     """A caller P^(n) whose row 0 spreads over 30 coarse nodes (a 3 x 3 x 3 +
     3 block of aggregates) gives fine edges with |T_i| = 30: the widest
     local-system layout the library has (32).  Pattern, local pairs and D_H
-    bit for bit, P^(e) within the usual tolerance, the solve."""
+    bit for bit, P^(e) within the usual tolerance (also with the masked
+    product searching in every launch: up to 105 pattern entries per row), the
+    solve."""
     import scipy.sparse as sp
     P = _lib()
     pr = synth.problem(6, sigma=("const", 1.0), f_seed=2)
@@ -163,6 +165,14 @@ def test_largest_local_systems_against_oracle():
     lp = H.export_vec(0, "local_pairs")
     assert np.array_equal(lp & 255, lv["lt"]) and np.array_equal(lp >> 8, lv["lh"])
     assert np.max(abs(Pe.data - O.csr(lv["Pe"]).data)) <= 1e-10 * abs(lv["Pe"].data).max()
+    # pattern rows of more than 64 entries put the masked product in its wide
+    # row blocks; the recorded codes and the searching form agree there too
+    assert np.diff(N.indptr).max() > 64
+    H0 = P.Hierarchy(pr["A"], synth.gradient_csr(pr["tail"], pr["head"]), [agg], n_nodes=m, nodal_prolongator=given,
+                     emin_codes=0)
+    Pe0 = H0.export_csr(0, "Pe")[0][2]
+    H0.close()
+    assert np.max(abs(Pe.data - Pe0)) <= 1e-13 * abs(Pe0).max()
     a, r = H.commute_residual(0)
     assert a <= 1e-12 * r
     n = pr["A"][0].shape[0] - 1
