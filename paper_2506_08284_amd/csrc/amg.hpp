@@ -28,6 +28,9 @@ struct Level {
   Csr An;                // nodal operator D^T A D
   Csr DTA;               // (A D)^T = D^T A (A symmetric): the Hiptmair nodal right-hand
                          // side D^T (b - A x) is formed as D^T b - DTA x
+  Csr ADshape, APshape;  // row pointers and nnz of the setup's A D and A P^(e) (the
+                         // products themselves are dropped): an update with the
+                         // same patterns redoes only their numeric passes
   DBuf<double> dinvA, dinvAn;
   DBuf<float> dinvA32, dinvAn32;
 

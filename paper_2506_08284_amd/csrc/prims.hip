@@ -325,6 +325,37 @@ void transpose(const Csr& A, Csr& AT, bool values, Ctx& c) {
   sort_rows(AT, c);
 }
 
+// AT's values from A on AT's kept pattern: entry (j, i) of AT is A(i, j),
+// found by a binary search of column j in row i of A (sorted columns).  One
+// wave per row of AT.
+__global__ void __launch_bounds__(256) k_transpose_values(int nT, const int* __restrict__ Trp,
+                                                          const int* __restrict__ Tcol, double* __restrict__ Tval,
+                                                          const int* __restrict__ Arp, const int* __restrict__ Acol,
+                                                          const double* __restrict__ Aval) {
+  const int j = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (j >= nT) return;
+  for (int q = Trp[j] + lane_id(); q < Trp[j + 1]; q += 64) {
+    const int i = Tcol[q];
+    int lo = Arp[i], hi = Arp[i + 1] - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (Acol[mid] < j) lo = mid + 1; else hi = mid;
+    }
+    Tval[q] = Aval[lo];
+  }
+}
+
+void transpose_refill(const Csr& A, Csr& AT, Ctx& c) {
+  if (AT.nrows != A.ncols || AT.ncols != A.nrows || AT.nnz != A.nnz || !A.val.p || !AT.rowptr.p)
+    fail(HCURL_EINVAL, "transpose_refill: the kept transpose does not match");
+  if (AT.val.n < (size_t)AT.nnz) AT.val.alloc(AT.nnz, c.s);
+  if (AT.nrows && AT.nnz)
+    c.run("transpose_values", 36.0 * A.nnz, [&] {
+      k_transpose_values<<<ceil_div(AT.nrows, 4), 256, 0, c.s>>>(AT.nrows, AT.rowptr.p, AT.col.p, AT.val.p, A.rowptr.p,
+                                                                 A.col.p, A.val.p);
+    });
+}
+
 // ---------------------------------------------------------------------------
 // SpGEMM: one wave per row; the products of a row are flattened over 64
 // lanes (prefix sum of the B-row lengths of each chunk of 64 A entries) and
@@ -441,7 +472,7 @@ __global__ void __launch_bounds__(64) k_spgemm_fill(const int* __restrict__ rows
   for (int t = blockIdx.x; t < n; t += gridDim.x) {
     const int i = rows ? rows[t] : t;
     int u = hash_row<HT, NUMERIC>(H, i, Arp, Acol, Aval, Brp, Bcol, Bval);
-    if (u < 0) continue;  // cannot happen: counts came from the same table size
+    if (u < 0) continue;  // an overflowing row: the large table's pass writes it
     // compact occupied slots
     int base = 0;
     for (int s0 = 0; s0 < HT; s0 += 64) {
@@ -745,6 +776,56 @@ void spgemm(const Csr& A, const Csr& B, Csr& C, bool numeric, Ctx& c, const char
         });
     }
   }
+}
+
+// Rows whose product has more distinct columns than the small table holds
+// (hash_row overflows exactly then), from the product's row pointers.
+__global__ void k_rows_longer(const int* __restrict__ rp, int n, int limit, int* __restrict__ list,
+                              int* __restrict__ nlist) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && rp[i + 1] - rp[i] > limit) list[atomicAdd(nlist, 1)] = i;
+}
+
+void spgemm_refill(const Csr& A, const Csr& B, Csr& C, Ctx& c, const char* tag) {
+  if (A.ncols != B.nrows || C.nrows != A.nrows || C.ncols != B.ncols || !A.val.p || !B.val.p)
+    fail(HCURL_EINVAL, "spgemm_refill: operands do not match the kept product");
+  if (!C.nrows) return;
+  if (C.col.n < (size_t)C.nnz) C.col.alloc(C.nnz, c.s);
+  if (C.val.n < (size_t)C.nnz) C.val.alloc(C.nnz, c.s);
+  const std::string t = std::string(tag ? tag : "spgemm") + "_num";
+  unsigned long long* mx = (unsigned long long*)(c.iscal.p + 11);
+  HC_HIP(hipMemsetAsync(mx, 0, sizeof(unsigned long long), c.s));
+  k_row_products<<<ceil_div(A.nrows, 256), 256, 0, c.s>>>(A.nrows, A.rowptr.p, A.col.p, B.rowptr.p, mx);
+  HC_LAUNCH_CHECK();
+  unsigned long long hmax = 0;
+  d2h(&hmax, mx, 1, c);
+  if (hmax <= 64) {
+    c.run(t.c_str(), 12.0 * A.nnz + 12.0 * C.nnz, [&] {
+      k_spgemm_wave<true, true><<<ceil_div(C.nrows, 4), 256, 0, c.s>>>(C.nrows, A.rowptr.p, A.col.p, A.val.p, B.rowptr.p,
+                                                                       B.col.p, B.val.p, nullptr, C.rowptr.p, C.col.p,
+                                                                       C.val.p);
+    });
+    return;
+  }
+  const int nb = std::max(1, std::min(C.nrows, 1 << 17));
+  const double est_bytes = 12.0 * A.nnz + 8.0 * B.nnz;
+  c.run(t.c_str(), est_bytes + 12.0 * C.nnz, [&] {
+    k_spgemm_fill<kHtSmall, true><<<nb, 64, 0, c.s>>>(nullptr, 0, A.nrows, A.rowptr.p, A.col.p, A.val.p, B.rowptr.p,
+                                                      B.col.p, B.val.p, C.rowptr.p, C.col.p, C.val.p);
+  });
+  DBuf<int> olist(C.nrows, c.s);
+  int* nover = (int*)(c.iscal.p + 1);
+  HC_HIP(hipMemsetAsync(nover, 0, sizeof(int), c.s));
+  k_rows_longer<<<ceil_div(C.nrows, 256), 256, 0, c.s>>>(C.rowptr.p, C.nrows, kHtSmall * 3 / 4, olist.p, nover);
+  HC_LAUNCH_CHECK();
+  int hover = 0;
+  d2h(&hover, nover, 1, c);
+  if (hover > 0)
+    c.run("spgemm_numeric_large", est_bytes, [&] {
+      k_spgemm_fill<kHtLarge, true><<<std::min(hover, 65536), 64, 0, c.s>>>(olist.p, hover, A.nrows, A.rowptr.p, A.col.p,
+                                                                            A.val.p, B.rowptr.p, B.col.p, B.val.p,
+                                                                            C.rowptr.p, C.col.p, C.val.p);
+    });
 }
 
 // ---------------------------------------------------------------------------

@@ -11,6 +11,10 @@ int64_t exclusive_scan(const int* in, int* out, int64_t n, Ctx& c);
 // C = A B on the symbolic pattern of |A||B| (structural zeros kept, columns
 // sorted).  numeric: also the values (A and B must carry values).
 void spgemm(const Csr& A, const Csr& B, Csr& C, bool numeric, Ctx& c, const char* tag = nullptr);
+// C = A B again on the pattern C holds: C.rowptr (and C.nnz) must come from
+// spgemm of matrices with the patterns of A and B; columns and values are
+// rewritten (the same columns).
+void spgemm_refill(const Csr& A, const Csr& B, Csr& C, Ctx& c, const char* tag = nullptr);
 
 // C = D B for a discrete gradient D (rows of one or two entries +-1): the
 // same pattern and values as spgemm(D, B), by merging rows of B; any other D
@@ -19,6 +23,9 @@ void gradient_product(const Csr& D, const Csr& B, Csr& C, Ctx& c, const char* ta
 
 // AT = A^T with sorted columns; values copied when A has them and `values`.
 void transpose(const Csr& A, Csr& AT, bool values, Ctx& c);
+// AT's values again from A with the pattern AT already holds (A's pattern
+// unchanged since the transpose, columns sorted within A's rows).
+void transpose_refill(const Csr& A, Csr& AT, Ctx& c);
 
 // Builds a device CSR from host or device arrays with int64 row pointers.
 void upload_csr(const hcurl_csr& in, bool device_ptrs, Csr& out, bool values, Ctx& c);

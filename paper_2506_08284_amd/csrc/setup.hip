@@ -1417,12 +1417,39 @@ static void coarsest_factor(Hierarchy& H, Level& L) {
 
 // nodal operator, diagonals, colourings of one level (all levels)
 // A^(n) = D^T A D, (A D)^T and the diagonals, from the level's current A
-static void nodal_operators(Hierarchy& H, Level& L) {
+// A product's row pointers kept for spgemm_refill, and taken back.
+static void keep_shape(Csr& M, Csr& shape) {
+  shape.nrows = M.nrows;
+  shape.ncols = M.ncols;
+  shape.nnz = M.nnz;
+  shape.rowptr = std::move(M.rowptr);
+}
+static bool take_shape(Csr& shape, Csr& M) {
+  if (!shape.rowptr.p) return false;
+  M.nrows = shape.nrows;
+  M.ncols = shape.ncols;
+  M.nnz = shape.nnz;
+  M.rowptr = std::move(shape.rowptr);
+  return true;
+}
+
+// reuse: A has the pattern of the setup's A, so A D and D^T (A D) keep
+// theirs and only their numeric passes run
+static void nodal_operators(Hierarchy& H, Level& L, bool reuse = false) {
   Ctx& c = H.ctx;
+  const char* tAD = L.fine ? "spgemm_AD_l0" : "spgemm_AD";
+  const char* tDtAD = L.fine ? "spgemm_DtAD_l0" : "spgemm_DtAD";
   Csr AD;
-  spgemm(L.A, L.D, AD, true, c, L.fine ? "spgemm_AD_l0" : "spgemm_AD");
-  spgemm(L.DT, AD, L.An, true, c, L.fine ? "spgemm_DtAD_l0" : "spgemm_DtAD");
-  transpose(AD, L.DTA, true, c);
+  if (reuse && L.An.rowptr.p && L.DTA.rowptr.p && take_shape(L.ADshape, AD)) {
+    spgemm_refill(L.A, L.D, AD, c, tAD);
+    spgemm_refill(L.DT, AD, L.An, c, tDtAD);
+    transpose_refill(AD, L.DTA, c);
+  } else {
+    spgemm(L.A, L.D, AD, true, c, tAD);
+    spgemm(L.DT, AD, L.An, true, c, tDtAD);
+    transpose(AD, L.DTA, true, c);
+  }
+  keep_shape(AD, L.ADshape);
   L.dinvA.alloc(L.n, c.s);
   L.dinvAn.alloc(L.m, c.s);
   diagonal(L.A, L.dinvA.p, true, c);
@@ -1811,6 +1838,7 @@ static std::unique_ptr<Level> coarsen(Hierarchy& H, Level& L, const int32_t* agg
     Csr AP;
     spgemm(L.A, L.Pe, AP, true, c, L.fine ? "spgemm_AP_l0" : "spgemm_AP");
     spgemm(L.PeT, AP, next->A, true, c, L.fine ? "spgemm_PtAP_l0" : "spgemm_PtAP");
+    keep_shape(AP, L.APshape);
   }
   L.has_transfer = true;
   return next;
@@ -1915,18 +1943,28 @@ void update_hierarchy(Hierarchy& H, const hcurl_csr& A, int mode, int iters) {
   for (size_t l = 0; l + 1 < H.lv.size(); ++l) {
     Level& L = *H.lv[l];
     Level& N = *H.lv[l + 1];
-    nodal_operators(H, L);
+    nodal_operators(H, L, true);
     if (mode == HCURL_REUSE_WARM) {
       if (!(l == 0 && H.pn_given)) smoothed_aggregation(H, L, L.agg.p, L.Pn.ncols);
       gradient_product(L.D, L.Pn, L.R, c, L.fine ? "grad_DPn_l0" : "grad_DPn");
       energy_minimisation(H, L, &N, K, true, L.Pe.val.p, true, false);
-      transpose(L.Pe, L.PeT, true, c);
+      transpose_refill(L.Pe, L.PeT, c);
     } else {
       L.energy.clear();
     }
+    // P^(e) keeps its pattern in both modes: A P^(e) and the Galerkin
+    // product keep theirs
     Csr AP;
-    spgemm(L.A, L.Pe, AP, true, c, L.fine ? "spgemm_AP_l0" : "spgemm_AP");
-    spgemm(L.PeT, AP, N.A, true, c, L.fine ? "spgemm_PtAP_l0" : "spgemm_PtAP");
+    const char* tAP = L.fine ? "spgemm_AP_l0" : "spgemm_AP";
+    const char* tPtAP = L.fine ? "spgemm_PtAP_l0" : "spgemm_PtAP";
+    if (N.A.rowptr.p && take_shape(L.APshape, AP)) {
+      spgemm_refill(L.A, L.Pe, AP, c, tAP);
+      spgemm_refill(L.PeT, AP, N.A, c, tPtAP);
+    } else {
+      spgemm(L.A, L.Pe, AP, true, c, tAP);
+      spgemm(L.PeT, AP, N.A, true, c, tPtAP);
+    }
+    keep_shape(AP, L.APshape);
   }
   coarsest_factor(H, *H.lv.back());
   prepare_solve(H);
