@@ -154,7 +154,9 @@ typedef struct {
                               row i's pattern), and the later products of that
                               minimisation read the codes back instead of searching.
                               The codes live while the minimisation runs; a level
-                              whose codes would take more than 16 GiB searches.
+                              whose codes would take more than 16 GiB or half the
+                              free device memory, or whose allocation for them
+                              fails with HCURL_ENOMEM, searches.
                               0: every product searches.  Both give the same
                               P^(e) to rounding (the sums are LDS atomics). */
   int profile;             /* 0: off.  1: time every eagerly launched kernel with HIP

@@ -1055,8 +1055,20 @@ static void emin_map_prepare(Level& L, EminMap& m, Ctx& c) {
   d2h(&m.nprod, m.off.p + grid, 1, c);
   m.built = false;
   m.on = m.nprod > 0 && 2.0 * (double)m.nprod <= kEminMapMaxBytes;
-  if (m.on) m.codes.alloc((size_t)m.nprod, c.s);
-  else m.off.release();
+  // the codes are an optimisation: without room for them every launch searches
+  size_t free_b = 0, total_b = 0;
+  if (m.on && hipMemGetInfo(&free_b, &total_b) == hipSuccess && 2.0 * (double)m.nprod > 0.5 * (double)free_b)
+    m.on = false;
+  if (m.on) {
+    try {
+      m.codes.alloc((size_t)m.nprod, c.s);
+    } catch (const Error& e) {
+      if (e.code != HCURL_ENOMEM) throw;
+      (void)hipGetLastError();
+      m.on = false;
+    }
+  }
+  if (!m.on) m.off.release();
 }
 
 static int emin_apply(Level& L, const double* dscale, const double* X, double* Out, int flags, double* part, double* Y,

@@ -77,6 +77,38 @@ def test_refusing_allocator_gives_enomem_and_leaks_nothing():
         assert not t.live and t.bad_free == 0 and t.n_alloc == limit
 
 
+def test_masked_product_codes_fall_back_when_their_allocation_fails():
+    """A NULL from the caller's allocator for the masked product's codes (2
+    bytes per product a_ik x_kj of A X on the pattern) makes that energy
+    minimisation search in every product instead of failing: the setup
+    completes, with the P^(e) of the default run to rounding."""
+    import paper_2506_08284_amd as P
+    pr, m, Dh = _case()
+    levels = O.setup(pr["A"], pr["tail"], pr["head"], m, pr["aggregates"])
+    A, N = O.csr(levels[0]["A"]), O.csr(levels[0]["N"])
+    codes = 2 * int(np.sum(np.diff(N.indptr)[A.indices]))
+
+    class RefuseCodes(Tracker):
+        def __init__(self):
+            super().__init__()
+            self.refused = 0
+
+        def alloc(self, nbytes, stream):
+            if nbytes == codes:
+                self.refused += 1
+                return 0
+            return super().alloc(nbytes, stream)
+
+    t = RefuseCodes()
+    H = P.Hierarchy(pr["A"], Dh, pr["aggregates"], n_nodes=m, allocator=(t.alloc, t.free))
+    H0 = P.Hierarchy(pr["A"], Dh, pr["aggregates"], n_nodes=m)
+    pe, pe0 = H.export_csr(0, "Pe")[0][2], H0.export_csr(0, "Pe")[0][2]
+    H.close()
+    H0.close()
+    assert t.refused == 1 and not t.live and t.bad_free == 0
+    assert np.max(np.abs(pe - pe0)) <= 1e-13 * np.max(np.abs(pe0))
+
+
 def test_torch_allocator_on_a_stream_with_graphs():
     import torch
     import paper_2506_08284_amd as P
