@@ -669,8 +669,8 @@ __global__ void k_make_feasible(int n, const int* __restrict__ Prp, double* __re
 // of the A-columns of each chunk of 64 A entries); each product finds its
 // owner (the chunk's A entry) and its slot in the owner row's pattern (binary
 // searches in LDS) and accumulates there with an LDS atomic.  Two products
-// per lane are in flight at a time.  With EM_DOT the block also sums X * Y
-// (the energy <P, A P>).
+// per lane are in flight at a time (kMapBatch when reading codes back).  With
+// EM_DOT the block also sums X * Y (the energy <P, A P>).
 //
 // The pattern stays fixed over the iterations of an energy minimisation, so
 // the first launch can record both searches per product (MAP = 1) and the
