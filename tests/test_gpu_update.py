@@ -7,7 +7,8 @@ two systems on one mesh (lognormal sigma from two seeds, same pattern).
   Galerkin operators and the solve;
 * device pointers on a stream (graphs captured before the update are
   dropped and captured again) against the host-pointer run;
-* errors: a different pattern is refused and leaves the handle usable."""
+* errors: a different pattern is refused and leaves the handle usable;
+* updates in a row on one handle (the products' kept patterns reused)."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -178,3 +179,35 @@ def test_update_errors_leave_the_handle_usable():
     it, rel, rc = H.solve(other["f"], u)
     assert rc == 0 and rel <= 1e-8
     H.close()
+
+
+def test_repeated_updates_reuse_the_kept_product_patterns():
+    """Updates in a row on one handle (A1 -> A2 -> A1, transfers kept, then A2
+    warm) run only the numeric passes of the products on the patterns kept
+    from the setup: going back to A1 gives the setup's operators on every
+    level, and the final warm update the operators of a fresh setup on A1
+    followed by the same warm update, both to rounding."""
+    p1, p2, m, lv = _pair()
+    H = _hierarchy(p1, m)
+    nl = H.num_levels()
+    ref = [(_export(H, l, "A"), _export(H, l, "An") if l + 1 < nl else None) for l in range(nl)]
+    H.update(p2["A"], "transfers")
+    H.update(p1["A"], "transfers")
+    for l in range(nl):
+        _close(_export(H, l, "A"), ref[l][0], 1e-12)
+        if ref[l][1] is not None:
+            _close(_export(H, l, "An"), ref[l][1], 1e-12)
+    H.update(p2["A"], "warm", 3)
+    H2 = _hierarchy(p1, m)
+    H2.update(p2["A"], "warm", 3)
+    for l in range(nl):
+        _close(_export(H, l, "A"), _export(H2, l, "A"), 1e-12)
+    for l in range(nl - 1):
+        _close(_export(H, l, "Pe"), _export(H2, l, "Pe"), 1e-12)
+    n = p2["A"][0].shape[0] - 1
+    u, u2 = np.empty(n), np.empty(n)
+    it, rel, rc = H.solve(p2["f"], u)
+    it2, rel2, rc2 = H2.solve(p2["f"], u2)
+    assert rc == rc2 == 0 and rel <= 1e-8 and abs(it - it2) <= 1
+    H.close()
+    H2.close()
