@@ -775,8 +775,10 @@ __global__ void __launch_bounds__(64) k_emin_masked(int nrows, int R, const int*
                                                     const double* __restrict__ dscale, const int* __restrict__ Prp,
                                                     const int* __restrict__ Pcol, const double* __restrict__ X,
                                                     double* __restrict__ Y, int flags, double* __restrict__ part,
-                                                    uint16_t* __restrict__ pmap, const long long* __restrict__ moff) {
-  __shared__ int pcol[MAP == 2 ? 1 : CAP];
+                                                    uint16_t* __restrict__ pmap, const long long* __restrict__ moff,
+                                                    int2* __restrict__ asl) {
+  static_assert(MAP == 0 || MAP == 1, "the read-back launches use k_emin_masked_codes");
+  __shared__ int pcol[CAP];
   __shared__ double acc[CAP];
   __shared__ int pofs[kRowsCap + 1];
   __shared__ int arp[kRowsCap + 1];
@@ -790,7 +792,7 @@ __global__ void __launch_bounds__(64) k_emin_masked(int nrows, int R, const int*
     const int r0 = rb * R, r1 = min(r0 + R, nrows), nr = r1 - r0;
     const int p0 = Prp[r0], pn = Prp[r1] - p0;
     for (int t = l; t < pn; t += 64) {
-      if (MAP != 2) pcol[t] = Pcol[p0 + t];
+      pcol[t] = Pcol[p0 + t];
       acc[t] = 0.0;
     }
     for (int t = l; t <= nr; t += 64) { pofs[t] = Prp[r0 + t] - p0; arp[t] = Arp[r0 + t]; }
@@ -801,54 +803,31 @@ __global__ void __launch_bounds__(64) k_emin_masked(int nrows, int R, const int*
       int st = 0, len = 0, rl = 0;
       double a = 0.0;
       if (q < a1) {
-        // the owner row of A entry q is only needed for the slot search (a
-        // row with an empty pattern gets no hits)
-        if (MAP != 2) {
-          int lo = 0, hi = nr - 1;
-          while (lo < hi) {  // largest rl with arp[rl] <= q
-            const int mid = (lo + hi + 1) >> 1;
-            if (arp[mid] <= q) lo = mid; else hi = mid - 1;
-          }
-          rl = lo;
+        // the owner row of A entry q, for the slot search (a row with an
+        // empty pattern gets no hits)
+        int lo = 0, hi = nr - 1;
+        while (lo < hi) {  // largest rl with arp[rl] <= q
+          const int mid = (lo + hi + 1) >> 1;
+          if (arp[mid] <= q) lo = mid; else hi = mid - 1;
         }
+        rl = lo;
         const int k = Acol[q];
         a = Aval[q];
         st = Prp[k];
         len = Prp[k + 1] - st;
+        if (MAP == 1) asl[q] = make_int2(st, len);
       }
       const int incl = wave_incl_scan(len);
       const int total = __shfl(incl, 63, 64);
       kst[l] = st; pre[l] = incl - len; arow[l] = rl; av[l] = a;
       __syncthreads();
       int p = l;
-      if (MAP == 2) {
-        // kMapBatch products per lane: their codes, then their X gathers,
-        // then their LDS sums, so the loads of a batch are in flight together
-        const uint16_t* mp = pmap + mb;
-        for (; p < total; p += 64 * kMapBatch) {
-          unsigned m[kMapBatch];
-#pragma unroll
-          for (int u = 0; u < kMapBatch; ++u) m[u] = p + 64 * u < total ? mp[p + 64 * u] : kNoSlot;
-          double xv[kMapBatch];
-          int sl[kMapBatch];
-#pragma unroll
-          for (int u = 0; u < kMapBatch; ++u) {
-            const int o = m[u] & 63;
-            sl[u] = (int)(m[u] >> 6);
-            xv[u] = m[u] != kNoSlot ? av[o] * X[kst[o] + (p + 64 * u - pre[o])] : 0.0;
-          }
-#pragma unroll
-          for (int u = 0; u < kMapBatch; ++u)
-            if (m[u] != kNoSlot) atomicAdd(&acc[sl[u]], xv[u]);
-        }
-      } else {
-        uint16_t* mp = MAP ? pmap + mb : nullptr;
-        for (; p + 64 < total; p += 128) {
-          emin_product<MAP == 1>(p, pre, kst, arow, av, pofs, pcol, acc, Pcol, X, mp);
-          emin_product<MAP == 1>(p + 64, pre, kst, arow, av, pofs, pcol, acc, Pcol, X, mp);
-        }
-        if (p < total) emin_product<MAP == 1>(p, pre, kst, arow, av, pofs, pcol, acc, Pcol, X, mp);
+      uint16_t* mp = MAP ? pmap + mb : nullptr;
+      for (; p + 64 < total; p += 128) {
+        emin_product<MAP == 1>(p, pre, kst, arow, av, pofs, pcol, acc, Pcol, X, mp);
+        emin_product<MAP == 1>(p + 64, pre, kst, arow, av, pofs, pcol, acc, Pcol, X, mp);
       }
+      if (p < total) emin_product<MAP == 1>(p, pre, kst, arow, av, pofs, pcol, acc, Pcol, X, mp);
       mb += total;
       __syncthreads();
     }
@@ -866,6 +845,95 @@ __global__ void __launch_bounds__(64) k_emin_masked(int nrows, int R, const int*
       if (flags & EM_DOT) dsum += X[p0 + t] * v;
     }
     __syncthreads();
+  }
+  dsum = wave_sum(dsum);
+  if (l == 0) part[blockIdx.x] = dsum;
+}
+
+// LDS-only barrier for single-wave workgroups: waits for this wave's LDS
+// operations, not its global loads, so loads issued before it stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// The read-back launches of the masked product (codes recorded by
+// k_emin_masked<CAP, 1>, which also stored every A entry's pattern start and
+// length of its column in asl).  The same products, in the same order, go to
+// the same LDS sums; the next chunk's A entries are loaded while the current
+// chunk's products run.
+template <int CAP>
+__global__ void __launch_bounds__(64) k_emin_masked_codes(int nrows, int R, const int* __restrict__ Arp,
+                                                          const double* __restrict__ Aval, const int2* __restrict__ asl,
+                                                          const double* __restrict__ dscale, const int* __restrict__ Prp,
+                                                          const double* __restrict__ X, double* __restrict__ Y, int flags,
+                                                          double* __restrict__ part, const uint16_t* __restrict__ codes,
+                                                          const long long* __restrict__ moff) {
+  __shared__ double acc[CAP];
+  __shared__ int pofs[kRowsCap + 1];
+  __shared__ int kst[64], pre[64];
+  __shared__ double av[64];
+  const int l = threadIdx.x;
+  const RowBlocks B(nrows, R);
+  long long mb = moff[blockIdx.x];
+  double dsum = 0.0;
+  for (int rb = B.first(); rb < B.end(); rb += B.nw) {
+    const int r0 = rb * R, r1 = min(r0 + R, nrows), nr = r1 - r0;
+    const int p0 = Prp[r0], pn = Prp[r1] - p0;
+    const int a0 = Arp[r0], a1 = Arp[r1];
+    int2 nsl = make_int2(0, 0);
+    double na = 0.0;
+    if (a0 + l < a1) { nsl = asl[a0 + l]; na = Aval[a0 + l]; }
+    for (int t = l; t < pn; t += 64) acc[t] = 0.0;
+    for (int t = l; t <= nr; t += 64) pofs[t] = Prp[r0 + t] - p0;
+    lds_barrier();
+    for (int c0 = a0; c0 < a1; c0 += 64) {
+      const int st = nsl.x, len = nsl.y;
+      const double a = na;
+      nsl = make_int2(0, 0);
+      na = 0.0;
+      if (c0 + 64 + l < a1) { nsl = asl[c0 + 64 + l]; na = Aval[c0 + 64 + l]; }
+      const int incl = wave_incl_scan(len);
+      const int total = __shfl(incl, 63, 64);
+      kst[l] = st; pre[l] = incl - len; av[l] = a;
+      lds_barrier();
+      // kMapBatch products per lane: their codes, then their X gathers,
+      // then their LDS sums, so the loads of a batch are in flight together
+      const uint16_t* mp = codes + mb;
+      for (int p = l; p < total; p += 64 * kMapBatch) {
+        unsigned m[kMapBatch];
+#pragma unroll
+        for (int u = 0; u < kMapBatch; ++u) m[u] = p + 64 * u < total ? mp[p + 64 * u] : kNoSlot;
+        double xv[kMapBatch];
+        int sl[kMapBatch];
+#pragma unroll
+        for (int u = 0; u < kMapBatch; ++u) {
+          const int o = m[u] & 63;
+          sl[u] = (int)(m[u] >> 6);
+          xv[u] = m[u] != kNoSlot ? av[o] * X[kst[o] + (p + 64 * u - pre[o])] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kMapBatch; ++u)
+          if (m[u] != kNoSlot) atomicAdd(&acc[sl[u]], xv[u]);
+      }
+      mb += total;
+      lds_barrier();
+    }
+    for (int t = l; t < pn; t += 64) {
+      double v = acc[t];
+      if (dscale) {
+        int lo = 0, hi = nr - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (pofs[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        v *= dscale[r0 + lo];
+      }
+      Y[p0 + t] = v;
+      if (flags & EM_DOT) dsum += X[p0 + t] * v;
+    }
+    lds_barrier();
   }
   dsum = wave_sum(dsum);
   if (l == 0) part[blockIdx.x] = dsum;
@@ -1035,6 +1103,7 @@ static int emin_rows_per_block(const Level& L) {
 // The product codes of one energy minimisation (see k_emin_masked).
 struct EminMap {
   DBuf<uint16_t> codes;
+  DBuf<int2> asl;  // per A entry: pattern start and length of its column
   DBuf<long long> off;
   long long nprod = 0;
   bool on = false, built = false;
@@ -1054,21 +1123,22 @@ static void emin_map_prepare(Level& L, EminMap& m, Ctx& c) {
   c.run("emin_map_offsets", 16.0 * grid, [&] { k_emin_map_offsets<<<1, 1024, 0, c.s>>>(cnt.p, grid, m.off.p); });
   d2h(&m.nprod, m.off.p + grid, 1, c);
   m.built = false;
-  m.on = m.nprod > 0 && 2.0 * (double)m.nprod <= kEminMapMaxBytes;
+  const double need = 2.0 * (double)m.nprod + 8.0 * (double)L.A.nnz;
+  m.on = m.nprod > 0 && need <= kEminMapMaxBytes;
   // the codes are an optimisation: without room for them every launch searches
   size_t free_b = 0, total_b = 0;
-  if (m.on && hipMemGetInfo(&free_b, &total_b) == hipSuccess && 2.0 * (double)m.nprod > 0.5 * (double)free_b)
-    m.on = false;
+  if (m.on && hipMemGetInfo(&free_b, &total_b) == hipSuccess && need > 0.5 * (double)free_b) m.on = false;
   if (m.on) {
     try {
       m.codes.alloc((size_t)m.nprod, c.s);
+      m.asl.alloc((size_t)L.A.nnz, c.s);
     } catch (const Error& e) {
       if (e.code != HCURL_ENOMEM) throw;
       (void)hipGetLastError();
       m.on = false;
     }
   }
-  if (!m.on) m.off.release();
+  if (!m.on) { m.codes.release(); m.asl.release(); m.off.release(); }
 }
 
 static int emin_apply(Level& L, const double* dscale, const double* X, double* Out, int flags, double* part, double* Y,
@@ -1077,20 +1147,27 @@ static int emin_apply(Level& L, const double* dscale, const double* X, double* O
   const bool small = L.maxNp * 4 <= kPatSmall;
   const int grid = emin_grid(L.n, R);
   const int mode = em && em->on ? (em->built ? 2 : 1) : 0;
-  // the read-back launch does not read the pattern's columns
+  // the read-back launch reads the A entries' recorded pattern starts and
+  // lengths (8 bytes) in place of their columns, and not the pattern's columns
+  const double abytes = mode == 2 ? 16.0 * L.A.nnz : 12.0 * L.A.nnz + (mode == 1 ? 8.0 * L.A.nnz : 0.0);
   const double pbytes = mode == 2 ? 16.0 * L.Pe.nnz : 20.0 * L.Pe.nnz;
   const double mbytes = mode ? 2.0 * (double)em->nprod : 0.0;
-  const double bytes = 12.0 * L.A.nnz + 4.0 * (L.n + 1) * 2 + pbytes + mbytes;
+  const double bytes = abytes + 4.0 * (L.n + 1) * 2 + pbytes + mbytes;
   const bool proj = flags & EM_PROJECT;
   double* tgt = proj ? Y : Out;
   uint16_t* codes = mode ? em->codes.p : nullptr;
+  int2* asl = mode ? em->asl.p : nullptr;
   const long long* moff = mode ? em->off.p : nullptr;
   const char* tag = mode == 1 ? (L.fine ? "emin_masked_build_l0" : "emin_masked_build")
                               : (L.fine ? "emin_masked_spgemm_l0" : "emin_masked_spgemm");
   auto launch = [&](auto cap, auto md) {
-    k_emin_masked<decltype(cap)::value, decltype(md)::value><<<grid, 64, 0, c.s>>>(
-        L.n, R, L.A.rowptr.p, L.A.col.p, L.A.val.p, dscale, L.Pe.rowptr.p, L.Pe.col.p, X, tgt, proj ? 0 : flags, part,
-        codes, moff);
+    constexpr int CAPV = decltype(cap)::value, MD = decltype(md)::value;
+    if constexpr (MD == 2)
+      k_emin_masked_codes<CAPV><<<grid, 64, 0, c.s>>>(L.n, R, L.A.rowptr.p, L.A.val.p, asl, dscale, L.Pe.rowptr.p, X, tgt,
+                                                      proj ? 0 : flags, part, codes, moff);
+    else
+      k_emin_masked<CAPV, MD><<<grid, 64, 0, c.s>>>(L.n, R, L.A.rowptr.p, L.A.col.p, L.A.val.p, dscale, L.Pe.rowptr.p,
+                                                    L.Pe.col.p, X, tgt, proj ? 0 : flags, part, codes, moff, asl);
   };
   using SmallCap = std::integral_constant<int, kPatSmall>;
   using BigCap = std::integral_constant<int, kPatCap>;
