@@ -88,6 +88,50 @@ __global__ void k_scatter_eq(const int* __restrict__ key, int n, int k, const in
   if (v < n && key[v] == k) rows[base + pos[v]] = v;
 }
 
+// Stable grouping of the rows by colour in two passes over blocks of 256
+// rows: per-block counts of every colour (stored colour-major, so that one
+// exclusive scan gives every (colour, block) its first slot), then every row
+// goes to its slot plus its rank among the block's earlier rows of its colour
+// (wave ballots per colour present in the wave, then the counts of the
+// block's earlier waves).
+static constexpr int kGroupLds = 1024;
+__global__ void __launch_bounds__(256) k_block_colour_count(const int* __restrict__ color, int n, int ncol, int nb,
+                                                            int* __restrict__ cnt) {
+  __shared__ int h[kGroupLds];
+  for (int k = threadIdx.x; k < ncol; k += 256) h[k] = 0;
+  __syncthreads();
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  if (v < n) atomicAdd(&h[color[v]], 1);
+  __syncthreads();
+  for (int k = threadIdx.x; k < ncol; k += 256) cnt[(int64_t)k * nb + blockIdx.x] = h[k];
+}
+
+__global__ void __launch_bounds__(256) k_block_colour_scatter(const int* __restrict__ color, int n, int ncol, int nb,
+                                                              const int* __restrict__ off, int* __restrict__ rows) {
+  __shared__ int wc[4][kGroupLds];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  for (int k = l; k < ncol; k += 64) wc[w][k] = 0;
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  const int k = v < n ? color[v] : -1;
+  // rank among the wave's earlier lanes of the same colour
+  int rank = 0;
+  unsigned long long todo = __ballot(k >= 0);
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int kc = __shfl(k, leader, 64);
+    const unsigned long long m = __ballot(k == kc);
+    if (k == kc) rank = __popcll(m & ((1ull << l) - 1ull));
+    if (l == leader) wc[w][kc] = __popcll(m);
+    todo &= ~m;
+  }
+  __syncthreads();
+  if (k >= 0) {
+    int base = off[(int64_t)k * nb + blockIdx.x];
+    for (int u = 0; u < w; ++u) base += wc[u][k];
+    rows[base + rank] = v;
+  }
+}
+
 void color_rows(const Csr& A, DBuf<int>& color, DBuf<int>& rows, std::vector<int>& cptr, int& ncol, Ctx& c) {
   const int n = A.nrows;
   color.alloc(n, c.s);
@@ -110,22 +154,35 @@ void color_rows(const Csr& A, DBuf<int>& color, DBuf<int>& rows, std::vector<int
   ncol = 0;
   for (int v : hc_) ncol = std::max(ncol, v + 1);
   const int nk = ncol;
-  DBuf<int> key(n + 1, c.s), hist(nk, c.s), flag(n + 1, c.s), pos(n + 1, c.s);
+  DBuf<int> key(n + 1, c.s), hist(nk, c.s);
   HC_HIP(hipMemsetAsync(hist.p, 0, sizeof(int) * nk, c.s));
   if (n) k_group_key<<<(int)std::min<int64_t>(ceil_div(n, 256), 2048), 256, 0, c.s>>>(color.p, n, ncol, key.p, hist.p);
   HC_LAUNCH_CHECK();
   std::vector<int> hh(nk);
   d2h(hh.data(), hist.p, nk, c);
   cptr.assign(ncol + 1, 0);
-  int base = 0;
-  for (int k = 0; k < nk; ++k) {
-    if (hh[k] == 0) continue;
-    k_flag_eq<<<ceil_div(n, 256), 256, 0, c.s>>>(key.p, n, k, flag.p);
-    HC_LAUNCH_CHECK();
-    exclusive_scan(flag.p, pos.p, n, c);
-    k_scatter_eq<<<ceil_div(n, 256), 256, 0, c.s>>>(key.p, n, k, pos.p, base, rows.p);
-    HC_LAUNCH_CHECK();
-    base += hh[k];
+  const int nb = ceil_div(n, 256);
+  if (nk <= kGroupLds && (int64_t)nk * nb < (int64_t)1 << 31) {
+    DBuf<int> bcnt((int64_t)nk * nb, c.s), boff((int64_t)nk * nb + 1, c.s);
+    c.run("colour_group", 4.0 * n + 4.0 * nk * nb, [&] {
+      k_block_colour_count<<<nb, 256, 0, c.s>>>(color.p, n, nk, nb, bcnt.p);
+    });
+    exclusive_scan(bcnt.p, boff.p, (int64_t)nk * nb, c);
+    c.run("colour_group", 8.0 * n + 4.0 * nk * nb, [&] {
+      k_block_colour_scatter<<<nb, 256, 0, c.s>>>(color.p, n, nk, nb, boff.p, rows.p);
+    });
+  } else {
+    DBuf<int> flag(n + 1, c.s), pos(n + 1, c.s);
+    int base = 0;
+    for (int k = 0; k < nk; ++k) {
+      if (hh[k] == 0) continue;
+      k_flag_eq<<<ceil_div(n, 256), 256, 0, c.s>>>(key.p, n, k, flag.p);
+      HC_LAUNCH_CHECK();
+      exclusive_scan(flag.p, pos.p, n, c);
+      k_scatter_eq<<<ceil_div(n, 256), 256, 0, c.s>>>(key.p, n, k, pos.p, base, rows.p);
+      HC_LAUNCH_CHECK();
+      base += hh[k];
+    }
   }
   for (int k = 0; k < nk; ++k) cptr[k + 1] += hh[k];
   for (int k = 0; k < ncol; ++k) cptr[k + 1] += cptr[k];
