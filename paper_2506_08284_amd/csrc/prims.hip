@@ -222,12 +222,27 @@ __global__ void __launch_bounds__(64) k_sort_rows(const int* __restrict__ rowptr
       if (val) vv[t] = val[a + t];
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < len; t += 64) {
-      const int key = kk[t];
-      int r = 0;
-      for (int u = 0; u < len; ++u) r += kk[u] < key;
-      col[a + r] = key;
-      if (val) val[a + r] = vv[t];
+    // up to four keys per lane ranked in one pass over the row
+    for (int t0 = threadIdx.x; t0 < len; t0 += 256) {
+      int key[4], r[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        key[j] = t0 + 64 * j < len ? kk[t0 + 64 * j] : 0x7fffffff;
+        r[j] = 0;
+      }
+      for (int u = 0; u < len; ++u) {
+        const int kv = kk[u];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) r[j] += kv < key[j];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int t = t0 + 64 * j;
+        if (t < len) {
+          col[a + r[j]] = key[j];
+          if (val) val[a + r[j]] = vv[t];
+        }
+      }
     }
     __syncthreads();
   }
