@@ -184,20 +184,44 @@ void copy_csr(const Csr& A, Csr& B, Ctx& c) {
 // ---------------------------------------------------------------------------
 // transpose: count, scan, scatter with cursors, then sort every output row
 // ---------------------------------------------------------------------------
-__global__ void k_col_count(const int* __restrict__ col, int64_t nnz, int* __restrict__ cnt) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nnz) atomicAdd(&cnt[col[i]], 1);
-}
-
-__global__ void k_transpose_scatter(const int* __restrict__ rowptr, const int* __restrict__ col,
-                                    const double* __restrict__ val, int nrows, int* __restrict__ cursor,
-                                    int* __restrict__ tcol, double* __restrict__ tval) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nrows) return;
-  for (int q = rowptr[i]; q < rowptr[i + 1]; ++q) {
-    int pos = atomicAdd(&cursor[col[q]], 1);
-    tcol[pos] = i;
-    if (val) tval[pos] = val[q];
+// One wave takes 64 consecutive rows and walks their entries slot by slot;
+// the lanes whose rows hold the same column in a slot share one atomic (the
+// rows of a mesh operator's neighbourhood repeat each other's columns).
+// Positions inside an output row are in no particular order: sort_rows
+// orders them.
+template <bool SCATTER>
+__global__ void __launch_bounds__(256) k_transpose_pass(const int* __restrict__ rowptr, const int* __restrict__ col,
+                                                        const double* __restrict__ val, int nrows,
+                                                        int* __restrict__ cursor, int* __restrict__ tcol,
+                                                        double* __restrict__ tval) {
+  const int i = (int)((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  const int l = threadIdx.x & 63;
+  const int a = i < nrows ? rowptr[i] : 0, len = i < nrows ? rowptr[i + 1] - a : 0;
+  int maxlen = len;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, o, 64));
+  for (int j = 0; j < maxlen; ++j) {
+    const int c = j < len ? col[a + j] : -1;
+    unsigned long long todo = __ballot(c >= 0);
+    int pos = 0;
+    while (todo) {
+      const int leader = __ffsll((long long)todo) - 1;
+      const int cc = __shfl(c, leader, 64);
+      const unsigned long long m = __ballot(c == cc);
+      if (SCATTER) {
+        int base = 0;
+        if (l == leader) base = atomicAdd(&cursor[cc], __popcll(m));
+        base = __shfl(base, leader, 64);
+        if (c == cc) pos = base + __popcll(m & ((1ull << l) - 1ull));
+      } else if (l == leader) {
+        atomicAdd(&cursor[cc], __popcll(m));
+      }
+      todo &= ~m;
+    }
+    if (SCATTER && c >= 0) {
+      tcol[pos] = i;
+      if (val) tval[pos] = val[a + j];
+    }
   }
 }
 
@@ -329,13 +353,18 @@ void transpose(const Csr& A, Csr& AT, bool values, Ctx& c) {
   if (values) AT.val.alloc(A.nnz, c.s); else AT.val.release();
   DBuf<int> cnt(AT.nrows + 1, c.s);
   HC_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int) * (AT.nrows + 1), c.s));
-  if (A.nnz) c.run("transpose", 8.0 * A.nnz, [&] { k_col_count<<<ceil_div(A.nnz, 256), 256, 0, c.s>>>(A.col.p, A.nnz, cnt.p); });
+  if (A.nnz)
+    c.run("transpose", 8.0 * A.nnz, [&] {
+      k_transpose_pass<false><<<ceil_div(A.nrows, 256), 256, 0, c.s>>>(A.rowptr.p, A.col.p, nullptr, A.nrows, cnt.p,
+                                                                     nullptr, nullptr);
+    });
   exclusive_scan(cnt.p, AT.rowptr.p, AT.nrows, c);
   d2d(cnt.p, AT.rowptr.p, AT.nrows, c);
   if (A.nrows)
     c.run("transpose", 24.0 * A.nnz, [&] {
-      k_transpose_scatter<<<ceil_div(A.nrows, 256), 256, 0, c.s>>>(A.rowptr.p, A.col.p, values ? A.val.p : nullptr,
-                                                                  A.nrows, cnt.p, AT.col.p, values ? AT.val.p : nullptr);
+      k_transpose_pass<true><<<ceil_div(A.nrows, 256), 256, 0, c.s>>>(A.rowptr.p, A.col.p, values ? A.val.p : nullptr,
+                                                                    A.nrows, cnt.p, AT.col.p,
+                                                                    values ? AT.val.p : nullptr);
     });
   sort_rows(AT, c);
 }
