@@ -813,16 +813,21 @@ static void make32(Csr& A, Ctx& c) {
 // |S||x|: an operator rounded with relative error u leaves an error of about
 // u times this ratio relative to the result.
 // s_e = sum_f |a_ef| (|D| 1)_f: two per edge, one per Dirichlet edge
-__global__ void k_abs_rowsum(const int* __restrict__ rp, const int* __restrict__ col, const double* __restrict__ val,
-                             const int* __restrict__ drp, int n, double* __restrict__ s) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// eight lanes per row (coalesced loads of the row's entries), shuffle sum
+__global__ void __launch_bounds__(256) k_abs_rowsum(const int* __restrict__ rp, const int* __restrict__ col,
+                                                    const double* __restrict__ val, const int* __restrict__ drp, int n,
+                                                    double* __restrict__ s) {
+  const int i = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3);
+  const int l = threadIdx.x & 7;
   double t = 0.0;
-  for (int q = rp[i]; q < rp[i + 1]; ++q) {
-    const int f = col[q];
-    t += fabs(val[q]) * (double)(drp[f + 1] - drp[f]);
-  }
-  s[i] = t;
+  if (i < n)
+    for (int q = rp[i] + l; q < rp[i + 1]; q += 8) {
+      const int f = col[q];
+      t += fabs(val[q]) * (double)(drp[f + 1] - drp[f]);
+    }
+#pragma unroll
+  for (int o = 4; o > 0; o >>= 1) t += __shfl_xor(t, o, 8);
+  if (i < n && l == 0) s[i] = t;
 }
 __global__ void __launch_bounds__(256) k_cancel_max(const int* __restrict__ rp, const int* __restrict__ col, int m,
                                                     const double* __restrict__ s, const double* __restrict__ dinv,
@@ -854,7 +859,8 @@ static double cancellation_ratio(Level& L, Ctx& c) {
   s.alloc(L.n, c.s);
   HC_HIP(hipMemsetAsync(out, 0, sizeof(unsigned long long), c.s));
   c.run("cancel_rowsum", 16.0 * L.A.nnz, [&] {
-    k_abs_rowsum<<<ceil_div(L.n, 256), 256, 0, c.s>>>(L.A.rowptr.p, L.A.col.p, L.A.val.p, L.D.rowptr.p, L.n, s.p);
+    k_abs_rowsum<<<ceil_div((int64_t)L.n * 8, 256), 256, 0, c.s>>>(L.A.rowptr.p, L.A.col.p, L.A.val.p, L.D.rowptr.p,
+                                                                  L.n, s.p);
   });
   c.run("cancel_max", 12.0 * L.DT.nnz, [&] {
     k_cancel_max<<<ceil_div(L.m, 256), 256, 0, c.s>>>(L.DT.rowptr.p, L.DT.col.p, L.m, s.p, L.dinvAn.p, out);
