@@ -699,6 +699,8 @@ struct RowBlocks {
   __device__ int end() const { return min(nbr, (xcd + 1) * chunk); }
 };
 
+// code of a product whose column is not in its owner row's pattern (owner
+// lane 63 with slot 1023, which no row block reaches: slots stay below kPatCap)
 static constexpr unsigned kNoSlot = 0xFFFFu;
 
 template <bool BUILD>
@@ -724,6 +726,8 @@ __device__ __forceinline__ void emin_product(int p, const int* pre, const int* k
   if (BUILD) mp[p] = hit ? (uint16_t)(lo | (s << 6)) : (uint16_t)kNoSlot;
 }
 
+// products per lane in flight in the read-back launches: four keep eight
+// waves per SIMD; eight need more registers and ran slower
 static constexpr int kMapBatch = 4;
 
 // Products per workgroup of k_emin_masked (same grid, same row blocks): the
@@ -1109,7 +1113,8 @@ struct EminMap {
   bool on = false, built = false;
 };
 
-// Codes take 2 bytes per product; above this size the searches are repeated.
+// Codes take 2 bytes per product and the A-entry records 8 bytes per entry;
+// above this size the searches are repeated.
 static constexpr double kEminMapMaxBytes = 16.0 * (1 << 30);
 
 static void emin_map_prepare(Level& L, EminMap& m, Ctx& c) {
